@@ -1,0 +1,328 @@
+"""Plain FP64 trace-minimization eigensolver (CPU oracle, test infrastructure).
+
+Follows Tsuchida & Choe, "Iterative diagonalization of symmetric matrices in
+mixed precision":
+
+* E(C) = trace(C^T H C) minimized subject to C^T C = I (Sec. 2.1, Eq. 4-7);
+  at the minimum E equals E_G, the sum of the m lowest eigenvalues (Eq. 2).
+* Nonlinear conjugate gradients (Fig. 1) with the Polak-Ribiere gamma (Eq. 8).
+* Energy and gradient (Fig. 2): Algorithm-1 is the plain form used here;
+  Algorithm-2 is provided to check that the two agree.
+* Cholesky orthonormalization (Fig. 4), read as Cholesky-QR: S = C^T C = R^T R
+  with R upper triangular (R = L^T), and C_out = C_in R^{-1}.  Taken
+  literally, C_in L^{-1} with S = L L^T does not give orthonormal columns; the
+  only product of C_in with a triangular factor of S that does is C_in L^{-T}.
+* Optional diagonal preconditioner G' = M G (Sec. 4, Eq. 18).
+* Explicit eigenpairs from diagonalizing the m x m H once HC = CH (Eq. 9),
+  also used as the occasional subspace rotation (Sec. 3, MP2 discussion).
+
+Everything is FP64.  Library primitives used as single steps: the sparse
+product H C (scipy CSR times dense) and dense matrix products (numpy).  The
+Cholesky factorization, the triangular inverse and the eigensolver are written
+out (the eigensolver in plain C, ``jacobi.c``).
+
+Readings where the paper is silent (listed with their reasons in the design
+notes of the repository):
+* line minimization (Sec. 2.1 cites it without detail): second-order model of
+  E along P, see ``line_step``;
+* convergence test: rho = ||X - C A||_F = ||G||_F / 2 <= tol;
+* CG restarts (gamma = 0): at i = 0, after a subspace rotation, when E rose
+  by more than ``rise_tol * |E|``, and when P is not a descent direction.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Tuple
+
+import numpy as np
+import scipy.sparse
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def _jacobi_lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "_tmo_jacobi.so")
+        if not os.path.exists(path):
+            from . import build as _build
+            _build.build()
+        lib = ctypes.CDLL(path)
+        lib.tmo_jacobi_eigh.restype = ctypes.c_int
+        lib.tmo_jacobi_eigh.argtypes = [
+            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_double, ctypes.c_int]
+        _LIB = lib
+    return _LIB
+
+
+# --------------------------------------------------------------------------
+# Building blocks
+# --------------------------------------------------------------------------
+
+def csr_matrix(rowptr, col, val, n: int):
+    """The sparse symmetric H (Sec. 2.1) as a scipy CSR matrix in FP64."""
+    return scipy.sparse.csr_matrix(
+        (np.asarray(val, dtype=np.float64), np.asarray(col), np.asarray(rowptr)),
+        shape=(n, n))
+
+
+def spmm(H, C: np.ndarray) -> np.ndarray:
+    """X = H C (Fig. 2, step (1) of both algorithms)."""
+    return np.asarray(H @ C)
+
+
+def energy_gradient_alg1(H, C: np.ndarray):
+    """Fig. 2, Algorithm-1: X = HC, A = C^T X, E = tr A, G = -2 (X - C A).
+
+    A is symmetric in exact arithmetic; it is symmetrized before use.
+    Returns (E, G, X, A).
+    """
+    X = spmm(H, C)
+    A = C.T @ X
+    A = 0.5 * (A + A.T)
+    E = float(np.trace(A))
+    G = -2.0 * (X - C @ A)
+    return E, G, X, A
+
+
+def energy_gradient_alg2(H, C: np.ndarray, zero_diag: bool = True):
+    """Fig. 2, Algorithm-2 (mathematically equal to Algorithm-1).
+
+    X = HC; H_D = diag(C^T X); E = tr H_D; X' = X - C H_D; H' = C^T X';
+    G = -2 (X' - C H').  diag(H') is zero in exact arithmetic and is set to
+    zero explicitly (Sec. 2.2, MP2).  Returns (E, G, X, h, Hp) with h the
+    diagonal of H_D.
+    """
+    X = spmm(H, C)
+    h = np.einsum("ij,ij->j", C, X)
+    E = float(np.sum(h))
+    Xp = X - C * h[None, :]
+    Hp = C.T @ Xp
+    if zero_diag:
+        np.fill_diagonal(Hp, 0.0)
+    G = -2.0 * (Xp - C @ Hp)
+    return E, G, X, h, Hp
+
+
+class NotPositiveDefinite(ArithmeticError):
+    pass
+
+
+def cholesky_upper(S: np.ndarray) -> np.ndarray:
+    """Textbook Cholesky S = R^T R, R upper triangular (Fig. 4, step (2)).
+
+    Row j of R: r_jj = sqrt(s_jj - sum_k<j r_kj^2) and
+    r_jl = (s_jl - sum_k<j r_kj r_kl) / r_jj for l > j.  No pivoting; a pivot
+    that is not positive raises NotPositiveDefinite.
+    """
+    m = S.shape[0]
+    R = np.zeros_like(S, dtype=np.float64)
+    for j in range(m):
+        d = S[j, j] - R[:j, j] @ R[:j, j]
+        if not d > 0.0:
+            raise NotPositiveDefinite(f"pivot {j} is {d}")
+        R[j, j] = np.sqrt(d)
+        R[j, j + 1:] = (S[j, j + 1:] - R[:j, j] @ R[:j, j + 1:]) / R[j, j]
+    return R
+
+
+def upper_triangular_inverse(R: np.ndarray) -> np.ndarray:
+    """W = R^{-1} for upper-triangular R (Fig. 4, step (3)).
+
+    Back substitution on R W = I, one row of W at a time from the bottom:
+    w_i = (e_i - sum_{k>i} r_ik w_k) / r_ii.
+    """
+    m = R.shape[0]
+    W = np.zeros_like(R, dtype=np.float64)
+    for i in range(m - 1, -1, -1):
+        rhs = -(R[i, i + 1:] @ W[i + 1:, :])
+        rhs[i] += 1.0
+        W[i, :] = rhs / R[i, i]
+    return W
+
+
+def orthonormalize(C: np.ndarray) -> np.ndarray:
+    """Fig. 4 as Cholesky-QR: S = C^T C = R^T R, C_out = C R^{-1}."""
+    S = C.T @ C
+    R = cholesky_upper(S)
+    W = upper_triangular_inverse(R)
+    return C @ W
+
+
+def jacobi_eigh(A: np.ndarray, tol: float = 1e-15, max_sweeps: int = 100):
+    """Eigenvalues (ascending) and eigenvectors of a symmetric matrix.
+
+    Cyclic Jacobi, in plain C (``jacobi.c``).  Returns (w, V, sweeps).
+    """
+    A = np.ascontiguousarray(A, dtype=np.float64).copy()
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n))
+    sweeps = _jacobi_lib().tmo_jacobi_eigh(
+        n, A.ctypes.data, w.ctypes.data, V.ctypes.data, tol, max_sweeps)
+    if sweeps < 0:
+        raise ArithmeticError("Jacobi eigensolver did not converge")
+    return w, V, sweeps
+
+
+def rayleigh_ritz(H, C: np.ndarray):
+    """Diagonalize the m x m H = C^T H C and rotate C into its eigenbasis.
+
+    Eq. 9: at convergence HC = CH, so the eigenvalues of the m x m matrix are
+    eigenvalues of H.  Returns (C U, w) with w ascending.
+    """
+    X = spmm(H, C)
+    A = C.T @ X
+    A = 0.5 * (A + A.T)
+    w, U, _ = jacobi_eigh(A)
+    return C @ U, w
+
+
+def jacobi_preconditioner(H) -> np.ndarray:
+    """Diagonal preconditioner M (Eq. 18): M_ii = 1 / (H_ii - sigma).
+
+    sigma = min(0, min_i H_ii - 1/2) keeps M symmetric positive definite.
+    M approximates the inverse Hessian only through the diagonal of H; this
+    particular choice is a reading (the paper fixes M only as diagonal and SPD).
+    """
+    d = np.asarray(H.diagonal(), dtype=np.float64)
+    sigma = min(0.0, float(d.min()) - 0.5)
+    return 1.0 / (d - sigma)
+
+
+def line_step(P: np.ndarray, Y: np.ndarray, G: np.ndarray,
+              a_diag: np.ndarray) -> Tuple[float, dict]:
+    """Step length alpha along P (Fig. 1, the line minimization).
+
+    The paper cites a line minimization without giving one.  Reading: minimize
+    a second-order model of the orthonormality-invariant energy
+    Omega(a) = tr[((C+aP)^T (C+aP))^{-1} (C+aP)^T H (C+aP)].  Its slope at
+    a = 0 is -tr(P^T G) exactly; its curvature is taken as
+    2 sum_j (p_j^T H p_j - A_jj p_j^T p_j), exact when P is orthogonal to C
+    and A = C^T H C is diagonal.  alpha = tr(P^T G) / curvature, capped at
+    1 / max_j ||p_j|| (no column turns by more than 45 degrees); the cap is
+    also the step when the curvature is not positive.
+    """
+    pg = float(np.sum(P * G))
+    pp = np.einsum("ij,ij->j", P, P)
+    py = np.einsum("ij,ij->j", P, Y)
+    curv = 2.0 * float(np.sum(py - a_diag * pp))
+    cap = 1.0 / np.sqrt(float(pp.max())) if pp.max() > 0 else 0.0
+    if curv > 0.0:
+        alpha = min(pg / curv, cap)
+    else:
+        alpha = cap
+    return alpha, dict(pg=pg, curv=curv, cap=cap)
+
+
+# --------------------------------------------------------------------------
+# Driver
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class OracleOptions:
+    tol: float = 1e-10          # stop when ||X - C A||_F <= tol
+    max_iter: int = 20000
+    k_rot: int = 0              # subspace rotation every k_rot iterations (0: never)
+    precondition: bool = False  # diagonal M of Eq. 18
+    rise_tol: float = 1e-13     # restart CG when E rises by more than this * |E|
+
+
+@dataclasses.dataclass
+class OracleResult:
+    E_G: float
+    eigenvalues: np.ndarray
+    C: np.ndarray
+    iterations: int
+    converged: bool
+    energies: List[float]
+    residual_norms: List[float]
+    alphas: List[float]
+    gammas: List[float]
+    restarts: int
+    max_residual: float
+    frob_residual: float
+    orth_err: float
+
+
+def solve(H, C0: np.ndarray, opts: Optional[OracleOptions] = None,
+          callback=None) -> OracleResult:
+    """Trace minimization by nonlinear CG (Fig. 1), all in FP64.
+
+    for i = 0, 1, ...:  E_i, G_i = -grad E(C_i) (Fig. 2); stop if converged;
+    P_i = Z_i + gamma_i P_{i-1} with Z = M G (Eq. 18, Z = G without M) and the
+    Polak-Ribiere gamma of Eq. 8 (M-weighted when preconditioned); alpha_i
+    from ``line_step``; C_{i+1} = orthonormalize(C_i + alpha_i P_i) (Fig. 4).
+    """
+    o = opts or OracleOptions()
+    M = jacobi_preconditioner(H) if o.precondition else None
+    C = orthonormalize(np.asarray(C0, dtype=np.float64))
+    energies, rhos, alphas, gammas = [], [], [], []
+    G_prev = Z_prev = P_prev = None
+    E_prev = None
+    restart = True
+    restarts = 0
+    converged = False
+    it = 0
+    for it in range(o.max_iter):
+        if o.k_rot > 0 and it > 0 and it % o.k_rot == 0:
+            C, _ = rayleigh_ritz(H, C)
+            restart = True
+        E, G, X, A = energy_gradient_alg1(H, C)
+        rho = 0.5 * float(np.linalg.norm(G))
+        energies.append(E)
+        rhos.append(rho)
+        if callback is not None:
+            callback(it, E, rho)
+        if rho <= o.tol:
+            converged = True
+            break
+        if E_prev is not None and E > E_prev + o.rise_tol * abs(E_prev):
+            restart = True
+        Z = G * M[:, None] if M is not None else G
+        if restart:
+            gamma = 0.0
+        else:
+            gamma = float(np.sum((G - G_prev) * Z)) / float(np.sum(G_prev * Z_prev))
+        P = Z + gamma * P_prev if gamma != 0.0 else Z.copy()
+        if float(np.sum(P * G)) <= 0.0:
+            P = Z.copy()
+            gamma = 0.0
+        if gamma == 0.0:
+            restarts += 1
+        Y = spmm(H, P)
+        alpha, _ = line_step(P, Y, G, np.diag(A).copy())
+        alphas.append(alpha)
+        gammas.append(gamma)
+        C = orthonormalize(C + alpha * P)
+        G_prev, Z_prev, P_prev, E_prev = G, Z, P, E
+        restart = False
+    iterations = it + 1 if not converged else it
+    C, w = rayleigh_ritz(H, C)
+    X = spmm(H, C)
+    R = X - C * w[None, :]
+    col_res = np.sqrt(np.einsum("ij,ij->j", R, R))
+    S = C.T @ C
+    orth = float(np.max(np.abs(S - np.eye(S.shape[0]))))
+    return OracleResult(
+        E_G=float(np.sum(w)), eigenvalues=w, C=C, iterations=iterations,
+        converged=converged, energies=energies, residual_norms=rhos,
+        alphas=alphas, gammas=gammas, restarts=restarts,
+        max_residual=float(col_res.max()),
+        frob_residual=float(np.sqrt(np.sum(col_res ** 2))), orth_err=orth)
+
+
+def brute_force_lowest(H_dense: np.ndarray, m: int):
+    """Brute force for tiny N: all eigenvalues of the dense H by cyclic Jacobi.
+
+    Returns (E_G, eigenvalues ascending, gap lambda_{m+1} - lambda_m) per
+    Eq. 2 and Eq. 3.
+    """
+    w, _, _ = jacobi_eigh(np.asarray(H_dense, dtype=np.float64))
+    gap = float(w[m] - w[m - 1]) if m < len(w) else float("nan")
+    return float(np.sum(w[:m])), w, gap

@@ -1,0 +1,277 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: each check is a closed form
+(Eq. 16 of the paper, the Fourier spectra of periodic stencils, the 1-D
+Dirichlet Laplacian), a value printed in the paper (Table 1), an invariant of
+the method (Sec. 2.1: C^T C = I, E invariant under C -> CU, Ky Fan bound), a
+finite-difference derivative, brute force on tiny inputs, or a library routine
+the oracle does not use (numpy's eigvalsh / qr) as an outside witness.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from workloads import StencilSpec, config_problem, make_problem
+from workloads.problems import stencil_csr
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------- closed forms
+
+def eq16_spectrum(n):
+    """Eq. 16: lambda_pq = 4 (sin^2(p pi / 2(n+1)) + sin^2(q pi / 2(n+1)))."""
+    p = np.arange(1, n + 1)
+    s = 4.0 * np.sin(p * np.pi / (2 * (n + 1))) ** 2
+    return np.sort((s[:, None] + s[None, :]).reshape(-1))
+
+
+def periodic_spectrum(n, order, ndim=3):
+    """Fourier spectrum of -(1/2) Lap_h on an n^ndim periodic grid."""
+    th = 2 * np.pi * np.arange(n) / n
+    if order == 2:
+        f = 1.0 - np.cos(th)
+    else:
+        f = (1.0 - np.cos(th)) * (7.0 - np.cos(th)) / 6.0
+    total = f
+    for _ in range(ndim - 1):
+        total = (total[..., None] + f).reshape(-1)
+    return np.sort(total)
+
+
+def _H(oracle_mod, problem):
+    return oracle_mod.csr_matrix(*problem.csr(), problem.N)
+
+
+# ------------------------------------------------------------------ eigensolver
+
+def test_jacobi_1d_dirichlet_closed_form(oracle_mod):
+    n = 40
+    A = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    w, V, _ = oracle_mod.jacobi_eigh(A)
+    k = np.arange(1, n + 1)
+    exact = np.sort(2 - 2 * np.cos(k * np.pi / (n + 1)))
+    assert np.max(np.abs(w - exact)) < 1e-13
+    assert np.max(np.abs(A @ V - V * w)) < 1e-13
+    assert np.max(np.abs(V.T @ V - np.eye(n))) < 1e-13
+
+
+def test_jacobi_random_symmetric(oracle_mod):
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 7, 64, 150):
+        B = rng.standard_normal((n, n))
+        A = B + B.T
+        w, V, _ = oracle_mod.jacobi_eigh(A)
+        assert np.all(np.diff(w) >= 0)
+        scale = np.linalg.norm(A)
+        assert np.max(np.abs(A @ V - V * w)) < 1e-13 * scale
+        assert np.max(np.abs(V.T @ V - np.eye(n))) < 1e-13
+        assert abs(np.sum(w) - np.trace(A)) < 1e-12 * scale
+        # outside witness: LAPACK via numpy (not used by the oracle)
+        assert np.max(np.abs(w - np.linalg.eigvalsh(A))) < 1e-12 * scale
+
+
+def test_jacobi_two_by_two_and_diagonal(oracle_mod):
+    a, b, d = 1.0, 2.0, -3.0
+    w, _, _ = oracle_mod.jacobi_eigh(np.array([[a, b], [b, d]]))
+    mid, rad = (a + d) / 2, math.hypot((a - d) / 2, b)
+    assert np.allclose(w, [mid - rad, mid + rad], atol=1e-15, rtol=0)
+    D = np.diag([3.0, -1.0, 2.0])
+    w, V, sweeps = oracle_mod.jacobi_eigh(D)
+    assert np.array_equal(w, [-1.0, 2.0, 3.0]) and sweeps == 0
+    assert np.array_equal(np.abs(V), np.abs(np.eye(3)[:, [1, 2, 0]]))
+
+
+# ---------------------------------------------------------- orthonormalization
+
+def test_cholesky_recovers_known_factor(oracle_mod):
+    rng = np.random.default_rng(1)
+    m = 30
+    R = 0.3 * np.triu(rng.standard_normal((m, m)), 1)
+    R[np.diag_indices(m)] = rng.uniform(1.0, 3.0, m)   # well conditioned
+    S = R.T @ R
+    Rc = oracle_mod.cholesky_upper(S)
+    assert np.max(np.abs(Rc - R)) < 1e-13
+    with pytest.raises(ArithmeticError):
+        oracle_mod.cholesky_upper(np.array([[1.0, 2.0], [2.0, 1.0]]))
+
+
+def test_upper_inverse_closed_form(oracle_mod):
+    m, beta = 12, 0.7
+    R = np.eye(m) - beta * np.eye(m, k=1)
+    W = oracle_mod.upper_triangular_inverse(R)
+    i, j = np.indices((m, m))
+    exact = np.where(j >= i, beta ** (j - i), 0.0)
+    assert np.max(np.abs(W - exact)) < 1e-14
+
+
+def test_orthonormalize_is_cholesky_qr(oracle_mod):
+    rng = np.random.default_rng(2)
+    C = rng.standard_normal((500, 20))
+    Q = oracle_mod.orthonormalize(C)
+    assert np.max(np.abs(Q.T @ Q - np.eye(20))) < 1e-13
+    # same as Householder QR with a positive-diagonal R (outside witness)
+    Qh, Rh = np.linalg.qr(C)
+    Qh = Qh * np.sign(np.diag(Rh))[None, :]
+    assert np.max(np.abs(Q - Qh)) < 1e-12
+    # C = Q T with T upper triangular, positive diagonal (Fig. 4 convention)
+    T = Q.T @ C
+    assert np.max(np.abs(np.tril(T, -1))) < 1e-12
+    assert np.all(np.diag(T) > 0)
+
+
+# --------------------------------------------------------- energy and gradient
+
+@pytest.fixture(scope="module")
+def small_well_problem():
+    return make_problem("w6", StencilSpec(3, (6, 6, 6), 2, "periodic", 0.5),
+                        m=10, seed=3, n_wells=3)
+
+
+def test_alg1_equals_alg2(oracle_mod, small_well_problem):
+    p = small_well_problem
+    H = _H(oracle_mod, p)
+    C = oracle_mod.orthonormalize(p.C0())
+    E1, G1, _, _ = oracle_mod.energy_gradient_alg1(H, C)
+    E2, G2, _, _, _ = oracle_mod.energy_gradient_alg2(H, C)
+    assert abs(E1 - E2) < 1e-13 * abs(E1)
+    assert np.linalg.norm(G1 - G2) < 1e-13 * np.linalg.norm(G1)
+
+
+def test_gradient_is_directional_derivative(oracle_mod, small_well_problem):
+    """-tr(P^T G) is the slope of E(orthonormalize(C + eps P)) at eps = 0."""
+    p = small_well_problem
+    H = _H(oracle_mod, p)
+    C = oracle_mod.orthonormalize(p.C0())
+    E0, G, _, _ = oracle_mod.energy_gradient_alg1(H, C)
+    P = np.random.default_rng(9).standard_normal(C.shape)
+    eps = 1e-5
+
+    def E_at(e):
+        return oracle_mod.energy_gradient_alg1(H, oracle_mod.orthonormalize(C + e * P))[0]
+
+    fd = (E_at(eps) - E_at(-eps)) / (2 * eps)
+    assert abs(fd - (-np.sum(P * G))) < 1e-6 * abs(fd)
+
+
+def test_unitary_invariance_and_tangency(oracle_mod, small_well_problem):
+    p = small_well_problem
+    H = _H(oracle_mod, p)
+    C = oracle_mod.orthonormalize(p.C0())
+    E, G, _, _ = oracle_mod.energy_gradient_alg1(H, C)
+    Q, _ = np.linalg.qr(np.random.default_rng(4).standard_normal((p.m, p.m)))
+    E2, G2, _, _ = oracle_mod.energy_gradient_alg1(H, C @ Q)
+    assert abs(E - E2) < 1e-13 * abs(E)
+    assert np.linalg.norm(G @ Q - G2) < 1e-12 * np.linalg.norm(G)
+    assert np.max(np.abs(C.T @ G)) < 1e-12 * np.linalg.norm(G)
+
+
+# ---------------------------------------------------------------- full solves
+
+def test_c1_closed_form_shell():
+    """16^3 periodic 7-point, m = 27: E_G = 54 (1 - cos(pi/8)) in closed form."""
+    lam = periodic_spectrum(16, 2)
+    assert abs(np.sum(lam[:27]) - 54 * (1 - math.cos(math.pi / 8))) < 1e-12
+    assert lam[27] - lam[26] > 0.06
+
+
+def test_solve_c1_matches_closed_form(oracle_mod):
+    p = config_problem("c1")
+    r = oracle_mod.solve(_H(oracle_mod, p), p.C0(),
+                         oracle_mod.OracleOptions(tol=1e-9, k_rot=50))
+    exact = periodic_spectrum(16, 2)[:27]
+    assert r.converged
+    assert abs(r.E_G - 54 * (1 - math.cos(math.pi / 8))) < 1e-12 * r.E_G
+    assert np.max(np.abs(r.eigenvalues - exact)) < 1e-12
+    assert r.max_residual <= 1e-9
+    assert r.orth_err < 1e-13
+    # Ky Fan: every iterate's trace is an upper bound of E_G
+    assert min(r.energies) >= r.E_G - 1e-12
+    # preconditioned run reaches the same answer (Eq. 18 changes only the path)
+    rp = oracle_mod.solve(_H(oracle_mod, p), p.C0(),
+                          oracle_mod.OracleOptions(tol=1e-9, k_rot=50, precondition=True))
+    assert abs(rp.E_G - r.E_G) < 1e-12 * r.E_G
+
+
+def test_solve_13_point_closed_shell(oracle_mod):
+    """8^3 periodic 13-point, m = 7 (k = 0 plus the six +-1 modes)."""
+    p = make_problem("o4", StencilSpec(3, (8, 8, 8), 4, "periodic", 0.5), m=7, seed=11)
+    lam = periodic_spectrum(8, 4)
+    r = oracle_mod.solve(_H(oracle_mod, p), p.C0(),
+                         oracle_mod.OracleOptions(tol=1e-10, k_rot=50))
+    assert r.converged
+    assert np.max(np.abs(r.eigenvalues - lam[:7])) < 1e-12
+
+
+def test_solve_2d_dirichlet_eq16_small(oracle_mod):
+    """The paper's H_N (Eq. 14-15) at n = 24; E_G from the closed form Eq. 16."""
+    n = 24
+    lam = eq16_spectrum(n)
+    m = next(k for k in range(30, 60) if lam[k] - lam[k - 1] > 1e-3)
+    p = make_problem("d24", StencilSpec(2, (n, n), 2, "dirichlet", 1.0), m=m, seed=7)
+    r = oracle_mod.solve(_H(oracle_mod, p), p.C0(),
+                         oracle_mod.OracleOptions(tol=1e-9, k_rot=50))
+    assert r.converged
+    assert abs(r.E_G - lam[:m].sum()) < 1e-11 * lam[:m].sum()
+
+
+def test_table1_first_row(oracle_mod):
+    """Table 1, N = 96^2, m = 220: printed E_G = 35.25 and gap 6.2e-3."""
+    with open(os.path.join(HERE, "golden", "table1.json")) as f:
+        row = json.load(f)["rows"][0]
+    lam = eq16_spectrum(row["n"])
+    m = row["m"]
+    assert round(float(lam[:m].sum()), 2) == row["E_G"]
+    assert abs((lam[m] - lam[m - 1]) - row["gap"]) < 0.05e-3
+    p = config_problem("t1_96_220")
+    r = oracle_mod.solve(_H(oracle_mod, p), p.C0(),
+                         oracle_mod.OracleOptions(tol=1e-7, k_rot=50))
+    assert r.converged
+    assert abs(r.E_G - lam[:m].sum()) < 1e-10 * lam[:m].sum()
+    assert round(r.E_G, 2) == row["E_G"]
+
+
+def test_wells_brute_force(oracle_mod):
+    """Tiny grids with wells: iterative E_G equals brute-force dense Jacobi."""
+    for n, m, K, seed in ((4, 5, 2, 21), (6, 12, 3, 22)):
+        p = make_problem("bf", StencilSpec(3, (n, n, n), 2, "periodic", 0.5),
+                         m=m, seed=seed, n_wells=K)
+        Hd = p.dense()
+        assert np.array_equal(Hd, Hd.T)
+        E_bf, w, gap = oracle_mod.brute_force_lowest(Hd, m)
+        assert gap > 1e-3
+        assert np.max(np.abs(w - np.linalg.eigvalsh(Hd))) < 1e-12   # witness
+        r = oracle_mod.solve(_H(oracle_mod, p), p.C0(),
+                             oracle_mod.OracleOptions(tol=1e-10, k_rot=50))
+        assert r.converged
+        assert abs(r.E_G - E_bf) < 1e-12 * abs(E_bf)
+        assert np.max(np.abs(r.eigenvalues - w[:m])) < 1e-11
+
+
+def test_potential_shift_and_scaling(oracle_mod):
+    """V -> V + v shifts E_G by m v; H -> a H scales E_G by a."""
+    p = make_problem("s", StencilSpec(3, (6, 6, 6), 2, "periodic", 0.5),
+                     m=7, seed=31, n_wells=2)
+    H = _H(oracle_mod, p)
+    base = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(tol=1e-10, k_rot=50))
+    v = 0.375
+    shifted = oracle_mod.csr_matrix(*stencil_csr(p.spec, p.V + v), p.N)
+    r1 = oracle_mod.solve(shifted, p.C0(), oracle_mod.OracleOptions(tol=1e-10, k_rot=50))
+    assert abs(r1.E_G - (base.E_G + p.m * v)) < 1e-12 * abs(base.E_G)
+    r2 = oracle_mod.solve(2.5 * H, p.C0(), oracle_mod.OracleOptions(tol=1e-10, k_rot=50))
+    assert abs(r2.E_G - 2.5 * base.E_G) < 1e-12 * abs(base.E_G)
+
+
+def test_single_vector_rayleigh_minimum(oracle_mod):
+    """m = 1: the minimum of the Rayleigh quotient is lambda_1 (periodic: 0)."""
+    p = make_problem("m1", StencilSpec(3, (8, 8, 8), 2, "periodic", 0.5), m=1, seed=41)
+    r = oracle_mod.solve(_H(oracle_mod, p), p.C0(),
+                         oracle_mod.OracleOptions(tol=1e-10))
+    assert r.converged
+    assert abs(r.E_G) < 1e-15 + 1e-12
+    c = r.C[:, 0]
+    assert np.max(np.abs(np.abs(c) - 1 / math.sqrt(p.N))) < 1e-9

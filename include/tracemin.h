@@ -1,0 +1,248 @@
+/*
+ * tracemin.h -- C ABI of the MI355X (gfx950) trace-minimization eigensolver.
+ *
+ * Computes the m lowest eigenpairs of a real, symmetric, sparse N x N matrix
+ * H: the sum E_G of the m lowest eigenvalues (Eq. 2 of Tsuchida & Choe,
+ * "Iterative diagonalization of symmetric matrices in mixed precision") and an
+ * orthonormal basis C of their subspace, by minimizing E(C) = tr(C^T H C)
+ * subject to C^T C = I (Sec. 2.1, Eq. 4-7) with nonlinear conjugate gradients
+ * (Fig. 1).  Every step of the iteration runs in hand-written HIP kernels on
+ * the device.
+ *
+ * Conventions used by every entry point
+ *   - Blocks of m vectors (C, X = HC, G, P, ...) are N x ld row-major arrays:
+ *     element (r, j) lives at index r * ld + j.  ld = tm_leading_dim(m) (m
+ *     rounded up to a multiple of 32); columns m .. ld-1 must hold zeros and
+ *     are kept at zero.
+ *   - m x m matrices are dense row-major with leading dimension m.
+ *   - Pointers documented as "device" must point to device memory on the
+ *     context's device; "host" pointers to host memory.  The library never
+ *     frees memory it did not allocate.  All device work is enqueued on the
+ *     context's stream; an entry point returns once its work is enqueued,
+ *     except where "synchronous" is stated.
+ *   - Every entry point returns a tm_status.  On failure the detail text is
+ *     available from tm_last_error() (thread-local).  No C++ exception crosses
+ *     this boundary.
+ *   - One context per host thread at a time; a context is not thread-safe.
+ */
+#ifndef TRACEMIN_H
+#define TRACEMIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+typedef enum tm_status {
+    TM_OK = 0,
+    TM_EINVAL = -1,   /* invalid argument (sizes, pointers, malformed CSR)     */
+    TM_ENOMEM = -2,   /* device allocation failed                             */
+    TM_ENOTSPD = -3,  /* C^T C not positive definite in the Cholesky step     */
+    TM_ENOCONV = -4,  /* max_iter reached; result filled, converged = 0       */
+    TM_ENAN = -5,     /* NaN or Inf in the energy or gradient norm            */
+    TM_EDEVICE = -6,  /* HIP runtime error (text in tm_last_error)            */
+    TM_ENOTSUP = -7   /* option combination not supported                    */
+} tm_status;
+
+typedef enum tm_dtype { TM_F64 = 0, TM_F32 = 1 } tm_dtype;
+
+/* Precision policies (Sec. 2.2).  Every policy keeps the m x m Cholesky,
+ * triangular inverse and Rayleigh-Ritz eigensolve in FP64, and reports E_G and
+ * residuals from an FP64 evaluation at the end.
+ *   TM_FULL_DP  every operation in FP64 (the paper's "full DP").
+ *   TM_FULL_SP  every N-sized operation in FP32 (the paper's "full SP").
+ *   TM_MP2      the paper's MP2: SpMM, X' = X - C H_D and S = C^T C in FP64;
+ *               H' = C^T X' and C H' on FP32 matrix cores; G and P stored
+ *               in FP32; C_out = C L_D + C L' with the second term in FP32.
+ *   TM_MIXED    FULL_SP until the residual reaches switch_tol (or the FP32
+ *               energy stalls), then MP2 with subspace rotations every k_rot
+ *               iterations until tol -- the switch the paper recommends in
+ *               Sec. 3 and Sec. 5. */
+typedef enum tm_precision {
+    TM_FULL_DP = 0,
+    TM_FULL_SP = 1,
+    TM_MP2 = 2,
+    TM_MIXED = 3
+} tm_precision;
+
+/* ---------------------------------------------------------------- objects */
+typedef struct tm_ctx tm_ctx;
+typedef struct tm_mat tm_mat;
+
+/* Device allocator hook.  alloc returns device memory of at least `bytes`
+ * bytes (256-byte aligned) or NULL; free releases it.  Both are called on
+ * the thread that calls into the library. */
+typedef struct tm_allocator {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} tm_allocator;
+
+/* Matrix-free H = kinetic_scale * (-Lap_h) + diag(V) on a regular grid with
+ * spacing 1.  order 2: 1-D stencil (-1, 2, -1); order 4: (1, -16, 30, -16, 1)/12.
+ * dims[0] is the fastest axis; grid point (x, y, z) is row (z*ny + y)*nx + x.
+ * With ndim = 2, periodic = 0, kinetic_scale = 1 and V = NULL this is the
+ * paper's 2-D Dirichlet Laplacian H_N (Eq. 14-15). */
+typedef struct tm_stencil {
+    int32_t ndim;          /* 2 or 3                                         */
+    int32_t dims[3];       /* grid extents (dims[2] ignored when ndim = 2)   */
+    int32_t order;         /* 2 (7-point in 3-D) or 4 (13-point in 3-D)      */
+    int32_t periodic;      /* 1 periodic, 0 Dirichlet (zero outside)         */
+    double kinetic_scale;  /* 0.5 for -1/2 Lap; 1.0 for the paper's H_N       */
+    const double *V;       /* host, N values added to the diagonal, or NULL  */
+} tm_stencil;
+
+typedef struct tm_opts {
+    int32_t precision;     /* tm_precision                                   */
+    int32_t max_iter;      /* total CG iterations over all phases            */
+    int32_t k_rot;         /* subspace rotation every k_rot iterations (0 = off) */
+    int32_t k_check;       /* host polls the device convergence flag every k_check iterations */
+    int32_t precondition;  /* 1: diagonal M of Eq. 18, M_ii = 1/(H_ii - sigma) */
+    int32_t history;       /* 1: record E_i and rho_i per iteration         */
+    double switch_tol;     /* TM_MIXED: leave FP32 when rho <= switch_tol (<= 0: automatic) */
+    double rise_tol;       /* restart CG when E rises by more than rise_tol*|E| */
+} tm_opts;
+
+typedef struct tm_result {
+    double E_G;            /* sum of the m Ritz values after the final FP64 Rayleigh-Ritz */
+    double rho;            /* ||X - C A||_F at the last iteration            */
+    double max_residual;   /* max_j ||H c_j - lambda_j c_j||_2, FP64        */
+    double frob_residual;  /* sqrt(sum_j ||H c_j - lambda_j c_j||^2), FP64  */
+    double orth_err;       /* max |C^T C - I|, FP64                          */
+    double seconds;        /* wall time of the solve (synchronous)           */
+    int32_t iterations;    /* CG iterations taken (all phases)               */
+    int32_t iters_sp;      /* iterations in the FP32 phase (TM_MIXED/TM_FULL_SP) */
+    int32_t converged;     /* 1 if rho <= tol was reached                    */
+    int32_t restarts;      /* CG restarts (gamma = 0), including i = 0       */
+    int32_t rotations;     /* subspace rotations performed                   */
+    int32_t reserved;
+} tm_result;
+
+/* ------------------------------------------------------------- lifecycle */
+
+/* Leading dimension used for an m-column block: m rounded up to 32. */
+int32_t tm_leading_dim(int32_t m);
+
+/* Create a context on HIP device `device`.  alloc may be NULL (hipMalloc /
+ * hipFree are used).  stream is a hipStream_t or NULL for the null stream;
+ * the caller keeps ownership of it. */
+tm_status tm_create(int32_t device, const tm_allocator *alloc, void *stream,
+                    tm_ctx **out);
+void tm_destroy(tm_ctx *ctx);
+const char *tm_status_string(int32_t status);
+const char *tm_last_error(void);
+
+/* H from CSR arrays (Sec. 2.1: real, symmetric, sparse with O(N) nonzeros).
+ * rowptr (n+1, int64), col (nnz, int32) and val (nnz, FP64) are host arrays
+ * that are copied to the device; the caller may free them afterwards.
+ * Columns must lie in [0, n) and rowptr must be non-decreasing with
+ * rowptr[0] = 0; symmetry is the caller's responsibility. */
+tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr,
+                            const int32_t *col, const double *val,
+                            tm_mat **out);
+tm_status tm_set_matrix_stencil(tm_ctx *ctx, const tm_stencil *s,
+                                tm_mat **out);
+void tm_free_matrix(tm_mat *mat);
+int64_t tm_matrix_rows(const tm_mat *mat);
+
+/* ------------------------------------------------------------------ solve */
+
+void tm_opts_default(tm_opts *opts);
+
+/* Trace minimization (Fig. 1) from the start block C0 (device, N x ld FP64,
+ * need not be orthonormal; it is orthonormalized first by Fig. 4) until
+ * rho = ||X - C A||_F <= tol, where X = HC and A = C^T X.  Synchronous.
+ *   C_out     device N x ld FP64 or NULL: the Ritz vectors, ascending.
+ *   eig_out   device m FP64 or NULL: the Ritz values lambda_1..lambda_m.
+ *   history   host array of 2*history_len doubles or NULL: (E_i, rho_i)
+ *             for i < min(iterations, history_len) (opts->history = 1).
+ * Returns TM_ENOCONV (with *res filled) if max_iter was reached. */
+tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol,
+                   const tm_opts *opts, const double *C0, double *C_out,
+                   double *eig_out, tm_result *res, double *history,
+                   int32_t history_len);
+
+/* ------------------------------------------------ steps of the iteration
+ * The kernels of one iteration, exposed one by one so that each can be
+ * checked on its own.  All pointers are device pointers; dtype selects FP64
+ * or FP32 blocks; sizes: n = rows, m = columns, ld = tm_leading_dim(m). */
+
+/* X = H C (Fig. 2, step (1)). */
+tm_status tm_spmm(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t dtype,
+                  const void *C, void *X);
+
+/* out = A^T B, an m x m FP64 result (the Gram products H' = C^T X' of
+ * Fig. 2 step (6) and S = C^T C of Fig. 4 step (1)).  When h is not NULL, B
+ * is replaced by B - A diag(h) (Fig. 2 step (5), formed on the fly).  The
+ * products run on matrix cores in the block's precision with FP64 sums
+ * across row chunks. */
+tm_status tm_gram(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype,
+                  const void *A, const void *B, const double *h, double *out);
+
+/* out = A W with A an n x ld block and W an m x m FP64 matrix (the subspace
+ * rotation C U of the Rayleigh-Ritz step, Eq. 9).  W is rounded to the
+ * block's precision. */
+tm_status tm_rotate(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype,
+                    const void *A, const double *W, void *out);
+
+/* Energy and gradient by Fig. 2, Algorithm-2, with FP64 blocks:
+ * X = HC; h = diag(C^T X); E = sum h; X' = X - C diag(h); H' = C^T X' with
+ * diag(H') := 0; G = -2 (X' - C H').  Outputs: X (n x ld), G (n x ld),
+ * h (m), Hp (m x m), E (1 double); all device.
+ * precision TM_FULL_DP: all FP64.  TM_MP2: steps (6) and (7) on FP32
+ * matrix cores (Sec. 2.2, MP2); G is still returned in FP64. */
+tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m,
+                         int32_t precision, const double *C, double *X,
+                         double *G, double *h, double *Hp, double *E);
+
+/* In-place Cholesky orthonormalization of an FP64 block (Fig. 4, read as
+ * Cholesky-QR): S = C^T C = R^T R, C <- C R^{-1}.  precision TM_FULL_DP uses
+ * an FP64 triangular product; TM_MP2 uses the MP1 (ii) split
+ * C R^{-1} = C D + C R' with D = diag(R^{-1}) in FP64 and R' in FP32 (Eq. 11-13). */
+tm_status tm_orthonormalize(tm_ctx *ctx, int64_t n, int32_t m,
+                            int32_t precision, double *C);
+
+/* R^{-1} of the Cholesky factor S = R^T R, R upper triangular (Fig. 4,
+ * steps (2)-(3)), for an m x m FP64 S.  Rinv is m x m, upper triangular with
+ * zeros below the diagonal.  Synchronous; TM_ENOTSPD if a pivot is not
+ * positive. */
+tm_status tm_cholesky_inverse(tm_ctx *ctx, int32_t m, const double *S,
+                              double *Rinv);
+
+/* Eigen-decomposition of a symmetric m x m FP64 A by parallel cyclic Jacobi
+ * (the diagonalization of H in Eq. 9): w ascending (m), U (m x m, column j is
+ * the eigenvector of w[j]).  A is not modified. */
+tm_status tm_sym_eig(tm_ctx *ctx, int32_t m, const double *A, double *U,
+                     double *w);
+
+/* ----------------------------------------------------------- measurement
+ * Average device duration of one kernel of the iteration at H's size,
+ * measured with HIP events on the context's stream around `reps` back-to-back
+ * launches (after two warm-up launches), on library-allocated blocks filled
+ * with a constant byte pattern.  Synchronous.  kernel selects:
+ *   TM_K_SPMM       X = H C                               (dtype)
+ *   TM_K_GRAM_SHIFT H' = C^T (X - C diag(h)), split-K part  (dtype)
+ *   TM_K_GRAM_SYM   S = C^T C upper tiles, split-K part     (dtype)
+ *   TM_K_ROT_GRAD   G = -2 (X' - C H')                     (dtype)
+ *   TM_K_TRMM       C D + C R'                             (dtype)
+ *   TM_K_GRAM_MP2   H' from FP64 blocks on FP32 matrix cores (dtype ignored) */
+typedef enum tm_kernel_id {
+    TM_K_SPMM = 0,
+    TM_K_GRAM_SHIFT = 1,
+    TM_K_GRAM_SYM = 2,
+    TM_K_ROT_GRAD = 3,
+    TM_K_TRMM = 4,
+    TM_K_GRAM_MP2 = 5
+} tm_kernel_id;
+
+tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m,
+                         int32_t dtype, int32_t reps, double *avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRACEMIN_H */

@@ -1,0 +1,303 @@
+"""MI355X-native trace-minimization eigensolver (Tsuchida & Choe, arXiv 1108.4509).
+
+Thin Python binding over the C ABI in include/tracemin.h.  PyTorch provides
+device memory (the library's allocator hook is bound to torch's caching
+allocator) and the stream; every step of the solver runs in the HIP kernels of
+libtracemin.so.  Functions keep the C names without the ``tm_`` prefix.
+"""
+
+from __future__ import annotations
+
+import atexit
+import ctypes
+import sys
+import weakref
+from typing import Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import (TM_F32, TM_F64, TM_FULL_DP, TM_FULL_SP, TM_MIXED, TM_MP2,  # noqa: F401
+                   TM_ENOCONV, TM_ENOTSPD, TM_EINVAL, TM_OK, TraceminError)
+
+PRECISIONS = {"full_dp": TM_FULL_DP, "full_sp": TM_FULL_SP, "mp2": TM_MP2, "mixed": TM_MIXED}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# Matrices must be freed before their context is destroyed.  At interpreter
+# exit the garbage collector gives no such order, so live handles are
+# released explicitly by an exit hook registered after torch is imported (the
+# hooks run in reverse order, so ours runs while torch is still usable).
+_live_matrices: "weakref.WeakSet" = weakref.WeakSet()
+_live_contexts: "weakref.WeakSet" = weakref.WeakSet()
+_exit_hook_installed = False
+
+
+def _release_all():
+    for mat in list(_live_matrices):
+        mat.free()
+    for ctx in list(_live_contexts):
+        ctx.close()
+
+
+def leading_dim(m: int) -> int:
+    return int(_abi.lib().tm_leading_dim(int(m)))
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr()) if t is not None else 0
+
+
+class Context:
+    """A library context on one GPU, using torch's allocator and current stream."""
+
+    def __init__(self, device: int = 0, torch_allocator: bool = True):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the trace-minimization library needs a HIP device")
+        self.device = int(device)
+        torch.cuda.set_device(self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        L = _abi.lib()
+        self._alloc = None
+        alloc_ptr = None
+        if torch_allocator:
+            dev, stream = self.device, self.stream
+
+            def _a(nbytes, _user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+                except Exception:  # reported to the library as a failed allocation
+                    return None
+
+            def _f(ptr, _user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._alloc = _abi.tm_allocator(_abi.ALLOC_FN(_a), _abi.FREE_FN(_f), None)
+            alloc_ptr = ctypes.byref(self._alloc)
+        h = ctypes.c_void_p()
+        _abi.check(L.tm_create(self.device, alloc_ptr, ctypes.c_void_p(self.stream.cuda_stream),
+                               ctypes.byref(h)), "tm_create")
+        self.handle = h
+        global _exit_hook_installed
+        if not _exit_hook_installed:
+            atexit.register(_release_all)
+            _exit_hook_installed = True
+        _live_contexts.add(self)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            for mat in list(_live_matrices):
+                if mat.ctx is self:
+                    mat.free()
+            _abi.lib().tm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Matrix:
+    """A device-resident H (CSR or stencil) owned by a Context."""
+
+    def __init__(self, ctx: Context, handle: ctypes.c_void_p, n: int):
+        self.ctx, self.handle, self.n = ctx, handle, n
+        _live_matrices.add(self)
+
+    def free(self):
+        if self.handle and self.ctx.handle:
+            _abi.lib().tm_free_matrix(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def set_matrix_csr(ctx: Context, rowptr, col, val) -> Matrix:
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    n = rowptr.shape[0] - 1
+    h = ctypes.c_void_p()
+    _abi.check(_abi.lib().tm_set_matrix_csr(ctx.handle, n, rowptr.ctypes.data, col.ctypes.data,
+                                            val.ctypes.data, ctypes.byref(h)), "tm_set_matrix_csr")
+    return Matrix(ctx, h, n)
+
+
+def set_matrix_stencil(ctx: Context, ndim: int, dims, order: int = 2, periodic: bool = True,
+                       kinetic_scale: float = 0.5, V: Optional[np.ndarray] = None) -> Matrix:
+    s = _abi.tm_stencil()
+    s.ndim = ndim
+    d = list(dims) + [1] * (3 - len(dims))
+    for i in range(3):
+        s.dims[i] = int(d[i])
+    s.order = order
+    s.periodic = 1 if periodic else 0
+    s.kinetic_scale = kinetic_scale
+    keep = None
+    if V is not None:
+        keep = np.ascontiguousarray(V, dtype=np.float64).reshape(-1)
+        s.V = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    _abi.check(_abi.lib().tm_set_matrix_stencil(ctx.handle, ctypes.byref(s), ctypes.byref(h)),
+               "tm_set_matrix_stencil")
+    n = int(np.prod(d[:ndim]))
+    return Matrix(ctx, h, n)
+
+
+def matrix_from_problem(ctx: Context, problem, stencil: bool = False) -> Matrix:
+    """Upload a ``workloads.Problem`` as CSR or as a stencil."""
+    if stencil:
+        sp = problem.spec
+        return set_matrix_stencil(ctx, sp.ndim, sp.dims, sp.order, sp.bc == "periodic",
+                                  sp.kinetic_scale, problem.V)
+    return set_matrix_csr(ctx, *problem.csr())
+
+
+def to_block(C: np.ndarray, dtype=None, device=None):
+    """N x m host array -> zero-padded N x ld device tensor (FP64 unless dtype)."""
+    torch = _torch()
+    N, m = C.shape
+    ld = leading_dim(m)
+    dt = dtype or torch.float64
+    out = torch.zeros((N, ld), dtype=dt, device=device or "cuda")
+    out[:, :m] = torch.from_numpy(np.ascontiguousarray(C)).to(out.device, dt)
+    return out
+
+
+def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition=False,
+         history=False, switch_tol=0.0, rise_tol=1e-13) -> _abi.tm_opts:
+    o = _abi.tm_opts()
+    _abi.lib().tm_opts_default(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.max_iter = max_iter
+    o.k_rot = k_rot
+    o.k_check = k_check
+    o.precondition = 1 if precondition else 0
+    o.history = 1 if history else 0
+    o.switch_tol = switch_tol
+    o.rise_tol = rise_tol
+    return o
+
+
+def solve(ctx: Context, H: Matrix, m: int, tol: float, C0, options=None, history_len: int = 0,
+          want_vectors: bool = True, allow_noconv: bool = True):
+    """Run tm_solve.  C0: N x ld FP64 device tensor (see ``to_block``).
+
+    Returns (result dict, C tensor or None, eigenvalue tensor, history array or None).
+    """
+    torch = _torch()
+    N, ld = C0.shape
+    if C0.dtype != torch.float64 or not C0.is_contiguous():
+        raise ValueError("C0 must be a contiguous FP64 device tensor")
+    o = options or opts()
+    Cout = torch.empty_like(C0) if want_vectors else None
+    eig = torch.empty(max(m, 1), dtype=torch.float64, device=C0.device)
+    hist = np.zeros(2 * history_len) if history_len > 0 else None
+    res = _abi.tm_result()
+    st = _abi.lib().tm_solve(ctx.handle, H.handle, m, tol, ctypes.byref(o), _ptr(C0), _ptr(Cout),
+                             _ptr(eig), ctypes.byref(res),
+                             hist.ctypes.data if hist is not None else None, history_len)
+    _abi.check(st, "tm_solve", allow=(TM_OK, TM_ENOCONV) if allow_noconv else (TM_OK,))
+    r = res.as_dict()
+    r["status"] = st
+    if hist is not None:
+        n = min(history_len, r["iterations"] + (1 if r["converged"] else 0))
+        hist = hist.reshape(-1, 2)[:n]
+    return r, Cout, eig[:m], hist
+
+
+# ------------------------------------------------------------- single steps
+
+def _dtype_code(t):
+    torch = _torch()
+    return TM_F64 if t.dtype == torch.float64 else TM_F32
+
+
+def spmm(ctx: Context, H: Matrix, m: int, C, X):
+    _abi.check(_abi.lib().tm_spmm(ctx.handle, H.handle, m, _dtype_code(C), _ptr(C), _ptr(X)),
+               "tm_spmm")
+
+
+def gram(ctx: Context, m: int, A, B, h=None, out=None):
+    torch = _torch()
+    n = A.shape[0]
+    out = out if out is not None else torch.empty((m, m), dtype=torch.float64, device=A.device)
+    _abi.check(_abi.lib().tm_gram(ctx.handle, n, m, _dtype_code(A), _ptr(A), _ptr(B), _ptr(h),
+                                  _ptr(out)), "tm_gram")
+    return out
+
+
+def rotate(ctx: Context, m: int, A, W, out=None):
+    torch = _torch()
+    out = out if out is not None else torch.empty_like(A)
+    _abi.check(_abi.lib().tm_rotate(ctx.handle, A.shape[0], m, _dtype_code(A), _ptr(A), _ptr(W),
+                                    _ptr(out)), "tm_rotate")
+    return out
+
+
+def energy_grad(ctx: Context, H: Matrix, m: int, C, precision="full_dp"):
+    torch = _torch()
+    X = torch.empty_like(C)
+    G = torch.empty_like(C)
+    h = torch.empty(m, dtype=torch.float64, device=C.device)
+    Hp = torch.empty((m, m), dtype=torch.float64, device=C.device)
+    E = torch.empty(1, dtype=torch.float64, device=C.device)
+    p = PRECISIONS[precision] if isinstance(precision, str) else precision
+    _abi.check(_abi.lib().tm_energy_grad(ctx.handle, H.handle, m, p, _ptr(C), _ptr(X), _ptr(G),
+                                         _ptr(h), _ptr(Hp), _ptr(E)), "tm_energy_grad")
+    return float(E.item()), G, X, h, Hp
+
+
+def orthonormalize(ctx: Context, m: int, C, precision="full_dp"):
+    p = PRECISIONS[precision] if isinstance(precision, str) else precision
+    _abi.check(_abi.lib().tm_orthonormalize(ctx.handle, C.shape[0], m, p, _ptr(C)),
+               "tm_orthonormalize")
+    return C
+
+
+def cholesky_inverse(ctx: Context, S):
+    torch = _torch()
+    m = S.shape[0]
+    R = torch.empty_like(S)
+    _abi.check(_abi.lib().tm_cholesky_inverse(ctx.handle, m, _ptr(S), _ptr(R)),
+               "tm_cholesky_inverse")
+    return R
+
+
+def sym_eig(ctx: Context, A):
+    torch = _torch()
+    m = A.shape[0]
+    U = torch.empty_like(A)
+    w = torch.empty(m, dtype=torch.float64, device=A.device)
+    _abi.check(_abi.lib().tm_sym_eig(ctx.handle, m, _ptr(A), _ptr(U), _ptr(w)), "tm_sym_eig")
+    return w, U
+
+
+KERNELS = {"spmm": _abi.TM_K_SPMM, "gram_shift": _abi.TM_K_GRAM_SHIFT,
+           "gram_sym": _abi.TM_K_GRAM_SYM, "rot_grad": _abi.TM_K_ROT_GRAD,
+           "trmm": _abi.TM_K_TRMM, "gram_mp2": _abi.TM_K_GRAM_MP2}
+
+
+def time_kernel(ctx: Context, H: Matrix, kernel: str, m: int, dtype: str = "f32",
+                reps: int = 20) -> float:
+    """Average duration (ms) of one kernel launch, timed with HIP events."""
+    out = ctypes.c_double()
+    code = TM_F64 if dtype == "f64" else TM_F32
+    _abi.check(_abi.lib().tm_time_kernel(ctx.handle, H.handle, KERNELS[kernel], m, code, reps,
+                                         ctypes.byref(out)), "tm_time_kernel")
+    return out.value

@@ -1,0 +1,327 @@
+// O(mN) block kernels: column dot products, the CG vector updates of Fig. 1,
+// precision conversions, and the single-workgroup CG controller that decides
+// gamma (Eq. 8), restarts, alpha and convergence without a host round trip.
+#include "tm_common.h"
+
+#include <cmath>
+
+namespace tmin {
+namespace {
+
+constexpr int kDotThreads = 256;
+
+// Column-dot partial sums.  grid.x = row chunks, grid.y = 256-column slabs.
+// Within a slab of width w, 256 / w rows are visited at once; the per-row
+// partial sums are folded in LDS in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(kDotThreads) void coldots_kernel(
+    int64_t n, int ld, int64_t rows_per_chunk, DotArgs<T> args,
+    double *__restrict__ partials) {
+    __shared__ double red[4][kDotThreads];
+    const int slab0 = blockIdx.y * kDotThreads;
+    int w = ld - slab0;
+    if (w > kDotThreads) w = kDotThreads;
+    const int ri = kDotThreads / w;
+    const int t = threadIdx.x;
+    const int ro = t / w;
+    const int j = slab0 + (t - ro * w);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+    int64_t r1 = r0 + rows_per_chunk;
+    if (r1 > n) r1 = n;
+    if (ro < ri) {
+        const double scj = (args.kind == 1) ? args.sc[j] : 0.0;
+        for (int64_t r = r0 + ro; r < r1; r += ri) {
+            const int64_t e = r * ld + j;
+            const double wr = args.w ? args.w[r] : 1.0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                if (p >= args.nprod) break;
+                const double a = (double)args.a[p][e];
+                const double b = (double)args.b[p][e];
+                double v;
+                if (args.kind == 1) {
+                    const double d = a - scj * b;
+                    v = d * d;
+                } else {
+                    v = a * b;
+                }
+                if (args.weighted[p]) v *= wr;
+                acc[p] += v;
+            }
+        }
+    }
+    for (int p = 0; p < 4; ++p) red[p][t] = acc[p];
+    __syncthreads();
+    if (t < w) {
+        for (int p = 0; p < args.nprod; ++p) {
+            double s = 0.0;
+            for (int q = 0; q < ri; ++q) s += red[p][q * w + t];
+            partials[((int64_t)p * gridDim.x + blockIdx.x) * ld + slab0 + t] = s;
+        }
+    }
+}
+
+__global__ void coldots_reduce_kernel(int nprod, int nchunk, int ld,
+                                      const double *__restrict__ partials,
+                                      double *__restrict__ out) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nprod * ld) return;
+    const int p = idx / ld, j = idx - p * ld;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += partials[((int64_t)p * nchunk + c) * ld + j];
+    out[idx] = s;
+}
+
+int dot_chunks(int64_t n) {
+    int64_t c = n / 128;
+    if (c < 1) c = 1;
+    if (c > 1024) c = 1024;
+    return (int)c;
+}
+
+template <typename TG, typename TP>
+__global__ void p_update_kernel(int64_t count, int ld, const TG *__restrict__ G,
+                                const double *__restrict__ M,
+                                const CgState *__restrict__ st,
+                                TP *__restrict__ P) {
+    const double gamma = st->gamma;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double z = (double)G[e];
+        if (M) z *= M[e / ld];
+        const double p = (gamma != 0.0) ? z + gamma * (double)P[e] : z;
+        P[e] = (TP)p;
+    }
+}
+
+template <typename TC, typename TP>
+__global__ void c_update_kernel(int64_t count, const TC *__restrict__ C,
+                                const TP *__restrict__ P,
+                                const CgState *__restrict__ st,
+                                TC *__restrict__ Cn) {
+    const TC alpha = (TC)st->alpha;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        Cn[e] = C[e] + alpha * (TC)P[e];
+}
+
+template <typename TI, typename TO>
+__global__ void convert_kernel(int64_t count, const TI *__restrict__ in,
+                               TO *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = (TO)in[e];
+}
+
+int elem_grid(int64_t count) {
+    int64_t g = (count + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// Fixed-order sum of v[0..m) by one workgroup of 256 lanes.
+__device__ double block_sum(const double *v, int m, double *red) {
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int j = t; j < m; j += 256) s += v[j];
+    red[t] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (t < k) red[t] += red[t + k];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_max(const double *v, int m, double *red) {
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int j = t; j < m; j += 256) s = fmax(s, v[j]);
+    red[t] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (t < k) red[t] = fmax(red[t], red[t + k]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Controller, part 1 (after the gradient): energy, residual norm,
+// convergence and phase-switch tests, restart decision and Polak-Ribiere gamma.
+// dots rows: 0 gg = tr(G^T G), 1 gz = tr(G^T Z), 2 tr(G_prev^T Z), 3 tr(P_prev^T G).
+__global__ __launch_bounds__(256) void control_gamma_kernel(
+    int m, int ld, const double *__restrict__ h, const double *__restrict__ dots,
+    CgState *st, double *history) {
+    __shared__ double red[256];
+    const double E = block_sum(h, m, red);
+    const double gg = block_sum(dots, m, red);
+    const double gz = block_sum(dots + ld, m, red);
+    const double gpz = block_sum(dots + 2 * ld, m, red);
+    const double ppg = block_sum(dots + 3 * ld, m, red);
+    if (threadIdx.x != 0) return;
+    const double rho = 0.5 * sqrt(gg);
+    st->E = E;
+    st->rho = rho;
+    const bool finite = isfinite(E) && isfinite(rho);
+    if (!finite) st->nan_seen = 1;
+    const bool active = !st->done && !st->phase_end;
+    if (active) {
+        if (history && st->it < st->history_len) {
+            history[2 * st->it] = E;
+            history[2 * st->it + 1] = rho;
+        }
+        st->it += 1;
+    }
+    if (active && (rho <= st->tol || !finite)) st->done = 1;
+    if (active && !st->done && st->phase_gate) {
+        if (rho <= st->switch_tol) st->phase_end = 1;
+        if (st->stall_window > 0) {
+            if (st->window_it == 0) st->E_window = E;
+            st->window_it += 1;
+            if (st->window_it > st->stall_window) {
+                if (st->E_window - E < st->stall_tol * fabs(E)) st->phase_end = 1;
+                st->window_it = 0;
+            }
+        }
+    }
+    if (st->done || st->phase_end) {
+        st->gamma = 0.0;
+        st->pg = 0.0;
+        return;
+    }
+    bool restart = st->force_restart || !st->have_prev;
+    if (st->have_prev && E > st->E_prev + st->rise_tol * fabs(st->E_prev)) restart = true;
+    double gamma = 0.0;
+    if (!restart) gamma = (gz - gpz) / st->gz_prev;
+    double pg = gz;
+    if (gamma != 0.0) pg += gamma * ppg;
+    if (!(pg > 0.0) || !isfinite(gamma) || !isfinite(pg)) {  // not a descent direction
+        gamma = 0.0;
+        pg = gz;
+    }
+    if (gamma == 0.0) st->restarts += 1;
+    st->gamma = gamma;
+    st->pg = pg;
+    st->E_prev = E;
+    st->gz_prev = gz;
+    st->have_prev = 1;
+    st->force_restart = 0;
+}
+
+// Controller, part 2 (after Y = HP): step length from the second-order model
+// curvature = 2 sum_j (p_j.y_j - h_j p_j.p_j), capped at 1 / max_j |p_j|.
+__global__ __launch_bounds__(256) void control_alpha_kernel(
+    int m, int ld, const double *__restrict__ h, const double *__restrict__ dots2,
+    CgState *st) {
+    __shared__ double red[256];
+    const double ppmax = block_max(dots2, m, red);
+    // curvature terms, summed in a fixed order
+    double local = 0.0;
+    for (int j = threadIdx.x; j < m; j += 256)
+        local += dots2[ld + j] - h[j] * dots2[j];
+    red[threadIdx.x] = local;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    if (st->done || st->phase_end) {
+        st->alpha = 0.0;
+        return;
+    }
+    const double curv = 2.0 * red[0];
+    const double cap = ppmax > 0.0 ? 1.0 / sqrt(ppmax) : 0.0;
+    double alpha = cap;
+    if (curv > 0.0) alpha = fmin(st->pg / curv, cap);
+    if (!isfinite(alpha)) alpha = 0.0;
+    st->alpha = alpha;
+}
+
+__global__ void sum_vector_kernel(int m, const double *v, double *out) {
+    __shared__ double red[256];
+    const double s = block_sum(v, m, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+}  // namespace
+
+size_t coldots_workspace(int64_t n, int ld) {
+    return (size_t)4 * dot_chunks(n) * ld * sizeof(double);
+}
+
+template <typename T>
+void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
+             double *partials, double *out) {
+    const int nchunk = dot_chunks(n);
+    const int64_t rows = (n + nchunk - 1) / nchunk;
+    const int nslab = (ld + kDotThreads - 1) / kDotThreads;
+    hipLaunchKernelGGL(coldots_kernel<T>, dim3(nchunk, nslab), dim3(kDotThreads), 0,
+                       s, n, ld, rows, args, partials);
+    const int total = args.nprod * ld;
+    hipLaunchKernelGGL(coldots_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0,
+                       s, args.nprod, nchunk, ld, partials, out);
+    TM_HIP(hipGetLastError());
+}
+
+template <typename TG, typename TP>
+void p_update(hipStream_t s, int64_t n, int ld, const TG *G, const double *M,
+              const CgState *st, TP *P) {
+    const int64_t count = n * ld;
+    hipLaunchKernelGGL((p_update_kernel<TG, TP>), dim3(elem_grid(count)), dim3(256),
+                       0, s, count, ld, G, M, st, P);
+    TM_HIP(hipGetLastError());
+}
+
+template <typename TC, typename TP>
+void c_update(hipStream_t s, int64_t n, int ld, const TC *C, const TP *P,
+              const CgState *st, TC *Cn) {
+    const int64_t count = n * ld;
+    hipLaunchKernelGGL((c_update_kernel<TC, TP>), dim3(elem_grid(count)), dim3(256),
+                       0, s, count, C, P, st, Cn);
+    TM_HIP(hipGetLastError());
+}
+
+template <typename TI, typename TO>
+void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out) {
+    hipLaunchKernelGGL((convert_kernel<TI, TO>), dim3(elem_grid(count)), dim3(256),
+                       0, s, count, in, out);
+    TM_HIP(hipGetLastError());
+}
+
+void cg_control_gamma(hipStream_t s, int m, int ld, const double *h,
+                      const double *dots, CgState *st, double *history) {
+    hipLaunchKernelGGL(control_gamma_kernel, dim3(1), dim3(256), 0, s, m, ld, h,
+                       dots, st, history);
+    TM_HIP(hipGetLastError());
+}
+
+void cg_control_alpha(hipStream_t s, int m, int ld, const double *h,
+                      const double *dots2, CgState *st) {
+    hipLaunchKernelGGL(control_alpha_kernel, dim3(1), dim3(256), 0, s, m, ld, h,
+                       dots2, st);
+    TM_HIP(hipGetLastError());
+}
+
+void sum_vector(hipStream_t s, int m, const double *v, double *out) {
+    hipLaunchKernelGGL(sum_vector_kernel, dim3(1), dim3(256), 0, s, m, v, out);
+    TM_HIP(hipGetLastError());
+}
+
+template void coldots<double>(hipStream_t, int64_t, int, const DotArgs<double> &, double *, double *);
+template void coldots<float>(hipStream_t, int64_t, int, const DotArgs<float> &, double *, double *);
+template void p_update<double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *);
+template void p_update<float, float>(hipStream_t, int64_t, int, const float *, const double *, const CgState *, float *);
+template void c_update<double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *);
+template void c_update<float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *);
+template void c_update<double, float>(hipStream_t, int64_t, int, const double *, const float *, const CgState *, double *);
+template void convert_block<double, float>(hipStream_t, int64_t, const double *, float *);
+template void convert_block<float, double>(hipStream_t, int64_t, const float *, double *);
+
+}  // namespace tmin

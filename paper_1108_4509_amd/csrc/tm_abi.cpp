@@ -1,0 +1,511 @@
+// extern "C" entry points declared in include/tracemin.h.  Validates
+// arguments, owns the matrix uploads, and converts internal errors into
+// tm_status codes (no exception leaves this file).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "tm_solver.h"
+
+using namespace tmin;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+tm_status guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return TM_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return TM_EINVAL;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return TM_EINVAL;
+    }
+}
+
+void use_device(const tm_ctx *ctx) {
+    TM_REQUIRE(ctx != nullptr, TM_EINVAL, "null context");
+    TM_HIP(hipSetDevice(ctx->device));
+}
+
+void sync(const tm_ctx *ctx) { TM_HIP(hipStreamSynchronize(ctx->stream)); }
+
+template <typename T>
+T *upload(tm_ctx *ctx, const T *host, size_t count) {
+    T *d = (T *)ctx->dalloc(count * sizeof(T) + 16);
+    TM_REQUIRE(d != nullptr, TM_ENOMEM, "device allocation failed");
+    TM_HIP(hipMemcpyAsync(d, host, count * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    return d;
+}
+
+void free_matrix_arrays(tm_mat *m) {
+    tm_ctx *c = m->ctx;
+    void *arrs[] = {m->rowptr, m->col, m->val64, m->val32, m->V64, m->V32, m->diag};
+    for (void *p : arrs)
+        if (p) c->dfree(p);
+}
+
+void check_block_args(const tm_ctx *ctx, int64_t n, int32_t m) {
+    use_device(ctx);
+    TM_REQUIRE(n >= 1, TM_EINVAL, "n must be positive");
+    TM_REQUIRE(m >= 1 && m <= 4096, TM_EINVAL, "m must be in [1, 4096]");
+    TM_REQUIRE(m <= n, TM_EINVAL, "m must not exceed n");
+}
+
+}  // namespace
+
+void *tm_ctx::dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    if (custom_alloc) return alloc.alloc(bytes, alloc.user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void tm_ctx::dfree(void *p) {
+    if (!p) return;
+    if (custom_alloc) alloc.free(p, alloc.user);
+    else (void)hipFree(p);
+}
+
+extern "C" {
+
+int32_t tm_leading_dim(int32_t m) { return leading_dim(m); }
+
+const char *tm_last_error(void) { return g_last_error.c_str(); }
+
+const char *tm_status_string(int32_t status) {
+    switch (status) {
+    case TM_OK: return "ok";
+    case TM_EINVAL: return "invalid argument";
+    case TM_ENOMEM: return "out of device memory";
+    case TM_ENOTSPD: return "C^T C not positive definite";
+    case TM_ENOCONV: return "not converged within max_iter";
+    case TM_ENAN: return "NaN or Inf encountered";
+    case TM_EDEVICE: return "HIP runtime error";
+    case TM_ENOTSUP: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+tm_status tm_create(int32_t device, const tm_allocator *alloc, void *stream, tm_ctx **out) {
+    return guarded([&]() {
+        TM_REQUIRE(out != nullptr, TM_EINVAL, "out is null");
+        *out = nullptr;
+        int count = 0;
+        TM_HIP(hipGetDeviceCount(&count));
+        TM_REQUIRE(device >= 0 && device < count, TM_EINVAL, "no such device");
+        TM_HIP(hipSetDevice(device));
+        tm_ctx *c = new tm_ctx;
+        c->device = device;
+        c->stream = (hipStream_t)stream;
+        if (alloc) {
+            if (!alloc->alloc || !alloc->free) {
+                delete c;
+                throw Error{TM_EINVAL, "allocator needs alloc and free"};
+            }
+            c->alloc = *alloc;
+            c->custom_alloc = true;
+        }
+        *out = c;
+        return TM_OK;
+    });
+}
+
+void tm_destroy(tm_ctx *ctx) { delete ctx; }
+
+void tm_opts_default(tm_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = TM_FULL_DP;
+    o->max_iter = 20000;
+    o->k_rot = 50;
+    o->k_check = 10;
+    o->precondition = 0;
+    o->history = 0;
+    o->switch_tol = 0.0;
+    o->rise_tol = 1e-13;
+}
+
+tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr, const int32_t *col,
+                            const double *val, tm_mat **out) {
+    return guarded([&]() {
+        use_device(ctx);
+        TM_REQUIRE(out && rowptr && col && val, TM_EINVAL, "null argument");
+        TM_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), TM_EINVAL, "n out of range");
+        *out = nullptr;
+        TM_REQUIRE(rowptr[0] == 0, TM_EINVAL, "rowptr[0] must be 0");
+        for (int64_t r = 0; r < n; ++r)
+            TM_REQUIRE(rowptr[r + 1] >= rowptr[r], TM_EINVAL, "rowptr must be non-decreasing");
+        const int64_t nnz = rowptr[n];
+        std::vector<double> diag(n, 0.0);
+        std::vector<float> v32(nnz);
+        for (int64_t r = 0; r < n; ++r)
+            for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+                TM_REQUIRE(col[k] >= 0 && col[k] < n, TM_EINVAL, "column index out of range");
+                TM_REQUIRE(std::isfinite(val[k]), TM_EINVAL, "non-finite matrix value");
+                if (col[k] == r) diag[r] += val[k];
+            }
+        for (int64_t k = 0; k < nnz; ++k) v32[k] = (float)val[k];
+        tm_mat *m = new tm_mat;
+        m->ctx = ctx;
+        m->n = n;
+        try {
+            m->rowptr = upload(ctx, rowptr, n + 1);
+            m->col = upload(ctx, col, nnz);
+            m->val64 = upload(ctx, val, nnz);
+            m->val32 = upload(ctx, v32.data(), nnz);
+            m->diag = upload(ctx, diag.data(), n);
+            sync(ctx);
+        } catch (...) {
+            free_matrix_arrays(m);
+            delete m;
+            throw;
+        }
+        m->diag_min = *std::min_element(diag.begin(), diag.end());
+        m->diag_max = *std::max_element(diag.begin(), diag.end());
+        // Gershgorin-type scale of ||H|| for the automatic switch tolerance
+        double gmax = 0.0;
+        for (int64_t r = 0; r < n; ++r) {
+            double s = 0.0;
+            for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) s += std::fabs(val[k]);
+            gmax = std::max(gmax, s);
+        }
+        m->diag_max = std::max(m->diag_max, 0.5 * gmax);
+        m->csr.n = n;
+        m->csr.nnz = nnz;
+        m->csr.rowptr = m->rowptr;
+        m->csr.col = m->col;
+        m->csr.val64 = m->val64;
+        m->csr.val32 = m->val32;
+        *out = m;
+        return TM_OK;
+    });
+}
+
+tm_status tm_set_matrix_stencil(tm_ctx *ctx, const tm_stencil *s, tm_mat **out) {
+    return guarded([&]() {
+        use_device(ctx);
+        TM_REQUIRE(out && s, TM_EINVAL, "null argument");
+        *out = nullptr;
+        TM_REQUIRE(s->ndim == 2 || s->ndim == 3, TM_EINVAL, "ndim must be 2 or 3");
+        TM_REQUIRE(s->order == 2 || s->order == 4, TM_EINVAL, "order must be 2 or 4");
+        TM_REQUIRE(std::isfinite(s->kinetic_scale), TM_EINVAL, "bad kinetic_scale");
+        const int nz = s->ndim == 3 ? s->dims[2] : 1;
+        TM_REQUIRE(s->dims[0] >= 1 && s->dims[1] >= 1 && nz >= 1, TM_EINVAL, "bad grid extents");
+        const int64_t n = (int64_t)s->dims[0] * s->dims[1] * nz;
+        TM_REQUIRE(n < ((int64_t)1 << 31), TM_EINVAL, "grid too large");
+        tm_mat *m = new tm_mat;
+        m->ctx = ctx;
+        m->n = n;
+        m->is_stencil = true;
+        const double ks = s->kinetic_scale;
+        StencilDev &d = m->st;
+        d.ndim = s->ndim;
+        d.nx = s->dims[0];
+        d.ny = s->dims[1];
+        d.nz = nz;
+        d.order = s->order;
+        d.periodic = s->periodic ? 1 : 0;
+        if (s->order == 2) {
+            d.c0 = s->ndim * 2.0 * ks;
+            d.c1 = -ks;
+            d.c2 = 0.0;
+        } else {
+            d.c0 = s->ndim * (30.0 / 12.0) * ks;
+            d.c1 = -(16.0 / 12.0) * ks;
+            d.c2 = (1.0 / 12.0) * ks;
+        }
+        std::vector<double> diag(n, d.c0);
+        try {
+            if (s->V) {
+                std::vector<float> v32(n);
+                for (int64_t r = 0; r < n; ++r) {
+                    TM_REQUIRE(std::isfinite(s->V[r]), TM_EINVAL, "non-finite potential value");
+                    v32[r] = (float)s->V[r];
+                    diag[r] += s->V[r];
+                }
+                m->V64 = upload(ctx, s->V, n);
+                m->V32 = upload(ctx, v32.data(), n);
+                d.V64 = m->V64;
+                d.V32 = m->V32;
+            }
+            m->diag = upload(ctx, diag.data(), n);
+            sync(ctx);
+        } catch (...) {
+            free_matrix_arrays(m);
+            delete m;
+            throw;
+        }
+        m->diag_min = *std::min_element(diag.begin(), diag.end());
+        const double off = s->ndim * (2.0 * std::fabs(d.c1) + 2.0 * std::fabs(d.c2));
+        m->diag_max = std::max(*std::max_element(diag.begin(), diag.end()),
+                               0.5 * (std::fabs(d.c0) + off));
+        *out = m;
+        return TM_OK;
+    });
+}
+
+void tm_free_matrix(tm_mat *mat) {
+    if (!mat) return;
+    (void)hipSetDevice(mat->ctx->device);
+    (void)hipStreamSynchronize(mat->ctx->stream);
+    free_matrix_arrays(mat);
+    delete mat;
+}
+
+int64_t tm_matrix_rows(const tm_mat *mat) { return mat ? mat->n : -1; }
+
+tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol, const tm_opts *opts,
+                   const double *C0, double *C_out, double *eig_out, tm_result *res,
+                   double *history, int32_t history_len) {
+    return guarded([&]() {
+        TM_REQUIRE(H && C0 && res, TM_EINVAL, "null argument");
+        check_block_args(ctx, H->n, m);
+        TM_REQUIRE(H->ctx == ctx, TM_EINVAL, "matrix belongs to another context");
+        TM_REQUIRE(tol > 0.0 && std::isfinite(tol), TM_EINVAL, "tol must be positive");
+        TM_REQUIRE(m <= 1024, TM_ENOTSUP, "m > 1024 is not supported");
+        tm_opts o;
+        if (opts) o = *opts; else tm_opts_default(&o);
+        TM_REQUIRE(o.max_iter >= 0, TM_EINVAL, "max_iter must be >= 0");
+        TM_REQUIRE(o.precision >= TM_FULL_DP && o.precision <= TM_MIXED, TM_EINVAL, "unknown precision");
+        TM_REQUIRE(history_len >= 0, TM_EINVAL, "history_len must be >= 0");
+        std::memset(res, 0, sizeof(*res));
+        Solver solver(ctx, H, m, tol, o);
+        return solver.run(C0, C_out, eig_out, res, history, history_len);
+    });
+}
+
+tm_status tm_spmm(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t dtype, const void *C, void *X) {
+    return guarded([&]() {
+        TM_REQUIRE(H && C && X, TM_EINVAL, "null argument");
+        check_block_args(ctx, H->n, m);
+        TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
+        spmm_any(ctx->stream, H, leading_dim(m), C, X, dtype == TM_F64);
+        sync(ctx);
+        return TM_OK;
+    });
+}
+
+tm_status tm_gram(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype, const void *A, const void *B,
+                  const double *h, double *out) {
+    return guarded([&]() {
+        TM_REQUIRE(A && B && out, TM_EINVAL, "null argument");
+        check_block_args(ctx, n, m);
+        TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
+        const int ld = leading_dim(m);
+        DevMem ws(ctx, gram_workspace(n, m));
+        DevMem hp(ctx, ld * sizeof(double));
+        const double *hv = nullptr;
+        if (h) {
+            TM_HIP(hipMemsetAsync(hp.ptr, 0, ld * sizeof(double), ctx->stream));
+            TM_HIP(hipMemcpyAsync(hp.ptr, h, m * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+            hv = (const double *)hp.ptr;
+        }
+        const bool sym = (A == B) && !h;
+        if (dtype == TM_F64)
+            gram<double, double>(ctx->stream, n, m, (const double *)A, (const double *)B, hv, false, sym,
+                                 (double *)ws.ptr, out);
+        else
+            gram<float, float>(ctx->stream, n, m, (const float *)A, (const float *)B, hv, false, sym,
+                               (double *)ws.ptr, out);
+        sync(ctx);
+        return TM_OK;
+    });
+}
+
+tm_status tm_rotate(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype, const void *A, const double *W,
+                    void *out) {
+    return guarded([&]() {
+        TM_REQUIRE(A && W && out, TM_EINVAL, "null argument");
+        check_block_args(ctx, n, m);
+        TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
+        TM_REQUIRE(A != out, TM_EINVAL, "out must not alias A");
+        const int ld = leading_dim(m);
+        DevMem wp(ctx, (size_t)ld * ld * sizeof(double));
+        if (dtype == TM_F64) {
+            pad_matrix<double>(ctx->stream, m, W, false, (double *)wp.ptr, nullptr);
+            rot<double, double, double>(ctx->stream, n, m, (const double *)A, (const double *)wp.ptr,
+                                        EPI_NONE, nullptr, nullptr, (double *)out);
+        } else {
+            pad_matrix<float>(ctx->stream, m, W, false, (float *)wp.ptr, nullptr);
+            rot<float, float, float>(ctx->stream, n, m, (const float *)A, (const float *)wp.ptr,
+                                     EPI_NONE, nullptr, nullptr, (float *)out);
+        }
+        sync(ctx);
+        return TM_OK;
+    });
+}
+
+tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t precision, const double *C,
+                         double *X, double *G, double *h, double *Hp, double *E) {
+    return guarded([&]() {
+        TM_REQUIRE(H && C && X && G && h && Hp && E, TM_EINVAL, "null argument");
+        check_block_args(ctx, H->n, m);
+        TM_REQUIRE(precision == TM_FULL_DP || precision == TM_MP2, TM_EINVAL,
+                   "precision must be TM_FULL_DP or TM_MP2");
+        const int ld = leading_dim(m);
+        const int64_t n = H->n;
+        hipStream_t s = ctx->stream;
+        DevMem hv(ctx, ld * sizeof(double)), dws(ctx, coldots_workspace(n, ld)),
+            gws(ctx, gram_workspace(n, m)), wp(ctx, (size_t)ld * ld * sizeof(double));
+        spmm_any(s, H, ld, C, X, true);
+        DotArgs<double> a;
+        a.nprod = 1; a.a[0] = C; a.b[0] = X;
+        coldots<double>(s, n, ld, a, (double *)dws.ptr, (double *)hv.ptr);
+        if (precision == TM_FULL_DP) {
+            gram<double, double>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp);
+            pad_matrix<double>(s, m, Hp, false, (double *)wp.ptr, nullptr);
+            rot<double, double, double>(s, n, m, C, (double *)wp.ptr, EPI_GRAD, X, (double *)hv.ptr, G);
+        } else {
+            gram<double, float>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp);
+            pad_matrix<float>(s, m, Hp, false, (float *)wp.ptr, nullptr);
+            rot<double, float, double>(s, n, m, C, (float *)wp.ptr, EPI_GRAD, X, (double *)hv.ptr, G);
+        }
+        sum_vector(s, m, (double *)hv.ptr, E);
+        TM_HIP(hipMemcpyAsync(h, hv.ptr, m * sizeof(double), hipMemcpyDeviceToDevice, s));
+        sync(ctx);
+        return TM_OK;
+    });
+}
+
+tm_status tm_orthonormalize(tm_ctx *ctx, int64_t n, int32_t m, int32_t precision, double *C) {
+    return guarded([&]() {
+        TM_REQUIRE(C, TM_EINVAL, "null argument");
+        check_block_args(ctx, n, m);
+        TM_REQUIRE(precision == TM_FULL_DP || precision == TM_MP2, TM_EINVAL,
+                   "precision must be TM_FULL_DP or TM_MP2");
+        const int ld = leading_dim(m);
+        hipStream_t s = ctx->stream;
+        const size_t md = (size_t)m * m * sizeof(double);
+        DevMem S(ctx, md), R(ctx, md), ws(ctx, gram_workspace(n, m)), cw(ctx, chol_workspace(m)),
+            info(ctx, 16), wp(ctx, (size_t)ld * ld * sizeof(double)), dv(ctx, ld * sizeof(double)),
+            Cout(ctx, (size_t)n * ld * sizeof(double));
+        TM_HIP(hipMemsetAsync(info.ptr, 0, 16, s));
+        gram<double, double>(s, n, m, C, C, nullptr, false, true, (double *)ws.ptr, (double *)S.ptr);
+        chol_inverse(s, m, (double *)S.ptr, (double *)R.ptr, (double *)cw.ptr, (int32_t *)info.ptr);
+        int32_t bad = 0;
+        TM_HIP(hipMemcpyAsync(&bad, info.ptr, 4, hipMemcpyDeviceToHost, s));
+        sync(ctx);
+        TM_REQUIRE(bad == 0, TM_ENOTSPD, "C^T C is not positive definite");
+        if (precision == TM_FULL_DP) {
+            pad_matrix<double>(s, m, (double *)R.ptr, true, (double *)wp.ptr, (double *)dv.ptr);
+            rot<double, double, double>(s, n, m, C, (double *)wp.ptr, EPI_TRMM, nullptr, (double *)dv.ptr,
+                                        (double *)Cout.ptr);
+        } else {
+            pad_matrix<float>(s, m, (double *)R.ptr, true, (float *)wp.ptr, (double *)dv.ptr);
+            rot<double, float, double>(s, n, m, C, (float *)wp.ptr, EPI_TRMM, nullptr, (double *)dv.ptr,
+                                       (double *)Cout.ptr);
+        }
+        TM_HIP(hipMemcpyAsync(C, Cout.ptr, (size_t)n * ld * sizeof(double), hipMemcpyDeviceToDevice, s));
+        sync(ctx);
+        return TM_OK;
+    });
+}
+
+tm_status tm_cholesky_inverse(tm_ctx *ctx, int32_t m, const double *S, double *Rinv) {
+    return guarded([&]() {
+        TM_REQUIRE(S && Rinv, TM_EINVAL, "null argument");
+        use_device(ctx);
+        TM_REQUIRE(m >= 1 && m <= 4096, TM_EINVAL, "m out of range");
+        DevMem cw(ctx, chol_workspace(m)), info(ctx, 16);
+        TM_HIP(hipMemsetAsync(info.ptr, 0, 16, ctx->stream));
+        chol_inverse(ctx->stream, m, S, Rinv, (double *)cw.ptr, (int32_t *)info.ptr);
+        int32_t bad = 0;
+        TM_HIP(hipMemcpyAsync(&bad, info.ptr, 4, hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+        TM_REQUIRE(bad == 0, TM_ENOTSPD, "S is not positive definite (pivot " + std::to_string(bad) + ")");
+        return TM_OK;
+    });
+}
+
+tm_status tm_sym_eig(tm_ctx *ctx, int32_t m, const double *A, double *U, double *w) {
+    return guarded([&]() {
+        TM_REQUIRE(A && U && w, TM_EINVAL, "null argument");
+        use_device(ctx);
+        TM_REQUIRE(m >= 1 && m <= 1024, TM_EINVAL, "m must be in [1, 1024]");
+        DevMem jw(ctx, jacobi_workspace(m)), info(ctx, 16);
+        jacobi_eig(ctx->stream, m, A, U, w, (double *)jw.ptr, (int32_t *)info.ptr);
+        sync(ctx);
+        return TM_OK;
+    });
+}
+
+tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m, int32_t dtype,
+                         int32_t reps, double *avg_ms) {
+    return guarded([&]() {
+        TM_REQUIRE(H && avg_ms, TM_EINVAL, "null argument");
+        check_block_args(ctx, H->n, m);
+        TM_REQUIRE(reps >= 1 && reps <= 100000, TM_EINVAL, "reps out of range");
+        TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
+        TM_REQUIRE(kernel >= TM_K_SPMM && kernel <= TM_K_GRAM_MP2, TM_EINVAL, "unknown kernel");
+        const int ld = leading_dim(m);
+        const int64_t n = H->n;
+        const bool f64 = dtype == TM_F64 || kernel == TM_K_GRAM_MP2;
+        const size_t blk = (size_t)n * ld * (f64 ? 8 : 4);
+        hipStream_t s = ctx->stream;
+        DevMem A(ctx, blk), B(ctx, blk), O(ctx, blk), vec(ctx, ld * sizeof(double)),
+            ws(ctx, gram_workspace(n, m)), wp(ctx, (size_t)ld * ld * sizeof(double)),
+            mm(ctx, (size_t)m * m * sizeof(double));
+        TM_HIP(hipMemsetAsync(A.ptr, 0x3c, blk, s));
+        TM_HIP(hipMemsetAsync(B.ptr, 0x3c, blk, s));
+        TM_HIP(hipMemsetAsync(vec.ptr, 0, ld * sizeof(double), s));
+        TM_HIP(hipMemsetAsync(wp.ptr, 0x3c, (size_t)ld * ld * sizeof(double), s));
+        auto launch = [&]() {
+            double *ws_p = (double *)ws.ptr, *mm_p = (double *)mm.ptr, *v = (double *)vec.ptr;
+            switch (kernel) {
+            case TM_K_SPMM: spmm_any(s, H, ld, A.ptr, O.ptr, f64); break;
+            case TM_K_GRAM_SHIFT:
+                if (f64) gram<double, double>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false);
+                else gram<float, float>(s, n, m, (float *)A.ptr, (float *)B.ptr, v, true, false, ws_p, mm_p, false);
+                break;
+            case TM_K_GRAM_SYM:
+                if (f64) gram<double, double>(s, n, m, (double *)A.ptr, (double *)A.ptr, nullptr, false, true, ws_p, mm_p, false);
+                else gram<float, float>(s, n, m, (float *)A.ptr, (float *)A.ptr, nullptr, false, true, ws_p, mm_p, false);
+                break;
+            case TM_K_ROT_GRAD:
+                if (f64) rot<double, double, double>(s, n, m, (double *)A.ptr, (double *)wp.ptr, EPI_GRAD, (double *)B.ptr, v, (double *)O.ptr);
+                else rot<float, float, float>(s, n, m, (float *)A.ptr, (float *)wp.ptr, EPI_GRAD, (float *)B.ptr, v, (float *)O.ptr);
+                break;
+            case TM_K_TRMM:
+                if (f64) rot<double, double, double>(s, n, m, (double *)A.ptr, (double *)wp.ptr, EPI_TRMM, nullptr, v, (double *)O.ptr);
+                else rot<float, float, float>(s, n, m, (float *)A.ptr, (float *)wp.ptr, EPI_TRMM, nullptr, v, (float *)O.ptr);
+                break;
+            case TM_K_GRAM_MP2:
+                gram<double, float>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false);
+                break;
+            }
+        };
+        launch();
+        launch();
+        hipEvent_t e0, e1;
+        TM_HIP(hipEventCreate(&e0));
+        TM_HIP(hipEventCreate(&e1));
+        TM_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch();
+        TM_HIP(hipEventRecord(e1, s));
+        TM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *avg_ms = (double)ms / reps;
+        sync(ctx);
+        return TM_OK;
+    });
+}
+
+}  // extern "C"

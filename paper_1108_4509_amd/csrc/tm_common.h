@@ -1,0 +1,190 @@
+// Internal declarations shared by the host driver and the HIP kernels of the
+// trace-minimization library.  Not part of the public ABI (include/tracemin.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/tracemin.h"
+
+namespace tmin {
+
+// Internal error, converted to a tm_status at the C boundary.
+struct Error {
+    tm_status status;
+    std::string msg;
+};
+
+#define TM_HIP(call)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            throw ::tmin::Error{TM_EDEVICE, std::string(#call) + ": " +         \
+                                              hipGetErrorString(e_)};         \
+    } while (0)
+
+#define TM_REQUIRE(cond, st, text)                                            \
+    do {                                                                      \
+        if (!(cond)) throw ::tmin::Error{(st), (text)};                         \
+    } while (0)
+
+inline int leading_dim(int m) { return (m + 31) / 32 * 32; }
+
+// Device-resident scalars of the CG controller (one per solve).
+struct CgState {
+    // inputs set by the host
+    double tol;          // stop when rho <= tol
+    double rise_tol;     // restart when E > E_prev + rise_tol |E_prev|
+    double switch_tol;   // phase switch when rho <= switch_tol
+    double stall_tol;    // phase switch when E decreased by < stall_tol |E| over stall_window
+    int32_t stall_window;
+    int32_t history_len;
+    int32_t force_restart;   // host sets to 1 before an iteration that must restart
+    int32_t phase_gate;      // 1: this phase ends at switch_tol/stall (sets phase_end)
+    // evolving state
+    double E, E_prev, rho, gz_prev, gamma, pg, alpha;
+    double E_window;         // E at the start of the stall window
+    int32_t it;              // iterations recorded (stops advancing once done)
+    int32_t done;            // rho <= tol reached
+    int32_t phase_end;       // switch requested (FP32 phase)
+    int32_t restarts;
+    int32_t nan_seen;
+    int32_t window_it;
+    int32_t have_prev;       // E_prev, G_prev valid
+    int32_t pad_;
+};
+
+// ---------------------------------------------------------------- kernels
+// All launchers enqueue on `s` and return immediately.  Blocks are n x ld
+// row-major.  "partials" arguments are device workspaces sized by the
+// matching *_workspace() helper.
+
+// SpMM X = H C ---------------------------------------------------------------
+struct CsrDev {
+    int64_t n = 0, nnz = 0;
+    const int64_t *rowptr = nullptr;
+    const int32_t *col = nullptr;
+    const double *val64 = nullptr;
+    const float *val32 = nullptr;
+};
+struct StencilDev {
+    int32_t ndim = 3, nx = 1, ny = 1, nz = 1, order = 2, periodic = 1;
+    double c0 = 0;          // kinetic diagonal
+    double c1 = 0, c2 = 0;  // per-axis coefficients of offsets +-1, +-2
+    const double *V64 = nullptr;
+    const float *V32 = nullptr;
+};
+template <typename T>
+void spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X);
+template <typename T>
+void spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld,
+                  const T *C, T *X);
+
+// Column dot products ----------------------------------------------------
+// out[p * ld + j] = sum_r w_p(r) * f_p(a_p[r, j], b_p[r, j]) for p < nprod,
+// with f = a*b (kind 0) or (a - sc[j] * b)^2 (kind 1, sc device m-vector).
+// Accumulated in FP64, reduced in a fixed order (deterministic).
+template <typename T>
+struct DotArgs {
+    int nprod = 0;
+    const T *a[4] = {nullptr, nullptr, nullptr, nullptr};
+    const T *b[4] = {nullptr, nullptr, nullptr, nullptr};
+    int weighted[4] = {0, 0, 0, 0};
+    int kind = 0;
+    const double *w = nullptr;   // per-row weights (n)
+    const double *sc = nullptr;  // per-column scale (kind 1)
+};
+size_t coldots_workspace(int64_t n, int ld);
+template <typename T>
+void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
+             double *partials, double *out);
+
+// Gram products out = A^T B' (m x m, FP64), B' = B - A diag(h) if h --------
+size_t gram_workspace(int64_t n, int m);
+// reduce = false launches only the split-K product (used to time it alone).
+template <typename TA, typename TM>
+void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
+          const double *h, bool zero_diag, bool symmetric, double *partials,
+          double *out, bool reduce = true);
+
+// Tall-skinny products out = A W (+ epilogue) ------------------------------
+enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2 };
+// EPI_NONE:  out = A W
+// EPI_GRAD:  out = -2 ((X - A diag(h)) - A W)          (Fig. 2, step (7))
+// EPI_TRMM:  out = A diag(d) + A W, W strictly upper   (Eq. 13)
+template <typename TA, typename TM, typename TO>
+void rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad,
+         int epi, const TA *X, const double *vec, TO *out);
+// Copy an m x m FP64 matrix into an ld x ld zero-padded matrix of type TM,
+// keeping the strict upper triangle only (strict_upper) and returning the
+// diagonal in diag (when not null).
+template <typename TM>
+void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
+                TM *Wpad, double *diag);
+
+// Dense m x m FP64 kernels -------------------------------------------------
+size_t chol_workspace(int m);
+// Rinv = R^{-1}, S = R^T R.  info[0] = 0 or the 1-based failing pivot.
+void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
+                  double *work, int32_t *info);
+size_t jacobi_workspace(int m);
+// Eigenpairs of symmetric A: w ascending, U columns.  info[0] = sweeps.
+void jacobi_eig(hipStream_t s, int m, const double *A, double *U, double *w,
+                double *work, int32_t *info);
+// A = 0.5 (H' + H'^T) + diag(h): the m x m H of Eq. 9 from Algorithm-2 pieces.
+void assemble_subspace_matrix(hipStream_t s, int m, const double *Hp,
+                              const double *h, double *A);
+
+// Elementwise block kernels -------------------------------------------------
+// P = M G + gamma P   (gamma read from st->gamma; M = per-row weights or null)
+template <typename TG, typename TP>
+void p_update(hipStream_t s, int64_t n, int ld, const TG *G, const double *M,
+              const CgState *st, TP *P);
+// Cn = C + alpha P    (alpha read from st->alpha)
+template <typename TC, typename TP>
+void c_update(hipStream_t s, int64_t n, int ld, const TC *C, const TP *P,
+              const CgState *st, TC *Cn);
+template <typename TI, typename TO>
+void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out);
+
+// CG controller (single workgroup) -----------------------------------------
+// After the gradient: dots = [gg | gz | gprev_z | pprev_g] (4 x ld), h (ld).
+void cg_control_gamma(hipStream_t s, int m, int ld, const double *h,
+                      const double *dots, CgState *st, double *history);
+// After Y = HP: dots2 = [pp | py] (2 x ld).
+void cg_control_alpha(hipStream_t s, int m, int ld, const double *h,
+                      const double *dots2, CgState *st);
+// Sum of the m entries of v into *out (single workgroup, fixed order).
+void sum_vector(hipStream_t s, int m, const double *v, double *out);
+
+}  // namespace tmin
+
+// Objects behind the opaque handles of the C ABI ----------------------------
+struct tm_ctx {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    tm_allocator alloc{};
+    bool custom_alloc = false;
+    void *dalloc(size_t bytes);
+    void dfree(void *p);
+};
+
+struct tm_mat {
+    tm_ctx *ctx = nullptr;
+    int64_t n = 0;
+    bool is_stencil = false;
+    tmin::CsrDev csr;
+    tmin::StencilDev st;
+    // owned device arrays
+    int64_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    double *val64 = nullptr;
+    float *val32 = nullptr;
+    double *V64 = nullptr;
+    float *V32 = nullptr;
+    double *diag = nullptr;      // H_ii (n), FP64
+    double diag_min = 0, diag_max = 0;
+};

@@ -1,0 +1,408 @@
+// Host driver of the trace-minimization eigensolver: enqueues the kernels of
+// one nonlinear-CG iteration (Fig. 1) -- energy and gradient by Algorithm-2
+// (Fig. 2), Polak-Ribiere direction (Eq. 8), line step, Cholesky
+// orthonormalization (Fig. 4) -- and the precision phases of Sec. 2.2.
+// All scalars (gamma, alpha, convergence) live on the device; the host only
+// polls a small state record every k_check iterations.
+#include "tm_solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace tmin {
+
+// ------------------------------------------------------------------ buffers
+
+DevMem::DevMem(tm_ctx *c, size_t bytes) : ctx(c), size(bytes) {
+    if (bytes == 0) return;
+    ptr = ctx->dalloc(bytes);
+    TM_REQUIRE(ptr != nullptr, TM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+}
+DevMem::~DevMem() {
+    if (ptr) ctx->dfree(ptr);
+}
+
+void spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64) {
+    if (H->is_stencil) {
+        if (f64) spmm_stencil<double>(s, H->st, H->n, ld, (const double *)C, (double *)X);
+        else spmm_stencil<float>(s, H->st, H->n, ld, (const float *)C, (float *)X);
+    } else {
+        if (f64) spmm_csr<double>(s, H->csr, ld, (const double *)C, (double *)X);
+        else spmm_csr<float>(s, H->csr, ld, (const float *)C, (float *)X);
+    }
+}
+
+namespace {
+
+template <typename T> constexpr bool is_f64() { return sizeof(T) == 8; }
+
+struct Phase {
+    // storage of C and X; storage of G, G_prev, P, Y; matrix-core precision
+    // of H'/G and of the TRMM; precision of S = C^T C
+    bool c64, g64, mh64, ms64;
+};
+
+Phase phase_of(int precision) {
+    switch (precision) {
+    case TM_FULL_DP: return {true, true, true, true};
+    case TM_FULL_SP: return {false, false, false, false};
+    case TM_MP2: return {true, false, false, true};
+    default: return {true, true, true, true};
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ solver
+
+struct Solver::Impl {
+    tm_ctx *ctx;
+    const tm_mat *H;
+    int m, ld;
+    int64_t n;
+    double tol;
+    tm_opts o;
+    hipStream_t s;
+
+    // blocks (allocated per precision of C and of G)
+    std::unique_ptr<DevMem> C64, Cn64, X64, C32, Cn32, X32;
+    std::unique_ptr<DevMem> G, Gp, P, Y;  // element size set by g64
+    bool g64_alloc = false;
+    // small buffers
+    std::unique_ptr<DevMem> h, d, w, dots, dots2, Hp, S, Rinv, Amat, U, Wp;
+    std::unique_ptr<DevMem> gram_ws, dot_ws, chol_ws, jac_ws, info, state, hist, M;
+    CgState *st = nullptr;
+    CgState *st_host = nullptr;
+    int32_t *info_host = nullptr;
+    int rotations = 0;
+
+    Impl(tm_ctx *c, const tm_mat *Hm, int mm, double t, const tm_opts &oo)
+        : ctx(c), H(Hm), m(mm), ld(leading_dim(mm)), n(Hm->n), tol(t), o(oo), s(c->stream) {}
+
+    ~Impl() {
+        if (st_host) (void)hipHostFree(st_host);
+        if (info_host) (void)hipHostFree(info_host);
+    }
+
+    void alloc_small() {
+        const size_t md = (size_t)m * m * sizeof(double);
+        h.reset(new DevMem(ctx, ld * sizeof(double)));
+        d.reset(new DevMem(ctx, ld * sizeof(double)));
+        w.reset(new DevMem(ctx, ld * sizeof(double)));
+        dots.reset(new DevMem(ctx, 4 * ld * sizeof(double)));
+        dots2.reset(new DevMem(ctx, 4 * ld * sizeof(double)));
+        Hp.reset(new DevMem(ctx, md));
+        S.reset(new DevMem(ctx, md));
+        Rinv.reset(new DevMem(ctx, md));
+        Amat.reset(new DevMem(ctx, md));
+        U.reset(new DevMem(ctx, md));
+        Wp.reset(new DevMem(ctx, (size_t)ld * ld * sizeof(double)));
+        gram_ws.reset(new DevMem(ctx, gram_workspace(n, m)));
+        dot_ws.reset(new DevMem(ctx, coldots_workspace(n, ld)));
+        chol_ws.reset(new DevMem(ctx, chol_workspace(m)));
+        jac_ws.reset(new DevMem(ctx, jacobi_workspace(m)));
+        info.reset(new DevMem(ctx, 64));
+        state.reset(new DevMem(ctx, sizeof(CgState)));
+        st = (CgState *)state->ptr;
+        TM_HIP(hipMemsetAsync(h->ptr, 0, ld * sizeof(double), s));
+        TM_HIP(hipMemsetAsync(d->ptr, 0, ld * sizeof(double), s));
+        TM_HIP(hipMemsetAsync(w->ptr, 0, ld * sizeof(double), s));
+        TM_HIP(hipHostMalloc((void **)&st_host, sizeof(CgState), hipHostMallocDefault));
+        TM_HIP(hipHostMalloc((void **)&info_host, 64, hipHostMallocDefault));
+        if (o.precondition) {
+            TM_REQUIRE(H->diag != nullptr, TM_EINVAL, "matrix has no diagonal");
+            M.reset(new DevMem(ctx, n * sizeof(double)));
+            std::vector<double> diag(n);
+            TM_HIP(hipMemcpy(diag.data(), H->diag, n * sizeof(double), hipMemcpyDeviceToHost));
+            const double sigma = std::min(0.0, H->diag_min - 0.5);
+            for (auto &x : diag) x = 1.0 / (x - sigma);
+            TM_HIP(hipMemcpyAsync(M->ptr, diag.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+            TM_HIP(hipStreamSynchronize(s));
+        }
+    }
+
+    size_t blk(bool f64) const { return (size_t)n * ld * (f64 ? 8 : 4); }
+
+    void alloc_c(bool f64) {
+        if (f64 && !C64) {
+            C64.reset(new DevMem(ctx, blk(true)));
+            Cn64.reset(new DevMem(ctx, blk(true)));
+            X64.reset(new DevMem(ctx, blk(true)));
+        }
+        if (!f64 && !C32) {
+            C32.reset(new DevMem(ctx, blk(false)));
+            Cn32.reset(new DevMem(ctx, blk(false)));
+            X32.reset(new DevMem(ctx, blk(false)));
+        }
+    }
+    void free_c(bool f64) {
+        if (f64) { C64.reset(); Cn64.reset(); X64.reset(); }
+        else { C32.reset(); Cn32.reset(); X32.reset(); }
+    }
+    void alloc_g(bool f64) {
+        if (G && g64_alloc == f64) return;
+        G.reset(); Gp.reset(); P.reset(); Y.reset();
+        G.reset(new DevMem(ctx, blk(f64)));
+        Gp.reset(new DevMem(ctx, blk(f64)));
+        P.reset(new DevMem(ctx, blk(f64)));
+        Y.reset(new DevMem(ctx, blk(f64)));
+        g64_alloc = f64;
+    }
+    void zero_g() {
+        TM_HIP(hipMemsetAsync(Gp->ptr, 0, Gp->size, s));
+        TM_HIP(hipMemsetAsync(P->ptr, 0, P->size, s));
+    }
+
+    void set_restart() { TM_HIP(hipMemsetD32Async((hipDeviceptr_t)&st->force_restart, 1, 1, s)); }
+
+    // ---- orthonormalization (Fig. 4): Cn -> C
+    template <typename TC, typename TS, typename TT>
+    void orthonormalize(TC *Cin, TC *Cout) {
+        gram<TC, TS>(s, n, m, Cin, Cin, nullptr, false, true, (double *)gram_ws->ptr, (double *)S->ptr);
+        chol_inverse(s, m, (double *)S->ptr, (double *)Rinv->ptr, (double *)chol_ws->ptr, (int32_t *)info->ptr);
+        pad_matrix<TT>(s, m, (double *)Rinv->ptr, true, (TT *)Wp->ptr, (double *)d->ptr);
+        rot<TC, TT, TC>(s, n, m, Cin, (TT *)Wp->ptr, EPI_TRMM, nullptr, (double *)d->ptr, Cout);
+    }
+
+    // ---- Rayleigh-Ritz (Eq. 9): C <- C U, ascending Ritz values into w
+    template <typename TC, typename TM>
+    void rayleigh_ritz(TC *&C, TC *&Cn, TC *X) {
+        spmm_any(s, H, ld, C, X, is_f64<TC>());
+        DotArgs<TC> a;
+        a.nprod = 1; a.a[0] = C; a.b[0] = X;
+        coldots<TC>(s, n, ld, a, (double *)dot_ws->ptr, (double *)h->ptr);
+        gram<TC, TM>(s, n, m, C, X, (double *)h->ptr, false, false, (double *)gram_ws->ptr, (double *)Hp->ptr);
+        assemble_subspace_matrix(s, m, (double *)Hp->ptr, (double *)h->ptr, (double *)Amat->ptr);
+        jacobi_eig(s, m, (double *)Amat->ptr, (double *)U->ptr, (double *)w->ptr, (double *)jac_ws->ptr,
+                   (int32_t *)info->ptr + 1);
+        pad_matrix<TM>(s, m, (double *)U->ptr, false, (TM *)Wp->ptr, nullptr);
+        rot<TC, TM, TC>(s, n, m, C, (TM *)Wp->ptr, EPI_NONE, nullptr, nullptr, Cn);
+        std::swap(C, Cn);
+        ++rotations;
+    }
+
+    // ---- one CG iteration (Fig. 1) with Algorithm-2 (Fig. 2)
+    template <typename TC, typename TG, typename TMH, typename TMS>
+    void iterate(TC *&C, TC *&Cn, TC *X, bool rotate, double *hist_dev) {
+        if (rotate) {
+            // the rotation keeps C's own precision (FP64 C stays FP64-accurate)
+            rayleigh_ritz<TC, TC>(C, Cn, X);
+            set_restart();
+        }
+        TG *Gv = (TG *)G->ptr, *Gpv = (TG *)Gp->ptr, *Pv = (TG *)P->ptr, *Yv = (TG *)Y->ptr;
+        const double *Mv = M ? (const double *)M->ptr : nullptr;
+        // (1)-(3): X = HC, h = diag(C^T X)
+        spmm_any(s, H, ld, C, X, is_f64<TC>());
+        {
+            DotArgs<TC> a;
+            a.nprod = 1; a.a[0] = C; a.b[0] = X;
+            coldots<TC>(s, n, ld, a, (double *)dot_ws->ptr, (double *)h->ptr);
+        }
+        // (5)-(6): H' = C^T (X - C H_D), diag(H') = 0
+        gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, false, (double *)gram_ws->ptr, (double *)Hp->ptr);
+        // (7): G = -2 (X' - C H')
+        pad_matrix<TMH>(s, m, (double *)Hp->ptr, false, (TMH *)Wp->ptr, nullptr);
+        rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, EPI_GRAD, X, (double *)h->ptr, Gv);
+        // traces for Eq. 8 and the descent test
+        {
+            DotArgs<TG> a;
+            a.nprod = 4;
+            a.a[0] = Gv; a.b[0] = Gv;
+            a.a[1] = Gv; a.b[1] = Gv; a.weighted[1] = Mv != nullptr;
+            a.a[2] = Gpv; a.b[2] = Gv; a.weighted[2] = Mv != nullptr;
+            a.a[3] = Pv; a.b[3] = Gv;
+            a.w = Mv;
+            coldots<TG>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr);
+        }
+        cg_control_gamma(s, m, ld, (double *)h->ptr, (double *)dots->ptr, st, hist_dev);
+        // P = M G + gamma P
+        p_update<TG, TG>(s, n, ld, Gv, Mv, st, Pv);
+        // line step: Y = HP, p.p and p.y
+        spmm_any(s, H, ld, Pv, Yv, is_f64<TG>());
+        {
+            DotArgs<TG> a;
+            a.nprod = 2;
+            a.a[0] = Pv; a.b[0] = Pv;
+            a.a[1] = Pv; a.b[1] = Yv;
+            coldots<TG>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots2->ptr);
+        }
+        cg_control_alpha(s, m, ld, (double *)h->ptr, (double *)dots2->ptr, st);
+        // C_{i+1} = orthonormalize(C_i + alpha P)
+        c_update<TC, TG>(s, n, ld, C, Pv, st, Cn);
+        orthonormalize<TC, TMS, TMH>(Cn, C);
+        std::swap(G, Gp);
+    }
+
+    void reset_state(double switch_tol, int gate, int hist_len) {
+        CgState init{};
+        init.tol = tol;
+        init.rise_tol = o.rise_tol;
+        init.switch_tol = switch_tol;
+        init.stall_tol = 1e-6;
+        init.stall_window = gate ? 25 : 0;
+        init.history_len = hist_len;
+        init.phase_gate = gate;
+        TM_HIP(hipMemcpyAsync(st, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+    }
+
+    void poll() {
+        TM_HIP(hipMemcpyAsync(st_host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        TM_HIP(hipMemcpyAsync(info_host, info->ptr, 16, hipMemcpyDeviceToHost, s));
+        TM_HIP(hipStreamSynchronize(s));
+        if (info_host[0] != 0)
+            throw Error{TM_ENOTSPD, "C^T C is not positive definite (pivot " + std::to_string(info_host[0]) + ")"};
+    }
+
+    double auto_switch_tol() const {
+        // FP32 rounding floor of rho ~ eps32 * ||H|| * sqrt(m); leave well above it
+        const double hnorm = std::max(std::fabs(H->diag_max), std::fabs(H->diag_min)) * 2.0;
+        return 64.0 * 5.96e-8 * hnorm * std::sqrt((double)m);
+    }
+
+    tm_status run(const double *C0, double *C_out, double *eig_out, tm_result *res,
+                  double *hist_host, int hist_len) {
+        auto t0 = std::chrono::steady_clock::now();
+        alloc_small();
+        int hl = (o.history && hist_host) ? hist_len : 0;
+        if (hl > 0) hist.reset(new DevMem(ctx, (size_t)2 * hl * sizeof(double)));
+        double *hist_dev = hl > 0 ? (double *)hist->ptr : nullptr;
+        TM_HIP(hipMemsetAsync(info->ptr, 0, 64, s));
+
+        const int prec = o.precision;
+        const bool mixed = prec == TM_MIXED;
+        Phase ph = phase_of(mixed ? TM_FULL_SP : prec);
+        alloc_c(ph.c64);
+        alloc_g(ph.g64);
+        // start block -> C (cast), orthonormalize
+        if (ph.c64) {
+            TM_HIP(hipMemcpyAsync(Cn64->ptr, C0, blk(true), hipMemcpyDeviceToDevice, s));
+        } else {
+            convert_block<double, float>(s, n * ld, C0, (float *)Cn32->ptr);
+        }
+        const bool gate = mixed || prec == TM_FULL_SP;
+        double sw = o.switch_tol > 0 ? o.switch_tol : auto_switch_tol();
+        reset_state(sw, gate ? 1 : 0, hl);
+        zero_g();
+
+        double *c64 = C64 ? (double *)C64->ptr : nullptr, *cn64 = Cn64 ? (double *)Cn64->ptr : nullptr;
+        float *c32 = C32 ? (float *)C32->ptr : nullptr, *cn32 = Cn32 ? (float *)Cn32->ptr : nullptr;
+        if (ph.c64) orthonormalize<double, double, double>(cn64, c64);
+        else orthonormalize<float, float, float>(cn32, c32);
+
+        int it_host = 0;        // active iterations known to the host
+        int iters_sp = 0;
+        bool sp_phase = !ph.c64;
+        const int kcheck = std::max(1, o.k_check);
+        while (true) {
+            int it_dev_done = 0;
+            for (int b = 0; b < kcheck && it_host + b < o.max_iter; ++b) {
+                const int i = it_host + b;
+                const bool rotate = o.k_rot > 0 && i > 0 && (i % o.k_rot) == 0;
+                if (!ph.c64) iterate<float, float, float, float>(c32, cn32, (float *)X32->ptr, rotate, hist_dev);
+                else if (!ph.g64) iterate<double, float, float, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
+                else iterate<double, double, double, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
+                it_dev_done = b + 1;
+            }
+            poll();
+            it_host = st_host->it;
+            if (st_host->nan_seen) throw Error{TM_ENAN, "NaN or Inf in the energy or gradient"};
+            if (st_host->done) break;
+            if (st_host->phase_end) {
+                if (mixed && sp_phase) {
+                    // FP32 bulk done: cast C up (exact), re-orthonormalize in FP64,
+                    // restart CG under MP2 (Sec. 3: switch when the residual is small)
+                    iters_sp = st_host->it;
+                    ph = phase_of(TM_MP2);
+                    alloc_c(true);
+                    c64 = (double *)C64->ptr;
+                    cn64 = (double *)Cn64->ptr;
+                    convert_block<float, double>(s, n * ld, c32, cn64);
+                    free_c(false);
+                    c32 = cn32 = nullptr;
+                    alloc_g(ph.g64);
+                    zero_g();
+                    orthonormalize<double, double, double>(cn64, c64);
+                    CgState cur = *st_host;
+                    cur.phase_end = 0;
+                    cur.phase_gate = 0;
+                    cur.stall_window = 0;
+                    cur.have_prev = 0;
+                    cur.window_it = 0;
+                    TM_HIP(hipMemcpyAsync(st, &cur, sizeof(CgState), hipMemcpyHostToDevice, s));
+                    sp_phase = false;
+                    continue;
+                }
+                if (sp_phase) iters_sp = st_host->it;
+                break;   // FULL_SP: the FP32 phase ends the solve
+            }
+            if (it_host >= o.max_iter || it_dev_done == 0) break;
+        }
+        if (sp_phase && iters_sp == 0) iters_sp = st_host->it;
+        const bool converged = st_host->done != 0;
+        const int iterations = converged ? st_host->it - 1 : st_host->it;
+
+        // ---- final FP64 Rayleigh-Ritz, residuals and orthonormality
+        if (!c64) {
+            alloc_c(true);
+            c64 = (double *)C64->ptr;
+            cn64 = (double *)Cn64->ptr;
+            convert_block<float, double>(s, n * ld, c32, c64);
+            free_c(false);
+        }
+        double *X = (double *)X64->ptr;
+        rayleigh_ritz<double, double>(c64, cn64, X);
+        --rotations;   // the final one is not a subspace rotation of the iteration
+        spmm_any(s, H, ld, c64, X, true);
+        {
+            DotArgs<double> a;
+            a.nprod = 1; a.kind = 1; a.a[0] = X; a.b[0] = c64; a.sc = (double *)w->ptr;
+            coldots<double>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr);
+        }
+        gram<double, double>(s, n, m, c64, c64, nullptr, false, true, (double *)gram_ws->ptr, (double *)S->ptr);
+        std::vector<double> wv(m), res2(m), Sh((size_t)m * m);
+        TM_HIP(hipMemcpyAsync(wv.data(), w->ptr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        TM_HIP(hipMemcpyAsync(res2.data(), dots->ptr, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        TM_HIP(hipMemcpyAsync(Sh.data(), S->ptr, Sh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (C_out) TM_HIP(hipMemcpyAsync(C_out, c64, blk(true), hipMemcpyDeviceToDevice, s));
+        if (eig_out) TM_HIP(hipMemcpyAsync(eig_out, w->ptr, m * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (hl > 0) TM_HIP(hipMemcpyAsync(hist_host, hist_dev, (size_t)2 * hl * sizeof(double), hipMemcpyDeviceToHost, s));
+        TM_HIP(hipStreamSynchronize(s));
+
+        double eg = 0.0, mx = 0.0, fr = 0.0, orth = 0.0;
+        for (int j = 0; j < m; ++j) {
+            eg += wv[j];
+            mx = std::max(mx, std::sqrt(res2[j]));
+            fr += res2[j];
+        }
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j)
+                orth = std::max(orth, std::fabs(Sh[(size_t)i * m + j] - (i == j ? 1.0 : 0.0)));
+        auto t1 = std::chrono::steady_clock::now();
+        res->E_G = eg;
+        res->rho = st_host->rho;
+        res->max_residual = mx;
+        res->frob_residual = std::sqrt(fr);
+        res->orth_err = orth;
+        res->seconds = std::chrono::duration<double>(t1 - t0).count();
+        res->iterations = iterations;
+        res->iters_sp = iters_sp;
+        res->converged = converged ? 1 : 0;
+        res->restarts = st_host->restarts;
+        res->rotations = rotations;
+        res->reserved = 0;
+        return converged ? TM_OK : TM_ENOCONV;
+    }
+};
+
+Solver::Solver(tm_ctx *ctx, const tm_mat *H, int m, double tol, const tm_opts &o)
+    : impl_(new Impl(ctx, H, m, tol, o)) {}
+Solver::~Solver() = default;
+tm_status Solver::run(const double *C0, double *C_out, double *eig_out, tm_result *res,
+                      double *hist, int hist_len) {
+    return impl_->run(C0, C_out, eig_out, res, hist, hist_len);
+}
+
+}  // namespace tmin

@@ -1,0 +1,36 @@
+// Host-side solver object behind tm_solve().
+#pragma once
+
+#include <memory>
+
+#include "tm_common.h"
+
+namespace tmin {
+
+// Device allocation through the context's allocator hook (RAII).
+struct DevMem {
+    tm_ctx *ctx = nullptr;
+    void *ptr = nullptr;
+    size_t size = 0;
+    DevMem(tm_ctx *c, size_t bytes);
+    ~DevMem();
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+};
+
+// X = H C for a CSR or stencil H, FP64 (f64) or FP32 blocks.
+void spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64);
+
+class Solver {
+  public:
+    Solver(tm_ctx *ctx, const tm_mat *H, int m, double tol, const tm_opts &o);
+    ~Solver();
+    tm_status run(const double *C0, double *C_out, double *eig_out, tm_result *res,
+                  double *hist, int hist_len);
+
+  private:
+    struct Impl;
+    std::unique_ptr<Impl> impl_;
+};
+
+}  // namespace tmin

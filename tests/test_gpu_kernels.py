@@ -1,0 +1,302 @@
+"""Parity of each kernel of the iteration against the FP64 CPU oracle.
+
+Every comparison is element by element on seeded inputs, with a tolerance
+derived a priori from the arithmetic: a k-term FP64 (FP32) sum of products
+carries at most gamma_k(u) * sum |a_i b_i| rounding error (Higham), and both
+sides round, so the tests allow twice that.  Sizes span several tiles and a
+ragged tail (N not a multiple of the row tiles, ld > m, partial 64-column
+tiles).  Full-size cases check sampled outputs that the oracle computes one by
+one.
+"""
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import U32, U64, ctx_or_skip, gamma, host, print_case, rand_block
+from workloads import StencilSpec, config_problem, make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return ctx_or_skip()
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import paper_1108_4509_amd as tm
+    return tm
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import build
+    build.build()
+    import oracle
+    return oracle
+
+
+def _problems():
+    return [
+        ("c1", config_problem("c1")),
+        ("w12", make_problem("w12", StencilSpec(3, (12, 12, 12), 2, "periodic", 0.5), m=76,
+                             seed=5, n_wells=6)),
+        ("o4", make_problem("o4", StencilSpec(3, (10, 11, 9), 4, "periodic", 0.5), m=40,
+                            seed=6)),
+        ("d2", make_problem("d2", StencilSpec(2, (37, 29), 2, "dirichlet", 1.0), m=33, seed=7)),
+        ("o4d", make_problem("o4d", StencilSpec(3, (7, 6, 5), 4, "dirichlet", 0.5), m=5, seed=8)),
+    ]
+
+
+@pytest.mark.parametrize("name,prob", _problems(), ids=[p[0] for p in _problems()])
+@pytest.mark.parametrize("stencil", [False, True], ids=["csr", "stencil"])
+def test_spmm_f64(ctx, tm, orc, name, prob, stencil):
+    import torch
+    print_case(test="spmm_f64", problem=name, stencil=stencil, N=prob.N, m=prob.m)
+    H = orc.csr_matrix(*prob.csr(), prob.N)
+    Hd = tm.matrix_from_problem(ctx, prob, stencil=stencil)
+    C = rand_block(np.random.default_rng(1), prob.N, prob.m)
+    Cd = tm.to_block(C)
+    Xd = torch.full_like(Cd, np.nan)
+    tm.spmm(ctx, Hd, prob.m, Cd, Xd)
+    X = orc.spmm(H, C)
+    absHC = abs(H) @ np.abs(C)
+    nnz_row = int(np.max(np.diff(prob.csr()[0])))
+    tol = 2 * gamma(nnz_row + 1, U64) * absHC
+    got = host(Xd)
+    assert np.all(np.abs(got[:, :prob.m] - X) <= tol + 1e-300)
+    assert np.all(got[:, prob.m:] == 0)          # padded columns stay zero
+
+
+@pytest.mark.parametrize("stencil", [False, True], ids=["csr", "stencil"])
+def test_spmm_f32(ctx, tm, orc, stencil):
+    import torch
+    prob = _problems()[1][1]
+    print_case(test="spmm_f32", stencil=stencil)
+    H = orc.csr_matrix(*prob.csr(), prob.N)
+    Hd = tm.matrix_from_problem(ctx, prob, stencil=stencil)
+    C = rand_block(np.random.default_rng(2), prob.N, prob.m).astype(np.float32)
+    Cd = tm.to_block(C, dtype=torch.float32)
+    Xd = torch.empty_like(Cd)
+    tm.spmm(ctx, Hd, prob.m, Cd, Xd)
+    # the FP32 kernel multiplies by FP32-rounded matrix values
+    X = orc.spmm(H, C.astype(np.float64))
+    absHC = abs(H) @ np.abs(C.astype(np.float64))
+    tol = 2 * gamma(9, U32) * absHC
+    assert np.all(np.abs(host(Xd, prob.m) - X) <= tol)
+
+
+@pytest.mark.parametrize("n,m", [(5000, 27), (3001, 76), (4099, 130), (2050, 256), (1500, 512),
+                                 (700, 1), (64, 64)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_gram(ctx, tm, n, m, dt):
+    import torch
+    print_case(test="gram", n=n, m=m, dt=dt)
+    rng = np.random.default_rng(n + m)
+    A = rand_block(rng, n, m)
+    B = rand_block(rng, n, m)
+    h = rng.standard_normal(m)
+    tdt, u = (torch.float64, U64) if dt == "f64" else (torch.float32, U32)
+    if dt == "f32":
+        A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+    Ad, Bd = tm.to_block(A, dtype=tdt), tm.to_block(B, dtype=tdt)
+    hd = torch.from_numpy(h).cuda()
+    # plain product
+    got = host(tm.gram(ctx, m, Ad, Bd))
+    ref = A.T @ B
+    tol = 2 * gamma(n, u) * (np.abs(A).T @ np.abs(B))
+    assert np.all(np.abs(got - ref) <= tol)
+    # symmetric product (upper tiles only, mirrored)
+    got = host(tm.gram(ctx, m, Ad, Ad))
+    ref = A.T @ A
+    tol = 2 * gamma(n, u) * (np.abs(A).T @ np.abs(A))
+    assert np.all(np.abs(got - ref) <= tol)
+    # shifted product A^T (B - A diag(h)) (Fig. 2, steps (5)-(6)); the shift is
+    # formed in FP64 and rounded once to the matrix-core precision
+    got = host(tm.gram(ctx, m, Ad, Bd, h=hd))
+    Bs = B - A * h[None, :]
+    ref = A.T @ Bs
+    tol = 2 * gamma(n + 2, u) * (np.abs(A).T @ (np.abs(B) + np.abs(A) * np.abs(h)[None, :]))
+    assert np.all(np.abs(got - ref) <= tol)
+
+
+@pytest.mark.parametrize("n,m", [(5000, 27), (3001, 76), (2050, 256), (1100, 512)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_rotate(ctx, tm, n, m, dt):
+    import torch
+    print_case(test="rotate", n=n, m=m, dt=dt)
+    rng = np.random.default_rng(3 * n + m)
+    A = rand_block(rng, n, m)
+    W = rng.standard_normal((m, m))
+    tdt, u = (torch.float64, U64) if dt == "f64" else (torch.float32, U32)
+    if dt == "f32":
+        A = A.astype(np.float32).astype(np.float64)
+        W = W.astype(np.float32).astype(np.float64)
+    Ad = tm.to_block(A, dtype=tdt)
+    out = tm.rotate(ctx, m, Ad, torch.from_numpy(W).cuda())
+    ref = A @ W
+    tol = 2 * gamma(m, u) * (np.abs(A) @ np.abs(W))
+    got = host(out)
+    assert np.all(np.abs(got[:, :m] - ref) <= tol)
+    assert np.all(got[:, m:] == 0)
+
+
+@pytest.mark.parametrize("name,prob", _problems()[:3], ids=[p[0] for p in _problems()[:3]])
+def test_energy_grad_alg2_full_dp(ctx, tm, orc, name, prob):
+    print_case(test="energy_grad_dp", problem=name)
+    H = orc.csr_matrix(*prob.csr(), prob.N)
+    Hd = tm.matrix_from_problem(ctx, prob)
+    C = orc.orthonormalize(prob.C0())
+    E, G, X, h, Hp = tm.energy_grad(ctx, Hd, prob.m, tm.to_block(C))
+    E_o, G_o, X_o, h_o, Hp_o = orc.energy_gradient_alg2(H, C)
+    n, m = C.shape
+    # scales: |X| <= |H||C|; every quantity is a sum of at most n products
+    absX = abs(H) @ np.abs(C)
+    g = gamma(n + 16, U64)
+    assert abs(E - E_o) <= 4 * g * np.sum(np.abs(C) * absX)
+    assert np.all(np.abs(host(h) - h_o) <= 4 * g * np.sum(np.abs(C) * absX, axis=0))
+    absXp = absX + np.abs(C) * np.abs(h_o)[None, :]
+    assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * g * (np.abs(C).T @ absXp))
+    absG = 2 * (absXp + np.abs(C) @ np.abs(Hp_o))
+    bound = 8 * g * (absG + 2 * np.abs(C) @ (np.abs(C).T @ absXp))
+    assert np.all(np.abs(host(G, m) - G_o) <= bound)
+    assert np.all(np.abs(host(X, m) - X_o) <= 2 * gamma(14, U64) * absX)
+
+
+def test_energy_grad_mp2(ctx, tm, orc):
+    """MP2 (Sec. 2.2): steps (6)-(7) on FP32 matrix cores.  The error of G is
+    bounded by FP32 rounding of H' and of C H' (u32 relative), not of X'."""
+    prob = _problems()[1][1]
+    print_case(test="energy_grad_mp2")
+    H = orc.csr_matrix(*prob.csr(), prob.N)
+    Hd = tm.matrix_from_problem(ctx, prob)
+    C = orc.orthonormalize(prob.C0())
+    E, G, X, h, Hp = tm.energy_grad(ctx, Hd, prob.m, tm.to_block(C), precision="mp2")
+    E_o, G_o, X_o, h_o, Hp_o = orc.energy_gradient_alg2(H, C)
+    n, m = C.shape
+    absX = abs(H) @ np.abs(C)
+    assert abs(E - E_o) <= 4 * gamma(n + 16, U64) * np.sum(np.abs(C) * absX)  # DP energy
+    absXp = absX + np.abs(C) * np.abs(h_o)[None, :]
+    assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * gamma(n + 4, U32) * (np.abs(C).T @ absXp))
+    bound = 8 * gamma(n + m + 4, U32) * (np.abs(C) @ (np.abs(C).T @ absXp)) \
+        + 8 * gamma(n + 16, U64) * absXp
+    assert np.all(np.abs(host(G, m) - G_o) <= bound)
+
+
+@pytest.mark.parametrize("n,m", [(4096, 27), (3001, 76), (2050, 256)])
+@pytest.mark.parametrize("precision", ["full_dp", "mp2"])
+def test_orthonormalize(ctx, tm, orc, n, m, precision):
+    print_case(test="orthonormalize", n=n, m=m, precision=precision)
+    rng = np.random.default_rng(n * 7 + m)
+    # near-orthonormal input, as inside the iteration (C + alpha P), plus a
+    # random one, as at the start (Fig. 1, C_0)
+    Q = orc.orthonormalize(rng.standard_normal((n, m)))
+    for C in (Q + 1e-3 * rng.standard_normal((n, m)), rng.standard_normal((n, m))):
+        Cd = tm.to_block(C)
+        tm.orthonormalize(ctx, m, Cd, precision=precision)
+        got = host(Cd, m)
+        ref = orc.orthonormalize(C)
+        S = got.T @ got
+        if precision == "full_dp":
+            assert np.max(np.abs(S - np.eye(m))) < 64 * m * U64 * 10
+            assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.linalg.cond(C))
+        else:
+            # MP1 (ii): C R' in FP32; error ~ u32 * |R'|, which is small only
+            # when C is already close to orthonormal (Eq. 11-13)
+            Rp = np.abs(np.triu(orc.upper_triangular_inverse(orc.cholesky_upper(C.T @ C)), 1))
+            bound = 4 * gamma(m, U32) * (np.abs(C) @ Rp) + 1e-13
+            assert np.all(np.abs(got - ref) <= bound)
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 16, 17, 33, 100, 256, 300])
+def test_cholesky_inverse(ctx, tm, orc, m):
+    import torch
+    print_case(test="cholesky_inverse", m=m)
+    rng = np.random.default_rng(m)
+    B = rng.standard_normal((3 * m + 5, m))
+    S = B.T @ B
+    R_inv = host(tm.cholesky_inverse(ctx, torch.from_numpy(S).cuda()))
+    R = orc.cholesky_upper(S)
+    ref = orc.upper_triangular_inverse(R)
+    cond = np.linalg.cond(R)
+    assert np.all(np.tril(R_inv, -1) == 0)
+    assert np.max(np.abs(R_inv - ref)) <= 64 * m * U64 * cond * np.max(np.abs(ref))
+    # the defining property: R^-T S R^-1 = I
+    assert np.max(np.abs(R_inv.T @ S @ R_inv - np.eye(m))) < 64 * m * U64 * cond
+
+
+def test_cholesky_not_spd(ctx, tm):
+    import torch
+    S = np.eye(20)
+    S[7, 7] = -1.0
+    with pytest.raises(tm.TraceminError) as ei:
+        tm.cholesky_inverse(ctx, torch.from_numpy(S).cuda())
+    assert ei.value.status == tm.TM_ENOTSPD
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 27, 64, 101, 256])
+def test_sym_eig(ctx, tm, orc, m):
+    import torch
+    print_case(test="sym_eig", m=m)
+    rng = np.random.default_rng(100 + m)
+    B = rng.standard_normal((m, m))
+    A = B + B.T
+    w, U = tm.sym_eig(ctx, torch.from_numpy(A).cuda())
+    w, U = host(w), host(U)
+    w_o, _, _ = orc.jacobi_eigh(A)
+    scale = np.linalg.norm(A)
+    assert np.max(np.abs(w - w_o)) <= 64 * m * U64 * scale
+    assert np.max(np.abs(A @ U - U * w[None, :])) <= 64 * m * U64 * scale
+    assert np.max(np.abs(U.T @ U - np.eye(m))) <= 64 * m * U64
+
+
+def test_sym_eig_closed_form(ctx, tm):
+    """1-D Dirichlet Laplacian: eigenvalues 2 - 2 cos(k pi / (n + 1))."""
+    import torch
+    n = 50
+    A = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    w, _ = tm.sym_eig(ctx, torch.from_numpy(A).cuda())
+    exact = np.sort(2 - 2 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    assert np.max(np.abs(host(w) - exact)) < 1e-13
+
+
+# ------------------------------------------------------- full-size sampling
+
+@pytest.fixture(scope="module")
+def c2():
+    return config_problem("c2")
+
+
+@pytest.mark.parametrize("stencil", [False, True], ids=["csr", "stencil"])
+def test_c2_spmm_sampled(ctx, tm, orc, c2, stencil):
+    import torch
+    print_case(test="c2_spmm_sampled", stencil=stencil)
+    H = orc.csr_matrix(*c2.csr(), c2.N)
+    Hd = tm.matrix_from_problem(ctx, c2, stencil=stencil)
+    C = c2.C0()
+    for dt, u in ((torch.float64, U64), (torch.float32, U32)):
+        Cd = tm.to_block(C, dtype=dt)
+        Xd = torch.empty_like(Cd)
+        tm.spmm(ctx, Hd, c2.m, Cd, Xd)
+        rows = np.random.default_rng(0).choice(c2.N, 2000, replace=False)
+        Cr = host(Cd, c2.m).astype(np.float64)
+        ref = np.asarray(H[rows] @ Cr)
+        absref = np.asarray(abs(H)[rows] @ np.abs(Cr))
+        assert np.all(np.abs(host(Xd[rows], c2.m) - ref) <= 2 * gamma(8, u) * absref)
+
+
+def test_c2_gram_sampled(ctx, tm, c2):
+    import torch
+    print_case(test="c2_gram_sampled")
+    C = c2.C0()
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal(C.shape)
+    for dt, u in ((torch.float64, U64), (torch.float32, U32)):
+        Cd, Xd = tm.to_block(C, dtype=dt), tm.to_block(X, dtype=dt)
+        G = host(tm.gram(ctx, c2.m, Cd, Xd))
+        Ch, Xh = host(Cd, c2.m).astype(np.float64), host(Xd, c2.m).astype(np.float64)
+        for i, j in rng.integers(0, c2.m, size=(64, 2)):
+            ref = float(Ch[:, i] @ Xh[:, j])
+            bound = 2 * gamma(c2.N, u) * float(np.abs(Ch[:, i]) @ np.abs(Xh[:, j]))
+            assert abs(G[i, j] - ref) <= bound

@@ -1,0 +1,224 @@
+"""End-to-end parity of tm_solve with the FP64 CPU oracle.
+
+Tolerances: |Delta E_G| / |E_G| <= 1e-10 against the oracle and against
+closed forms, and max_j ||H c_j - lambda_j c_j|| <= tol (1e-8) -- the accuracy
+targets of the solver.  In FULL_DP the GPU and the oracle run the same
+iteration from the same C_0, so their energy trajectories are also compared
+step by step while the iterates are still far from converged (where rounding
+has not yet been amplified by the CG recurrences).
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import ctx_or_skip, host, print_case
+from workloads import StencilSpec, config_problem, make_problem
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return ctx_or_skip()
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import paper_1108_4509_amd as tm
+    return tm
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import build
+    build.build()
+    import oracle
+    return oracle
+
+
+def periodic_spectrum(n, order=2):
+    th = 2 * np.pi * np.arange(n) / n
+    f = (1 - np.cos(th)) if order == 2 else (1 - np.cos(th)) * (7 - np.cos(th)) / 6
+    return np.sort((f[:, None, None] + f[None, :, None] + f[None, None, :]).reshape(-1))
+
+
+def eq16_spectrum(n):
+    s = 4.0 * np.sin(np.arange(1, n + 1) * np.pi / (2 * (n + 1))) ** 2
+    return np.sort((s[:, None] + s[None, :]).reshape(-1))
+
+
+def _solve(tm, ctx, prob, precision="full_dp", tol=1e-8, stencil=False, hist=0, **kw):
+    H = tm.matrix_from_problem(ctx, prob, stencil=stencil)
+    C0 = tm.to_block(prob.C0())
+    o = tm.opts(precision=precision, history=hist > 0, **kw)
+    return tm.solve(ctx, H, prob.m, tol, C0, o, history_len=hist)
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(orc):
+    p = config_problem("c1")
+    return orc.solve(orc.csr_matrix(*p.csr(), p.N), p.C0(),
+                     orc.OracleOptions(tol=1e-8, k_rot=50))
+
+
+@pytest.mark.parametrize("stencil", [False, True], ids=["csr", "stencil"])
+def test_c1_full_dp(ctx, tm, c1_oracle, stencil):
+    p = config_problem("c1")
+    print_case(test="c1_full_dp", stencil=stencil)
+    r, C, w, hist = _solve(tm, ctx, p, stencil=stencil, hist=400)
+    exact = 54 * (1 - math.cos(math.pi / 8))
+    assert r["converged"] == 1 and r["status"] == 0
+    assert abs(r["E_G"] - exact) <= 1e-10 * exact
+    assert abs(r["E_G"] - c1_oracle.E_G) <= 1e-10 * exact
+    assert r["max_residual"] <= 1e-8
+    assert r["orth_err"] < 1e-13
+    assert np.max(np.abs(host(w) - periodic_spectrum(16)[:27])) < 1e-9
+    # same iteration, step by step, while rounding has not been amplified
+    Eo = np.array(c1_oracle.energies)
+    k = 40
+    assert np.max(np.abs(hist[:k, 0] - Eo[:k]) / np.abs(Eo[:k])) < 1e-9
+    # and a comparable iteration count
+    assert abs(r["iterations"] - c1_oracle.iterations) <= 0.25 * c1_oracle.iterations + 10
+
+
+def test_c1_vectors_and_residual_definition(ctx, tm, orc):
+    """The returned C: orthonormal, and max_j ||H c_j - C (C^T H c_j)|| <= 1e-8."""
+    p = config_problem("c1")
+    r, C, w, _ = _solve(tm, ctx, p)
+    Ch = host(C, p.m)
+    H = orc.csr_matrix(*p.csr(), p.N)
+    X = orc.spmm(H, Ch)
+    R = X - Ch @ (Ch.T @ X)
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-8
+    assert np.max(np.abs(Ch.T @ Ch - np.eye(p.m))) < 1e-13
+    assert np.all(host(C)[:, p.m:] == 0)
+
+
+@pytest.fixture(scope="module")
+def wells_problem():
+    return make_problem("w12", StencilSpec(3, (12, 12, 12), 2, "periodic", 0.5), m=20, seed=5,
+                        n_wells=6)
+
+
+@pytest.fixture(scope="module")
+def wells_oracle(orc, wells_problem):
+    p = wells_problem
+    return orc.solve(orc.csr_matrix(*p.csr(), p.N), p.C0(),
+                     orc.OracleOptions(tol=1e-10, k_rot=50))
+
+
+@pytest.mark.parametrize("precision", ["full_dp", "mixed", "mp2"])
+def test_wells_precisions(ctx, tm, wells_problem, wells_oracle, precision):
+    print_case(test="wells", precision=precision)
+    r, C, w, _ = _solve(tm, ctx, wells_problem, precision=precision)
+    ref = wells_oracle.E_G
+    assert r["converged"] == 1
+    assert abs(r["E_G"] - ref) <= 1e-10 * abs(ref)
+    assert r["max_residual"] <= 1e-8
+    assert np.max(np.abs(host(w) - wells_oracle.eigenvalues)) <= 1e-9
+
+
+def test_wells_brute_force_and_full_sp(ctx, tm, orc):
+    """Brute-force dense Jacobi pins E_G; full SP reaches only FP32 accuracy."""
+    p = make_problem("bf", StencilSpec(3, (8, 8, 8), 2, "periodic", 0.5), m=12, seed=9,
+                     n_wells=4)
+    E_bf, wall, gap = orc.brute_force_lowest(p.dense(), p.m)
+    r, _, _, _ = _solve(tm, ctx, p)
+    assert abs(r["E_G"] - E_bf) <= 1e-10 * abs(E_bf)
+    r_sp, _, _, _ = _solve(tm, ctx, p, precision="full_sp")
+    err = abs(r_sp["E_G"] - E_bf) / abs(E_bf)
+    assert err < 1e-5          # FP32-level, and it reports itself as such:
+    assert r_sp["converged"] == 0 and r_sp["status"] == tm.TM_ENOCONV
+
+
+def test_paper_matrix_eq16(ctx, tm):
+    """2-D Dirichlet Laplacian (Eq. 14-15), stencil and CSR, vs Eq. 16."""
+    n = 40
+    lam = eq16_spectrum(n)
+    m = next(k for k in range(40, 80) if lam[k] - lam[k - 1] > 1e-3)
+    p = make_problem("d40", StencilSpec(2, (n, n), 2, "dirichlet", 1.0), m=m, seed=3)
+    for stencil in (False, True):
+        for precision in ("full_dp", "mixed"):
+            print_case(test="eq16", stencil=stencil, precision=precision)
+            r, _, w, _ = _solve(tm, ctx, p, precision=precision, stencil=stencil)
+            assert abs(r["E_G"] - lam[:m].sum()) <= 1e-10 * lam[:m].sum()
+            assert np.max(np.abs(host(w) - lam[:m])) < 1e-9
+
+
+def test_preconditioned(ctx, tm, wells_problem, wells_oracle):
+    r, _, _, _ = _solve(tm, ctx, wells_problem, precondition=True)
+    assert r["converged"] == 1
+    assert abs(r["E_G"] - wells_oracle.E_G) <= 1e-10 * abs(wells_oracle.E_G)
+
+
+def test_13_point_closed_shell(ctx, tm):
+    p = make_problem("o4", StencilSpec(3, (10, 10, 10), 4, "periodic", 0.5), m=7, seed=12)
+    lam = periodic_spectrum(10, 4)
+    for stencil in (False, True):
+        r, _, w, _ = _solve(tm, ctx, p, stencil=stencil, tol=1e-9)
+        assert np.max(np.abs(host(w) - lam[:7])) < 1e-10
+
+
+def test_edge_cases(ctx, tm, orc):
+    import torch
+    # m = 1: lowest eigenvalue of the periodic Laplacian is 0
+    p = make_problem("m1", StencilSpec(3, (8, 8, 8), 2, "periodic", 0.5), m=1, seed=4)
+    r, _, w, _ = _solve(tm, ctx, p)
+    assert abs(r["E_G"]) < 1e-12 and r["converged"] == 1
+    # m = N: the whole space; E_G = trace(H)
+    p = make_problem("full", StencilSpec(3, (4, 4, 2), 2, "periodic", 0.5), m=32, seed=4,
+                     n_wells=0)
+    r, _, _, _ = _solve(tm, ctx, p)
+    assert abs(r["E_G"] - np.trace(p.dense())) < 1e-11
+    # max_iter reached: TM_ENOCONV, result still filled
+    p = config_problem("c1")
+    r, _, _, _ = _solve(tm, ctx, p, max_iter=3)
+    assert r["status"] == tm.TM_ENOCONV and r["converged"] == 0 and r["iterations"] == 3
+    assert r["E_G"] > 4.110505244390517
+    # rank-deficient start block: duplicated columns -> Cholesky breakdown
+    C0 = p.C0().copy()
+    C0[:, 5] = C0[:, 4]
+    H = tm.matrix_from_problem(ctx, p)
+    with pytest.raises(tm.TraceminError) as ei:
+        tm.solve(ctx, H, p.m, 1e-8, tm.to_block(C0))
+    assert ei.value.status == tm.TM_ENOTSPD
+    # invalid arguments are rejected before any device work
+    with pytest.raises(tm.TraceminError) as ei:
+        tm.solve(ctx, H, 0, 1e-8, tm.to_block(C0))
+    assert ei.value.status == tm.TM_EINVAL
+    with pytest.raises(tm.TraceminError):
+        tm.solve(ctx, H, p.m, -1.0, tm.to_block(C0))
+    # empty matrix
+    with pytest.raises(tm.TraceminError):
+        tm.set_matrix_csr(ctx, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    # out-of-range column index
+    with pytest.raises(tm.TraceminError):
+        tm.set_matrix_csr(ctx, np.array([0, 1], np.int64), np.array([3], np.int32),
+                          np.array([1.0]))
+    del torch
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", f"oracle_{name}_s0.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "full_dp"])
+def test_c2_full_size(ctx, tm, precision):
+    """48^3 7-point + 64 wells, m = 256, as timed by the benchmark."""
+    g = _golden("c2")
+    p = config_problem("c2")
+    print_case(test="c2_full", precision=precision)
+    r, C, w, _ = _solve(tm, ctx, p, precision=precision)
+    assert r["converged"] == 1
+    assert abs(r["E_G"] - g["E_G"]) <= 1e-10 * abs(g["E_G"])
+    assert r["max_residual"] <= 1e-8
+    assert np.max(np.abs(host(w) - np.array(g["eigenvalues"]))) <= 1e-8

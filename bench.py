@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--precision", default="mixed", help="precision of the timed steps")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
@@ -93,15 +94,15 @@ def main():
         return time.perf_counter() - t0, r
 
     for i in range(a.warmup):
-        t, r = run("mixed")
+        t, r = run(a.precision)
         log(f"warmup mixed {t:.3f}s iters={r['iterations']} sp={r['iters_sp']}")
     times, res = [], None
     torch.cuda.synchronize()
     t_begin = time.perf_counter()
     for i in range(a.steps):
-        t, res = run("mixed")
+        t, res = run(a.precision)
         times.append(t)
-        log(f"step {i} mixed {t:.3f}s iters={res['iterations']} sp={res['iters_sp']} "
+        log(f"step {i} {a.precision} {t:.3f}s iters={res['iterations']} sp={res['iters_sp']} "
             f"E_G={res['E_G']:.15f} maxres={res['max_residual']:.2e}")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_begin

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build", "tracemin")
 LIB = os.path.join(HERE, "libtracemin.so")
 ARCH = os.environ.get("TRACEMIN_ARCH", "gfx950")
 
-SOURCES = ["k_spmm.hip", "k_gemm.hip", "k_vec.hip", "k_dense.hip",
+SOURCES = ["k_spmm.hip", "k_gemm.hip", "k_vec.hip", "k_dense.hip", "k_jacobi.hip",
            "tm_solver.cpp", "tm_abi.cpp"]
 
 FLAGS = [

@@ -1,11 +1,10 @@
 // Dense m x m FP64 kernels of the iteration: the Cholesky factorization and
-// triangular inverse of Fig. 4 (steps (2) and (3)), and the symmetric
-// eigensolve that diagonalizes the m x m H (Eq. 9) for the Rayleigh-Ritz step
-// and the occasional subspace rotation.
+// triangular inverse of Fig. 4 (steps (2) and (3)), and the assembly of the
+// m x m H of Eq. 9 from the pieces of Algorithm-2.
 //
-// These are O(m^3) with m <= ~1024, so they are latency-bound; each runs as one
-// workgroup of 1024 lanes with the matrix in a device workspace (resident in
-// L2) and 16-wide blocks cached in LDS.
+// The factorization is O(m^3) with m <= 1024, so it is latency-bound; it runs
+// as one workgroup of 1024 lanes with the matrix in a device workspace
+// (resident in L2) and the current panel staged in LDS.
 #include "tm_common.h"
 
 #include <cmath>
@@ -14,289 +13,237 @@ namespace tmin {
 namespace {
 
 constexpr int kDenseThreads = 1024;
-constexpr int NB = 16;
+constexpr int NBMAX = 32;
+constexpr int kStage = 17920;   // doubles of LDS staging (140 KiB)
 
-// Factor the nb x nb diagonal block D (lower, in LDS) in place and write its
-// inverse (lower) to Dinv.  Runs on one wave; returns false on a bad pivot.
+typedef double d4 __attribute__((ext_vector_type(4)));
+// v_mfma_f64_16x16x4: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+// D[i][j] in lane j + 16 (i % 4), register i / 4.
+__device__ inline d4 mfma64(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline int mfma64_row(int lane, int r) { return 4 * r + (lane >> 4); }
+
 // A pivot below kPivotTol times the original diagonal entry counts as a
 // breakdown: C^T C is then numerically singular (dependent columns of C).
 constexpr double kPivotTol = 1e-14;
 
-__device__ bool small_chol_inv(int nb, double (*D)[NB + 1], double (*Dinv)[NB + 1],
-                               const double *Sdiag, int lane) {
+__device__ inline void lower_pair(int p, int &bi, int &bj) {
+    int i = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > p) --i;
+    while ((i + 1) * (i + 2) / 2 <= p) ++i;
+    bi = i;
+    bj = p - i * (i + 1) / 2;
+}
+
+// Factor the nb x nb diagonal block D = L_kk L_kk^T (lower, in LDS) in place
+// and build Dinv = L_kk^{-1}, one element per lane of the workgroup
+// (requires NB * NB <= blockDim).  Returns false on a bad pivot.
+template <int NB>
+__device__ bool block_chol_inv(int nb, double (*D)[NB + 1], double (*Dinv)[NB + 1],
+                               const double *Sdiag) {
+    const int t = threadIdx.x;
+    const int i = t / NB, j = t % NB;
+    const bool mine = t < NB * NB && i < nb && j < nb;
     bool ok = true;
+    if (mine) Dinv[i][j] = (i == j) ? 1.0 : 0.0;
+    __syncthreads();
     for (int k = 0; k < nb; ++k) {
-        const double d = D[k][k];
-        if (!(d > kPivotTol * fabs(Sdiag[k]))) ok = false;
-        const double r = sqrt(fmax(d, 0.0));
-        __builtin_amdgcn_wave_barrier();
-        if (lane > k && lane < nb) D[lane][k] /= r;
-        if (lane == 0) D[k][k] = r;
-        __builtin_amdgcn_wave_barrier();
-        // trailing update inside the block: lanes own rows
-        if (lane > k && lane < nb)
-            for (int j = k + 1; j <= lane; ++j) D[lane][j] -= D[lane][k] * D[j][k];
-        __builtin_amdgcn_wave_barrier();
+        const double dkk = D[k][k];
+        if (!(dkk > kPivotTol * fabs(Sdiag[k]))) ok = false;
+        const double lik = mine ? D[i][k] : 0.0;
+        const double ljk = mine ? D[j][k] : 0.0;
+        __syncthreads();
+        if (mine) {
+            if (j > k && j <= i) D[i][j] -= lik * ljk / dkk;
+            else if (j == k && i > k) D[i][k] = lik / sqrt(dkk);
+            else if (i == k && j == k) D[k][k] = sqrt(dkk);
+        }
+        __syncthreads();
     }
     if (!ok) return false;
-    // inverse of the lower-triangular D, row by row: lane owns column c
-    for (int i = 0; i < nb; ++i) {
-        if (lane < nb) {
-            const int c = lane;
-            double v;
-            if (c > i) {
-                v = 0.0;
-            } else if (c == i) {
-                v = 1.0 / D[i][i];
-            } else {
-                double s = 0.0;
-                for (int k = c; k < i; ++k) s += D[i][k] * Dinv[k][c];
-                v = -s / D[i][i];
-            }
-            Dinv[i][c] = v;
-        }
-        __builtin_amdgcn_wave_barrier();
+    // Dinv = L^{-1}: row k scaled by 1/l_kk, then eliminated from the rows below
+    for (int k = 0; k < nb; ++k) {
+        if (mine && i == k) Dinv[k][j] /= D[k][k];
+        __syncthreads();
+        if (mine && i > k) Dinv[i][j] -= D[i][k] * Dinv[k][j];
+        __syncthreads();
     }
     return true;
 }
 
-// S = L L^T (L lower, S = R^T R with R = L^T); Rinv = L^{-T}.
-// work: m*m doubles (L), work + m*m: m*m doubles (L^{-1}), + m*NB (panel).
+// S = L L^T (L lower; S = R^T R with R = L^T) and Rinv = R^{-1} = L^{-T}.
+// Blocked right-looking Cholesky with NB-wide panels: the diagonal block is
+// factored and inverted in LDS by the whole workgroup, the panel
+// L_ik = S_ik L_kk^{-T} and the trailing update S_ij -= L_ik L_jk^T run on FP64
+// matrix cores (16 x 16 blocks spread over the 16 waves) with the panel staged
+// in LDS.  The inverse X = L^{-1} is then built block row by block row,
+// X_i,0:i = -L_ii^{-1} (L_i,0:i X_0:i,0:i), again on matrix cores.
+// work: L (m*m), X (m*m), T (NB*m) doubles.
+template <int NB>
 __global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
     int m, const double *__restrict__ S, double *__restrict__ Rinv,
     double *__restrict__ work, int32_t *__restrict__ info) {
+    __shared__ double stage[kStage];
     __shared__ double D[NB][NB + 1];
     __shared__ double Dinv[NB][NB + 1];
     __shared__ double Sd[NB];
-    __shared__ int bad;
+    constexpr int PS = NB + 1;   // row stride of the staged panel
     double *L = work;
-    double *X = work + (size_t)m * m;         // L^{-1}
-    double *panel = X + (size_t)m * m;        // m x NB
+    double *X = work + (size_t)m * m;
+    double *T = X + (size_t)m * m;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int nthr = blockDim.x;
-    if (tid == 0) bad = 0;
-    for (int64_t e = tid; e < (int64_t)m * m; e += nthr) {
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int nwaves = kDenseThreads / 64;
+    for (int64_t e = tid; e < (int64_t)m * m; e += kDenseThreads) {
         L[e] = S[e];
         X[e] = 0.0;
     }
     __syncthreads();
 
-    // ---- blocked right-looking Cholesky
     for (int kb = 0; kb < m; kb += NB) {
         const int nb = (m - kb < NB) ? (m - kb) : NB;
-        if (tid < 64) {
-            for (int e = lane; e < NB * NB; e += 64) {
-                const int i = e / NB, j = e % NB;
-                D[i][j] = (i < nb && j <= i) ? L[(size_t)(kb + i) * m + kb + j] : 0.0;
-                Dinv[i][j] = 0.0;
+        if (tid < NB * NB) {
+            const int i = tid / NB, j = tid % NB;
+            D[i][j] = (i < nb && j <= i) ? L[(size_t)(kb + i) * m + kb + j] : 0.0;
+        }
+        if (tid < nb) Sd[tid] = S[(size_t)(kb + tid) * m + kb + tid];
+        __syncthreads();
+        if (!block_chol_inv<NB>(nb, D, Dinv, Sd)) {
+            if (tid == 0) info[0] = kb + 1;
+            return;   // uniform: every lane saw the same pivots
+        }
+        if (tid < NB * NB) {
+            const int i = tid / NB, j = tid % NB;
+            if (i < nb && j <= i) {
+                L[(size_t)(kb + i) * m + kb + j] = D[i][j];
+                X[(size_t)(kb + i) * m + kb + j] = Dinv[i][j];
             }
-            __builtin_amdgcn_wave_barrier();
-            if (lane < nb) Sd[lane] = S[(size_t)(kb + lane) * m + kb + lane];
-            __builtin_amdgcn_wave_barrier();
-            const bool ok = small_chol_inv(nb, D, Dinv, Sd, lane);
-            if (!ok && lane == 0) bad = kb + 1;
-            for (int e = lane; e < nb * nb; e += 64) {
-                const int i = e / nb, j = e % nb;
-                if (j <= i) {
-                    L[(size_t)(kb + i) * m + kb + j] = D[i][j];
-                    X[(size_t)(kb + i) * m + kb + j] = Dinv[i][j];
+        }
+        const int R = m - kb - nb;          // rows below the diagonal block
+        // stage S_ik (R x nb), then the panel L_ik = S_ik Dinv^T on matrix cores
+        for (int e = tid; e < R * NB; e += kDenseThreads) {
+            const int r = e / NB, c = e % NB;
+            stage[r * PS + c] = (c < nb) ? L[(size_t)(kb + nb + r) * m + kb + c] : 0.0;
+        }
+        __syncthreads();
+        const int nbr = (R + 15) / 16;
+        // each wave computes whole 16-row strips of the panel (all NB columns);
+        // at most kStrips strips per wave (m / 16 / 16 for the largest m)
+        constexpr int kStrips = (NB == 32) ? 2 : 4;
+        d4 pacc[kStrips][NB / 16];
+#pragma unroll
+        for (int sidx = 0; sidx < kStrips; ++sidx) {
+            const int bi = wave + sidx * nwaves;
+            if (bi >= nbr) break;
+            const int ra = bi * 16 + (lane & 15);
+#pragma unroll
+            for (int bj = 0; bj < NB / 16; ++bj) {
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+                for (int t0 = 0; t0 < nb; t0 += 4) {
+                    const int k = t0 + (lane >> 4);
+                    const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
+                    const double b = Dinv[bj * 16 + (lane & 15)][k];   // B[k][j] = Dinv[j][k]
+                    acc = mfma64(a, b, acc);
+                }
+                pacc[sidx][bj] = acc;
+            }
+        }
+        __syncthreads();   // all reads of the staged S_ik done
+#pragma unroll
+        for (int sidx = 0; sidx < kStrips; ++sidx) {
+            const int bi = wave + sidx * nwaves;
+            if (bi >= nbr) break;
+#pragma unroll
+            for (int bj = 0; bj < NB / 16; ++bj) {
+                const d4 acc = pacc[sidx][bj];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = bi * 16 + mfma64_row(lane, r), c = bj * 16 + (lane & 15);
+                    if (i < R && c < nb) {
+                        stage[i * PS + c] = acc[r];
+                        L[(size_t)(kb + nb + i) * m + kb + c] = acc[r];
+                    }
                 }
             }
         }
         __syncthreads();
-        if (bad) break;
-        // panel: L_ik = S_ik L_kk^{-T}, rows i >= kb + nb
-        const int rows = m - kb - nb;
-        for (int e = tid; e < rows * nb; e += nthr) {
-            const int i = kb + nb + e / nb, c = e % nb;
-            double s = 0.0;
-            for (int t = 0; t <= c; ++t) s += L[(size_t)i * m + kb + t] * Dinv[c][t];
-            panel[(size_t)i * NB + c] = s;
+        // trailing update of the lower triangle (disjoint from the panel columns)
+        const int npairs = nbr * (nbr + 1) / 2;
+        for (int p = wave; p < npairs; p += nwaves) {
+            int bi, bj;
+            lower_pair(p, bi, bj);
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            const int ra = bi * 16 + (lane & 15), rb = bj * 16 + (lane & 15);
+            for (int t0 = 0; t0 < nb; t0 += 4) {
+                const int k = t0 + (lane >> 4);
+                const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
+                const double b = (rb < R) ? stage[rb * PS + k] : 0.0;
+                acc = mfma64(a, b, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                if (i < R && j <= i) L[(size_t)(kb + nb + i) * m + kb + nb + j] -= acc[r];
+            }
         }
         __syncthreads();
-        for (int e = tid; e < rows * nb; e += nthr) {
-            const int i = kb + nb + e / nb, c = e % nb;
-            L[(size_t)i * m + kb + c] = panel[(size_t)i * NB + c];
-        }
-        __syncthreads();
-        // trailing update of the lower triangle: S_ij -= L_ik L_jk^T
-        for (int64_t e = tid; e < (int64_t)rows * rows; e += nthr) {
-            const int i = kb + nb + (int)(e / rows);
-            const int j = kb + nb + (int)(e % rows);
-            if (j > i) continue;
-            double s = 0.0;
-            for (int t = 0; t < nb; ++t)
-                s += L[(size_t)i * m + kb + t] * L[(size_t)j * m + kb + t];
-            L[(size_t)i * m + j] -= s;
-        }
-        __syncthreads();
-    }
-    if (bad) {
-        if (tid == 0) info[0] = bad;
-        return;
     }
 
-    // ---- blocked inverse X = L^{-1}: diagonal blocks are already in X.
-    // Block row ib: X_ib,: = -Dinv_ib * sum_{k < ib} L_ib,k X_k,:
+    // inverse, block row ib: X_ib,0:ib = -Dinv_ib (L_ib,0:ib X_0:ib,0:ib)
     for (int ib = NB; ib < m; ib += NB) {
         const int nb = (m - ib < NB) ? (m - ib) : NB;
-        // T = L[ib:ib+nb, 0:ib] X[0:ib, 0:ib] into panel (nb x ib, row-major)
-        for (int e = tid; e < nb * ib; e += nthr) {
-            const int r = e / ib, c = e % ib;
-            double s = 0.0;
-            for (int k = c; k < ib; ++k) s += L[(size_t)(ib + r) * m + k] * X[(size_t)k * m + c];
-            panel[e] = s;
+        const int SS = ib + 1;
+        for (int e = tid; e < nb * ib; e += kDenseThreads) {
+            const int r = e / ib, k = e - (e / ib) * ib;
+            stage[r * SS + k] = L[(size_t)(ib + r) * m + k];
+        }
+        for (int e = tid; e < NB * NB; e += kDenseThreads) {
+            const int r = e / NB, c = e % NB;
+            Dinv[r][c] = (r < nb && c <= r) ? X[(size_t)(ib + r) * m + ib + c] : 0.0;
         }
         __syncthreads();
-        for (int e = tid; e < nb * ib; e += nthr) {
-            const int r = e / ib, c = e % ib;
-            double s = 0.0;
-            for (int t = 0; t <= r; ++t)
-                s += X[(size_t)(ib + r) * m + ib + t] * panel[(size_t)t * ib + c];
-            X[(size_t)(ib + r) * m + c] = -s;
+        const int nbi = (nb + 15) / 16, nbj = (ib + 15) / 16;
+        for (int p = wave; p < nbi * nbj; p += nwaves) {
+            const int bi = p / nbj, bj = p - (p / nbj) * nbj;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            const int ra = bi * 16 + (lane & 15), jc = bj * 16 + (lane & 15);
+            for (int k0 = (bj * 16) & ~3; k0 < ib; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                const double a = (ra < nb && k < ib) ? stage[ra * SS + k] : 0.0;
+                const double b = (k < ib && jc < ib) ? X[(size_t)k * m + jc] : 0.0;
+                acc = mfma64(a, b, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                if (i < nb && j < ib) T[(size_t)i * m + j] = acc[r];
+            }
+        }
+        __syncthreads();
+        // X_ib,0:ib = -Dinv (nb x nb) T (nb x ib) on matrix cores
+        for (int p = wave; p < nbi * nbj; p += nwaves) {
+            const int bi = p / nbj, bj = p - (p / nbj) * nbj;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            const int ra = bi * 16 + (lane & 15), jc = bj * 16 + (lane & 15);
+            for (int k0 = 0; k0 < nb; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                const double a = (ra < nb) ? Dinv[ra][k] : 0.0;
+                const double b = (k < nb && jc < ib) ? T[(size_t)k * m + jc] : 0.0;
+                acc = mfma64(a, b, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                if (i < nb && j < ib) X[(size_t)(ib + i) * m + j] = -acc[r];
+            }
         }
         __syncthreads();
     }
-    // Rinv = X^T (upper triangular)
-    for (int64_t e = tid; e < (int64_t)m * m; e += nthr) {
+    for (int64_t e = tid; e < (int64_t)m * m; e += kDenseThreads) {
         const int i = (int)(e / m), j = (int)(e % m);
         Rinv[e] = (j >= i) ? X[(size_t)j * m + i] : 0.0;
     }
-}
-
-// -------------------------------------------------------------- Jacobi
-// Parallel cyclic Jacobi with round-robin ("circle") pair ordering: in each
-// step the M/2 disjoint pairs (p, q) are rotated at once.  A <- J^T A J is
-// applied as independent 2 x 2 block updates; V <- V J.  M = m rounded up to
-// even; index m (when m is odd) is a dummy that never rotates.
-__device__ inline int rr_index(int pos, int step, int M) {
-    if (pos == 0) return 0;
-    return 1 + (pos - 1 + step) % (M - 1);
-}
-
-__global__ __launch_bounds__(kDenseThreads) void jacobi_kernel(
-    int m, const double *__restrict__ Ain, double *__restrict__ U,
-    double *__restrict__ w, double *__restrict__ work, int32_t *__restrict__ info,
-    int max_sweeps) {
-    __shared__ double cs_c[512], cs_s[512];
-    __shared__ int pp[512], qq[512];
-    __shared__ double red[kDenseThreads];
-    __shared__ int stop;
-    double *A = work;
-    double *V = work + (size_t)m * m;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int M = (m + 1) & ~1;
-    const int half = M / 2;
-    double fro2 = 0.0;
-    for (int64_t e = tid; e < (int64_t)m * m; e += nthr) {
-        const double a = Ain[e];
-        A[e] = a;
-        fro2 += a * a;
-        const int i = (int)(e / m), j = (int)(e % m);
-        V[e] = (i == j) ? 1.0 : 0.0;
-    }
-    red[tid] = fro2;
-    __syncthreads();
-    for (int k = kDenseThreads / 2; k > 0; k >>= 1) {
-        if (tid < k) red[tid] += red[tid + k];
-        __syncthreads();
-    }
-    const double anorm = sqrt(red[0]);
-    __syncthreads();
-    if (tid == 0) stop = 0;
-    double prev_off = 1e300;
-    int sweep = 0;
-    for (; sweep < max_sweeps; ++sweep) {
-        // off-diagonal norm
-        double o = 0.0;
-        for (int64_t e = tid; e < (int64_t)m * m; e += nthr) {
-            const int i = (int)(e / m), j = (int)(e % m);
-            if (i != j) o += A[e] * A[e];
-        }
-        red[tid] = o;
-        __syncthreads();
-        for (int k = kDenseThreads / 2; k > 0; k >>= 1) {
-            if (tid < k) red[tid] += red[tid + k];
-            __syncthreads();
-        }
-        if (tid == 0) {
-            const double off = sqrt(red[0]);
-            if (off <= 1e-15 * anorm || m < 2) stop = 1;
-            else if (sweep >= 3 && off > 0.5 * prev_off && off <= 1e-12 * anorm) stop = 1;
-            prev_off = off;
-        }
-        __syncthreads();
-        if (stop) break;
-        for (int step = 0; step < M - 1; ++step) {
-            if (tid < half) {
-                int p = rr_index(tid, step, M), q = rr_index(M - 1 - tid, step, M);
-                if (p > q) { const int t = p; p = q; q = t; }
-                double c = 1.0, s = 0.0;
-                if (q < m) {
-                    const double apq = A[(size_t)p * m + q];
-                    if (apq != 0.0) {
-                        const double app = A[(size_t)p * m + p], aqq = A[(size_t)q * m + q];
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                                      : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                    }
-                }
-                pp[tid] = p;
-                qq[tid] = q;
-                cs_c[tid] = c;
-                cs_s[tid] = s;
-            }
-            __syncthreads();
-            // A <- J^T A J on 2 x 2 blocks (pair a rows, pair b columns)
-            for (int64_t e = tid; e < (int64_t)half * half; e += nthr) {
-                const int a = (int)(e / half), b = (int)(e % half);
-                const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
-                const double ca = cs_c[a], sa = cs_s[a], cb = cs_c[b], sb = cs_s[b];
-                const bool qa_ok = qa < m, qb_ok = qb < m;
-                const double x00 = A[(size_t)pa * m + pb];
-                const double x01 = qb_ok ? A[(size_t)pa * m + qb] : 0.0;
-                const double x10 = qa_ok ? A[(size_t)qa * m + pb] : 0.0;
-                const double x11 = (qa_ok && qb_ok) ? A[(size_t)qa * m + qb] : 0.0;
-                // columns: B = X J_b
-                const double b00 = cb * x00 - sb * x01, b01 = sb * x00 + cb * x01;
-                const double b10 = cb * x10 - sb * x11, b11 = sb * x10 + cb * x11;
-                // rows: J_a^T B
-                double y00 = ca * b00 - sa * b10, y01 = ca * b01 - sa * b11;
-                double y10 = sa * b00 + ca * b10, y11 = sa * b01 + ca * b11;
-                if (a == b) { y01 = 0.0; y10 = 0.0; }
-                A[(size_t)pa * m + pb] = y00;
-                if (qb_ok) A[(size_t)pa * m + qb] = y01;
-                if (qa_ok) A[(size_t)qa * m + pb] = y10;
-                if (qa_ok && qb_ok) A[(size_t)qa * m + qb] = y11;
-            }
-            // V <- V J
-            for (int64_t e = tid; e < (int64_t)m * half; e += nthr) {
-                const int k = (int)(e / half), b = (int)(e % half);
-                const int pb = pp[b], qb = qq[b];
-                if (qb >= m) continue;
-                const double cb = cs_c[b], sb = cs_s[b];
-                const double vp = V[(size_t)k * m + pb], vq = V[(size_t)k * m + qb];
-                V[(size_t)k * m + pb] = cb * vp - sb * vq;
-                V[(size_t)k * m + qb] = sb * vp + cb * vq;
-            }
-            __syncthreads();
-        }
-    }
-    // sort ascending by rank (ties broken by index) and scatter
-    for (int i = tid; i < m; i += nthr) {
-        const double wi = A[(size_t)i * m + i];
-        int rank = 0;
-        for (int j = 0; j < m; ++j) {
-            const double wj = A[(size_t)j * m + j];
-            rank += (wj < wi) || (wj == wi && j < i);
-        }
-        w[rank] = wi;
-        for (int k = 0; k < m; ++k) U[(size_t)k * m + rank] = V[(size_t)k * m + i];
-    }
-    if (tid == 0) info[0] = sweep;
 }
 
 __global__ void assemble_kernel(int m, const double *__restrict__ Hp,
@@ -312,23 +259,19 @@ __global__ void assemble_kernel(int m, const double *__restrict__ Hp,
 }  // namespace
 
 size_t chol_workspace(int m) {
-    return ((size_t)2 * m * m + (size_t)m * NB) * sizeof(double);
+    return ((size_t)2 * m * m + (size_t)m * NBMAX) * sizeof(double);
 }
 
 void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
                   double *work, int32_t *info) {
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(kDenseThreads), 0, s, m, S,
-                       Rinv, work, info);
-    TM_HIP(hipGetLastError());
-}
-
-size_t jacobi_workspace(int m) { return (size_t)2 * m * m * sizeof(double); }
-
-void jacobi_eig(hipStream_t s, int m, const double *A, double *U, double *w,
-                double *work, int32_t *info) {
-    TM_REQUIRE(m <= 1024, TM_ENOTSUP, "eigensolver supports m <= 1024");
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kDenseThreads), 0, s, m, A, U,
-                       w, work, info, 40);
+    TM_REQUIRE(m >= 1 && m <= 1024, TM_ENOTSUP, "Cholesky supports m <= 1024");
+    // the staged panel (m x (NB+1) doubles) must fit the LDS staging area
+    if (m <= 512)
+        hipLaunchKernelGGL(chol_inv_kernel<32>, dim3(1), dim3(kDenseThreads), 0, s, m, S,
+                           Rinv, work, info);
+    else
+        hipLaunchKernelGGL(chol_inv_kernel<16>, dim3(1), dim3(kDenseThreads), 0, s, m, S,
+                           Rinv, work, info);
     TM_HIP(hipGetLastError());
 }
 

@@ -41,8 +41,29 @@ template <> struct Mfma<double> {
 };
 
 constexpr int kThreads = 256;
-constexpr int kGramKT = 16;   // rows of A and B per LDS stage
-constexpr int kRotKT = 16;    // columns of A (rows of W) per LDS stage
+constexpr int kPad = 16;   // LDS row padding (elements) against bank conflicts
+
+// 16-byte vector of T for global loads (clang vector types: element access
+// with a constant index stays in registers)
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = vf4; static constexpr int W = 4; };
+template <> struct Vec16<double> { using type = vd2; static constexpr int W = 2; };
+
+template <typename T>
+__device__ inline typename Vec16<T>::type vzero() {
+    return typename Vec16<T>::type(0);
+}
+
+template <typename T>
+__device__ inline T velem(const typename Vec16<T>::type &v, int i) {
+    return v[i];
+}
+
+// rows of A and B per LDS stage: the FP32 instruction is twice as fast, so
+// it gets twice the rows per synchronization
+template <typename TM> constexpr int stage_rows() { return sizeof(TM) == 4 ? 32 : 16; }
 
 __device__ inline int xcd_logical(int grid) {
     const int b = blockIdx.x;
@@ -60,19 +81,27 @@ __device__ inline void upper_tile(int t, int T, int &ti, int &tj) {
     tj = i + t;
 }
 
+// One workgroup: a BM x BM tile of A^T B' over a chunk of rows.  Each lane
+// loads 16-byte vectors from a fixed column group (so h is read once), the
+// LDS stage is double-buffered, one barrier per stage.
 template <typename TA, typename TM, int BM, bool SHIFT>
-__global__ __launch_bounds__(kThreads) void gram_kernel(
+__global__ __launch_bounds__(kThreads, 2) void gram_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TA *__restrict__ B,
     const double *__restrict__ h, int T, int ntiles, bool symmetric,
     int64_t rows_per_split, double *__restrict__ partials) {
-    constexpr int PAD = 4;
+    constexpr int KT = stage_rows<TM>();
     constexpr int WM = BM / 2;
     constexpr int NB = WM / 16;
-    constexpr int PER = kGramKT * BM / kThreads;   // elements per lane per operand
+    constexpr int VW = Vec16<TA>::W;
+    constexpr int VPR = BM / VW;            // vectors per tile row
+    constexpr int RPP = kThreads / VPR;     // tile rows per load pass
+    constexpr int PASSES = KT / RPP;
+    static_assert(KT % RPP == 0, "stage rows must be a multiple of rows per pass");
+    using V = typename Vec16<TA>::type;
     using Acc = typename Mfma<TM>::acc_t;
 
-    __shared__ TM As[kGramKT][BM + PAD];
-    __shared__ TM Bs[kGramKT][BM + PAD];
+    __shared__ TM As[2][KT][BM + kPad];
+    __shared__ TM Bs[2][KT][BM + kPad];
 
     const int logical = xcd_logical(gridDim.x);
     const int split = logical / ntiles;
@@ -88,6 +117,14 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wi = wave >> 1, wj = wave & 1;
+    const int cv = tid % VPR, rbase = tid / VPR;
+    const int ci = i0 + cv * VW, cj = j0 + cv * VW;
+    const bool ci_ok = ci < ld, cj_ok = cj < ld;   // ld is a multiple of 32
+    const bool same = (ti == tj);
+
+    double hv[VW];
+#pragma unroll
+    for (int w = 0; w < VW; ++w) hv[w] = (SHIFT && cj_ok) ? h[cj + w] : 0.0;
 
     Acc acc[NB][NB];
 #pragma unroll
@@ -95,54 +132,62 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-    TM ra[PER], rb[PER];
+    V ra[PASSES], rb[PASSES], rx[SHIFT ? PASSES : 1];
     auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * kThreads;
-            const int row = e / BM, col = e - (e / BM) * BM;
-            const int64_t k = k0 + row;
+        for (int q = 0; q < PASSES; ++q) {
+            const int64_t k = k0 + rbase + q * RPP;
             const bool rok = k < k_end;
-            const int ci = i0 + col, cj = j0 + col;
-            ra[q] = (rok && ci < ld) ? (TM)A[k * ld + ci] : (TM)0;
-            if (rok && cj < ld) {
+            ra[q] = (rok && ci_ok) ? *reinterpret_cast<const V *>(A + k * ld + ci) : vzero<TA>();
+            rb[q] = (rok && cj_ok) ? *reinterpret_cast<const V *>(B + k * ld + cj) : vzero<TA>();
+            if constexpr (SHIFT)
+                rx[q] = same ? ra[q]
+                             : ((rok && cj_ok) ? *reinterpret_cast<const V *>(A + k * ld + cj)
+                                               : vzero<TA>());
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PASSES; ++q) {
+            const int row = rbase + q * RPP;
+#pragma unroll
+            for (int w = 0; w < VW; ++w) {
+                As[buf][row][cv * VW + w] = (TM)velem<TA>(ra[q], w);
                 if constexpr (SHIFT) {
-                    const double x = (double)B[k * ld + cj] - (double)A[k * ld + cj] * h[cj];
-                    rb[q] = (TM)x;
+                    const double x = (double)velem<TA>(rb[q], w) - (double)velem<TA>(rx[q], w) * hv[w];
+                    Bs[buf][row][cv * VW + w] = (TM)x;
                 } else {
-                    rb[q] = (TM)B[k * ld + cj];
+                    Bs[buf][row][cv * VW + w] = (TM)velem<TA>(rb[q], w);
                 }
-            } else {
-                rb[q] = (TM)0;
             }
         }
     };
 
-    if (k_begin < k_end) load(k_begin);
-    for (int64_t k0 = k_begin; k0 < k_end; k0 += kGramKT) {
-        __syncthreads();
+    int buf = 0;
+    if (k_begin < k_end) {
+        load(k_begin);
+        store(0);
+    }
+    __syncthreads();
+    for (int64_t k0 = k_begin; k0 < k_end; k0 += KT) {
+        const bool more = k0 + KT < k_end;
+        if (more) load(k0 + KT);
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * kThreads;
-            const int row = e / BM, col = e - (e / BM) * BM;
-            As[row][col] = ra[q];
-            Bs[row][col] = rb[q];
-        }
-        __syncthreads();
-        if (k0 + kGramKT < k_end) load(k0 + kGramKT);
-#pragma unroll
-        for (int kk = 0; kk < kGramKT; kk += 4) {
+        for (int kk = 0; kk < KT; kk += 4) {
             TM fa[NB], fb[NB];
             const int kr = kk + (lane >> 4);
 #pragma unroll
-            for (int a = 0; a < NB; ++a) fa[a] = As[kr][wi * WM + a * 16 + (lane & 15)];
+            for (int a = 0; a < NB; ++a) fa[a] = As[buf][kr][wi * WM + a * 16 + (lane & 15)];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) fb[b] = Bs[kr][wj * WM + b * 16 + (lane & 15)];
+            for (int b = 0; b < NB; ++b) fb[b] = Bs[buf][kr][wj * WM + b * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) acc[a][b] = Mfma<TM>::op(fa[a], fb[b], acc[a][b]);
         }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
 
     double *P = partials + (int64_t)split * m * m;
@@ -173,39 +218,49 @@ __global__ void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
     out[idx] = s;
 }
 
-int gram_tile(int ld) { return ld >= 512 ? 128 : 64; }
+int gram_tile(int ld) { return ld >= 256 ? 128 : 64; }
 
 void gram_shape(int64_t n, int m, int &BM, int &T, int &nsplit) {
     const int ld = leading_dim(m);
     BM = gram_tile(ld);
     T = (ld + BM - 1) / BM;
-    // aim at ~1024 workgroups, at most 16 MiB of FP64 partials, and at least
-    // 64 rows per split; nsplit is a multiple of 8 (XCD mapping)
+    // aim at ~2 workgroups per CU, at most 64 MiB of FP64 partials, and at
+    // least 128 rows per split; nsplit is a multiple of 8 (XCD mapping)
     const int ntiles_full = T * T;
-    int64_t ns = 1024 / ntiles_full;
-    const int64_t cap_bytes = (int64_t)16 << 20;
+    int64_t ns = 512 / ntiles_full;
+    const int64_t cap_bytes = (int64_t)64 << 20;
     int64_t cap = cap_bytes / ((int64_t)m * m * 8);
     if (ns > cap) ns = cap;
-    int64_t cap_rows = n / 64;
+    int64_t cap_rows = n / 128;
     if (ns > cap_rows) ns = cap_rows;
     ns = (ns + 7) / 8 * 8;
     if (ns < 8) ns = 8;
     nsplit = (int)ns;
 }
 
+// One workgroup: a BR x BC tile of A W (+ epilogue), K looped in LDS stages.
 template <typename TA, typename TM, typename TO, int EPI, int BR, int BC>
-__global__ __launch_bounds__(kThreads) void rot_kernel(
+__global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TM *__restrict__ W,
     const TA *__restrict__ X, const double *__restrict__ vec, TO *__restrict__ out,
     int nrb, int ncb) {
+    constexpr int KT = stage_rows<TM>();
     constexpr int WR = BR / 2, WC = BC / 2;
     constexpr int NBR = WR / 16, NBC = WC / 16;
-    constexpr int PA = BR * kRotKT / kThreads;
-    constexpr int PW = BC * kRotKT / kThreads;
+    constexpr int VA = Vec16<TA>::W, VM = Vec16<TM>::W;
+    constexpr int APR = KT / VA;            // A vectors per tile row
+    constexpr int ARPP = kThreads / APR;    // A rows per pass
+    constexpr int PA = BR / ARPP;
+    constexpr int WPR = BC / VM;            // W vectors per tile row
+    constexpr int WRPP = kThreads / WPR;
+    constexpr int PW = KT / WRPP;
+    static_assert(BR % ARPP == 0 && KT % WRPP == 0, "tile shape");
+    using VAt = typename Vec16<TA>::type;
+    using VMt = typename Vec16<TM>::type;
     using Acc = typename Mfma<TM>::acc_t;
 
-    __shared__ TM As[BR][kRotKT + 1];
-    __shared__ TM Ws[kRotKT][BC + 4];
+    __shared__ TM As[2][BR][KT + 1];
+    __shared__ TM Ws[2][KT][BC + kPad];
 
     const int logical = xcd_logical(gridDim.x);
     if (logical >= nrb * ncb) return;
@@ -218,6 +273,9 @@ __global__ __launch_bounds__(kThreads) void rot_kernel(
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wr = wave >> 1, wc = wave & 1;
+    const int acv = tid % APR, arow = tid / APR;
+    const int wcv = tid % WPR, wrow = tid / WPR;
+    const bool wc_ok = c0 + wcv * VM < ld;
 
     Acc acc[NBR][NBC];
 #pragma unroll
@@ -225,52 +283,56 @@ __global__ __launch_bounds__(kThreads) void rot_kernel(
 #pragma unroll
         for (int b = 0; b < NBC; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-    TM ra[PA], rw[PW];
+    VAt ra[PA];
+    VMt rw[PW];
     auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PA; ++q) {
-            const int e = tid + q * kThreads;
-            const int row = e / kRotKT, col = e - (e / kRotKT) * kRotKT;
-            const int64_t r = r0 + row;
-            ra[q] = (r < n) ? (TM)A[r * ld + k0 + col] : (TM)0;
+            const int64_t r = r0 + arow + q * ARPP;
+            ra[q] = (r < n) ? *reinterpret_cast<const VAt *>(A + r * ld + k0 + acv * VA) : vzero<TA>();
         }
 #pragma unroll
         for (int q = 0; q < PW; ++q) {
-            const int e = tid + q * kThreads;
-            const int row = e / BC, col = e - (e / BC) * BC;
-            const int c = c0 + col;
-            rw[q] = (c < ld) ? W[(int64_t)(k0 + row) * ld + c] : (TM)0;
+            const int k = k0 + wrow + q * WRPP;
+            rw[q] = wc_ok ? *reinterpret_cast<const VMt *>(W + (int64_t)k * ld + c0 + wcv * VM)
+                          : vzero<TM>();
         }
     };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PA; ++q)
+#pragma unroll
+            for (int w = 0; w < VA; ++w)
+                As[buf][arow + q * ARPP][acv * VA + w] = (TM)velem<TA>(ra[q], w);
+#pragma unroll
+        for (int q = 0; q < PW; ++q)
+#pragma unroll
+            for (int w = 0; w < VM; ++w) Ws[buf][wrow + q * WRPP][wcv * VM + w] = velem<TM>(rw[q], w);
+    };
 
+    int buf = 0;
     load(0);
-    for (int k0 = 0; k0 < kend; k0 += kRotKT) {
-        __syncthreads();
+    store(0);
+    __syncthreads();
+    for (int k0 = 0; k0 < kend; k0 += KT) {
+        const bool more = k0 + KT < kend;
+        if (more) load(k0 + KT);
 #pragma unroll
-        for (int q = 0; q < PA; ++q) {
-            const int e = tid + q * kThreads;
-            As[e / kRotKT][e - (e / kRotKT) * kRotKT] = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < PW; ++q) {
-            const int e = tid + q * kThreads;
-            Ws[e / BC][e - (e / BC) * BC] = rw[q];
-        }
-        __syncthreads();
-        if (k0 + kRotKT < kend) load(k0 + kRotKT);
-#pragma unroll
-        for (int kk = 0; kk < kRotKT; kk += 4) {
+        for (int kk = 0; kk < KT; kk += 4) {
             TM fa[NBR], fb[NBC];
             const int kc = kk + (lane >> 4);
 #pragma unroll
-            for (int a = 0; a < NBR; ++a) fa[a] = As[wr * WR + a * 16 + (lane & 15)][kc];
+            for (int a = 0; a < NBR; ++a) fa[a] = As[buf][wr * WR + a * 16 + (lane & 15)][kc];
 #pragma unroll
-            for (int b = 0; b < NBC; ++b) fb[b] = Ws[kc][wc * WC + b * 16 + (lane & 15)];
+            for (int b = 0; b < NBC; ++b) fb[b] = Ws[buf][kc][wc * WC + b * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < NBR; ++a)
 #pragma unroll
                 for (int b = 0; b < NBC; ++b) acc[a][b] = Mfma<TM>::op(fa[a], fb[b], acc[a][b]);
         }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
 
 #pragma unroll
@@ -325,7 +387,8 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     gram_shape(n, m, BM, T, nsplit);
     if (h) symmetric = false;
     const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
-    const int64_t rows = ((n + nsplit - 1) / nsplit + kGramKT - 1) / kGramKT * kGramKT;
+    constexpr int KT = stage_rows<TM>();
+    const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
     const int grid = ntiles * nsplit;   // multiple of 8
 #define TM_GRAM(BMV, SH)                                                            \
     hipLaunchKernelGGL((gram_kernel<TA, TM, BMV, SH>), dim3(grid), dim3(kThreads), 0, s, \
@@ -348,17 +411,23 @@ template <typename TA, typename TM, typename TO>
 void rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
          const TA *X, const double *vec, TO *out) {
     const int ld = leading_dim(m);
-    constexpr int BR = 64, BC = 64;
-    const int nrb = (int)((n + BR - 1) / BR);
-    const int ncb = (ld + BC - 1) / BC;
+    const int B = ld >= 256 ? 128 : 64;
+    const int nrb = (int)((n + B - 1) / B);
+    const int ncb = (ld + B - 1) / B;
     int grid = nrb * ncb;
     grid = (grid + 7) / 8 * 8;
-#define TM_ROT(E)                                                                      \
-    hipLaunchKernelGGL((rot_kernel<TA, TM, TO, E, BR, BC>), dim3(grid), dim3(kThreads), \
+#define TM_ROT(E, BB)                                                                      \
+    hipLaunchKernelGGL((rot_kernel<TA, TM, TO, E, BB, BB>), dim3(grid), dim3(kThreads), \
                        0, s, n, m, ld, A, Wpad, X, vec, out, nrb, ncb)
-    if (epi == EPI_NONE) TM_ROT(EPI_NONE);
-    else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD);
-    else TM_ROT(EPI_TRMM);
+    if (B == 128) {
+        if (epi == EPI_NONE) TM_ROT(EPI_NONE, 128);
+        else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 128);
+        else TM_ROT(EPI_TRMM, 128);
+    } else {
+        if (epi == EPI_NONE) TM_ROT(EPI_NONE, 64);
+        else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 64);
+        else TM_ROT(EPI_TRMM, 64);
+    }
 #undef TM_ROT
     TM_HIP(hipGetLastError());
 }

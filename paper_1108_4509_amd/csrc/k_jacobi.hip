@@ -1,0 +1,304 @@
+// Symmetric eigensolver for the m x m H of Eq. 9 (Rayleigh-Ritz and the
+// occasional subspace rotation): block cyclic Jacobi in FP64.
+//
+// The index range is cut into blocks of BJ = 16 (m padded to M, a multiple of
+// 32; padded rows and columns are zero and never rotate).  A sweep visits every
+// pair of blocks once in round-robin order; in one step the nbk/2 disjoint
+// pairs are handled at once:
+//   bj_solve : each workgroup diagonalizes its 32 x 32 subproblem A[IJ, IJ]
+//              in LDS by cyclic Jacobi (the textbook 2 x 2 symmetric Schur
+//              rotations, 16 at a time) and writes the accumulated 32 x 32
+//              orthogonal Q_IJ;
+//   bj_apply : every (pair a, pair b) 32 x 32 block is updated as
+//              A_ab <- Q_a^T A_ab Q_b and V_ab <- V_ab Q_b (one workgroup each).
+// After each sweep bj_check measures off(A); once it is below 1e-15 ||A||_F
+// (or stops shrinking at the rounding level) the remaining launches exit at
+// once.  bj_sort orders the eigenvalues and gathers the eigenvectors.
+#include "tm_common.h"
+
+#include <cmath>
+
+namespace tmin {
+namespace {
+
+constexpr int BJ = 16;
+constexpr int PJ = 2 * BJ;
+constexpr int kInnerSweeps = 12;
+constexpr int kNormBlocks = 64;
+
+struct JacState {
+    double anorm2;     // ||A||_F^2
+    double off2;       // off(A)^2 after the last sweep
+    double prev_off2;
+    int32_t done;
+    int32_t sweeps;
+};
+
+__device__ inline int rr_pos(int pos, int step, int n) {
+    if (pos == 0) return 0;
+    return 1 + (pos - 1 + step) % (n - 1);
+}
+
+__device__ inline void pair_of(int k, int step, int n, int &I, int &J) {
+    I = rr_pos(k, step, n);
+    J = rr_pos(n - 1 - k, step, n);
+    if (I > J) { const int t = I; I = J; J = t; }
+}
+
+// global index of position t (0..31) of the pair of blocks (I, J)
+__device__ inline int pidx(int t, int I, int J) { return t < BJ ? I * BJ + t : J * BJ + (t - BJ); }
+
+__global__ void bj_init(int m, int M, const double *__restrict__ A, double *__restrict__ Aw,
+                        double *__restrict__ V, double *__restrict__ partial) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)M * M;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / M), j = (int)(e % M);
+        const double a = (i < m && j < m) ? A[(int64_t)i * m + j] : 0.0;
+        Aw[e] = a;
+        V[e] = (i == j) ? 1.0 : 0.0;
+        s += a * a;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void bj_norm(const double *__restrict__ partial, JacState *st) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < kNormBlocks; ++b) s += partial[b];
+    st->anorm2 = s;
+    st->off2 = 1e300;
+    st->prev_off2 = 1e300;
+    st->done = (s == 0.0) ? 1 : 0;
+    st->sweeps = 0;
+}
+
+__global__ __launch_bounds__(256) void bj_solve(int M, int step, const double *__restrict__ Aw,
+                                                double *__restrict__ Q, const JacState *st) {
+    if (st->done) return;
+    __shared__ double S[PJ][PJ + 1];
+    __shared__ double Ql[PJ][PJ + 1];
+    __shared__ double cc[BJ], ss[BJ];
+    __shared__ int pp[BJ], qq[BJ];
+    __shared__ double red[2][256];
+    const int nbk = M / BJ;
+    const int t = threadIdx.x;
+    int I, J;
+    pair_of(blockIdx.x, step, nbk, I, J);
+    for (int e = t; e < PJ * PJ; e += 256) {
+        const int a = e / PJ, b = e % PJ;
+        S[a][b] = Aw[(int64_t)pidx(a, I, J) * M + pidx(b, I, J)];
+        Ql[a][b] = (a == b) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
+        double off = 0.0, fro = 0.0;
+        for (int e = t; e < PJ * PJ; e += 256) {
+            const int a = e / PJ, b = e % PJ;
+            const double v = S[a][b] * S[a][b];
+            fro += v;
+            if (a != b) off += v;
+        }
+        red[0][t] = off;
+        red[1][t] = fro;
+        __syncthreads();
+        for (int k = 128; k > 0; k >>= 1) {
+            if (t < k) {
+                red[0][t] += red[0][t + k];
+                red[1][t] += red[1][t + k];
+            }
+            __syncthreads();
+        }
+        const bool stop = !(red[0][0] > 1e-30 * red[1][0]);
+        __syncthreads();
+        if (stop) break;
+        for (int s2 = 0; s2 < PJ - 1; ++s2) {
+            if (t < BJ) {
+                int p = rr_pos(t, s2, PJ), q = rr_pos(PJ - 1 - t, s2, PJ);
+                if (p > q) { const int x = p; p = q; q = x; }
+                double c = 1.0, sn = 0.0;
+                const double apq = S[p][q];
+                if (apq != 0.0) {
+                    const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
+                    const double tt = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                                   : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    sn = tt * c;
+                }
+                pp[t] = p;
+                qq[t] = q;
+                cc[t] = c;
+                ss[t] = sn;
+            }
+            __syncthreads();
+            {   // S <- J^T S J on the 2 x 2 blocks of pairs (a, b)
+                const int a = t / BJ, b = t % BJ;
+                const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+                const double ca = cc[a], sa = ss[a], cb = cc[b], sb = ss[b];
+                const double x00 = S[pa][pb], x01 = S[pa][qb], x10 = S[qa][pb], x11 = S[qa][qb];
+                const double b00 = cb * x00 - sb * x01, b01 = sb * x00 + cb * x01;
+                const double b10 = cb * x10 - sb * x11, b11 = sb * x10 + cb * x11;
+                double y00 = ca * b00 - sa * b10, y01 = ca * b01 - sa * b11;
+                double y10 = sa * b00 + ca * b10, y11 = sa * b01 + ca * b11;
+                if (a == b) { y01 = 0.0; y10 = 0.0; }
+                S[pa][pb] = y00;
+                S[pa][qb] = y01;
+                S[qa][pb] = y10;
+                S[qa][qb] = y11;
+            }
+            for (int e = t; e < PJ * BJ; e += 256) {   // Q <- Q J
+                const int row = e / BJ, b = e % BJ;
+                const int pb = pp[b], qb = qq[b];
+                const double vp = Ql[row][pb], vq = Ql[row][qb];
+                Ql[row][pb] = cc[b] * vp - ss[b] * vq;
+                Ql[row][qb] = ss[b] * vp + cc[b] * vq;
+            }
+            __syncthreads();
+        }
+    }
+    double *Qo = Q + (int64_t)blockIdx.x * PJ * PJ;
+    for (int e = t; e < PJ * PJ; e += 256) Qo[e] = Ql[e / PJ][e % PJ];
+}
+
+__global__ __launch_bounds__(256) void bj_apply(int M, int step, double *__restrict__ Aw,
+                                                double *__restrict__ V,
+                                                const double *__restrict__ Q,
+                                                const JacState *st) {
+    if (st->done) return;
+    __shared__ double Ab[PJ][PJ + 1], Vb[PJ][PJ + 1], Qa[PJ][PJ + 1], Qb[PJ][PJ + 1];
+    __shared__ double T[PJ][PJ + 1];
+    const int nbk = M / BJ, nbp = nbk / 2;
+    const int pa = blockIdx.x / nbp, pb = blockIdx.x % nbp;
+    int Ia, Ja, Ib, Jb;
+    pair_of(pa, step, nbk, Ia, Ja);
+    pair_of(pb, step, nbk, Ib, Jb);
+    const int t = threadIdx.x;
+    const double *qa = Q + (int64_t)pa * PJ * PJ, *qb = Q + (int64_t)pb * PJ * PJ;
+    for (int e = t; e < PJ * PJ; e += 256) {
+        const int a = e / PJ, b = e % PJ;
+        const int64_t g = (int64_t)pidx(a, Ia, Ja) * M + pidx(b, Ib, Jb);
+        Ab[a][b] = Aw[g];
+        Vb[a][b] = V[g];
+        Qa[a][b] = qa[e];
+        Qb[a][b] = qb[e];
+    }
+    __syncthreads();
+    // T = A_ab Q_b and V_ab Q_b (each lane: one row, four columns)
+    const int row = t / 8, c0 = (t % 8) * 4;
+    double ta[4] = {0, 0, 0, 0}, tv[4] = {0, 0, 0, 0};
+    for (int k = 0; k < PJ; ++k) {
+        const double a = Ab[row][k], v = Vb[row][k];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ta[c] += a * Qb[k][c0 + c];
+            tv[c] += v * Qb[k][c0 + c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) T[row][c0 + c] = ta[c];
+    __syncthreads();
+    // A_ab <- Q_a^T T
+    double out[4] = {0, 0, 0, 0};
+    for (int k = 0; k < PJ; ++k) {
+        const double q = Qa[k][row];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[c] += q * T[k][c0 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int64_t g = (int64_t)pidx(row, Ia, Ja) * M + pidx(c0 + c, Ib, Jb);
+        Aw[g] = out[c];
+        V[g] = tv[c];
+    }
+}
+
+__global__ __launch_bounds__(1024) void bj_check(int M, const double *__restrict__ Aw,
+                                                 JacState *st) {
+    if (st->done) return;
+    __shared__ double red[1024];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t e = t; e < (int64_t)M * M; e += 1024) {
+        const int i = (int)(e / M), j = (int)(e % M);
+        if (i != j) s += Aw[e] * Aw[e];
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int k = 512; k > 0; k >>= 1) {
+        if (t < k) red[t] += red[t + k];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double off2 = red[0];
+        st->sweeps += 1;
+        const double tol2 = 1e-30 * st->anorm2;
+        if (off2 <= tol2) st->done = 1;
+        else if (st->sweeps >= 3 && off2 > 0.25 * st->prev_off2 && off2 <= 1e-24 * st->anorm2)
+            st->done = 1;   // stopped shrinking at the rounding level
+        st->prev_off2 = off2;
+        st->off2 = off2;
+    }
+}
+
+__global__ __launch_bounds__(1024) void bj_sort(int m, int M, const double *__restrict__ Aw,
+                                                const double *__restrict__ V,
+                                                double *__restrict__ U, double *__restrict__ w) {
+    for (int i = threadIdx.x; i < m; i += 1024) {
+        const double wi = Aw[(int64_t)i * M + i];
+        int rank = 0;
+        for (int j = 0; j < m; ++j) {
+            const double wj = Aw[(int64_t)j * M + j];
+            rank += (wj < wi) || (wj == wi && j < i);
+        }
+        w[rank] = wi;
+        for (int k = 0; k < m; ++k) U[(int64_t)k * m + rank] = V[(int64_t)k * M + i];
+    }
+}
+
+}  // namespace
+
+size_t jacobi_workspace(int m) {
+    const int M = leading_dim(m);
+    return ((size_t)2 * M * M + (size_t)(M / BJ / 2) * PJ * PJ + kNormBlocks + 16) * sizeof(double);
+}
+
+void jacobi_eig(hipStream_t s, int m, const double *A, double *U, double *w, double *work,
+                int32_t *info) {
+    TM_REQUIRE(m >= 1 && m <= 1024, TM_ENOTSUP, "eigensolver supports m <= 1024");
+    const int M = leading_dim(m);
+    const int nbk = M / BJ, nbp = nbk / 2;
+    double *Aw = work;
+    double *V = Aw + (size_t)M * M;
+    double *Q = V + (size_t)M * M;
+    double *partial = Q + (size_t)nbp * PJ * PJ;
+    JacState *st = reinterpret_cast<JacState *>(partial + kNormBlocks);
+    hipLaunchKernelGGL(bj_init, dim3(kNormBlocks), dim3(256), 0, s, m, M, A, Aw, V, partial);
+    hipLaunchKernelGGL(bj_norm, dim3(1), dim3(64), 0, s, partial, st);
+    TM_HIP(hipGetLastError());
+    const int kMaxSweeps = 16;
+    int32_t done = 0;
+    for (int sweep = 0; sweep < kMaxSweeps && !done; ++sweep) {
+        for (int step = 0; step < nbk - 1; ++step) {
+            hipLaunchKernelGGL(bj_solve, dim3(nbp), dim3(256), 0, s, M, step, Aw, Q, st);
+            hipLaunchKernelGGL(bj_apply, dim3(nbp * nbp), dim3(256), 0, s, M, step, Aw, V, Q, st);
+        }
+        hipLaunchKernelGGL(bj_check, dim3(1), dim3(1024), 0, s, M, Aw, st);
+        TM_HIP(hipGetLastError());
+        if (sweep >= 3) {   // the first sweeps never converge; poll afterwards
+            TM_HIP(hipMemcpyAsync(&done, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            TM_HIP(hipStreamSynchronize(s));
+        }
+    }
+    hipLaunchKernelGGL(bj_sort, dim3(1), dim3(1024), 0, s, m, M, Aw, V, U, w);
+    TM_HIP(hipGetLastError());
+    TM_HIP(hipMemcpyAsync(info, &st->sweeps, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace tmin

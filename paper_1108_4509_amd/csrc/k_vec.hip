@@ -62,15 +62,25 @@ __global__ __launch_bounds__(kDotThreads) void coldots_kernel(
     }
 }
 
-__global__ void coldots_reduce_kernel(int nprod, int nchunk, int ld,
-                                      const double *__restrict__ partials,
-                                      double *__restrict__ out) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nprod * ld) return;
-    const int p = idx / ld, j = idx - p * ld;
+// Final fixed-order reduction over row chunks: block (p, slab of 32 columns),
+// 8 lane groups stride over the chunks, then the 8 group sums are added in order.
+__global__ __launch_bounds__(256) void coldots_reduce_kernel(
+    int nchunk, int ld, const double *__restrict__ partials, double *__restrict__ out) {
+    __shared__ double red[8][33];
+    const int p = blockIdx.x;
+    const int t = threadIdx.x;
+    const int j = blockIdx.y * 32 + (t & 31);
+    const int g = t >> 5;
     double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += partials[((int64_t)p * nchunk + c) * ld + j];
-    out[idx] = s;
+    if (j < ld)
+        for (int c = g; c < nchunk; c += 8) s += partials[((int64_t)p * nchunk + c) * ld + j];
+    red[g][t & 31] = s;
+    __syncthreads();
+    if (t < 32 && j < ld) {
+        double v = 0.0;
+        for (int q = 0; q < 8; ++q) v += red[q][t];
+        out[(int64_t)p * ld + j] = v;
+    }
 }
 
 int dot_chunks(int64_t n) {
@@ -264,9 +274,8 @@ void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
     const int nslab = (ld + kDotThreads - 1) / kDotThreads;
     hipLaunchKernelGGL(coldots_kernel<T>, dim3(nchunk, nslab), dim3(kDotThreads), 0,
                        s, n, ld, rows, args, partials);
-    const int total = args.nprod * ld;
-    hipLaunchKernelGGL(coldots_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0,
-                       s, args.nprod, nchunk, ld, partials, out);
+    hipLaunchKernelGGL(coldots_reduce_kernel, dim3(args.nprod, (ld + 31) / 32), dim3(256), 0,
+                       s, nchunk, ld, partials, out);
     TM_HIP(hipGetLastError());
 }
 

@@ -420,7 +420,7 @@ tm_status tm_cholesky_inverse(tm_ctx *ctx, int32_t m, const double *S, double *R
     return guarded([&]() {
         TM_REQUIRE(S && Rinv, TM_EINVAL, "null argument");
         use_device(ctx);
-        TM_REQUIRE(m >= 1 && m <= 4096, TM_EINVAL, "m out of range");
+        TM_REQUIRE(m >= 1 && m <= 1024, TM_EINVAL, "m must be in [1, 1024]");
         DevMem cw(ctx, chol_workspace(m)), info(ctx, 16);
         TM_HIP(hipMemsetAsync(info.ptr, 0, 16, ctx->stream));
         chol_inverse(ctx->stream, m, S, Rinv, (double *)cw.ptr, (int32_t *)info.ptr);

@@ -258,7 +258,8 @@ def test_sym_eig_closed_form(ctx, tm):
     A = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
     w, _ = tm.sym_eig(ctx, torch.from_numpy(A).cuda())
     exact = np.sort(2 - 2 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
-    assert np.max(np.abs(host(w) - exact)) < 1e-13
+    # Jacobi is backward stable: |dw| <= c n u ||A||_F with a modest c
+    assert np.max(np.abs(host(w) - exact)) <= 64 * n * U64 * np.linalg.norm(A)
 
 
 # ------------------------------------------------------- full-size sampling

@@ -61,6 +61,16 @@ __device__ inline T velem(const typename Vec16<T>::type &v, int i) {
     return v[i];
 }
 
+// Inputs of the gradient traces fused into the EPI_GRAD epilogue
+// (partials == nullptr: no fusion); see rot() in tm_common.h.
+template <typename TO>
+struct GradDots {
+    const TO *Gp = nullptr;
+    const TO *Pp = nullptr;
+    const double *M = nullptr;
+    double *partials = nullptr;
+};
+
 // rows of A and B per LDS stage: the FP32 instruction is twice as fast, so
 // it gets twice the rows per synchronization
 template <typename TM> constexpr int stage_rows() { return sizeof(TM) == 4 ? 32 : 16; }
@@ -213,6 +223,7 @@ __global__ void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
     int64_t src = idx;
     if (symmetric && (i / BM) > (j / BM)) src = (int64_t)j * m + i;
     double s = 0.0;
+#pragma unroll 8
     for (int p = 0; p < nsplit; ++p) s += partials[(int64_t)p * m * m + src];
     if (zero_diag && i == j) s = 0.0;
     out[idx] = s;
@@ -243,7 +254,7 @@ template <typename TA, typename TM, typename TO, int EPI, int BR, int BC>
 __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TM *__restrict__ W,
     const TA *__restrict__ X, const double *__restrict__ vec, TO *__restrict__ out,
-    int nrb, int ncb) {
+    int nrb, int ncb, GradDots<TO> gd) {
     constexpr int KT = stage_rows<TM>();
     constexpr int WR = BR / 2, WC = BC / 2;
     constexpr int NBR = WR / 16, NBC = WC / 16;
@@ -335,6 +346,14 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
         buf ^= 1;
     }
 
+    // column sums of the fused gradient traces: [dot][column block]
+    double dsum[EPI == EPI_GRAD ? 4 : 1][NBC];
+#pragma unroll
+    for (int p = 0; p < (EPI == EPI_GRAD ? 4 : 1); ++p)
+#pragma unroll
+        for (int b = 0; b < NBC; ++b) dsum[p][b] = 0.0;
+    const bool fuse = (EPI == EPI_GRAD) && gd.partials != nullptr;
+
 #pragma unroll
     for (int a = 0; a < NBR; ++a)
 #pragma unroll
@@ -350,11 +369,44 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
                     out[e] = (TO)v;
                 } else if constexpr (EPI == EPI_GRAD) {
                     const TA xp = X[e] - A[e] * (TA)vec[col];
-                    out[e] = (TO)((TA)-2 * (xp - v));
+                    const TO g = (TO)((TA)-2 * (xp - v));
+                    out[e] = g;
+                    if (fuse) {
+                        const double gv = (double)g;
+                        const double w = gd.M ? gd.M[row] : 1.0;
+                        dsum[0][b] += gv * gv;
+                        dsum[1][b] += w * gv * gv;
+                        dsum[2][b] += w * (double)gd.Gp[e] * gv;
+                        dsum[3][b] += (double)gd.Pp[e] * gv;
+                    }
                 } else {
                     out[e] = (TO)(A[e] * (TA)vec[col] + v);
                 }
             }
+
+    if constexpr (EPI == EPI_GRAD) {
+        if (fuse) {
+            // lanes l, l^16, l^32, l^48 share a column; then the two waves of a
+            // column half (wr = 0, 1) meet in LDS; fixed order throughout
+            __shared__ double dred[2][4][BC];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int b = 0; b < NBC; ++b) {
+                    double x = dsum[p][b];
+                    x += __shfl_xor(x, 16);
+                    x += __shfl_xor(x, 32);
+                    if (lane < 16) dred[wr][p][wc * WC + b * 16 + lane] = x;
+                }
+            __syncthreads();
+            for (int e = tid; e < 4 * BC; e += kThreads) {
+                const int p = e / BC, cc = e - (e / BC) * BC;
+                const int col = c0 + cc;
+                if (col < ld)
+                    gd.partials[((int64_t)p * nrb + rb) * ld + col] = dred[0][p][cc] + dred[1][p][cc];
+            }
+        }
+    }
 }
 
 template <typename TM>
@@ -408,17 +460,23 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
 }
 
 template <typename TA, typename TM, typename TO>
-void rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
-         const TA *X, const double *vec, TO *out) {
+int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
+        const TA *X, const double *vec, TO *out, const TO *Gp, const TO *Pp,
+        const double *M, double *partials) {
     const int ld = leading_dim(m);
     const int B = ld >= 256 ? 128 : 64;
     const int nrb = (int)((n + B - 1) / B);
     const int ncb = (ld + B - 1) / B;
     int grid = nrb * ncb;
     grid = (grid + 7) / 8 * 8;
+    GradDots<TO> gd;
+    gd.Gp = Gp;
+    gd.Pp = Pp;
+    gd.M = M;
+    gd.partials = (epi == EPI_GRAD) ? partials : nullptr;
 #define TM_ROT(E, BB)                                                                      \
     hipLaunchKernelGGL((rot_kernel<TA, TM, TO, E, BB, BB>), dim3(grid), dim3(kThreads), \
-                       0, s, n, m, ld, A, Wpad, X, vec, out, nrb, ncb)
+                       0, s, n, m, ld, A, Wpad, X, vec, out, nrb, ncb, gd)
     if (B == 128) {
         if (epi == EPI_NONE) TM_ROT(EPI_NONE, 128);
         else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 128);
@@ -430,6 +488,13 @@ void rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
     }
 #undef TM_ROT
     TM_HIP(hipGetLastError());
+    return nrb;
+}
+
+size_t rot_partials_workspace(int64_t n, int m) {
+    const int ld = leading_dim(m);
+    const int B = ld >= 256 ? 128 : 64;
+    return (size_t)4 * ((n + B - 1) / B) * ld * sizeof(double);
 }
 
 template <typename TM>
@@ -445,10 +510,10 @@ void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
 template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool);
 template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool);
 template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool);
-template void rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *);
-template void rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *);
-template void rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *);
-template void rot<double, float, double>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, double *);
+template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *);
+template int rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *, const float *, const float *, const double *, double *);
+template int rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *, const float *, const float *, const double *, double *);
+template int rot<double, float, double>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, double *, const double *, const double *, const double *, double *);
 template void pad_matrix<double>(hipStream_t, int, const double *, bool, double *, double *);
 template void pad_matrix<float>(hipStream_t, int, const double *, bool, float *, double *);
 

@@ -1,4 +1,8 @@
-// Sparse product X = H C (Fig. 2, step (1)) for row-major N x ld blocks.
+// Sparse product X = H C (Fig. 2, step (1)) for row-major N x ld blocks, with
+// optional column dot products of the input and output fused into the
+// epilogue: h_j = c_j . x_j (Fig. 2, steps (2)-(3)) after X = HC, and
+// p_j . p_j, p_j . y_j (the line step) after Y = HP.  The fusion saves a full
+// pass over both blocks.
 //
 // HBM-bound: every row of C is gathered by its neighbours' rows, so the
 // kernels keep each XCD on one contiguous slab of rows (neighbour rows then
@@ -8,30 +12,19 @@
 namespace tmin {
 namespace {
 
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Vec;
-template <> struct Vec<double> { using type = double2; static constexpr int W = 2; };
-template <> struct Vec<float> { using type = float4; static constexpr int W = 4; };
+template <> struct Vec<double> { using type = vd2; static constexpr int W = 2; };
+template <> struct Vec<float> { using type = vf4; static constexpr int W = 4; };
 
-__device__ inline double2 fma_v(double a, double2 c, double2 acc) {
-    acc.x = fma(a, c.x, acc.x);
-    acc.y = fma(a, c.y, acc.y);
-    return acc;
-}
-__device__ inline float4 fma_v(float a, float4 c, float4 acc) {
-    acc.x = fmaf(a, c.x, acc.x);
-    acc.y = fmaf(a, c.y, acc.y);
-    acc.z = fmaf(a, c.z, acc.z);
-    acc.w = fmaf(a, c.w, acc.w);
-    return acc;
-}
-template <typename V> __device__ inline V zero_v();
-template <> __device__ inline double2 zero_v<double2>() { return make_double2(0.0, 0.0); }
-template <> __device__ inline float4 zero_v<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+constexpr int kMaxCv = 2;     // column vectors per lane (ld <= 1024)
+constexpr int kGridCap = 1024;
 
-// Launch geometry shared by both kernels: a workgroup of 256 lanes holds
-// `rpb` rows at once with `tpr` lanes per row (each lane loops over the
-// row's vectors with stride tpr).  Workgroup b runs on XCD b % 8; it is given
-// the contiguous row range of logical slab (b % 8) * (grid / 8) + b / 8.
+// Launch geometry: a workgroup of 256 lanes holds `rpb` rows at once with
+// `tpr` lanes per row (each lane loops over the row's vectors with stride
+// tpr).  Workgroup b runs on XCD b % 8; it is given the contiguous row range
+// of logical slab (b % 8) * (grid / 8) + b / 8.
 struct Geometry {
     int tpr, rpb;
     int64_t rows_per_block;
@@ -42,8 +35,8 @@ Geometry geometry(int64_t n, int ldv) {
     Geometry g;
     g.tpr = ldv < 256 ? ldv : 256;
     g.rpb = 256 / g.tpr;
-    int64_t blocks = (n + g.rpb * 4 - 1) / (g.rpb * 4);  // ~4 row passes per block
-    if (blocks > 8192) blocks = 8192;
+    int64_t blocks = (n + g.rpb - 1) / g.rpb;
+    if (blocks > kGridCap) blocks = kGridCap;
     blocks = (blocks + 7) / 8 * 8;
     g.rows_per_block = (n + blocks - 1) / blocks;
     g.grid = (int)((n + g.rows_per_block - 1) / g.rows_per_block);
@@ -56,35 +49,104 @@ __device__ inline int64_t logical_block(int grid) {
     return (int64_t)(b & 7) * (grid >> 3) + (b >> 3);
 }
 
+template <typename V, typename T>
+__device__ inline V fma_v(T a, V c, V acc) {
+#pragma unroll
+    for (int w = 0; w < Vec<T>::W; ++w) acc[w] = fma(a, c[w], acc[w]);
+    return acc;
+}
+
+// Per-lane FP64 accumulators of the fused dots: [cv slot][dot][vector element]
+template <typename T>
+struct DotAcc {
+    double v[kMaxCv][2][Vec<T>::W];
+    __device__ void zero() {
+#pragma unroll
+        for (int q = 0; q < kMaxCv; ++q)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int w = 0; w < Vec<T>::W; ++w) v[q][p][w] = 0.0;
+    }
+    // dot 0: a . b, dot 1: a . a
+    __device__ void add(int q, const typename Vec<T>::type &a, const typename Vec<T>::type &b,
+                        int ndot) {
+#pragma unroll
+        for (int w = 0; w < Vec<T>::W; ++w) {
+            const double x = (double)a[w], y = (double)b[w];
+            v[q][0][w] += x * y;
+            if (ndot > 1) v[q][1][w] += x * x;
+        }
+    }
+};
+
+// Fold the per-lane sums over the rows of the workgroup (fixed order) and
+// write partials[(p * grid + lb) * ld + col].
+template <typename T>
+__device__ void flush_dots(const DotAcc<T> &acc, int ndot, int rr, int lane, int tpr, int rpb,
+                           int ldv, int64_t lb, double *__restrict__ partials, double *red) {
+    constexpr int W = Vec<T>::W;
+    const int ld = ldv * W;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        if (p >= ndot) break;
+        if (rr < rpb) {
+#pragma unroll
+            for (int q = 0; q < kMaxCv; ++q) {
+                const int cv = lane + q * tpr;
+                if (cv < ldv)
+#pragma unroll
+                    for (int w = 0; w < W; ++w) red[rr * ld + cv * W + w] = acc.v[q][p][w];
+            }
+        }
+        __syncthreads();
+        for (int col = t; col < ld; col += 256) {
+            double s = 0.0;
+            for (int g = 0; g < rpb; ++g) s += red[g * ld + col];
+            partials[((int64_t)p * gridDim.x + lb) * ld + col] = s;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void spmm_csr_kernel(
     int64_t n, int ldv, int tpr, int rpb, int64_t rows_per_block,
     const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     const T *__restrict__ val, const typename Vec<T>::type *__restrict__ C,
-    typename Vec<T>::type *__restrict__ X) {
+    typename Vec<T>::type *__restrict__ X, int ndot, double *__restrict__ partials) {
     using V = typename Vec<T>::type;
+    __shared__ double red[1024];
     const int t = threadIdx.x;
     const int rr = t / tpr;
     const int lane = t - rr * tpr;
-    if (rr >= rpb) return;
     const int64_t lb = logical_block(gridDim.x);
     const int64_t r_begin = lb * rows_per_block;
     int64_t r_end = r_begin + rows_per_block;
     if (r_end > n) r_end = n;
-    for (int64_t r = r_begin + rr; r < r_end; r += rpb) {
-        const int64_t k0 = rowptr[r], k1 = rowptr[r + 1];
-        for (int cv = lane; cv < ldv; cv += tpr) {
-            V acc = zero_v<V>();
-            for (int64_t k = k0; k < k1; ++k)
-                acc = fma_v(val[k], C[(int64_t)col[k] * ldv + cv], acc);
-            X[r * ldv + cv] = acc;
+    DotAcc<T> dacc;
+    dacc.zero();
+    if (rr < rpb) {
+        for (int64_t r = r_begin + rr; r < r_end; r += rpb) {
+            const int64_t k0 = rowptr[r], k1 = rowptr[r + 1];
+#pragma unroll
+            for (int q = 0; q < kMaxCv; ++q) {
+                const int cv = lane + q * tpr;
+                if (cv >= ldv) break;
+                V acc = V(0);
+                for (int64_t k = k0; k < k1; ++k)
+                    acc = fma_v<V, T>(val[k], C[(int64_t)col[k] * ldv + cv], acc);
+                X[r * ldv + cv] = acc;
+                if (ndot > 0) dacc.add(q, C[r * ldv + cv], acc, ndot);
+            }
         }
     }
+    if (ndot > 0) flush_dots<T>(dacc, ndot, rr, lane, tpr, rpb, ldv, lb, partials, red);
 }
 
 // Neighbour index along one axis with periodic wrap or Dirichlet cut-off.
-__device__ inline bool neighbour(int coord, int off, int extent, int periodic,
-                                 int &out) {
+__device__ inline bool neighbour(int coord, int off, int extent, int periodic, int &out) {
     int c = coord + off;
     if (periodic) {
         c %= extent;
@@ -98,15 +160,14 @@ __device__ inline bool neighbour(int coord, int off, int extent, int periodic,
 
 template <typename T, int ORDER, int NDIM>
 __global__ __launch_bounds__(256) void spmm_stencil_kernel(
-    int64_t n, int ldv, int tpr, int rpb, int64_t rows_per_block,
-    StencilDev H, const T *__restrict__ V,
-    const typename Vec<T>::type *__restrict__ C,
-    typename Vec<T>::type *__restrict__ X) {
-    using Vv = typename Vec<T>::type;
+    int64_t n, int ldv, int tpr, int rpb, int64_t rows_per_block, StencilDev H,
+    const T *__restrict__ Vpot, const typename Vec<T>::type *__restrict__ C,
+    typename Vec<T>::type *__restrict__ X, int ndot, double *__restrict__ partials) {
+    using V = typename Vec<T>::type;
+    __shared__ double red[1024];
     const int t = threadIdx.x;
     const int rr = t / tpr;
     const int lane = t - rr * tpr;
-    if (rr >= rpb) return;
     const T c0 = (T)H.c0, c1 = (T)H.c1, c2 = (T)H.c2;
     const int64_t lb = logical_block(gridDim.x);
     const int64_t r_begin = lb * rows_per_block;
@@ -114,58 +175,298 @@ __global__ __launch_bounds__(256) void spmm_stencil_kernel(
     if (r_end > n) r_end = n;
     const int ext[3] = {H.nx, H.ny, H.nz};
     const int64_t stride[3] = {1, (int64_t)H.nx, (int64_t)H.nx * H.ny};
-    for (int64_t r = r_begin + rr; r < r_end; r += rpb) {
-        int crd[3];
-        crd[0] = (int)(r % H.nx);
-        crd[1] = (int)((r / H.nx) % H.ny);
-        crd[2] = NDIM == 3 ? (int)(r / ((int64_t)H.nx * H.ny)) : 0;
-        const T diag = c0 + (V ? V[r] : (T)0);
-        for (int cv = lane; cv < ldv; cv += tpr) {
-            Vv acc = fma_v(diag, C[r * ldv + cv], zero_v<Vv>());
+    DotAcc<T> dacc;
+    dacc.zero();
+    if (rr < rpb) {
+        for (int64_t r = r_begin + rr; r < r_end; r += rpb) {
+            int crd[3];
+            crd[0] = (int)(r % H.nx);
+            crd[1] = (int)((r / H.nx) % H.ny);
+            crd[2] = NDIM == 3 ? (int)(r / ((int64_t)H.nx * H.ny)) : 0;
+            const T diag = c0 + (Vpot ? Vpot[r] : (T)0);
+            int64_t nb[3][4];
+            bool has[3][4];
 #pragma unroll
             for (int ax = 0; ax < NDIM; ++ax) {
+                int s = 0;
 #pragma unroll
                 for (int o = -ORDER / 2; o <= ORDER / 2; ++o) {
                     if (o == 0) continue;
                     int c;
-                    if (!neighbour(crd[ax], o, ext[ax], H.periodic, c)) continue;
-                    const int64_t nb = r + (int64_t)(c - crd[ax]) * stride[ax];
-                    const T coef = (o == 1 || o == -1) ? c1 : c2;
-                    acc = fma_v(coef, C[nb * ldv + cv], acc);
+                    has[ax][s] = neighbour(crd[ax], o, ext[ax], H.periodic, c);
+                    nb[ax][s] = r + (int64_t)(c - crd[ax]) * stride[ax];
+                    ++s;
                 }
             }
-            X[r * ldv + cv] = acc;
+#pragma unroll
+            for (int q = 0; q < kMaxCv; ++q) {
+                const int cv = lane + q * tpr;
+                if (cv >= ldv) break;
+                const V center = C[r * ldv + cv];
+                V acc = fma_v<V, T>(diag, center, V(0));
+#pragma unroll
+                for (int ax = 0; ax < NDIM; ++ax) {
+                    int s = 0;
+#pragma unroll
+                    for (int o = -ORDER / 2; o <= ORDER / 2; ++o) {
+                        if (o == 0) continue;
+                        const T coef = (o == 1 || o == -1) ? c1 : c2;
+                        if (has[ax][s]) acc = fma_v<V, T>(coef, C[nb[ax][s] * ldv + cv], acc);
+                        ++s;
+                    }
+                }
+                X[r * ldv + cv] = acc;
+                if (ndot > 0) dacc.add(q, center, acc, ndot);
+            }
         }
     }
+    if (ndot > 0) flush_dots<T>(dacc, ndot, rr, lane, tpr, rpb, ldv, lb, partials, red);
+}
+
+// Wide blocks (at least 64 vectors per row): one wave per row at a time, so
+// the row index, its CSR range, column indices and values are wave-uniform
+// and come through the scalar cache; each lane owns NCV vectors of the row.
+// The four waves of a workgroup walk interleaved rows of its slab.
+template <typename T, int NCV>
+__device__ void flush_wave_dots(const double (&ds)[NCV][2][Vec<T>::W], int ndot, int wave, int lane,
+                                int64_t lb, double *__restrict__ partials, double *red) {
+    constexpr int W = Vec<T>::W;
+    constexpr int ld = NCV * 64 * W;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        if (p >= ndot) break;
+#pragma unroll
+        for (int q = 0; q < NCV; ++q)
+#pragma unroll
+            for (int w = 0; w < W; ++w) red[wave * ld + (lane + 64 * q) * W + w] = ds[q][p][w];
+        __syncthreads();
+        for (int col = t; col < ld; col += 256) {
+            const double sum = ((red[col] + red[ld + col]) + red[2 * ld + col]) + red[3 * ld + col];
+            partials[((int64_t)p * gridDim.x + lb) * ld + col] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NCV>
+__global__ __launch_bounds__(256) void spmm_csr_wave_kernel(
+    int64_t n, int64_t rows_per_block, const int64_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const T *__restrict__ val,
+    const typename Vec<T>::type *__restrict__ C, typename Vec<T>::type *__restrict__ X,
+    int ndot, double *__restrict__ partials) {
+    using V = typename Vec<T>::type;
+    constexpr int W = Vec<T>::W;
+    constexpr int ldv = NCV * 64;
+    __shared__ double red[4 * ldv * W];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t lb = logical_block(gridDim.x);
+    const int64_t r_begin = lb * rows_per_block;
+    int64_t r_end = r_begin + rows_per_block;
+    if (r_end > n) r_end = n;
+    double ds[NCV][2][W];
+#pragma unroll
+    for (int q = 0; q < NCV; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int w = 0; w < W; ++w) ds[q][p][w] = 0.0;
+    for (int64_t r = r_begin + wave; r < r_end; r += 4) {
+        const int64_t k0 = rowptr[r], k1 = rowptr[r + 1];
+        V acc[NCV];
+#pragma unroll
+        for (int q = 0; q < NCV; ++q) acc[q] = V(0);
+        // U nonzeros at a time keep U * NCV vector loads in flight
+        constexpr int U = NCV >= 4 ? 1 : 4;
+        int64_t k = k0;
+        for (; k + U <= k1; k += U) {
+            V v[U][NCV];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const V *src = C + (int64_t)col[k + u] * ldv + lane;
+#pragma unroll
+                for (int q = 0; q < NCV; ++q) v[u][q] = src[64 * q];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < NCV; ++q) acc[q] = fma_v<V, T>(val[k + u], v[u][q], acc[q]);
+        }
+        for (; k < k1; ++k) {
+            const V *src = C + (int64_t)col[k] * ldv + lane;
+#pragma unroll
+            for (int q = 0; q < NCV; ++q) acc[q] = fma_v<V, T>(val[k], src[64 * q], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NCV; ++q) X[r * ldv + lane + 64 * q] = acc[q];
+        if (ndot > 0) {
+#pragma unroll
+            for (int q = 0; q < NCV; ++q) {
+                const V c = C[r * ldv + lane + 64 * q];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    ds[q][0][w] += (double)c[w] * (double)acc[q][w];
+                    if (ndot > 1) ds[q][1][w] += (double)c[w] * (double)c[w];
+                }
+            }
+        }
+    }
+    if (ndot > 0) flush_wave_dots<T, NCV>(ds, ndot, wave, lane, lb, partials, red);
+}
+
+template <typename T, int NCV, int ORDER, int NDIM>
+__global__ __launch_bounds__(256) void spmm_stencil_wave_kernel(
+    int64_t n, int64_t rows_per_block, StencilDev H, const T *__restrict__ Vpot,
+    const typename Vec<T>::type *__restrict__ C, typename Vec<T>::type *__restrict__ X,
+    int ndot, double *__restrict__ partials) {
+    using V = typename Vec<T>::type;
+    constexpr int W = Vec<T>::W;
+    constexpr int ldv = NCV * 64;
+    __shared__ double red[4 * ldv * W];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const T c0 = (T)H.c0, c1 = (T)H.c1, c2 = (T)H.c2;
+    const int64_t lb = logical_block(gridDim.x);
+    const int64_t r_begin = lb * rows_per_block;
+    int64_t r_end = r_begin + rows_per_block;
+    if (r_end > n) r_end = n;
+    const int ext[3] = {H.nx, H.ny, H.nz};
+    const int64_t stride[3] = {1, (int64_t)H.nx, (int64_t)H.nx * H.ny};
+    double ds[NCV][2][W];
+#pragma unroll
+    for (int q = 0; q < NCV; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int w = 0; w < W; ++w) ds[q][p][w] = 0.0;
+    for (int64_t r = r_begin + wave; r < r_end; r += 4) {
+        int crd[3];
+        crd[0] = (int)(r % H.nx);
+        crd[1] = (int)((r / H.nx) % H.ny);
+        crd[2] = NDIM == 3 ? (int)(r / ((int64_t)H.nx * H.ny)) : 0;
+        const T diag = c0 + (Vpot ? Vpot[r] : (T)0);
+        V center[NCV], acc[NCV];
+#pragma unroll
+        for (int q = 0; q < NCV; ++q) {
+            center[q] = C[r * ldv + lane + 64 * q];
+            acc[q] = fma_v<V, T>(diag, center[q], V(0));
+        }
+#pragma unroll
+        for (int ax = 0; ax < NDIM; ++ax) {
+#pragma unroll
+            for (int o = -ORDER / 2; o <= ORDER / 2; ++o) {
+                if (o == 0) continue;
+                int c;
+                if (!neighbour(crd[ax], o, ext[ax], H.periodic, c)) continue;
+                const int64_t nb = r + (int64_t)(c - crd[ax]) * stride[ax];
+                const T coef = (o == 1 || o == -1) ? c1 : c2;
+#pragma unroll
+                for (int q = 0; q < NCV; ++q)
+                    acc[q] = fma_v<V, T>(coef, C[nb * ldv + lane + 64 * q], acc[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NCV; ++q) {
+            X[r * ldv + lane + 64 * q] = acc[q];
+            if (ndot > 0) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    ds[q][0][w] += (double)center[q][w] * (double)acc[q][w];
+                    if (ndot > 1) ds[q][1][w] += (double)center[q][w] * (double)center[q][w];
+                }
+            }
+        }
+    }
+    if (ndot > 0) flush_wave_dots<T, NCV>(ds, ndot, wave, lane, lb, partials, red);
+}
+
+// grid for the wave kernels: ~kGridCap workgroups of 4 waves, multiple of 8
+Geometry wave_geometry(int64_t n) {
+    Geometry g;
+    g.tpr = 64;
+    g.rpb = 4;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > kGridCap) blocks = kGridCap;
+    blocks = (blocks + 7) / 8 * 8;
+    g.rows_per_block = (n + blocks - 1) / blocks;
+    g.grid = (int)((n + g.rows_per_block - 1) / g.rows_per_block);
+    g.grid = (g.grid + 7) / 8 * 8;
+    return g;
 }
 
 }  // namespace
 
+size_t spmm_partials_workspace(int ld) { return (size_t)2 * (kGridCap + 8) * ld * sizeof(double); }
+
 template <typename T>
-void spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X) {
+int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
+             double *partials) {
     const int ldv = ld / Vec<T>::W;
+    TM_REQUIRE(ldv <= kMaxCv * 256, TM_ENOTSUP, "block too wide for the SpMM kernel");
     Geometry g = geometry(H.n, ldv);
     const T *val;
     if constexpr (sizeof(T) == 8) val = H.val64; else val = H.val32;
-    hipLaunchKernelGGL(spmm_csr_kernel<T>, dim3(g.grid), dim3(256), 0, s, H.n,
-                       ldv, g.tpr, g.rpb, g.rows_per_block, H.rowptr, H.col, val,
-                       reinterpret_cast<const typename Vec<T>::type *>(C),
-                       reinterpret_cast<typename Vec<T>::type *>(X));
+    auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
+    auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
+    if (ldv % 64 == 0 && ldv <= 512) {
+        Geometry w = wave_geometry(H.n);
+#define TM_CSR_WAVE(NCV)                                                                   \
+    hipLaunchKernelGGL((spmm_csr_wave_kernel<T, NCV>), dim3(w.grid), dim3(256), 0, s, H.n, \
+                       w.rows_per_block, H.rowptr, H.col, val, Cv, Xv, ndot, partials)
+        switch (ldv / 64) {
+        case 1: TM_CSR_WAVE(1); break;
+        case 2: TM_CSR_WAVE(2); break;
+        case 4: TM_CSR_WAVE(4); break;
+        case 8: TM_CSR_WAVE(8); break;
+        default: goto generic;
+        }
+#undef TM_CSR_WAVE
+        TM_HIP(hipGetLastError());
+        return w.grid;
+    }
+generic:
+    hipLaunchKernelGGL(spmm_csr_kernel<T>, dim3(g.grid), dim3(256), 0, s, H.n, ldv, g.tpr, g.rpb,
+                       g.rows_per_block, H.rowptr, H.col, val, Cv, Xv, ndot, partials);
     TM_HIP(hipGetLastError());
+    return g.grid;
 }
 
 template <typename T>
-void spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld,
-                  const T *C, T *X) {
+int spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld, const T *C, T *X,
+                 int ndot, double *partials) {
     const int ldv = ld / Vec<T>::W;
+    TM_REQUIRE(ldv <= kMaxCv * 256, TM_ENOTSUP, "block too wide for the SpMM kernel");
     Geometry g = geometry(n, ldv);
-    const T *V;
-    if constexpr (sizeof(T) == 8) V = H.V64; else V = H.V32;
+    const T *Vp;
+    if constexpr (sizeof(T) == 8) Vp = H.V64; else Vp = H.V32;
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
     auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
-#define TM_STENCIL_LAUNCH(ORD, ND)                                                 \
-    hipLaunchKernelGGL((spmm_stencil_kernel<T, ORD, ND>), dim3(g.grid), dim3(256), \
-                       0, s, n, ldv, g.tpr, g.rpb, g.rows_per_block, H, V, Cv, Xv)
+    const int ncv = ldv / 64;
+    if (ldv % 64 == 0 && (ncv == 1 || ncv == 2 || ncv == 4 || ncv == 8)) {
+        Geometry w = wave_geometry(n);
+#define TM_STW(NCV, ORD, ND)                                                                 \
+    hipLaunchKernelGGL((spmm_stencil_wave_kernel<T, NCV, ORD, ND>), dim3(w.grid), dim3(256), 0, \
+                       s, n, w.rows_per_block, H, Vp, Cv, Xv, ndot, partials)
+#define TM_STW_ORD(NCV)                                                                      \
+    if (H.ndim == 3 && H.order == 2) TM_STW(NCV, 2, 3);                                      \
+    else if (H.ndim == 3 && H.order == 4) TM_STW(NCV, 4, 3);                                 \
+    else if (H.ndim == 2 && H.order == 2) TM_STW(NCV, 2, 2);                                 \
+    else TM_STW(NCV, 4, 2);
+        switch (ncv) {
+        case 1: TM_STW_ORD(1); break;
+        case 2: TM_STW_ORD(2); break;
+        case 4: TM_STW_ORD(4); break;
+        default: TM_STW_ORD(8); break;
+        }
+#undef TM_STW_ORD
+#undef TM_STW
+        TM_HIP(hipGetLastError());
+        return w.grid;
+    }
+#define TM_STENCIL_LAUNCH(ORD, ND)                                                         \
+    hipLaunchKernelGGL((spmm_stencil_kernel<T, ORD, ND>), dim3(g.grid), dim3(256), 0, s, n, \
+                       ldv, g.tpr, g.rpb, g.rows_per_block, H, Vp, Cv, Xv, ndot, partials)
     if (H.ndim == 3 && H.order == 2) TM_STENCIL_LAUNCH(2, 3);
     else if (H.ndim == 3 && H.order == 4) TM_STENCIL_LAUNCH(4, 3);
     else if (H.ndim == 2 && H.order == 2) TM_STENCIL_LAUNCH(2, 2);
@@ -173,11 +474,12 @@ void spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld,
     else throw Error{TM_EINVAL, "unsupported stencil"};
 #undef TM_STENCIL_LAUNCH
     TM_HIP(hipGetLastError());
+    return g.grid;
 }
 
-template void spmm_csr<double>(hipStream_t, const CsrDev &, int, const double *, double *);
-template void spmm_csr<float>(hipStream_t, const CsrDev &, int, const float *, float *);
-template void spmm_stencil<double>(hipStream_t, const StencilDev &, int64_t, int, const double *, double *);
-template void spmm_stencil<float>(hipStream_t, const StencilDev &, int64_t, int, const float *, float *);
+template int spmm_csr<double>(hipStream_t, const CsrDev &, int, const double *, double *, int, double *);
+template int spmm_csr<float>(hipStream_t, const CsrDev &, int, const float *, float *, int, double *);
+template int spmm_stencil<double>(hipStream_t, const StencilDev &, int64_t, int, const double *, double *, int, double *);
+template int spmm_stencil<float>(hipStream_t, const StencilDev &, int64_t, int, const float *, float *, int, double *);
 
 }  // namespace tmin

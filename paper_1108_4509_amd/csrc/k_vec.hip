@@ -63,22 +63,26 @@ __global__ __launch_bounds__(kDotThreads) void coldots_kernel(
 }
 
 // Final fixed-order reduction over row chunks: block (p, slab of 32 columns),
-// 8 lane groups stride over the chunks, then the 8 group sums are added in order.
-__global__ __launch_bounds__(256) void coldots_reduce_kernel(
+// 32 lane groups stride over the chunks (loads unrolled to keep many in
+// flight), then the group sums are added in order.
+__global__ __launch_bounds__(1024) void coldots_reduce_kernel(
     int nchunk, int ld, const double *__restrict__ partials, double *__restrict__ out) {
-    __shared__ double red[8][33];
+    __shared__ double red[32][33];
     const int p = blockIdx.x;
     const int t = threadIdx.x;
     const int j = blockIdx.y * 32 + (t & 31);
     const int g = t >> 5;
     double s = 0.0;
-    if (j < ld)
-        for (int c = g; c < nchunk; c += 8) s += partials[((int64_t)p * nchunk + c) * ld + j];
+    if (j < ld) {
+        const double *base = partials + (int64_t)p * nchunk * ld + j;
+#pragma unroll 8
+        for (int c = g; c < nchunk; c += 32) s += base[(int64_t)c * ld];
+    }
     red[g][t & 31] = s;
     __syncthreads();
     if (t < 32 && j < ld) {
         double v = 0.0;
-        for (int q = 0; q < 8; ++q) v += red[q][t];
+        for (int q = 0; q < 32; ++q) v += red[q][t];
         out[(int64_t)p * ld + j] = v;
     }
 }
@@ -226,15 +230,16 @@ __global__ __launch_bounds__(256) void control_gamma_kernel(
 
 // Controller, part 2 (after Y = HP): step length from the second-order model
 // curvature = 2 sum_j (p_j.y_j - h_j p_j.p_j), capped at 1 / max_j |p_j|.
+// dots2 rows: 0 p_j.y_j, 1 p_j.p_j.
 __global__ __launch_bounds__(256) void control_alpha_kernel(
     int m, int ld, const double *__restrict__ h, const double *__restrict__ dots2,
     CgState *st) {
     __shared__ double red[256];
-    const double ppmax = block_max(dots2, m, red);
+    const double ppmax = block_max(dots2 + ld, m, red);
     // curvature terms, summed in a fixed order
     double local = 0.0;
     for (int j = threadIdx.x; j < m; j += 256)
-        local += dots2[ld + j] - h[j] * dots2[j];
+        local += dots2[j] - h[j] * dots2[ld + j];
     red[threadIdx.x] = local;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
@@ -274,8 +279,14 @@ void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
     const int nslab = (ld + kDotThreads - 1) / kDotThreads;
     hipLaunchKernelGGL(coldots_kernel<T>, dim3(nchunk, nslab), dim3(kDotThreads), 0,
                        s, n, ld, rows, args, partials);
-    hipLaunchKernelGGL(coldots_reduce_kernel, dim3(args.nprod, (ld + 31) / 32), dim3(256), 0,
-                       s, nchunk, ld, partials, out);
+    reduce_partials(s, args.nprod, nchunk, ld, partials, out);
+    TM_HIP(hipGetLastError());
+}
+
+void reduce_partials(hipStream_t s, int nprod, int nchunk, int ld, const double *partials,
+                     double *out) {
+    hipLaunchKernelGGL(coldots_reduce_kernel, dim3(nprod, (ld + 31) / 32), dim3(1024), 0, s,
+                       nchunk, ld, partials, out);
     TM_HIP(hipGetLastError());
 }
 

@@ -360,12 +360,10 @@ tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t precis
         const int ld = leading_dim(m);
         const int64_t n = H->n;
         hipStream_t s = ctx->stream;
-        DevMem hv(ctx, ld * sizeof(double)), dws(ctx, coldots_workspace(n, ld)),
+        DevMem hv(ctx, ld * sizeof(double)), dws(ctx, spmm_partials_workspace(ld)),
             gws(ctx, gram_workspace(n, m)), wp(ctx, (size_t)ld * ld * sizeof(double));
-        spmm_any(s, H, ld, C, X, true);
-        DotArgs<double> a;
-        a.nprod = 1; a.a[0] = C; a.b[0] = X;
-        coldots<double>(s, n, ld, a, (double *)dws.ptr, (double *)hv.ptr);
+        const int nch = spmm_any(s, H, ld, C, X, true, 1, (double *)dws.ptr);
+        reduce_partials(s, 1, nch, ld, (double *)dws.ptr, (double *)hv.ptr);
         if (precision == TM_FULL_DP) {
             gram<double, double>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp);
             pad_matrix<double>(s, m, Hp, false, (double *)wp.ptr, nullptr);

@@ -77,11 +77,21 @@ struct StencilDev {
     const double *V64 = nullptr;
     const float *V32 = nullptr;
 };
+// ndot = 0: X = H C only.  ndot = 1: also per-workgroup partial sums of
+// c_j . x_j; ndot = 2: of c_j . x_j and c_j . c_j, written to
+// partials[(p * nchunk + chunk) * ld + j].  Returns nchunk (for
+// reduce_partials).  partials needs spmm_partials_workspace(ld) bytes.
+size_t spmm_partials_workspace(int ld);
 template <typename T>
-void spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X);
+int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
+             double *partials);
 template <typename T>
-void spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld,
-                  const T *C, T *X);
+int spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld,
+                 const T *C, T *X, int ndot, double *partials);
+// out[p * ld + j] = sum over chunks of partials[(p * nchunk + c) * ld + j],
+// in a fixed order.
+void reduce_partials(hipStream_t s, int nprod, int nchunk, int ld,
+                     const double *partials, double *out);
 
 // Column dot products ----------------------------------------------------
 // out[p * ld + j] = sum_r w_p(r) * f_p(a_p[r, j], b_p[r, j]) for p < nprod,
@@ -115,9 +125,16 @@ enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2 };
 // EPI_NONE:  out = A W
 // EPI_GRAD:  out = -2 ((X - A diag(h)) - A W)          (Fig. 2, step (7))
 // EPI_TRMM:  out = A diag(d) + A W, W strictly upper   (Eq. 13)
+// With EPI_GRAD and partials != nullptr the epilogue also accumulates, per
+// output column j, the traces of the Polak-Ribiere step (Eq. 8) and the descent
+// test: p = 0: g.g, 1: g.(M g), 2: g_prev.(M g), 3: p_prev.g, written to
+// partials[(p * nchunk + chunk) * ld + j]; returns nchunk (row blocks).
+// partials needs rot_partials_workspace(n, m) bytes.
+size_t rot_partials_workspace(int64_t n, int m);
 template <typename TA, typename TM, typename TO>
-void rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad,
-         int epi, const TA *X, const double *vec, TO *out);
+int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad,
+        int epi, const TA *X, const double *vec, TO *out, const TO *Gp = nullptr,
+        const TO *Pp = nullptr, const double *M = nullptr, double *partials = nullptr);
 // Copy an m x m FP64 matrix into an ld x ld zero-padded matrix of type TM,
 // keeping the strict upper triangle only (strict_upper) and returning the
 // diagonal in diag (when not null).
@@ -154,7 +171,7 @@ void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out);
 // After the gradient: dots = [gg | gz | gprev_z | pprev_g] (4 x ld), h (ld).
 void cg_control_gamma(hipStream_t s, int m, int ld, const double *h,
                       const double *dots, CgState *st, double *history);
-// After Y = HP: dots2 = [pp | py] (2 x ld).
+// After Y = HP: dots2 = [py | pp] (2 x ld).
 void cg_control_alpha(hipStream_t s, int m, int ld, const double *h,
                       const double *dots2, CgState *st);
 // Sum of the m entries of v into *out (single workgroup, fixed order).

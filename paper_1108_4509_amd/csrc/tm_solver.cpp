@@ -25,14 +25,18 @@ DevMem::~DevMem() {
     if (ptr) ctx->dfree(ptr);
 }
 
-void spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64) {
+int spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64, int ndot,
+             double *partials) {
     if (H->is_stencil) {
-        if (f64) spmm_stencil<double>(s, H->st, H->n, ld, (const double *)C, (double *)X);
-        else spmm_stencil<float>(s, H->st, H->n, ld, (const float *)C, (float *)X);
-    } else {
-        if (f64) spmm_csr<double>(s, H->csr, ld, (const double *)C, (double *)X);
-        else spmm_csr<float>(s, H->csr, ld, (const float *)C, (float *)X);
+        if (f64)
+            return spmm_stencil<double>(s, H->st, H->n, ld, (const double *)C, (double *)X, ndot,
+                                        partials);
+        return spmm_stencil<float>(s, H->st, H->n, ld, (const float *)C, (float *)X, ndot,
+                                   partials);
     }
+    if (f64)
+        return spmm_csr<double>(s, H->csr, ld, (const double *)C, (double *)X, ndot, partials);
+    return spmm_csr<float>(s, H->csr, ld, (const float *)C, (float *)X, ndot, partials);
 }
 
 namespace {
@@ -101,7 +105,8 @@ struct Solver::Impl {
         U.reset(new DevMem(ctx, md));
         Wp.reset(new DevMem(ctx, (size_t)ld * ld * sizeof(double)));
         gram_ws.reset(new DevMem(ctx, gram_workspace(n, m)));
-        dot_ws.reset(new DevMem(ctx, coldots_workspace(n, ld)));
+        dot_ws.reset(new DevMem(ctx, std::max({coldots_workspace(n, ld), spmm_partials_workspace(ld),
+                                               rot_partials_workspace(n, m)})));
         chol_ws.reset(new DevMem(ctx, chol_workspace(m)));
         jac_ws.reset(new DevMem(ctx, jacobi_workspace(m)));
         info.reset(new DevMem(ctx, 64));
@@ -170,10 +175,8 @@ struct Solver::Impl {
     // ---- Rayleigh-Ritz (Eq. 9): C <- C U, ascending Ritz values into w
     template <typename TC, typename TM>
     void rayleigh_ritz(TC *&C, TC *&Cn, TC *X) {
-        spmm_any(s, H, ld, C, X, is_f64<TC>());
-        DotArgs<TC> a;
-        a.nprod = 1; a.a[0] = C; a.b[0] = X;
-        coldots<TC>(s, n, ld, a, (double *)dot_ws->ptr, (double *)h->ptr);
+        const int nch = spmm_any(s, H, ld, C, X, is_f64<TC>(), 1, (double *)dot_ws->ptr);
+        reduce_partials(s, 1, nch, ld, (double *)dot_ws->ptr, (double *)h->ptr);
         gram<TC, TM>(s, n, m, C, X, (double *)h->ptr, false, false, (double *)gram_ws->ptr, (double *)Hp->ptr);
         assemble_subspace_matrix(s, m, (double *)Hp->ptr, (double *)h->ptr, (double *)Amat->ptr);
         jacobi_eig(s, m, (double *)Amat->ptr, (double *)U->ptr, (double *)w->ptr, (double *)jac_ws->ptr,
@@ -194,40 +197,29 @@ struct Solver::Impl {
         }
         TG *Gv = (TG *)G->ptr, *Gpv = (TG *)Gp->ptr, *Pv = (TG *)P->ptr, *Yv = (TG *)Y->ptr;
         const double *Mv = M ? (const double *)M->ptr : nullptr;
-        // (1)-(3): X = HC, h = diag(C^T X)
-        spmm_any(s, H, ld, C, X, is_f64<TC>());
+        // (1)-(3): X = HC with h = diag(C^T X) fused into the SpMM
         {
-            DotArgs<TC> a;
-            a.nprod = 1; a.a[0] = C; a.b[0] = X;
-            coldots<TC>(s, n, ld, a, (double *)dot_ws->ptr, (double *)h->ptr);
+            const int nch = spmm_any(s, H, ld, C, X, is_f64<TC>(), 1, (double *)dot_ws->ptr);
+            reduce_partials(s, 1, nch, ld, (double *)dot_ws->ptr, (double *)h->ptr);
         }
         // (5)-(6): H' = C^T (X - C H_D), diag(H') = 0
         gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, false, (double *)gram_ws->ptr, (double *)Hp->ptr);
         // (7): G = -2 (X' - C H')
         pad_matrix<TMH>(s, m, (double *)Hp->ptr, false, (TMH *)Wp->ptr, nullptr);
-        rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, EPI_GRAD, X, (double *)h->ptr, Gv);
-        // traces for Eq. 8 and the descent test
+        // with the traces for Eq. 8 and the descent test fused into the epilogue
         {
-            DotArgs<TG> a;
-            a.nprod = 4;
-            a.a[0] = Gv; a.b[0] = Gv;
-            a.a[1] = Gv; a.b[1] = Gv; a.weighted[1] = Mv != nullptr;
-            a.a[2] = Gpv; a.b[2] = Gv; a.weighted[2] = Mv != nullptr;
-            a.a[3] = Pv; a.b[3] = Gv;
-            a.w = Mv;
-            coldots<TG>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr);
+            const int nch = rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, EPI_GRAD, X,
+                                             (double *)h->ptr, Gv, Gpv, Pv, Mv,
+                                             (double *)dot_ws->ptr);
+            reduce_partials(s, 4, nch, ld, (double *)dot_ws->ptr, (double *)dots->ptr);
         }
         cg_control_gamma(s, m, ld, (double *)h->ptr, (double *)dots->ptr, st, hist_dev);
         // P = M G + gamma P
         p_update<TG, TG>(s, n, ld, Gv, Mv, st, Pv);
-        // line step: Y = HP, p.p and p.y
-        spmm_any(s, H, ld, Pv, Yv, is_f64<TG>());
+        // line step: Y = HP with p.y and p.p fused into the SpMM
         {
-            DotArgs<TG> a;
-            a.nprod = 2;
-            a.a[0] = Pv; a.b[0] = Pv;
-            a.a[1] = Pv; a.b[1] = Yv;
-            coldots<TG>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots2->ptr);
+            const int nch = spmm_any(s, H, ld, Pv, Yv, is_f64<TG>(), 2, (double *)dot_ws->ptr);
+            reduce_partials(s, 2, nch, ld, (double *)dot_ws->ptr, (double *)dots2->ptr);
         }
         cg_control_alpha(s, m, ld, (double *)h->ptr, (double *)dots2->ptr, st);
         // C_{i+1} = orthonormalize(C_i + alpha P)

@@ -18,8 +18,10 @@ struct DevMem {
     DevMem &operator=(const DevMem &) = delete;
 };
 
-// X = H C for a CSR or stencil H, FP64 (f64) or FP32 blocks.
-void spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64);
+// X = H C for a CSR or stencil H, FP64 (f64) or FP32 blocks, with the fused
+// column dots of spmm_csr (ndot, partials); returns the number of chunks.
+int spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64,
+             int ndot = 0, double *partials = nullptr);
 
 class Solver {
   public:

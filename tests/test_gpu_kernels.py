@@ -209,7 +209,7 @@ def test_orthonormalize(ctx, tm, orc, n, m, precision):
             assert np.all(np.abs(got - ref) <= bound)
 
 
-@pytest.mark.parametrize("m", [1, 2, 5, 16, 17, 33, 100, 256, 300])
+@pytest.mark.parametrize("m", [1, 2, 5, 16, 17, 33, 100, 256, 300, 520, 1000])
 def test_cholesky_inverse(ctx, tm, orc, m):
     import torch
     print_case(test="cholesky_inverse", m=m)
@@ -235,7 +235,7 @@ def test_cholesky_not_spd(ctx, tm):
     assert ei.value.status == tm.TM_ENOTSPD
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 27, 64, 101, 256])
+@pytest.mark.parametrize("m", [1, 2, 3, 27, 64, 101, 256, 600])
 def test_sym_eig(ctx, tm, orc, m):
     import torch
     print_case(test="sym_eig", m=m)

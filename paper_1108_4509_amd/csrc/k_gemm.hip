@@ -250,12 +250,51 @@ void gram_shape(int64_t n, int m, int &BM, int &T, int &nsplit) {
 }
 
 // One workgroup: a BR x BC tile of A W (+ epilogue), K looped in LDS stages.
+template <typename T> __device__ inline void load4(const T *p, T (&v)[4]);
+template <> __device__ inline void load4<float>(const float *p, float (&v)[4]) {
+    const vf4 x = *reinterpret_cast<const vf4 *>(p);
+    v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+}
+template <> __device__ inline void load4<double>(const double *p, double (&v)[4]) {
+    const vd2 x = *reinterpret_cast<const vd2 *>(p), y = *reinterpret_cast<const vd2 *>(p + 2);
+    v[0] = x[0]; v[1] = x[1]; v[2] = y[0]; v[3] = y[1];
+}
+template <typename T> __device__ inline void store4(T *p, const T (&v)[4]);
+template <> __device__ inline void store4<float>(float *p, const float (&v)[4]) {
+    vf4 x;
+    x[0] = v[0]; x[1] = v[1]; x[2] = v[2]; x[3] = v[3];
+    *reinterpret_cast<vf4 *>(p) = x;
+}
+template <> __device__ inline void store4<double>(double *p, const double (&v)[4]) {
+    vd2 x, y;
+    x[0] = v[0]; x[1] = v[1]; y[0] = v[2]; y[1] = v[3];
+    *reinterpret_cast<vd2 *>(p) = x;
+    *reinterpret_cast<vd2 *>(p + 2) = y;
+}
+
+template <typename TM, int BR, int BC>
+struct RotSmem {
+    static constexpr int KT = stage_rows<TM>();
+    static constexpr int stage_bytes =
+        (2 * BR * (KT + 1) + 2 * KT * (BC + kPad)) * (int)sizeof(TM);
+    // rows of the accumulator tile per epilogue pass (FP64 tiles go in halves)
+    static constexpr int EH = (BR * (BC + 4) * (int)sizeof(TM) <= stage_bytes) ? BR : BR / 2;
+    static constexpr int tile_bytes = EH * (BC + 4) * (int)sizeof(TM);
+    static constexpr int red_bytes = (kThreads / (BC / 4)) * 4 * BC * 8;
+    static constexpr int a = stage_bytes > tile_bytes ? stage_bytes : tile_bytes;
+    static constexpr int bytes = a > red_bytes ? a : red_bytes;
+};
+
+// One workgroup: a BR x BC tile of A W (+ epilogue), K looped in LDS stages.
+// The accumulators then go through LDS so that the epilogue reads X and A,
+// and writes the result, as row-contiguous 4-element vectors.
 template <typename TA, typename TM, typename TO, int EPI, int BR, int BC>
 __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TM *__restrict__ W,
     const TA *__restrict__ X, const double *__restrict__ vec, TO *__restrict__ out,
     int nrb, int ncb, GradDots<TO> gd) {
-    constexpr int KT = stage_rows<TM>();
+    using SM = RotSmem<TM, BR, BC>;
+    constexpr int KT = SM::KT;
     constexpr int WR = BR / 2, WC = BC / 2;
     constexpr int NBR = WR / 16, NBC = WC / 16;
     constexpr int VA = Vec16<TA>::W, VM = Vec16<TM>::W;
@@ -270,8 +309,11 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     using VMt = typename Vec16<TM>::type;
     using Acc = typename Mfma<TM>::acc_t;
 
-    __shared__ TM As[2][BR][KT + 1];
-    __shared__ TM Ws[2][KT][BC + kPad];
+    __shared__ __align__(16) char smem[SM::bytes];
+    typedef TM AsRow[KT + 1];
+    typedef TM WsRow[BC + kPad];
+    AsRow *As0 = reinterpret_cast<AsRow *>(smem);                 // [2][BR][KT + 1]
+    WsRow *Ws0 = reinterpret_cast<WsRow *>(smem + 2 * BR * (KT + 1) * sizeof(TM));   // [2][KT][BC+pad]
 
     const int logical = xcd_logical(gridDim.x);
     if (logical >= nrb * ncb) return;
@@ -310,15 +352,17 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
         }
     };
     auto store = [&](int buf) {
+        AsRow *As = As0 + buf * BR;
+        WsRow *Ws = Ws0 + buf * KT;
 #pragma unroll
         for (int q = 0; q < PA; ++q)
 #pragma unroll
             for (int w = 0; w < VA; ++w)
-                As[buf][arow + q * ARPP][acv * VA + w] = (TM)velem<TA>(ra[q], w);
+                As[arow + q * ARPP][acv * VA + w] = (TM)velem<TA>(ra[q], w);
 #pragma unroll
         for (int q = 0; q < PW; ++q)
 #pragma unroll
-            for (int w = 0; w < VM; ++w) Ws[buf][wrow + q * WRPP][wcv * VM + w] = velem<TM>(rw[q], w);
+            for (int w = 0; w < VM; ++w) Ws[wrow + q * WRPP][wcv * VM + w] = velem<TM>(rw[q], w);
     };
 
     int buf = 0;
@@ -328,14 +372,16 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     for (int k0 = 0; k0 < kend; k0 += KT) {
         const bool more = k0 + KT < kend;
         if (more) load(k0 + KT);
+        const AsRow *As = As0 + buf * BR;
+        const WsRow *Ws = Ws0 + buf * KT;
 #pragma unroll
         for (int kk = 0; kk < KT; kk += 4) {
             TM fa[NBR], fb[NBC];
             const int kc = kk + (lane >> 4);
 #pragma unroll
-            for (int a = 0; a < NBR; ++a) fa[a] = As[buf][wr * WR + a * 16 + (lane & 15)][kc];
+            for (int a = 0; a < NBR; ++a) fa[a] = As[wr * WR + a * 16 + (lane & 15)][kc];
 #pragma unroll
-            for (int b = 0; b < NBC; ++b) fb[b] = Ws[buf][kc][wc * WC + b * 16 + (lane & 15)];
+            for (int b = 0; b < NBC; ++b) fb[b] = Ws[kc][wc * WC + b * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < NBR; ++a)
 #pragma unroll
@@ -346,64 +392,98 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
         buf ^= 1;
     }
 
-    // column sums of the fused gradient traces: [dot][column block]
-    double dsum[EPI == EPI_GRAD ? 4 : 1][NBC];
+    // ---- epilogue through LDS, EH rows at a time
+    constexpr int EH = SM::EH;
+    constexpr int TS = BC + 4;                 // tile row stride
+    constexpr int CVN = BC / 4;                // 4-column vectors per row
+    constexpr int RPT = kThreads / CVN;        // rows per pass
+    TM *tile = reinterpret_cast<TM *>(smem);
+    const int ecv = tid % CVN, erow = tid / CVN;
+    const int ecol = c0 + 4 * ecv;
+    const bool col_ok = ecol < ld;             // ld is a multiple of 32
+    const bool fuse = (EPI == EPI_GRAD) && gd.partials != nullptr;
+    double vv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (EPI != EPI_NONE && col_ok) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) vv[w] = vec[ecol + w];
+    }
+    double dsum[EPI == EPI_GRAD ? 4 : 1][4];
 #pragma unroll
     for (int p = 0; p < (EPI == EPI_GRAD ? 4 : 1); ++p)
 #pragma unroll
-        for (int b = 0; b < NBC; ++b) dsum[p][b] = 0.0;
-    const bool fuse = (EPI == EPI_GRAD) && gd.partials != nullptr;
+        for (int w = 0; w < 4; ++w) dsum[p][w] = 0.0;
 
 #pragma unroll
-    for (int a = 0; a < NBR; ++a)
+    for (int half = 0; half < BR / EH; ++half) {
+        if (half > 0) __syncthreads();
 #pragma unroll
-        for (int b = 0; b < NBC; ++b)
+        for (int a = 0; a < NBR; ++a)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = r0 + wr * WR + a * 16 + Mfma<TM>::row(lane, r);
-                const int col = c0 + wc * WC + b * 16 + (lane & 15);
-                if (row >= n || col >= ld) continue;
-                const int64_t e = row * ld + col;
-                const TA v = (TA)acc[a][b][r];
-                if constexpr (EPI == EPI_NONE) {
-                    out[e] = (TO)v;
-                } else if constexpr (EPI == EPI_GRAD) {
-                    const TA xp = X[e] - A[e] * (TA)vec[col];
-                    const TO g = (TO)((TA)-2 * (xp - v));
-                    out[e] = g;
-                    if (fuse) {
-                        const double gv = (double)g;
-                        const double w = gd.M ? gd.M[row] : 1.0;
-                        dsum[0][b] += gv * gv;
-                        dsum[1][b] += w * gv * gv;
-                        dsum[2][b] += w * (double)gd.Gp[e] * gv;
-                        dsum[3][b] += (double)gd.Pp[e] * gv;
-                    }
-                } else {
-                    out[e] = (TO)(A[e] * (TA)vec[col] + v);
+            for (int b = 0; b < NBC; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rl = wr * WR + a * 16 + Mfma<TM>::row(lane, r) - half * EH;
+                    if (rl >= 0 && rl < EH) tile[rl * TS + wc * WC + b * 16 + (lane & 15)] = acc[a][b][r];
                 }
+        __syncthreads();
+        for (int rl = erow; rl < EH; rl += RPT) {
+            const int64_t row = r0 + half * EH + rl;
+            if (row >= n || !col_ok) continue;
+            const int64_t e = row * ld + ecol;
+            TA v[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) v[w] = (TA)tile[rl * TS + 4 * ecv + w];
+            TO o[4];
+            if constexpr (EPI == EPI_NONE) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) o[w] = (TO)v[w];
+            } else if constexpr (EPI == EPI_GRAD) {
+                TA xv[4], av[4];
+                load4<TA>(X + e, xv);
+                load4<TA>(A + e, av);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) o[w] = (TO)((TA)-2 * ((xv[w] - av[w] * (TA)vv[w]) - v[w]));
+                if (fuse) {
+                    TO gp[4], pp[4];
+                    load4<TO>(gd.Gp + e, gp);
+                    load4<TO>(gd.Pp + e, pp);
+                    const double wgt = gd.M ? gd.M[row] : 1.0;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        const double g = (double)o[w];
+                        dsum[0][w] += g * g;
+                        dsum[1][w] += wgt * g * g;
+                        dsum[2][w] += wgt * (double)gp[w] * g;
+                        dsum[3][w] += (double)pp[w] * g;
+                    }
+                }
+            } else {
+                TA av[4];
+                load4<TA>(A + e, av);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) o[w] = (TO)(av[w] * (TA)vv[w] + v[w]);
             }
+            store4<TO>(out + e, o);
+        }
+    }
 
     if constexpr (EPI == EPI_GRAD) {
         if (fuse) {
-            // lanes l, l^16, l^32, l^48 share a column; then the two waves of a
-            // column half (wr = 0, 1) meet in LDS; fixed order throughout
-            __shared__ double dred[2][4][BC];
+            // the RPT lanes of a column vector meet in LDS; fixed order
+            __syncthreads();
+            double *red = reinterpret_cast<double *>(smem);   // [RPT][4][BC]
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
-                for (int b = 0; b < NBC; ++b) {
-                    double x = dsum[p][b];
-                    x += __shfl_xor(x, 16);
-                    x += __shfl_xor(x, 32);
-                    if (lane < 16) dred[wr][p][wc * WC + b * 16 + lane] = x;
-                }
+                for (int w = 0; w < 4; ++w) red[(erow * 4 + p) * BC + 4 * ecv + w] = dsum[p][w];
             __syncthreads();
-            for (int e = tid; e < 4 * BC; e += kThreads) {
-                const int p = e / BC, cc = e - (e / BC) * BC;
+            for (int e2 = tid; e2 < 4 * BC; e2 += kThreads) {
+                const int p = e2 / BC, cc = e2 - (e2 / BC) * BC;
                 const int col = c0 + cc;
-                if (col < ld)
-                    gd.partials[((int64_t)p * nrb + rb) * ld + col] = dred[0][p][cc] + dred[1][p][cc];
+                if (col >= ld) continue;
+                double sum = 0.0;
+                for (int g = 0; g < RPT; ++g) sum += red[(g * 4 + p) * BC + cc];
+                gd.partials[((int64_t)p * nrb + rb) * ld + col] = sum;
             }
         }
     }

@@ -29,32 +29,88 @@ def log(*a):
 
 
 def cpu_baseline(problem, iters_full, seconds_budget=20.0):
-    """The FP64 CPU oracle on a bounded sample: a few CG iterations of the same
-    problem, scaled to a full solve by the iteration count of the GPU run."""
-    import numpy as np
+    """The FP64 CPU oracle on a bounded sample: a number of CG iterations of the
+    same problem sized to about ``seconds_budget`` of CPU time, scaled to a
+    full solve by the iteration count of the GPU run."""
     import oracle
     H = oracle.csr_matrix(*problem.csr(), problem.N)
-    opts = oracle.OracleOptions(tol=1e-8, k_rot=50, max_iter=1)
-    t0 = time.time()
-    oracle.solve(H, problem.C0(), opts)      # orthonormalization + 1 iteration + final RR
-    t_one = time.time() - t0
-    n_it = max(2, min(50, int(seconds_budget / max(t_one, 1e-3))))
-    opts.max_iter = n_it
-    t0 = time.time()
-    oracle.solve(H, problem.C0(), opts)
-    t_n = time.time() - t0
-    per_iter = max((t_n - t_one) / (n_it - 1), 1e-9)
-    est = per_iter * iters_full + t_one
+    C0 = problem.C0()
+
+    def timed(n_it):
+        t0 = time.time()
+        oracle.solve(H, C0, oracle.OracleOptions(tol=1e-8, k_rot=50, max_iter=n_it))
+        return time.time() - t0
+
+    t1, t3 = timed(1), timed(3)       # setup + final Rayleigh-Ritz + 1 or 3 iterations
+    per_iter = max((t3 - t1) / 2.0, 1e-6)
+    setup = max(t1 - per_iter, 0.0)
+    n_it = int(max(4, min(400, (seconds_budget - setup) / per_iter)))
+    t_n = timed(n_it)
+    per_iter = max((t_n - t1) / (n_it - 1), 1e-9)
+    est = per_iter * iters_full + setup
     try:
         threads = int(os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS")
                       or len(os.sched_getaffinity(0)))
     except Exception:
         threads = os.cpu_count() or 1
-    del np
     return {"value": round(est, 3), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_it} oracle CG iterations on the same 48^3 m=256 problem "
-                      f"({per_iter:.3f} s/iter) scaled to {iters_full} iterations "
-                      f"plus setup and final Rayleigh-Ritz ({t_n:.1f} s measured)"}
+            "sample": f"{n_it} oracle CG iterations of the same problem ({t_n:.1f} s measured, "
+                      f"{per_iter:.3f} s/iter, setup and final Rayleigh-Ritz {setup:.1f} s) "
+                      f"scaled to the GPU run's {iters_full} iterations"}
+
+
+def kernel_work(p, ld):
+    """Algorithmic flops and HBM bytes of one launch of each per-iteration kernel
+    of the refinement phase (the phase most iterations run in), and of the FP32
+    bulk-phase Gram.  Bytes count each operand block once (s = bytes/element)."""
+    N, m = p.N, p.m
+    nnz = len(p.csr()[1])
+    blk = N * ld
+    return {
+        # X = H C, FP64 CSR: read C, write X, read the matrix once
+        "spmm/f64": (2.0 * nnz * m, 16.0 * blk + 12.0 * nnz + 8.0 * (N + 1), "f64"),
+        # Y = H P with FP32 P
+        "spmm/f32": (2.0 * nnz * m, 8.0 * blk + 12.0 * nnz + 8.0 * (N + 1), "f32"),
+        # H' = C^T X' from FP64 C and X on FP32 matrix cores
+        "gram_mp2/f64": (2.0 * N * m * m, 16.0 * blk, "f32"),
+        # G = -2 (X' - C H'): read C, X (FP64), G_prev, P_prev (FP32), write G (FP32)
+        "rot_grad_mp2/f64": (2.0 * N * m * m, 28.0 * blk, "f32"),
+        # S = C^T C, FP64, upper tiles
+        "gram_sym/f64": (1.0 * N * m * (m + 1), 8.0 * blk, "f64"),
+        # C D + C R' with FP32 R', FP64 C in and out
+        "trmm_mp2/f64": (1.0 * N * m * (m + 1), 16.0 * blk, "f32"),
+        # FP32 bulk phase Gram H'
+        "gram_shift/f32": (2.0 * N * m * m, 8.0 * blk, "f32"),
+    }
+
+
+def kernel_rooflines(tm, ctx, H, p, reps=20):
+    """Time each kernel with HIP events on the library stream and place it on
+    the roofline; the dominant (longest) bulk kernel is the headline."""
+    ld = tm.leading_dim(p.m)
+    out = {}
+    for key, (flops, nbytes, mdtype) in kernel_work(p, ld).items():
+        name, dt = key.split("/")
+        ms = tm.time_kernel(ctx, H, name, p.m, dt, reps=reps)
+        t = ms * 1e-3
+        t_mfma = flops / (PEAK_TFLOPS[mdtype] * 1e12)
+        t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+        if t_hbm >= t_mfma:
+            ach, peak, unit, bound = nbytes / t / 1e9, PEAK_HBM_GBS, "GB/s", "hbm"
+        else:
+            ach, peak, unit, bound = flops / t / 1e12, PEAK_TFLOPS[mdtype], "TFLOP/s", "mfma"
+        out[key] = {"avg_ms": round(ms, 4), "bound": bound, "achieved": round(ach, 2), "peak": peak,
+                    "unit": unit, "frac": round(ach / peak, 4),
+                    "tflops": round(flops / t / 1e12, 2), "GB/s": round(nbytes / t / 1e9, 1)}
+    chol_ms = tm.time_kernel(ctx, H, "chol", p.m, "f64", reps=reps)
+    out["chol/f64"] = {"avg_ms": round(chol_ms, 4), "bound": "latency",
+                       "tflops": round((2.0 / 3.0) * p.m ** 3 / (chol_ms * 1e-3) / 1e12, 4)}
+    dom = max((k for k in out if k != "gram_shift/f32"), key=lambda k: out[k]["avg_ms"])
+    d = out[dom]
+    roof = {"bound": d["bound"], "achieved": d.get("achieved"), "peak": d.get("peak"),
+            "unit": d.get("unit"), "frac": d.get("frac"), "traffic": None,
+            "kernel": dom, "avg_ms": d["avg_ms"]}
+    return roof, out
 
 
 def main():
@@ -66,6 +122,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--precision", default="mixed", help="precision of the timed steps")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the per-kernel roofline timings and a copy of known size "
+                         "(for hardware-counter runs)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
@@ -81,6 +140,18 @@ def main():
     log(f"bench: config {a.config} N={p.N} m={p.m}")
     ctx = tm.Context(0)
     H = tm.matrix_from_problem(ctx, p)
+    if a.kernels_only:
+        # a plain device copy of known size (1 GiB read + 1 GiB written) that
+        # calibrates the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        roofline, kernels = kernel_rooflines(tm, ctx, H, p, reps=5)
+        print(json.dumps({"roofline": roofline, "kernels": kernels}), flush=True)
+        return
     C0 = tm.to_block(p.C0())
     torch.cuda.synchronize()
     tol = 1e-8
@@ -120,23 +191,7 @@ def main():
             g = json.load(f)
         rel_err = abs(res["E_G"] - g["E_G"]) / abs(g["E_G"])
 
-    # roofline of the dominant kernel (FP32 Gram H' = C^T X' of the bulk phase),
-    # timed with HIP events on the library stream
-    m, N, ld = p.m, p.N, tm.leading_dim(p.m)
-    k_ms = tm.time_kernel(ctx, H, "gram_shift", m, "f32", reps=20)
-    flops = 2.0 * N * m * m
-    achieved = flops / (k_ms * 1e-3) / 1e12
-    spmm_ms = tm.time_kernel(ctx, H, "spmm", m, "f32", reps=20)
-    nnz = len(p.csr()[1])
-    spmm_bytes = 2.0 * N * ld * 4 + 12.0 * nnz + 8.0 * (N + 1)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["f32"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32"], 4),
-                "traffic": None, "kernel": "gram_kernel<float,float,64,true> (H' = C^T X')",
-                "avg_ms": round(k_ms, 4),
-                "spmm_f32": {"avg_ms": round(spmm_ms, 4),
-                             "GB/s": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9, 1),
-                             "frac_hbm": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}}
-
+    roofline, kernels = kernel_rooflines(tm, ctx, H, p)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(p, res["iterations"])
@@ -151,14 +206,14 @@ def main():
         "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{a.config}: 48^3 periodic 7-point -1/2 Lap + 64 Gaussian wells, "
-                               f"FP64 CSR, N={N}, m={m}, tol 1e-8, MIXED (FP32 bulk + MP2 refinement)"
-                   if a.config == "c2" else f"{a.config}: N={N}, m={m}"},
+                               f"FP64 CSR, N={p.N}, m={p.m}, tol 1e-8, MIXED (FP32 bulk + MP2 refinement)"
+                   if a.config == "c2" else f"{a.config}: N={p.N}, m={p.m}"},
         "fp64_seconds": round(fp64, 4) if fp64 else None,
         "speedup_vs_fp64": round(fp64 / value, 3) if fp64 else None,
         "iterations": res["iterations"], "iters_fp32": res["iters_sp"],
         "iterations_fp64": res64["iterations"] if res64 else None,
         "E_G": res["E_G"], "rel_err_vs_oracle": rel_err, "max_residual": res["max_residual"],
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -102,6 +102,10 @@ typedef struct tm_opts {
     int32_t k_check;       /* host polls the device convergence flag every k_check iterations */
     int32_t precondition;  /* 1: diagonal M of Eq. 18, M_ii = 1/(H_ii - sigma) */
     int32_t history;       /* 1: record E_i and rho_i per iteration         */
+    int32_t transport;     /* 1 (default): a subspace rotation C <- C U also maps
+                              P <- P U and G_prev <- G_prev U and CG continues;
+                              0: CG restarts after each rotation */
+    int32_t reserved0;     /* must be 0 */
     double switch_tol;     /* TM_MIXED: leave FP32 when rho <= switch_tol (<= 0: automatic) */
     double rise_tol;       /* restart CG when E rises by more than rise_tol*|E| */
 } tm_opts;
@@ -228,14 +232,20 @@ tm_status tm_sym_eig(tm_ctx *ctx, int32_t m, const double *A, double *U,
  *   TM_K_GRAM_SYM   S = C^T C upper tiles, split-K part     (dtype)
  *   TM_K_ROT_GRAD   G = -2 (X' - C H')                     (dtype)
  *   TM_K_TRMM       C D + C R'                             (dtype)
- *   TM_K_GRAM_MP2   H' from FP64 blocks on FP32 matrix cores (dtype ignored) */
+ *   TM_K_GRAM_MP2   H' from FP64 blocks on FP32 matrix cores (dtype ignored)
+ *   TM_K_ROT_GRAD_MP2 G from FP64 C and X, FP32 H' and FP32 G (dtype ignored)
+ *   TM_K_TRMM_MP2   FP64 C D + C R' with R' on FP32 matrix cores (dtype ignored)
+ *   TM_K_CHOL       S = R^T R and R^{-1}, m x m FP64 (dtype ignored) */
 typedef enum tm_kernel_id {
     TM_K_SPMM = 0,
     TM_K_GRAM_SHIFT = 1,
     TM_K_GRAM_SYM = 2,
     TM_K_ROT_GRAD = 3,
     TM_K_TRMM = 4,
-    TM_K_GRAM_MP2 = 5
+    TM_K_GRAM_MP2 = 5,
+    TM_K_ROT_GRAD_MP2 = 6,
+    TM_K_TRMM_MP2 = 7,
+    TM_K_CHOL = 8
 } tm_kernel_id;
 
 tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m,

@@ -26,8 +26,9 @@ notes of the repository):
 * line minimization (Sec. 2.1 cites it without detail): second-order model of
   E along P, see ``line_step``;
 * convergence test: rho = ||X - C A||_F = ||G||_F / 2 <= tol;
-* CG restarts (gamma = 0): at i = 0, after a subspace rotation, when E rose
-  by more than ``rise_tol * |E|``, and when P is not a descent direction.
+* CG restarts (gamma = 0): at i = 0, after a subspace rotation (unless the
+  rotation also carries P and G_prev into the new basis, ``transport``), when
+  E rose by more than ``rise_tol * |E|``, and when P is not a descent direction.
 """
 
 from __future__ import annotations
@@ -170,16 +171,23 @@ def jacobi_eigh(A: np.ndarray, tol: float = 1e-15, max_sweeps: int = 100):
     return w, V, sweeps
 
 
+def ritz_rotation(H, C: np.ndarray):
+    """The m x m H = C^T H C (symmetrized) and its eigendecomposition:
+    returns (U, w), w ascending, so that (C U)^T H (C U) = diag(w)."""
+    X = spmm(H, C)
+    A = C.T @ X
+    A = 0.5 * (A + A.T)
+    w, U, _ = jacobi_eigh(A)
+    return U, w
+
+
 def rayleigh_ritz(H, C: np.ndarray):
     """Diagonalize the m x m H = C^T H C and rotate C into its eigenbasis.
 
     Eq. 9: at convergence HC = CH, so the eigenvalues of the m x m matrix are
     eigenvalues of H.  Returns (C U, w) with w ascending.
     """
-    X = spmm(H, C)
-    A = C.T @ X
-    A = 0.5 * (A + A.T)
-    w, U, _ = jacobi_eigh(A)
+    U, w = ritz_rotation(H, C)
     return C @ U, w
 
 
@@ -231,6 +239,7 @@ class OracleOptions:
     k_rot: int = 0              # subspace rotation every k_rot iterations (0: never)
     precondition: bool = False  # diagonal M of Eq. 18
     rise_tol: float = 1e-13     # restart CG when E rises by more than this * |E|
+    transport: bool = True      # at a rotation C <- C U, also P <- P U, G_prev <- G_prev U
 
 
 @dataclasses.dataclass
@@ -271,8 +280,15 @@ def solve(H, C0: np.ndarray, opts: Optional[OracleOptions] = None,
     it = 0
     for it in range(o.max_iter):
         if o.k_rot > 0 and it > 0 and it % o.k_rot == 0:
-            C, _ = rayleigh_ritz(H, C)
-            restart = True
+            U, _ = ritz_rotation(H, C)
+            C = C @ U
+            if o.transport and P_prev is not None:
+                # E(C U) = E(C) and G(C U) = G(C) U (Sec. 2.1): expressed in
+                # the rotated basis the previous direction and gradient are
+                # P U and G U, and the Polak-Ribiere traces are unchanged
+                P_prev, G_prev, Z_prev = P_prev @ U, G_prev @ U, Z_prev @ U
+            else:
+                restart = True
         E, G, X, A = energy_gradient_alg1(H, C)
         rho = 0.5 * float(np.linalg.norm(G))
         energies.append(E)

@@ -97,8 +97,10 @@ class Context:
             _abi.lib().tm_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check usable while module globals
+        # are being torn down at interpreter exit
+        if _finalizing():
             return
         try:
             self.close()
@@ -118,8 +120,8 @@ class Matrix:
             _abi.lib().tm_free_matrix(self.handle)
         self.handle = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.free()
@@ -180,7 +182,7 @@ def to_block(C: np.ndarray, dtype=None, device=None):
 
 
 def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition=False,
-         history=False, switch_tol=0.0, rise_tol=1e-13) -> _abi.tm_opts:
+         history=False, switch_tol=0.0, rise_tol=1e-13, transport=None) -> _abi.tm_opts:
     o = _abi.tm_opts()
     _abi.lib().tm_opts_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -191,6 +193,8 @@ def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition
     o.history = 1 if history else 0
     o.switch_tol = switch_tol
     o.rise_tol = rise_tol
+    if transport is not None:
+        o.transport = 1 if transport else 0
     return o
 
 
@@ -290,7 +294,9 @@ def sym_eig(ctx: Context, A):
 
 KERNELS = {"spmm": _abi.TM_K_SPMM, "gram_shift": _abi.TM_K_GRAM_SHIFT,
            "gram_sym": _abi.TM_K_GRAM_SYM, "rot_grad": _abi.TM_K_ROT_GRAD,
-           "trmm": _abi.TM_K_TRMM, "gram_mp2": _abi.TM_K_GRAM_MP2}
+           "trmm": _abi.TM_K_TRMM, "gram_mp2": _abi.TM_K_GRAM_MP2,
+           "rot_grad_mp2": _abi.TM_K_ROT_GRAD_MP2, "trmm_mp2": _abi.TM_K_TRMM_MP2,
+           "chol": _abi.TM_K_CHOL}
 
 
 def time_kernel(ctx: Context, H: Matrix, kernel: str, m: int, dtype: str = "f32",

@@ -40,6 +40,7 @@ class tm_stencil(ctypes.Structure):
 class tm_opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_iter", c_int32), ("k_rot", c_int32),
                 ("k_check", c_int32), ("precondition", c_int32), ("history", c_int32),
+                ("transport", c_int32), ("reserved0", c_int32),
                 ("switch_tol", c_double), ("rise_tol", c_double)]
 
 
@@ -83,7 +84,8 @@ SIGNATURES = {
                                  ctypes.POINTER(c_double)]),
 }
 
-TM_K_SPMM, TM_K_GRAM_SHIFT, TM_K_GRAM_SYM, TM_K_ROT_GRAD, TM_K_TRMM, TM_K_GRAM_MP2 = range(6)
+(TM_K_SPMM, TM_K_GRAM_SHIFT, TM_K_GRAM_SYM, TM_K_ROT_GRAD, TM_K_TRMM, TM_K_GRAM_MP2,
+ TM_K_ROT_GRAD_MP2, TM_K_TRMM_MP2, TM_K_CHOL) = range(9)
 
 _lib = None
 

@@ -7,6 +7,7 @@
 // (resident in L2) and the current panel staged in LDS.
 #include "tm_common.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace tmin {
@@ -35,120 +36,185 @@ __device__ inline void lower_pair(int p, int &bi, int &bj) {
     bj = p - i * (i + 1) / 2;
 }
 
-// Factor the nb x nb diagonal block D = L_kk L_kk^T and build L_kk^{-1} at the
-// same time, with the whole workgroup: Gaussian elimination without pivoting
-// on the augmented NB x 2NB matrix [D | I], double-buffered in LDS so that one
-// barrier per step suffices.  Afterwards the D half holds U = diag(d) L1^T and
-// the I half holds L1^{-1} (L1 unit lower), so L = L1 diag(d)^{1/2} and
-// L^{-1} = diag(d)^{-1/2} L1^{-1}.  Rows and columns at or beyond nb (last,
-// partial panel) are padded with the identity.  Writes L_kk (lower), the
-// diagonal block of X = L^{-1} (with zeros above its diagonal), the same block
-// of Rinv = X^T (upper), and Dinv = L_kk^{-1} in LDS.  Returns false (the
-// same on every lane) if a pivot is not clearly positive.
+// Factor the NB x NB diagonal block D = L_kk L_kk^T and invert it, by one
+// wave, on the augmented NB x 2NB matrix [D | I] staged in LDS (aug, row
+// stride 2NB + 1): lane c keeps column c in registers (rows a[0..NB)).
+// Gaussian elimination without pivoting: at step k lane k publishes the
+// multipliers a_ik / a_kk through LDS and every lane updates its own column;
+// wave-scope fences order the exchange, so no workgroup barrier is needed.  Afterwards the D half holds U = diag(d) L1^T and
+// the I half L1^{-1} (L1 unit lower), so L = L1 diag(d)^{1/2} and
+// L^{-1} = diag(d)^{-1/2} L1^{-1}.  Results go back to LDS: L_kk^T into the
+// D half of aug, L_kk^{-1} (zero above the diagonal) into Dinv, the pivots d
+// into piv.  For NB = 16 the upper 32 lanes repeat the last column.
 template <int NB>
-__device__ bool diag_factor(int m, int kb, int nb, const double *__restrict__ src,
-                            double *__restrict__ L, double *__restrict__ X,
-                            double *__restrict__ Rinv, const double *Sd, double *buf,
-                            double *piv, double (*Dinv)[NB + 1]) {
-    constexpr int W2 = 2 * NB, RS = W2 + 1;
-    double *A0 = buf, *A1 = buf + NB * RS;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < NB * W2; e += kDenseThreads) {
-        const int i = e / W2, c = e % W2;
-        double v;
-        if (c < NB) {
-            v = (i == c) ? 1.0 : 0.0;
-            if (i < nb && c < nb) {
-                const int r = i > c ? i : c, q = i > c ? c : i;   // lower part
-                v = src[(size_t)(kb + r) * m + kb + q];
-            }
-        } else {
-            v = (i == c - NB) ? 1.0 : 0.0;
-        }
-        A0[i * RS + c] = v;
-    }
-    __syncthreads();
-    bool ok = true;
+__device__ void diag_factor_wave(int lane, double *aug, double *piv, double *mult,
+                                 double (*Dinv)[NB + 1]) {
+    constexpr int NC = 2 * NB, RS = 2 * NB + 1;
+    const int c = lane < NC ? lane : NC - 1;
+    double a[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) a[i] = aug[i * RS + c];
+#pragma unroll
     for (int k = 0; k < NB; ++k) {
-        const double *cur = (k & 1) ? A1 : A0;
-        double *nxt = (k & 1) ? A0 : A1;
-        const double d = cur[k * RS + k];
-        if (!(d > kPivotTol * fabs(Sd[k]))) ok = false;
-        if (tid == 0) piv[k] = d;
-        const double inv = 1.0 / d;
-        for (int e = tid; e < NB * W2; e += kDenseThreads) {
-            const int i = e / W2, c = e % W2;
-            double v = cur[i * RS + c];
-            if (i > k) v -= cur[i * RS + k] * inv * cur[k * RS + c];
-            nxt[i * RS + c] = v;
+        double *mk = mult + (k & 1) * NB;   // double-buffered: no WAR between steps
+        if (lane == k) {
+            const double inv = 1.0 / a[k];
+            piv[k] = a[k];
+#pragma unroll
+            for (int i = k + 1; i < NB; ++i) mk[i] = a[i] * inv;
         }
-        __syncthreads();
+        // make lane k's LDS writes visible to the whole wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double rk = a[k];
+#pragma unroll
+        for (int i = k + 1; i < NB; ++i) a[i] = fma(-mk[i], rk, a[i]);
     }
-    if (!ok) return false;
-    const double *F = (NB & 1) ? A1 : A0;
-    for (int e = tid; e < NB * NB; e += kDenseThreads) {
-        const int i = e / NB, c = e % NB;
-        if (i < nb && c < nb) {
-            if (c <= i) L[(size_t)(kb + i) * m + kb + c] = F[c * RS + i] / sqrt(piv[c]);
-            const double xv = F[i * RS + NB + c] / sqrt(piv[i]);   // 0 above the diagonal
-            Dinv[i][c] = xv;
-            X[(size_t)(kb + i) * m + kb + c] = xv;
-            if (c <= i) Rinv[(size_t)(kb + c) * m + kb + i] = xv;
-        } else {
-            Dinv[i][c] = 0.0;
-        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < NB) {
+        // lane i: row i of L, L_iq = U_qi / sqrt(d_q) for q <= i, stored transposed
+#pragma unroll
+        for (int q = 0; q < NB; ++q) aug[q * RS + lane] = (q <= lane) ? a[q] / sqrt(piv[q]) : 0.0;
+    } else if (lane < NC) {
+        // lane NB + col: column col of X = diag(d)^{-1/2} L1^{-1}
+        const int col = lane - NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) Dinv[i][col] = (i >= col) ? a[i] / sqrt(piv[i]) : 0.0;
     }
-    return true;
 }
 
 // S = L L^T (L lower; S = R^T R with R = L^T) and Rinv = R^{-1} = L^{-T}
-// (upper triangle only; the caller clears the rest).
-// Blocked right-looking Cholesky with NB-wide panels: the diagonal block is
-// factored and inverted by diag_factor, the panel L_ik = S_ik L_kk^{-T} and the
-// trailing update S_ij -= L_ik L_jk^T run on FP64 matrix cores (16 x 16 blocks
-// spread over the 16 waves) with the panel staged in LDS.  The first panel
-// reads S directly, later ones the updated copy in L.  The inverse
-// X = L^{-1} is then assembled by recursive doubling from the NB x NB diagonal
-// inverses: for consecutive diagonal blocks A, C of size b,
-//   X_CA = -X_C (L_CA X_A),
-// all pairs of a level at once, b = NB, 2 NB, 4 NB, ...
-// work: L (m*m), X (m*m), T (m*m) doubles.
+// (upper triangle only; the caller clears the rest), in one right-looking
+// sweep over NB-wide panels that also carries the block forward substitution
+// L X = I:
+//   1. the diagonal block is factored and inverted by one wave (Dinv = L_kk^{-1});
+//   2. the panel's rows of the inverse are finished, X_k = Dinv W_k, where W
+//      holds I minus the updates of the earlier panels;
+//   3. the panel L_ik = S_ik Dinv^T;
+//   4. the trailing matrix S_ij -= L_ik L_jk^T (lower tiles) and the rows of W
+//      below, W_i -= L_ik X_k, both on FP64 matrix cores with L_ik and X_k
+//      staged in LDS.
+// W lives in the X workspace (rows below the panel), so each entry of X is
+// written once as final.  work: L (m*m), X (m*m) doubles.
 template <int NB>
 __global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
     int m, const double *__restrict__ S, double *__restrict__ Rinv,
     double *__restrict__ work, int32_t *__restrict__ info) {
     __shared__ double stage[kStage];
     __shared__ double Dinv[NB][NB + 1];
-    __shared__ double Sd[NB];
     __shared__ double piv[NB];
+    __shared__ double mult[2 * NB];
+    __shared__ int ok_flag;
     constexpr int PS = NB + 1;   // row stride of the staged panel
     double *L = work;
     double *X = work + (size_t)m * m;
-    double *T = X + (size_t)m * m;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
     constexpr int nwaves = kDenseThreads / 64;
 
     for (int kb = 0; kb < m; kb += NB) {
+        // the lane index is made opaque per panel so that the many per-lane
+        // offsets of the unrolled loops are not hoisted out of the panel loop
+        // (their live ranges would exceed the register file)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63, wave = tid >> 6;
         const int nb = (m - kb < NB) ? (m - kb) : NB;
         const double *src = (kb == 0) ? S : L;
-        if (tid < NB) Sd[tid] = (tid < nb) ? S[(size_t)(kb + tid) * m + kb + tid] : 1.0;
-        __syncthreads();
-        if (!diag_factor<NB>(m, kb, nb, src, L, X, Rinv, Sd, stage, piv, Dinv)) {
-            if (tid == 0) info[0] = kb + 1;
-            return;   // uniform: every lane saw the same pivots
-        }
-        __syncthreads();
         const int R = m - kb - nb;          // rows below the diagonal block
-        // stage S_ik (R x nb), then the panel L_ik = S_ik Dinv^T on matrix cores
+        const int kw = kb + nb;             // columns of X_k and of the W update
+        const int XSS = ((kw + 15) & ~15) + 1;
+        double *XS = stage + kStage - NB * XSS;   // X_k (NB x kw), after the panel
+        // (1) diagonal block: stage [D | I] (identity-padded beyond nb),
+        // factor and invert it with one wave, then publish L_kk, the
+        // diagonal block of X and of Rinv
+        {
+            constexpr int RSA = 2 * NB + 1;
+            for (int e = tid; e < NB * 2 * NB; e += kDenseThreads) {
+                const int i = e / (2 * NB), c = e - (e / (2 * NB)) * (2 * NB);
+                double v;
+                if (c < NB) {
+                    v = (i == c) ? 1.0 : 0.0;
+                    if (i < nb && c < nb) {
+                        const int r = i > c ? i : c, q = i > c ? c : i;   // lower part
+                        v = src[(size_t)(kb + r) * m + kb + q];
+                    }
+                } else {
+                    v = (i == c - NB) ? 1.0 : 0.0;
+                }
+                stage[i * RSA + c] = v;
+            }
+            __syncthreads();
+            if (wave == 0) {
+                diag_factor_wave<NB>(lane, stage, piv, mult, Dinv);
+                if (lane == 0) {
+                    int ok = 1;
+                    for (int k = 0; k < nb; ++k)
+                        if (!(piv[k] > kPivotTol * fabs(S[(size_t)(kb + k) * m + kb + k]))) ok = 0;
+                    ok_flag = ok;
+                }
+            }
+            __syncthreads();
+            if (!ok_flag) {
+                if (tid == 0) info[0] = kb + 1;
+                return;   // uniform
+            }
+            for (int e = tid; e < NB * NB; e += kDenseThreads) {
+                const int i = e / NB, c = e - (e / NB) * NB;
+                if (i < nb && c < nb) {
+                    if (c <= i) L[(size_t)(kb + i) * m + kb + c] = stage[c * RSA + i];
+                    const double xv = Dinv[i][c];
+                    X[(size_t)(kb + i) * m + kb + c] = xv;
+                    if (c <= i) Rinv[(size_t)(kb + c) * m + kb + i] = xv;
+                } else {
+                    Dinv[i][c] = 0.0;
+                }
+            }
+            __syncthreads();   // stage is reused below; Dinv padding visible
+        }
+        // (2) X_k = Dinv W_k on the columns left of the block; the block itself
+        // is Dinv.  Stage X_k (zero rows beyond nb) for the W update.
+        {
+            // one wave per 16-column tile of W_k, all NB rows: the tile is
+            // read completely before it is overwritten in place
+            const int nbj = kb / 16;
+            for (int bj = wave; bj < nbj; bj += nwaves) {
+                const int jc = bj * 16 + (lane & 15);
+                d4 acc[NB / 16];
+#pragma unroll
+                for (int bi = 0; bi < NB / 16; ++bi) acc[bi] = d4{0.0, 0.0, 0.0, 0.0};
+                for (int t0 = 0; t0 < nb; t0 += 4) {
+                    const int t = t0 + (lane >> 4);
+                    const double bv = (t < nb) ? X[(size_t)(kb + t) * m + jc] : 0.0;
+#pragma unroll
+                    for (int bi = 0; bi < NB / 16; ++bi)
+                        acc[bi] = mfma64(Dinv[bi * 16 + (lane & 15)][t], bv, acc[bi]);
+                }
+#pragma unroll
+                for (int bi = 0; bi < NB / 16; ++bi)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = bi * 16 + mfma64_row(lane, r);
+                        XS[i * XSS + jc] = (i < nb) ? acc[bi][r] : 0.0;
+                        if (i < nb) {
+                            X[(size_t)(kb + i) * m + jc] = acc[bi][r];
+                            Rinv[(size_t)jc * m + kb + i] = acc[bi][r];
+                        }
+                    }
+            }
+            for (int e = tid; e < NB * NB; e += kDenseThreads) {
+                const int i = e / NB, c = e - (e / NB) * NB;
+                if (kb + c < XSS - 1) XS[i * XSS + kb + c] = Dinv[i][c];
+            }
+        }
+        // (3) stage S_ik (R x nb), then the panel L_ik = S_ik Dinv^T
         for (int e = tid; e < R * NB; e += kDenseThreads) {
             const int r = e / NB, c = e % NB;
             stage[r * PS + c] = (c < nb) ? src[(size_t)(kb + nb + r) * m + kb + c] : 0.0;
         }
         __syncthreads();
         const int nbr = (R + 15) / 16;
-        // each wave computes whole 16-row strips of the panel (all NB columns);
-        // at most kStrips strips per wave (m / 16 / 16 for the largest m)
         constexpr int kStrips = (NB == 32) ? 2 : 4;
         d4 pacc[kStrips][NB / 16];
 #pragma unroll
@@ -187,98 +253,57 @@ __global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
             }
         }
         __syncthreads();
-        // trailing update of the lower triangle (disjoint from the panel columns)
+        // (4) trailing update of the lower triangle (disjoint from the panel
+        // columns) and of the W rows below the panel
         const int npairs = nbr * (nbr + 1) / 2;
-        for (int p = wave; p < npairs; p += nwaves) {
-            int bi, bj;
-            lower_pair(p, bi, bj);
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
-            const int ra = bi * 16 + (lane & 15), rb = bj * 16 + (lane & 15);
-            for (int t0 = 0; t0 < nb; t0 += 4) {
-                const int k = t0 + (lane >> 4);
-                const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
-                const double b = (rb < R) ? stage[rb * PS + k] : 0.0;
-                acc = mfma64(a, b, acc);
-            }
+        const int ncw = (kw + 15) / 16;
+        const int nwork = npairs + nbr * ncw;
+        for (int p = wave; p < nwork; p += nwaves) {
+            if (p < npairs) {
+                int bi, bj;
+                lower_pair(p, bi, bj);
+                // old values first, so their latency overlaps the products
+                double old[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
-                if (i < R && j <= i) {
-                    const size_t g = (size_t)(kb + nb + i) * m + kb + nb + j;
-                    L[g] = src[g] - acc[r];
+                for (int r = 0; r < 4; ++r) {
+                    const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                    old[r] = (i < R && j <= i) ? src[(size_t)(kb + nb + i) * m + kb + nb + j] : 0.0;
                 }
-            }
-        }
-        __syncthreads();
-    }
-
-    // recursive doubling of the inverse: level with block size b; operands
-    // are read from L2 eight k-steps at a time to keep loads in flight
-    for (int b = NB; b < m; b *= 2) {
-        const int nblk = (m + b - 1) / b;
-        const int npair = nblk / 2;
-        const int nbi = b / 16, nbj = b / 16;
-        const int work1 = npair * nbi * nbj;
-        // phase 1: T_q = L_CA X_A  (rows of C: up to b, columns of A: b)
-        for (int p = wave; p < work1; p += nwaves) {
-            const int q = p / (nbi * nbj), rem = p - q * (nbi * nbj);
-            const int bi = rem / nbj, bj = rem - (rem / nbj) * nbj;
-            const int cA = 2 * q * b, rC = cA + b;
-            const int nrC = (m - rC < b) ? (m - rC) : b;
-            if (bi * 16 >= nrC) continue;
-            const int ra = rC + bi * 16 + (lane & 15);
-            const int jc = cA + bj * 16 + (lane & 15);
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int k0 = (bj * 16) & ~3; k0 < b; k0 += 32) {
-                double av[8], bv[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int kk = k0 + 4 * u;
-                    const int k = cA + kk + (lane >> 4);
-                    const bool in = kk < b;
-                    av[u] = (in && ra < m) ? L[(size_t)ra * m + k] : 0.0;
-                    bv[u] = in ? X[(size_t)k * m + jc] : 0.0;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+                const int ra = bi * 16 + (lane & 15), rb = bj * 16 + (lane & 15);
+                for (int t0 = 0; t0 < nb; t0 += 4) {
+                    const int k = t0 + (lane >> 4);
+                    const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
+                    const double b = (rb < R) ? stage[rb * PS + k] : 0.0;
+                    acc = mfma64(a, b, acc);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc = mfma64(av[u], bv[u], acc);
-            }
-            double *Tq = T + (size_t)q * b * b;
+                for (int r = 0; r < 4; ++r) {
+                    const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                    if (i < R && j <= i) L[(size_t)(kb + nb + i) * m + kb + nb + j] = old[r] - acc[r];
+                }
+            } else {
+                const int q = p - npairs;
+                const int bi = q / ncw, bj = q - (q / ncw) * ncw;
+                double old[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
-                if (i < nrC) Tq[(size_t)i * b + j] = acc[r];
-            }
-        }
-        __syncthreads();
-        // phase 2: X_CA = -X_C T_q (and Rinv_AC = X_CA^T)
-        for (int p = wave; p < work1; p += nwaves) {
-            const int q = p / (nbi * nbj), rem = p - q * (nbi * nbj);
-            const int bi = rem / nbj, bj = rem - (rem / nbj) * nbj;
-            const int cA = 2 * q * b, rC = cA + b;
-            const int nrC = (m - rC < b) ? (m - rC) : b;
-            if (bi * 16 >= nrC) continue;
-            const int ra = rC + bi * 16 + (lane & 15);
-            const int kmax = (bi * 16 + 16 < nrC) ? bi * 16 + 16 : nrC;
-            const double *Tq = T + (size_t)q * b * b;
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < kmax; k0 += 32) {
-                double av[8], bv[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int k = k0 + 4 * u + (lane >> 4);
-                    const bool in = k < kmax;
-                    av[u] = (in && ra < m) ? X[(size_t)ra * m + rC + k] : 0.0;
-                    bv[u] = in ? Tq[(size_t)k * b + bj * 16 + (lane & 15)] : 0.0;
+                for (int r = 0; r < 4; ++r) {
+                    const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                    // columns of this panel were never updated: W = I there (0 off the diagonal)
+                    old[r] = (i < R && j < kb) ? X[(size_t)(kb + nb + i) * m + j] : 0.0;
+                }
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+                const int ra = bi * 16 + (lane & 15), jc = bj * 16 + (lane & 15);
+                for (int t0 = 0; t0 < nb; t0 += 4) {
+                    const int k = t0 + (lane >> 4);
+                    const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
+                    const double b = (jc < kw) ? XS[k * XSS + jc] : 0.0;
+                    acc = mfma64(a, b, acc);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc = mfma64(av[u], bv[u], acc);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
-                if (i < nrC) {
-                    X[(size_t)(rC + i) * m + cA + j] = -acc[r];
-                    Rinv[(size_t)(cA + j) * m + rC + i] = -acc[r];
+                for (int r = 0; r < 4; ++r) {
+                    const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                    if (i < R && j < kw) X[(size_t)(kb + nb + i) * m + j] = old[r] - acc[r];
                 }
             }
         }
@@ -306,13 +331,23 @@ __global__ void assemble_kernel(int m, const double *__restrict__ Hp,
 }  // namespace
 
 size_t chol_workspace(int m) {
-    return (size_t)3 * m * m * sizeof(double);
+    return (size_t)2 * m * m * sizeof(double);
 }
 
 void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
                   double *work, int32_t *info) {
     TM_REQUIRE(m >= 1 && m <= 1024, TM_ENOTSUP, "Cholesky supports m <= 1024");
-    // the staged panel (m x (NB+1) doubles) must fit the LDS staging area
+    // the staged panel (R x (NB+1)) and X_k (NB x (kb+nb) rounded to 16, +1)
+    // must fit the LDS staging area together, for every panel
+    {
+        const int NB = m <= 512 ? 32 : 16;
+        for (int kb = 0; kb < m; kb += NB) {
+            const int nb = std::min(NB, m - kb), R = m - kb - nb;
+            const int XSS = ((kb + nb + 15) & ~15) + 1;
+            TM_REQUIRE((size_t)R * (NB + 1) + (size_t)NB * XSS <= (size_t)kStage, TM_ENOTSUP,
+                       "Cholesky staging exceeds LDS");
+        }
+    }
     if (m <= 512)
         hipLaunchKernelGGL(chol_inv_kernel<32>, dim3(1), dim3(kDenseThreads), 0, s, m, S,
                            Rinv, work, info);

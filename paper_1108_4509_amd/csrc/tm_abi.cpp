@@ -136,6 +136,7 @@ void tm_opts_default(tm_opts *o) {
     o->k_check = 10;
     o->precondition = 0;
     o->history = 0;
+    o->transport = 1;
     o->switch_tol = 0.0;
     o->rise_tol = 1e-13;
 }
@@ -283,6 +284,7 @@ tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol, const tm
         TM_REQUIRE(o.max_iter >= 0, TM_EINVAL, "max_iter must be >= 0");
         TM_REQUIRE(o.precision >= TM_FULL_DP && o.precision <= TM_MIXED, TM_EINVAL, "unknown precision");
         TM_REQUIRE(history_len >= 0, TM_EINVAL, "history_len must be >= 0");
+        TM_REQUIRE(o.reserved0 == 0, TM_EINVAL, "tm_opts.reserved0 must be 0");
         std::memset(res, 0, sizeof(*res));
         Solver solver(ctx, H, m, tol, o);
         return solver.run(C0, C_out, eig_out, res, history, history_len);
@@ -449,19 +451,32 @@ tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m
         check_block_args(ctx, H->n, m);
         TM_REQUIRE(reps >= 1 && reps <= 100000, TM_EINVAL, "reps out of range");
         TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
-        TM_REQUIRE(kernel >= TM_K_SPMM && kernel <= TM_K_GRAM_MP2, TM_EINVAL, "unknown kernel");
+        TM_REQUIRE(kernel >= TM_K_SPMM && kernel <= TM_K_CHOL, TM_EINVAL, "unknown kernel");
         const int ld = leading_dim(m);
         const int64_t n = H->n;
-        const bool f64 = dtype == TM_F64 || kernel == TM_K_GRAM_MP2;
+        const bool mp2 = kernel == TM_K_GRAM_MP2 || kernel == TM_K_ROT_GRAD_MP2 || kernel == TM_K_TRMM_MP2;
+        const bool f64 = dtype == TM_F64 || mp2;
         const size_t blk = (size_t)n * ld * (f64 ? 8 : 4);
         hipStream_t s = ctx->stream;
         DevMem A(ctx, blk), B(ctx, blk), O(ctx, blk), vec(ctx, ld * sizeof(double)),
             ws(ctx, gram_workspace(n, m)), wp(ctx, (size_t)ld * ld * sizeof(double)),
-            mm(ctx, (size_t)m * m * sizeof(double));
+            mm(ctx, (size_t)m * m * sizeof(double)), g32(ctx, mp2 ? blk / 2 : 8),
+            ch(ctx, kernel == TM_K_CHOL ? chol_workspace(m) : 8), rinv(ctx, (size_t)m * m * sizeof(double)),
+            info(ctx, 64), dp(ctx, rot_partials_workspace(n, m));
         TM_HIP(hipMemsetAsync(A.ptr, 0x3c, blk, s));
+        TM_HIP(hipMemsetAsync(O.ptr, 0x3c, blk, s));
         TM_HIP(hipMemsetAsync(B.ptr, 0x3c, blk, s));
         TM_HIP(hipMemsetAsync(vec.ptr, 0, ld * sizeof(double), s));
         TM_HIP(hipMemsetAsync(wp.ptr, 0x3c, (size_t)ld * ld * sizeof(double), s));
+        if (kernel == TM_K_CHOL) {
+            // a well-conditioned SPD matrix: identity plus a small symmetric perturbation
+            std::vector<double> Sh((size_t)m * m);
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j)
+                    Sh[(size_t)i * m + j] = (i == j ? 1.0 : 0.0) + 1e-3 / (1.0 + i + j);
+            TM_HIP(hipMemcpyAsync(mm.ptr, Sh.data(), Sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            TM_HIP(hipStreamSynchronize(s));
+        }
         auto launch = [&]() {
             double *ws_p = (double *)ws.ptr, *mm_p = (double *)mm.ptr, *v = (double *)vec.ptr;
             switch (kernel) {
@@ -484,6 +499,19 @@ tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m
                 break;
             case TM_K_GRAM_MP2:
                 gram<double, float>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false);
+                break;
+            case TM_K_ROT_GRAD_MP2: {
+                // the refinement-phase gradient: FP64 C and X, FP32 H' and FP32 G, fused traces
+                float *G = (float *)g32.ptr, *Gprev = (float *)O.ptr, *Pprev = Gprev + n * ld;
+                rot<double, float, float>(s, n, m, (double *)A.ptr, (float *)wp.ptr, EPI_GRAD, (double *)B.ptr, v,
+                                          G, Gprev, Pprev, nullptr, (double *)dp.ptr);
+                break;
+            }
+            case TM_K_TRMM_MP2:
+                rot<double, float, double>(s, n, m, (double *)A.ptr, (float *)wp.ptr, EPI_TRMM, nullptr, v, (double *)O.ptr);
+                break;
+            case TM_K_CHOL:
+                chol_inverse(s, m, mm_p, (double *)rinv.ptr, (double *)ch.ptr, (int32_t *)info.ptr);
                 break;
             }
         };

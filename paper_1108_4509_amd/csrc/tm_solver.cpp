@@ -193,7 +193,18 @@ struct Solver::Impl {
         if (rotate) {
             // the rotation keeps C's own precision (FP64 C stays FP64-accurate)
             rayleigh_ritz<TC, TC>(C, Cn, X);
-            set_restart();
+            if (o.transport) {
+                // E(C U) = E(C) and G(C U) = G(C) U (Sec. 2.1): the previous
+                // direction and gradient carried into the rotated basis keep
+                // the Polak-Ribiere traces unchanged, so CG continues
+                pad_matrix<TG>(s, m, (double *)U->ptr, false, (TG *)Wp->ptr, nullptr);
+                rot<TG, TG, TG>(s, n, m, (TG *)P->ptr, (TG *)Wp->ptr, EPI_NONE, nullptr, nullptr, (TG *)Y->ptr);
+                std::swap(P, Y);
+                rot<TG, TG, TG>(s, n, m, (TG *)Gp->ptr, (TG *)Wp->ptr, EPI_NONE, nullptr, nullptr, (TG *)G->ptr);
+                std::swap(G, Gp);
+            } else {
+                set_restart();
+            }
         }
         TG *Gv = (TG *)G->ptr, *Gpv = (TG *)Gp->ptr, *Pv = (TG *)P->ptr, *Yv = (TG *)Y->ptr;
         const double *Mv = M ? (const double *)M->ptr : nullptr;

@@ -301,3 +301,45 @@ def test_c2_gram_sampled(ctx, tm, c2):
             ref = float(Ch[:, i] @ Xh[:, j])
             bound = 2 * gamma(c2.N, u) * float(np.abs(Ch[:, i]) @ np.abs(Xh[:, j]))
             assert abs(G[i, j] - ref) <= bound
+
+
+# Blocks of at least 65536 rows whose width cuts into 512-byte column slabs go
+# through the slab kernels (each XCD sweeps one slab's row range); ragged row
+# counts, both stencil orders, 1 to 16 slabs, and the fused column dots.
+_SLAB_CASES = [
+    ("7pt_m128", StencilSpec(3, (42, 42, 42), 2, "periodic", 0.5), 128, 3),
+    ("7pt_m512", StencilSpec(3, (41, 43, 40), 2, "periodic", 0.5), 512, 0),
+    ("13pt_m256", StencilSpec(3, (41, 41, 41), 4, "periodic", 0.5), 256, 4),
+    ("7pt_m1024", StencilSpec(3, (42, 40, 40), 2, "dirichlet", 0.5), 1000, 0),
+]
+
+
+@pytest.mark.parametrize("case", _SLAB_CASES, ids=[c[0] for c in _SLAB_CASES])
+@pytest.mark.parametrize("stencil", [False, True], ids=["csr", "stencil"])
+def test_spmm_slab_path(ctx, tm, orc, case, stencil):
+    import torch
+    name, spec, m, wells = case
+    prob = make_problem(name, spec, m=m, seed=11, n_wells=wells)
+    print_case(test="spmm_slab", case=name, stencil=stencil, N=prob.N, m=m)
+    H = orc.csr_matrix(*prob.csr(), prob.N)
+    Hd = tm.matrix_from_problem(ctx, prob, stencil=stencil)
+    C = rand_block(np.random.default_rng(3), prob.N, m)
+    rows = np.random.default_rng(4).choice(prob.N, 1500, replace=False)
+    nnz_row = int(np.max(np.diff(prob.csr()[0])))
+    for dt, u in ((torch.float64, U64), (torch.float32, U32)):
+        Cd = tm.to_block(C, dtype=dt)
+        Xd = torch.full_like(Cd, np.nan)
+        tm.spmm(ctx, Hd, m, Cd, Xd)
+        Cr = host(Cd, m).astype(np.float64)
+        ref = np.asarray(H[rows] @ Cr)
+        absref = np.asarray(abs(H)[rows] @ np.abs(Cr))
+        got = host(Xd[rows])
+        assert np.all(np.abs(got[:, :m] - ref) <= 2 * gamma(nnz_row + 1, u) * absref)
+        assert np.all(got[:, m:] == 0)
+    # the fused h_j = c_j . (H c_j) of Algorithm-2, step (2), FP64
+    Q = orc.orthonormalize(C)
+    E, G, X, h, Hp = tm.energy_grad(ctx, Hd, m, tm.to_block(Q))
+    Xo = orc.spmm(H, Q)
+    h_o = np.einsum("ij,ij->j", Q, Xo)
+    bound = 4 * gamma(prob.N + nnz_row, U64) * np.einsum("ij,ij->j", np.abs(Q), abs(H) @ np.abs(Q))
+    assert np.all(np.abs(host(h) - h_o) <= bound)

@@ -86,6 +86,25 @@ def test_c1_full_dp(ctx, tm, c1_oracle, stencil):
     assert abs(r["iterations"] - c1_oracle.iterations) <= 0.25 * c1_oracle.iterations + 10
 
 
+def test_c1_rotation_transport(ctx, tm, orc):
+    """With P and G_prev carried through each rotation (k_rot = 5) the GPU
+    iteration follows the oracle's: the energies agree while rounding has not
+    been amplified, the rotation at i = 5 leaves the energy curve of the
+    unrotated oracle run intact to the line-step weights, and E_G is exact."""
+    p = config_problem("c1")
+    print_case(test="c1_transport", k_rot=5)
+    Ho = orc.csr_matrix(*p.csr(), p.N)
+    ref = orc.solve(Ho, p.C0(), orc.OracleOptions(tol=1e-8, k_rot=5, transport=True))
+    r, C, w, hist = _solve(tm, ctx, p, hist=400, k_rot=5, transport=True)
+    exact = 54 * (1 - math.cos(math.pi / 8))
+    assert r["converged"] == 1 and r["restarts"] == 1
+    assert abs(r["E_G"] - exact) <= 1e-10 * exact
+    Eo = np.array(ref.energies)
+    k = 30
+    assert np.max(np.abs(hist[:k, 0] - Eo[:k]) / np.abs(Eo[:k])) < 1e-9
+    assert abs(r["iterations"] - ref.iterations) <= 0.25 * ref.iterations + 10
+
+
 def test_c1_vectors_and_residual_definition(ctx, tm, orc):
     """The returned C: orthonormal, and max_j ||H c_j - C (C^T H c_j)|| <= 1e-8."""
     p = config_problem("c1")

@@ -275,3 +275,26 @@ def test_single_vector_rayleigh_minimum(oracle_mod):
     assert abs(r.E_G) < 1e-15 + 1e-12
     c = r.C[:, 0]
     assert np.max(np.abs(np.abs(c) - 1 / math.sqrt(p.N))) < 1e-9
+
+
+def test_rotation_transport_leaves_cg_intact(oracle_mod):
+    """A subspace rotation C <- C U changes neither E nor the subspace
+    (Sec. 2.1), and the gradient maps as G -> G U, so the Polak-Ribiere gamma
+    (Eq. 8) computed after carrying P and G_prev through the same U equals the
+    gamma of the unrotated run to rounding; the step along the carried
+    direction differs only through the per-column curvature weights of the
+    line step (about 1 % here).  A transposed U or a block left uncarried moves
+    gamma by ~20 % or the step by ~80 %."""
+    from workloads import config_problem
+    p = config_problem("c1")
+    H = oracle_mod.csr_matrix(*p.csr(), p.N)
+    base = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(tol=1e-8, k_rot=0, max_iter=8))
+    rot = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(tol=1e-8, k_rot=5, transport=True,
+                                                               max_iter=8))
+    assert np.allclose(rot.energies[:6], base.energies[:6], rtol=1e-13, atol=0)
+    assert abs(rot.gammas[5] - base.gammas[5]) <= 1e-12 * abs(base.gammas[5])
+    assert abs(rot.alphas[5] - base.alphas[5]) <= 0.05 * base.alphas[5]
+    assert rot.restarts == 1          # only i = 0
+    full = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(tol=1e-8, k_rot=5, transport=True))
+    exact = 54 * (1 - math.cos(math.pi / 8))
+    assert full.converged and abs(full.E_G - exact) <= 1e-12 * exact

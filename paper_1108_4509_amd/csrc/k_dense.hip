@@ -39,16 +39,21 @@ __device__ inline void lower_pair(int p, int &bi, int &bj) {
 // Factor the NB x NB diagonal block D = L_kk L_kk^T and invert it, by one
 // wave, on the augmented NB x 2NB matrix [D | I] staged in LDS (aug, row
 // stride 2NB + 1): lane c keeps column c in registers (rows a[0..NB)).
-// Gaussian elimination without pivoting: at step k lane k publishes the
-// multipliers a_ik / a_kk through LDS and every lane updates its own column;
-// wave-scope fences order the exchange, so no workgroup barrier is needed.  Afterwards the D half holds U = diag(d) L1^T and
+// Gaussian elimination without pivoting: at step k every lane reads the
+// multipliers a_ik / a_kk of lane k's column by readlane and updates its own
+// column, so no barrier and no memory round trip is needed.  Afterwards the D half holds U = diag(d) L1^T and
 // the I half L1^{-1} (L1 unit lower), so L = L1 diag(d)^{1/2} and
 // L^{-1} = diag(d)^{-1/2} L1^{-1}.  Results go back to LDS: L_kk^T into the
 // D half of aug, L_kk^{-1} (zero above the diagonal) into Dinv, the pivots d
 // into piv.  For NB = 16 the upper 32 lanes repeat the last column.
+__device__ inline double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 template <int NB>
-__device__ void diag_factor_wave(int lane, double *aug, double *piv, double *mult,
-                                 double (*Dinv)[NB + 1]) {
+__device__ void diag_factor_wave(int lane, double *aug, double *piv, double (*Dinv)[NB + 1]) {
     constexpr int NC = 2 * NB, RS = 2 * NB + 1;
     const int c = lane < NC ? lane : NC - 1;
     double a[NB];
@@ -56,24 +61,14 @@ __device__ void diag_factor_wave(int lane, double *aug, double *piv, double *mul
     for (int i = 0; i < NB; ++i) a[i] = aug[i * RS + c];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        double *mk = mult + (k & 1) * NB;   // double-buffered: no WAR between steps
-        if (lane == k) {
-            const double inv = 1.0 / a[k];
-            piv[k] = a[k];
+        // the multipliers a_ik / a_kk come from lane k by readlane
+        const double dk = readlane_f64(a[k], k);
+        if (lane == 0) piv[k] = dk;
+        // a_ic -= a_ik (a_kc / a_kk): one scaling per lane, one FMA per row
+        const double rk = a[k] * (1.0 / dk);
 #pragma unroll
-            for (int i = k + 1; i < NB; ++i) mk[i] = a[i] * inv;
-        }
-        // make lane k's LDS writes visible to the whole wave
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double rk = a[k];
-#pragma unroll
-        for (int i = k + 1; i < NB; ++i) a[i] = fma(-mk[i], rk, a[i]);
+        for (int i = k + 1; i < NB; ++i) a[i] = fma(-readlane_f64(a[i], k), rk, a[i]);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane < NB) {
         // lane i: row i of L, L_iq = U_qi / sqrt(d_q) for q <= i, stored transposed
 #pragma unroll
@@ -106,7 +101,7 @@ __global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
     __shared__ double stage[kStage];
     __shared__ double Dinv[NB][NB + 1];
     __shared__ double piv[NB];
-    __shared__ double mult[2 * NB];
+    __shared__ double Sd[NB];
     __shared__ int ok_flag;
     constexpr int PS = NB + 1;   // row stride of the staged panel
     double *L = work;
@@ -131,27 +126,32 @@ __global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
         // diagonal block of X and of Rinv
         {
             constexpr int RSA = 2 * NB + 1;
-            for (int e = tid; e < NB * 2 * NB; e += kDenseThreads) {
+            constexpr int NA = NB * 2 * NB, UA = (NA + kDenseThreads - 1) / kDenseThreads;
+            double v[UA];
+#pragma unroll
+            for (int u = 0; u < UA; ++u) {
+                const int e = tid + u * kDenseThreads;
                 const int i = e / (2 * NB), c = e - (e / (2 * NB)) * (2 * NB);
-                double v;
-                if (c < NB) {
-                    v = (i == c) ? 1.0 : 0.0;
-                    if (i < nb && c < nb) {
-                        const int r = i > c ? i : c, q = i > c ? c : i;   // lower part
-                        v = src[(size_t)(kb + r) * m + kb + q];
-                    }
-                } else {
-                    v = (i == c - NB) ? 1.0 : 0.0;
+                v[u] = (i == c || i == c - NB) ? 1.0 : 0.0;
+                if (e < NA && c < NB && i < nb && c < nb) {
+                    const int r = i > c ? i : c, q = i > c ? c : i;   // lower part
+                    v[u] = src[(size_t)(kb + r) * m + kb + q];
                 }
-                stage[i * RSA + c] = v;
             }
+            const double sd = (tid < nb) ? S[(size_t)(kb + tid) * m + kb + tid] : 1.0;
+#pragma unroll
+            for (int u = 0; u < UA; ++u) {
+                const int e = tid + u * kDenseThreads;
+                if (e < NA) stage[(e / (2 * NB)) * RSA + e % (2 * NB)] = v[u];
+            }
+            if (tid < NB) Sd[tid] = sd;
             __syncthreads();
             if (wave == 0) {
-                diag_factor_wave<NB>(lane, stage, piv, mult, Dinv);
+                diag_factor_wave<NB>(lane, stage, piv, Dinv);
                 if (lane == 0) {
                     int ok = 1;
                     for (int k = 0; k < nb; ++k)
-                        if (!(piv[k] > kPivotTol * fabs(S[(size_t)(kb + k) * m + kb + k]))) ok = 0;
+                        if (!(piv[k] > kPivotTol * fabs(Sd[k]))) ok = 0;
                     ok_flag = ok;
                 }
             }
@@ -184,13 +184,17 @@ __global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
                 d4 acc[NB / 16];
 #pragma unroll
                 for (int bi = 0; bi < NB / 16; ++bi) acc[bi] = d4{0.0, 0.0, 0.0, 0.0};
-                for (int t0 = 0; t0 < nb; t0 += 4) {
-                    const int t = t0 + (lane >> 4);
-                    const double bv = (t < nb) ? X[(size_t)(kb + t) * m + jc] : 0.0;
+                double bv[NB / 4];   // all loads in flight before the products
+#pragma unroll
+                for (int u = 0; u < NB / 4; ++u) {
+                    const int t = 4 * u + (lane >> 4);
+                    bv[u] = (t < nb) ? X[(size_t)(kb + t) * m + jc] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NB / 4; ++u)
 #pragma unroll
                     for (int bi = 0; bi < NB / 16; ++bi)
-                        acc[bi] = mfma64(Dinv[bi * 16 + (lane & 15)][t], bv, acc[bi]);
-                }
+                        acc[bi] = mfma64(Dinv[bi * 16 + (lane & 15)][4 * u + (lane >> 4)], bv[u], acc[bi]);
 #pragma unroll
                 for (int bi = 0; bi < NB / 16; ++bi)
 #pragma unroll
@@ -209,9 +213,18 @@ __global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
             }
         }
         // (3) stage S_ik (R x nb), then the panel L_ik = S_ik Dinv^T
-        for (int e = tid; e < R * NB; e += kDenseThreads) {
-            const int r = e / NB, c = e % NB;
-            stage[r * PS + c] = (c < nb) ? src[(size_t)(kb + nb + r) * m + kb + c] : 0.0;
+        for (int e0 = tid; e0 < R * NB; e0 += 8 * kDenseThreads) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kDenseThreads, r = e / NB, c = e % NB;
+                v[u] = (e < R * NB && c < nb) ? src[(size_t)(kb + nb + r) * m + kb + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kDenseThreads;
+                if (e < R * NB) stage[(e / NB) * PS + e % NB] = v[u];
+            }
         }
         __syncthreads();
         const int nbr = (R + 15) / 16;
@@ -259,50 +272,45 @@ __global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
         const int ncw = (kw + 15) / 16;
         const int nwork = npairs + nbr * ncw;
         for (int p = wave; p < nwork; p += nwaves) {
-            if (p < npairs) {
-                int bi, bj;
+            const bool sym = p < npairs;
+            int bi, bj;
+            if (sym) {
                 lower_pair(p, bi, bj);
-                // old values first, so their latency overlaps the products
-                double old[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
-                    old[r] = (i < R && j <= i) ? src[(size_t)(kb + nb + i) * m + kb + nb + j] : 0.0;
-                }
-                d4 acc = {0.0, 0.0, 0.0, 0.0};
-                const int ra = bi * 16 + (lane & 15), rb = bj * 16 + (lane & 15);
-                for (int t0 = 0; t0 < nb; t0 += 4) {
-                    const int k = t0 + (lane >> 4);
-                    const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
-                    const double b = (rb < R) ? stage[rb * PS + k] : 0.0;
-                    acc = mfma64(a, b, acc);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
-                    if (i < R && j <= i) L[(size_t)(kb + nb + i) * m + kb + nb + j] = old[r] - acc[r];
-                }
             } else {
                 const int q = p - npairs;
-                const int bi = q / ncw, bj = q - (q / ncw) * ncw;
-                double old[4];
+                bi = q / ncw;
+                bj = q - bi * ncw;
+            }
+            // old values first, so their latency overlaps the products
+            double old[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+            for (int r = 0; r < 4; ++r) {
+                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                double v = 0.0;
+                if (sym) {
+                    if (i < R && j <= i) v = src[(size_t)(kb + nb + i) * m + kb + nb + j];
+                } else {
                     // columns of this panel were never updated: W = I there (0 off the diagonal)
-                    old[r] = (i < R && j < kb) ? X[(size_t)(kb + nb + i) * m + j] : 0.0;
+                    if (i < R && j < kb) v = X[(size_t)(kb + nb + i) * m + j];
                 }
-                d4 acc = {0.0, 0.0, 0.0, 0.0};
-                const int ra = bi * 16 + (lane & 15), jc = bj * 16 + (lane & 15);
-                for (int t0 = 0; t0 < nb; t0 += 4) {
-                    const int k = t0 + (lane >> 4);
-                    const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
-                    const double b = (jc < kw) ? XS[k * XSS + jc] : 0.0;
-                    acc = mfma64(a, b, acc);
-                }
+                old[r] = v;
+            }
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            const int ra = bi * 16 + (lane & 15), rb = bj * 16 + (lane & 15);
+            for (int t0 = 0; t0 < nb; t0 += 4) {
+                const int k = t0 + (lane >> 4);
+                const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
+                double b;
+                if (sym) b = (rb < R) ? stage[rb * PS + k] : 0.0;
+                else b = (rb < kw) ? XS[k * XSS + rb] : 0.0;
+                acc = mfma64(a, b, acc);
+            }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+            for (int r = 0; r < 4; ++r) {
+                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                if (sym) {
+                    if (i < R && j <= i) L[(size_t)(kb + nb + i) * m + kb + nb + j] = old[r] - acc[r];
+                } else {
                     if (i < R && j < kw) X[(size_t)(kb + nb + i) * m + j] = old[r] - acc[r];
                 }
             }

@@ -452,7 +452,9 @@ __device__ void slab_flush_dots(const double (&d)[2][SlabE<T>::W], int ndot, int
     __syncthreads();
 }
 
-template <typename T>
+// RW consecutive rows per wave and step: the first eight nonzeros of all RW
+// rows are gathered before any is consumed, so 8 RW loads are in flight.
+template <typename T, int RW>
 __global__ __launch_bounds__(256) void spmm_csr_slab_kernel(
     int64_t n, int ldE, int nslab, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const T *__restrict__ val,
@@ -476,30 +478,41 @@ __global__ __launch_bounds__(256) void spmm_csr_slab_kernel(
         for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int q = 0; q < W; ++q) d[p][q] = 0.0;
-        for (int64_t r = mp.r0 + w; r < mp.r1; r += wpx) {
-            const int64_t k0 = rowptr[r], k1 = rowptr[r + 1];
-            E acc = E(0);
-            // eight nonzeros at a time: a 7-point row is one batch of loads
-            for (int64_t k = k0; k < k1; k += 8) {
-                E v[8];
-                T a[8];
+        for (int64_t rb = mp.r0 + (int64_t)w * RW; rb < mp.r1; rb += (int64_t)wpx * RW) {
+            int64_t k0[RW], k1[RW];
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+                const bool in = rb + t < mp.r1;
+                k0[t] = in ? rowptr[rb + t] : 0;
+                k1[t] = in ? rowptr[rb + t + 1] : 0;
+            }
+            E v[RW][8];
+            T a[RW][8];
+#pragma unroll
+            for (int t = 0; t < RW; ++t)
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const bool in = k + u < k1;
-                    a[u] = in ? val[k + u] : T(0);
-                    v[u] = in ? Cs[(int64_t)col[k + u] * ldE] : E(0);
+                    const bool in = k0[t] + u < k1[t];
+                    a[t][u] = in ? val[k0[t] + u] : T(0);
+                    v[t][u] = in ? Cs[(int64_t)col[k0[t] + u] * ldE] : E(0);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc = a[u] * v[u] + acc;
-            }
-            Xs[r * ldE] = acc;
-            if (ndot > 0) {
-                const E c = Cs[r * ldE];
+            for (int t = 0; t < RW; ++t) {
+                if (rb + t >= mp.r1) break;
+                E acc = E(0);
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const double cq = slab_elem<T>(c, q);
-                    d[0][q] += cq * slab_elem<T>(acc, q);
-                    if (ndot > 1) d[1][q] += cq * cq;
+                for (int u = 0; u < 8; ++u) acc = a[t][u] * v[t][u] + acc;
+                for (int64_t k = k0[t] + 8; k < k1[t]; ++k) acc = val[k] * Cs[(int64_t)col[k] * ldE] + acc;
+                const int64_t r = rb + t;
+                Xs[r * ldE] = acc;
+                if (ndot > 0) {
+                    const E c = Cs[r * ldE];
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        const double cq = slab_elem<T>(c, q);
+                        d[0][q] += cq * slab_elem<T>(acc, q);
+                        if (ndot > 1) d[1][q] += cq * cq;
+                    }
                 }
             }
         }
@@ -579,6 +592,7 @@ int slab_count(int ld) {
 }
 
 constexpr int kSlabGrid = 1024;   // 128 workgroups (512 waves) per XCD
+constexpr int kSlabRows = 4;      // consecutive rows per wave step (CSR)
 
 // partial rows written by a slab launch
 inline int slab_partial_rows(int nslab) {
@@ -613,7 +627,7 @@ int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
     if constexpr (sizeof(T) == 8) val = H.val64; else val = H.val32;
     if (const int ns = slab_count<T>(ld); ns > 0 && H.n >= 64 * kSlabGrid) {
         using E = typename SlabE<T>::type;
-        hipLaunchKernelGGL(spmm_csr_slab_kernel<T>, dim3(kSlabGrid), dim3(256), 0, s, H.n,
+        hipLaunchKernelGGL((spmm_csr_slab_kernel<T, kSlabRows>), dim3(kSlabGrid), dim3(256), 0, s, H.n,
                            ld / SlabE<T>::W, ns, H.rowptr, H.col, val,
                            reinterpret_cast<const E *>(C), reinterpret_cast<E *>(X), ndot, partials);
         TM_HIP(hipGetLastError());

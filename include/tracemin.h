@@ -44,7 +44,8 @@ typedef enum tm_status {
     TM_ENOCONV = -4,  /* max_iter reached; result filled, converged = 0       */
     TM_ENAN = -5,     /* NaN or Inf in the energy or gradient norm            */
     TM_EDEVICE = -6,  /* HIP runtime error (text in tm_last_error)            */
-    TM_ENOTSUP = -7   /* option combination not supported                    */
+    TM_ENOTSUP = -7,  /* option combination not supported                    */
+    TM_EAGAIN = -8    /* a served request is still queued or running          */
 } tm_status;
 
 typedef enum tm_dtype { TM_F64 = 0, TM_F32 = 1 } tm_dtype;
@@ -168,6 +169,71 @@ tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol,
                    const tm_opts *opts, const double *C0, double *C_out,
                    double *eig_out, tm_result *res, double *history,
                    int32_t history_len);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of independent solves on one GPU (for callers that
+ * serve many eigenproblems of different N and m).  Requests queue in arrival
+ * order and are admitted as soon as one of max_slots slots is idle and the
+ * request's memory bound (tm_solve_footprint) fits the free part of
+ * hbm_budget; admitted requests run concurrently, each on its own HIP stream
+ * and host thread.  A request computes exactly what tm_solve computes for the
+ * same inputs: the kernels, launch shapes and reduction orders do not depend
+ * on what else is running.  The server is internally synchronized; all entry
+ * points may be called from any host thread. */
+typedef struct tm_server tm_server;
+
+typedef struct tm_server_opts {
+    int32_t device;        /* HIP device                                        */
+    int32_t max_slots;     /* solves in flight, 1..16                           */
+    uint64_t hbm_budget;   /* device bytes reserved at creation for requests    */
+} tm_server_opts;
+
+typedef struct tm_request {
+    int64_t n;             /* rows of H                                         */
+    const int64_t *rowptr; /* host CSR of H (as tm_set_matrix_csr); copied      */
+    const int32_t *col;
+    const double *val;
+    int32_t m;             /* eigenpairs wanted, 1 <= m <= n                    */
+    int32_t reserved;      /* must be 0 */
+    double tol;            /* stop when ||X - C A||_F <= tol                    */
+    const double *C0;      /* host n x m FP64 start block, row-major; copied    */
+    const tm_opts *opts;   /* NULL: tm_opts_default with precision TM_MIXED     */
+} tm_request;
+
+typedef struct tm_server_stats {
+    int64_t submitted, completed, failed, rejected, queued, running;
+    double p50_latency_s;  /* submit -> result, nearest-rank percentiles over   */
+    double p99_latency_s;  /* all finished requests                             */
+    double max_latency_s;
+    double mean_latency_s;
+    double span_s;         /* first submit -> last completion                   */
+    double solves_per_s;   /* finished requests / span_s                        */
+    uint64_t hbm_budget;
+    uint64_t hbm_peak;     /* largest sum of admitted memory bounds             */
+} tm_server_stats;
+
+/* Device bytes tm_solve may allocate for an n x m problem with nnz stored
+ * nonzeros under opts (NULL: defaults), plus the start block and the
+ * eigenvalues: the admission bound used by the server. */
+tm_status tm_solve_footprint(int64_t n, int64_t nnz, int32_t m, const tm_opts *opts,
+                             uint64_t *bytes);
+/* Reserves hbm_budget bytes on the device and starts max_slots worker
+ * threads.  TM_EINVAL for bad options, TM_ENOMEM if the reservation fails. */
+tm_status tm_server_create(const tm_server_opts *opts, tm_server **out);
+/* Queues a request (inputs are copied; the caller may free them on return).
+ * TM_ENOMEM if its memory bound exceeds the whole budget (counted as
+ * rejected), TM_EINVAL for malformed input. */
+tm_status tm_server_submit(tm_server *srv, const tm_request *req, uint64_t *id);
+/* TM_EAGAIN while the request is queued or running.  Once finished: fills
+ * *res and eig_out (host, m doubles; either may be NULL), returns the solve's
+ * status (tm_last_error holds its text) and forgets the request. */
+tm_status tm_server_poll(tm_server *srv, uint64_t id, tm_result *res, double *eig_out);
+/* As tm_server_poll, blocking up to timeout_s seconds (< 0: no limit). */
+tm_status tm_server_wait(tm_server *srv, uint64_t id, double timeout_s, tm_result *res,
+                         double *eig_out);
+tm_status tm_server_get_stats(tm_server *srv, tm_server_stats *out);
+/* Drops queued requests, waits for running ones, releases everything. */
+void tm_server_destroy(tm_server *srv);
 
 /* ------------------------------------------------ steps of the iteration
  * The kernels of one iteration, exposed one by one so that each can be

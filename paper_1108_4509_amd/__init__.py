@@ -307,3 +307,81 @@ def time_kernel(ctx: Context, H: Matrix, kernel: str, m: int, dtype: str = "f32"
     _abi.check(_abi.lib().tm_time_kernel(ctx.handle, H.handle, KERNELS[kernel], m, code, reps,
                                          ctypes.byref(out)), "tm_time_kernel")
     return out.value
+
+
+# ------------------------------------------------------------------ serving
+
+def solve_footprint(n: int, nnz: int, m: int, options=None) -> int:
+    """Device bytes the server reserves for one request (tm_solve_footprint)."""
+    out = ctypes.c_uint64()
+    o = ctypes.byref(options) if options is not None else None
+    _abi.check(_abi.lib().tm_solve_footprint(n, nnz, m, o, ctypes.byref(out)), "tm_solve_footprint")
+    return out.value
+
+
+class Server:
+    """Continuous-batching solve server (tm_server_*): requests are host CSR
+    matrices with a host start block; results are host eigenvalues."""
+
+    def __init__(self, device: int = 0, max_slots: int = 4, hbm_budget: int = 16 << 30):
+        o = _abi.tm_server_opts(device=device, max_slots=max_slots, hbm_budget=hbm_budget)
+        h = ctypes.c_void_p()
+        _abi.check(_abi.lib().tm_server_create(ctypes.byref(o), ctypes.byref(h)), "tm_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, rowptr, col, val, m: int, tol: float, C0, options=None) -> int:
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        C0 = np.ascontiguousarray(C0, dtype=np.float64)
+        n = len(rowptr) - 1
+        if C0.shape != (n, m):
+            raise ValueError("C0 must be n x m")
+        req = _abi.tm_request(n=n, rowptr=rowptr.ctypes.data, col=col.ctypes.data,
+                              val=val.ctypes.data, m=m, reserved=0, tol=tol,
+                              C0=C0.ctypes.data,
+                              opts=ctypes.pointer(options) if options is not None else None)
+        rid = ctypes.c_uint64()
+        _abi.check(_abi.lib().tm_server_submit(self.handle, ctypes.byref(req), ctypes.byref(rid)),
+                   "tm_server_submit")
+        self._keep[rid.value] = m
+        return rid.value
+
+    def _result(self, fn, rid: int, *args):
+        m = self._keep[rid]
+        res = _abi.tm_result()
+        eig = np.zeros(m)
+        st = fn(self.handle, rid, *args, ctypes.byref(res), eig.ctypes.data)
+        if st == _abi.TM_EAGAIN:
+            return None
+        del self._keep[rid]
+        _abi.check(st, "served solve", allow=(_abi.TM_OK, _abi.TM_ENOCONV))
+        d = res.as_dict()
+        d["status"] = st
+        return d, eig
+
+    def poll(self, rid: int):
+        """(result dict, eigenvalues) once finished, else None."""
+        return self._result(_abi.lib().tm_server_poll, rid)
+
+    def wait(self, rid: int, timeout: float = -1.0):
+        return self._result(_abi.lib().tm_server_wait, rid, float(timeout))
+
+    def stats(self) -> dict:
+        s = _abi.tm_server_stats()
+        _abi.check(_abi.lib().tm_server_get_stats(self.handle, ctypes.byref(s)), "tm_server_get_stats")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _abi.lib().tm_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass

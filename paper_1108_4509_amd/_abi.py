@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtracemin.so")
 
 # status codes
-TM_OK, TM_EINVAL, TM_ENOMEM, TM_ENOTSPD, TM_ENOCONV, TM_ENAN, TM_EDEVICE, TM_ENOTSUP = \
-    0, -1, -2, -3, -4, -5, -6, -7
+TM_OK, TM_EINVAL, TM_ENOMEM, TM_ENOTSPD, TM_ENOCONV, TM_ENAN, TM_EDEVICE, TM_ENOTSUP, TM_EAGAIN = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 TM_F64, TM_F32 = 0, 1
 TM_FULL_DP, TM_FULL_SP, TM_MP2, TM_MIXED = 0, 1, 2, 3
 
@@ -54,6 +54,28 @@ class tm_result(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class tm_server_opts(ctypes.Structure):
+    _fields_ = [("device", c_int32), ("max_slots", c_int32), ("hbm_budget", ctypes.c_uint64)]
+
+
+class tm_request(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("rowptr", c_void_p), ("col", c_void_p), ("val", c_void_p),
+                ("m", c_int32), ("reserved", c_int32), ("tol", c_double), ("C0", c_void_p),
+                ("opts", ctypes.POINTER(tm_opts))]
+
+
+class tm_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", c_int64), ("completed", c_int64), ("failed", c_int64),
+                ("rejected", c_int64), ("queued", c_int64), ("running", c_int64),
+                ("p50_latency_s", c_double), ("p99_latency_s", c_double),
+                ("max_latency_s", c_double), ("mean_latency_s", c_double),
+                ("span_s", c_double), ("solves_per_s", c_double),
+                ("hbm_budget", ctypes.c_uint64), ("hbm_peak", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # name -> (restype, argtypes); mirrors include/tracemin.h
 SIGNATURES = {
     "tm_leading_dim": (c_int32, [c_int32]),
@@ -82,6 +104,16 @@ SIGNATURES = {
     "tm_sym_eig": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "tm_time_kernel": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
                                  ctypes.POINTER(c_double)]),
+    "tm_solve_footprint": (c_int32, [c_int64, c_int64, c_int32, ctypes.POINTER(tm_opts),
+                                     ctypes.POINTER(ctypes.c_uint64)]),
+    "tm_server_create": (c_int32, [ctypes.POINTER(tm_server_opts), ctypes.POINTER(c_void_p)]),
+    "tm_server_submit": (c_int32, [c_void_p, ctypes.POINTER(tm_request),
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "tm_server_poll": (c_int32, [c_void_p, ctypes.c_uint64, ctypes.POINTER(tm_result), c_void_p]),
+    "tm_server_wait": (c_int32, [c_void_p, ctypes.c_uint64, c_double, ctypes.POINTER(tm_result),
+                                 c_void_p]),
+    "tm_server_get_stats": (c_int32, [c_void_p, ctypes.POINTER(tm_server_stats)]),
+    "tm_server_destroy": (None, [c_void_p]),
 }
 
 (TM_K_SPMM, TM_K_GRAM_SHIFT, TM_K_GRAM_SYM, TM_K_ROT_GRAD, TM_K_TRMM, TM_K_GRAM_MP2,

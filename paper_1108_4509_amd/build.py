@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libtracemin.so")
 ARCH = os.environ.get("TRACEMIN_ARCH", "gfx950")
 
 SOURCES = ["k_spmm.hip", "k_gemm.hip", "k_vec.hip", "k_dense.hip", "k_jacobi.hip",
-           "tm_solver.cpp", "tm_abi.cpp"]
+           "tm_solver.cpp", "tm_abi.cpp", "tm_server.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -67,12 +67,23 @@ void check_block_args(const tm_ctx *ctx, int64_t n, int32_t m) {
 
 }  // namespace
 
+void tmin::set_last_error(const std::string &msg) { g_last_error = msg; }
+
 void *tm_ctx::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 1;
     if (custom_alloc) return alloc.alloc(bytes, alloc.user);
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
     return p;
+}
+
+void *tm_ctx::pinned_buffer() {
+    if (!pinned) TM_HIP(hipHostMalloc(&pinned, 4096, hipHostMallocDefault));
+    return pinned;
+}
+
+tm_ctx::~tm_ctx() {
+    if (pinned) (void)hipHostFree(pinned);
 }
 
 void tm_ctx::dfree(void *p) {
@@ -97,6 +108,7 @@ const char *tm_status_string(int32_t status) {
     case TM_ENAN: return "NaN or Inf encountered";
     case TM_EDEVICE: return "HIP runtime error";
     case TM_ENOTSUP: return "not supported";
+    case TM_EAGAIN: return "not finished yet";
     default: return "unknown status";
     }
 }

@@ -12,6 +12,10 @@
 
 namespace tmin {
 
+// Sets the calling thread's tm_last_error() text.
+void set_last_error(const std::string &msg);
+
+
 // Internal error, converted to a tm_status at the C boundary.
 struct Error {
     tm_status status;
@@ -185,8 +189,11 @@ struct tm_ctx {
     hipStream_t stream = nullptr;
     tm_allocator alloc{};
     bool custom_alloc = false;
+    void *pinned = nullptr;      // 4 KiB of pinned host memory for polling, made on first use
     void *dalloc(size_t bytes);
     void dfree(void *p);
+    void *pinned_buffer();
+    ~tm_ctx();
 };
 
 struct tm_mat {

@@ -1,0 +1,412 @@
+// Serving: continuous batching of independent trace-minimization solves on
+// one GPU.  Requests (host CSR matrix, m, tol, start block) queue in arrival
+// order; a request is admitted as soon as a slot is idle and its memory bound
+// fits the free part of the server's HBM budget.  Each slot is a host thread
+// with its own HIP stream and context, so the kernels of admitted requests
+// overlap on the device while later arrivals wait.  Every solve runs the same
+// kernels with the same launch shapes and fixed-order reductions as tm_solve
+// alone, so a result does not depend on what else is running.
+//
+// Memory: one hipMalloc of the whole budget at creation; admission carves a
+// chunk of solve_footprint() bytes from it (first fit), and the request's
+// context allocates inside its chunk (first fit again), so an admitted
+// request cannot run out of memory and the budget is never exceeded.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "tm_solver.h"
+
+using namespace tmin;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class Arena {
+  public:
+    static constexpr size_t kAlign = 256;
+    void reset(size_t size) {
+        free_.clear();
+        used_.clear();
+        size_ = size;
+        if (size) free_[0] = size;
+    }
+    // returns the offset or SIZE_MAX
+    size_t alloc(size_t bytes) {
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                used_[off] = bytes;
+                in_use_ += bytes;
+                return off;
+            }
+        }
+        return SIZE_MAX;
+    }
+    void release(size_t off) {
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t size = u->second;
+        used_.erase(u);
+        in_use_ -= size;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + size == next->first) {
+            size += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += size;
+                return;
+            }
+        }
+        free_[off] = size;
+    }
+    size_t in_use() const { return in_use_; }
+
+  private:
+    std::map<size_t, size_t> free_, used_;
+    size_t size_ = 0, in_use_ = 0;
+};
+
+struct Request {
+    uint64_t id = 0;
+    int64_t n = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    std::vector<double> C0;      // n x ld, zero-padded
+    int32_t m = 0;
+    double tol = 0;
+    tm_opts opts{};
+    size_t footprint = 0;
+    // results
+    tm_status status = TM_EAGAIN;
+    std::string error;
+    tm_result res{};
+    std::vector<double> eig;
+    Clock::time_point t_submit, t_start, t_done;
+    bool finished = false;
+};
+
+struct Slot {
+    tm_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    char *chunk = nullptr;   // device base of the current request's chunk
+    Arena arena;             // allocations inside the chunk
+    std::thread thread;
+};
+
+void *slot_alloc(size_t bytes, void *user) {
+    Slot *s = (Slot *)user;
+    const size_t off = s->arena.alloc(bytes);
+    return off == SIZE_MAX ? nullptr : s->chunk + off;
+}
+
+void slot_free(void *p, void *user) {
+    Slot *s = (Slot *)user;
+    s->arena.release((size_t)((char *)p - s->chunk));
+}
+
+}  // namespace
+
+struct tm_server {
+    tm_server_opts opts{};
+    char *base = nullptr;
+    Arena budget;
+    size_t peak = 0;
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
+    uint64_t next_id = 1;
+    bool stop = false;
+    int running = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0;
+    std::vector<double> latencies;
+    Clock::time_point t0 = Clock::now(), t_first, t_last;
+    bool any_submit = false;
+
+    void worker(Slot *slot);
+    void execute(Slot *slot, Request *r);
+};
+
+void tm_server::execute(Slot *slot, Request *r) {
+    tm_ctx *ctx = slot->ctx;
+    tm_mat *H = nullptr;
+    tm_status st = tm_set_matrix_csr(ctx, r->n, r->rowptr.data(), r->col.data(), r->val.data(), &H);
+    if (st != TM_OK) {
+        r->status = st;
+        r->error = tm_last_error();
+        return;
+    }
+    const int ld = leading_dim(r->m);
+    void *C0d = ctx->dalloc((size_t)r->n * ld * sizeof(double));
+    void *eigd = ctx->dalloc((size_t)ld * sizeof(double));
+    if (!C0d || !eigd) {
+        r->status = TM_ENOMEM;
+        r->error = "request chunk too small";
+    } else if (hipMemcpyAsync(C0d, r->C0.data(), r->C0.size() * sizeof(double), hipMemcpyHostToDevice,
+                              ctx->stream) != hipSuccess) {
+        r->status = TM_EDEVICE;
+        r->error = "start block upload failed";
+    } else {
+        st = tm_solve(ctx, H, r->m, r->tol, &r->opts, (const double *)C0d, nullptr, (double *)eigd,
+                      &r->res, nullptr, 0);
+        r->status = st;
+        if (st != TM_OK) r->error = tm_last_error();
+        if (st == TM_OK || st == TM_ENOCONV) {
+            r->eig.resize(r->m);
+            if (hipMemcpyAsync(r->eig.data(), eigd, r->m * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess) {
+                r->status = TM_EDEVICE;
+                r->error = "result download failed";
+            }
+        }
+    }
+    if (C0d) ctx->dfree(C0d);
+    if (eigd) ctx->dfree(eigd);
+    tm_free_matrix(H);
+    // inputs are no longer needed
+    std::vector<int64_t>().swap(r->rowptr);
+    std::vector<int32_t>().swap(r->col);
+    std::vector<double>().swap(r->val);
+    std::vector<double>().swap(r->C0);
+}
+
+void tm_server::worker(Slot *slot) {
+    (void)hipSetDevice(opts.device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        size_t off = SIZE_MAX;
+        // first in, first out: the head waits until its memory is free
+        cv_work.wait(lk, [&] {
+            if (stop) return true;
+            if (queue.empty()) return false;
+            off = budget.alloc(queue.front()->footprint);
+            return off != SIZE_MAX;
+        });
+        if (stop) break;
+        Request *r = queue.front();
+        queue.pop_front();
+        ++running;
+        peak = std::max(peak, budget.in_use());
+        lk.unlock();
+
+        slot->chunk = base + off;
+        slot->arena.reset(r->footprint);
+        r->t_start = Clock::now();
+        execute(slot, r);
+        r->t_done = Clock::now();
+
+        lk.lock();
+        r->finished = true;
+        budget.release(off);
+        --running;
+        if (r->status == TM_OK || r->status == TM_ENOCONV) ++completed;
+        else ++failed;
+        latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
+        t_last = r->t_done;
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+}
+
+extern "C" {
+
+tm_status tm_solve_footprint(int64_t n, int64_t nnz, int32_t m, const tm_opts *opts,
+                             uint64_t *bytes) {
+    if (!bytes || n < 1 || m < 1 || m > n || nnz < 0) return TM_EINVAL;
+    tm_opts o;
+    if (opts) o = *opts; else tm_opts_default(&o);
+    *bytes = solve_footprint(n, nnz, m, o.precision, o.precondition != 0, 0) +
+             (uint64_t)n * leading_dim(m) * 8 + (uint64_t)leading_dim(m) * 8 + 64 * Arena::kAlign;
+    return TM_OK;
+}
+
+tm_status tm_server_create(const tm_server_opts *o, tm_server **out) {
+    if (!o || !out) return TM_EINVAL;
+    *out = nullptr;
+    if (o->max_slots < 1 || o->max_slots > 16 || o->hbm_budget < ((uint64_t)1 << 20)) return TM_EINVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || o->device < 0 || o->device >= count) return TM_EINVAL;
+    if (hipSetDevice(o->device) != hipSuccess) return TM_EDEVICE;
+    auto srv = std::make_unique<tm_server>();
+    srv->opts = *o;
+    void *base = nullptr;
+    if (hipMalloc(&base, o->hbm_budget) != hipSuccess) return TM_ENOMEM;
+    srv->base = (char *)base;
+    srv->budget.reset(o->hbm_budget);
+    for (int i = 0; i < o->max_slots; ++i) {
+        auto slot = std::make_unique<Slot>();
+        if (hipStreamCreateWithFlags(&slot->stream, hipStreamNonBlocking) != hipSuccess) {
+            tm_server_destroy(srv.release());
+            return TM_EDEVICE;
+        }
+        tm_allocator a;
+        a.alloc = slot_alloc;
+        a.free = slot_free;
+        a.user = slot.get();
+        if (tm_create(o->device, &a, slot->stream, &slot->ctx) != TM_OK) {
+            (void)hipStreamDestroy(slot->stream);
+            tm_server_destroy(srv.release());
+            return TM_EDEVICE;
+        }
+        srv->slots.push_back(std::move(slot));
+    }
+    for (auto &s : srv->slots) {
+        tm_server *p = srv.get();
+        Slot *sp = s.get();
+        s->thread = std::thread([p, sp] { p->worker(sp); });
+    }
+    *out = srv.release();
+    return TM_OK;
+}
+
+tm_status tm_server_submit(tm_server *s, const tm_request *q, uint64_t *id) {
+    if (!s || !q || !id) return TM_EINVAL;
+    if (!q->rowptr || !q->col || !q->val || !q->C0 || q->n < 1 || q->m < 1 || q->m > q->n || q->reserved != 0 ||
+        !(q->tol > 0))
+        return TM_EINVAL;
+    auto r = std::make_unique<Request>();
+    r->n = q->n;
+    r->m = q->m;
+    r->tol = q->tol;
+    if (q->opts) r->opts = *q->opts;
+    else {
+        tm_opts_default(&r->opts);
+        r->opts.precision = TM_MIXED;
+    }
+    r->opts.history = 0;
+    const int64_t nnz = q->rowptr[q->n];
+    if (nnz < 0) return TM_EINVAL;
+    uint64_t fp = 0;
+    if (tm_solve_footprint(q->n, nnz, q->m, &r->opts, &fp) != TM_OK) return TM_EINVAL;
+    r->footprint = fp;
+    if (fp > s->opts.hbm_budget) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        ++s->rejected;
+        return TM_ENOMEM;
+    }
+    r->rowptr.assign(q->rowptr, q->rowptr + q->n + 1);
+    r->col.assign(q->col, q->col + nnz);
+    r->val.assign(q->val, q->val + nnz);
+    const int ld = leading_dim(q->m);
+    r->C0.assign((size_t)q->n * ld, 0.0);
+    for (int64_t i = 0; i < q->n; ++i)
+        std::memcpy(&r->C0[(size_t)i * ld], q->C0 + (size_t)i * q->m, q->m * sizeof(double));
+    r->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->id = s->next_id++;
+    *id = r->id;
+    if (!s->any_submit) {
+        s->any_submit = true;
+        s->t_first = r->t_submit;
+    }
+    ++s->submitted;
+    s->queue.push_back(r.get());
+    s->requests[r->id] = std::move(r);
+    s->cv_work.notify_all();
+    return TM_OK;
+}
+
+static tm_status take_result(tm_server *s, uint64_t id, tm_result *res, double *eig_out,
+                             std::unique_lock<std::mutex> &lk, double timeout_s) {
+    auto it = s->requests.find(id);
+    if (it == s->requests.end()) return TM_EINVAL;
+    Request *r = it->second.get();
+    auto ready = [&] { return r->finished; };
+    if (timeout_s < 0) s->cv_done.wait(lk, ready);
+    else if (timeout_s > 0) s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
+    if (!r->finished) return TM_EAGAIN;
+    if (res) *res = r->res;
+    if (eig_out && !r->eig.empty()) std::memcpy(eig_out, r->eig.data(), r->eig.size() * sizeof(double));
+    const tm_status st = r->status;
+    set_last_error(r->error);
+    s->requests.erase(it);
+    return st;
+}
+
+tm_status tm_server_poll(tm_server *s, uint64_t id, tm_result *res, double *eig_out) {
+    if (!s) return TM_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    return take_result(s, id, res, eig_out, lk, 0.0);
+}
+
+tm_status tm_server_wait(tm_server *s, uint64_t id, double timeout_s, tm_result *res,
+                         double *eig_out) {
+    if (!s) return TM_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    return take_result(s, id, res, eig_out, lk, timeout_s < 0 ? -1.0 : std::max(timeout_s, 1e-9));
+}
+
+tm_status tm_server_get_stats(tm_server *s, tm_server_stats *out) {
+    if (!s || !out) return TM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->failed = s->failed;
+    out->rejected = s->rejected;
+    out->queued = (int64_t)s->queue.size();
+    out->running = s->running;
+    out->hbm_budget = s->opts.hbm_budget;
+    out->hbm_peak = s->peak;
+    std::vector<double> lat = s->latencies;
+    if (!lat.empty()) {
+        std::sort(lat.begin(), lat.end());
+        auto pct = [&](double q) {
+            // nearest-rank percentile
+            size_t k = (size_t)std::ceil(q * lat.size());
+            if (k < 1) k = 1;
+            return lat[std::min(k, lat.size()) - 1];
+        };
+        out->p50_latency_s = pct(0.50);
+        out->p99_latency_s = pct(0.99);
+        out->max_latency_s = lat.back();
+        double sum = 0;
+        for (double v : lat) sum += v;
+        out->mean_latency_s = sum / lat.size();
+        const double span = std::chrono::duration<double>(s->t_last - s->t_first).count();
+        out->span_s = span;
+        out->solves_per_s = span > 0 ? (double)lat.size() / span : 0.0;
+    }
+    return TM_OK;
+}
+
+void tm_server_destroy(tm_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;   // queued requests are dropped; running ones finish
+        s->queue.clear();
+    }
+    s->cv_work.notify_all();
+    for (auto &slot : s->slots)
+        if (slot->thread.joinable()) slot->thread.join();
+    for (auto &slot : s->slots) {
+        if (slot->ctx) tm_destroy(slot->ctx);
+        if (slot->stream) (void)hipStreamDestroy(slot->stream);
+    }
+    if (s->base) (void)hipFree(s->base);
+    delete s;
+}
+
+}  // extern "C"

@@ -60,6 +60,34 @@ Phase phase_of(int precision) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ footprint
+
+size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, bool precondition,
+                       int history_len) {
+    const size_t ld = (size_t)leading_dim(m);
+    const size_t blk8 = (size_t)n * ld * 8, blk4 = (size_t)n * ld * 4;
+    // blocks that can be alive together (C, C_next, X per precision of C;
+    // G, G_prev, P, Y), see alloc_c / alloc_g; the FP32 set and the FP64 set
+    // coexist at the MIXED switch and at the final FP64 Rayleigh-Ritz
+    size_t blocks;
+    switch (precision) {
+    case TM_FULL_DP: blocks = 3 * blk8 + 4 * blk8; break;
+    case TM_MP2: blocks = 3 * blk8 + 4 * blk4; break;
+    default: blocks = 3 * blk4 + 3 * blk8 + 4 * blk4; break;   // FULL_SP, MIXED
+    }
+    const size_t md = (size_t)m * m * 8;
+    size_t small = 3 * ld * 8 + 8 * ld * 8 + 5 * md + ld * ld * 8 + gram_workspace(n, m) +
+                   std::max({coldots_workspace(n, (int)ld), spmm_partials_workspace((int)ld),
+                             rot_partials_workspace(n, m)}) +
+                   chol_workspace(m) + jacobi_workspace(m) + 64 + sizeof(CgState) +
+                   (size_t)2 * std::max(history_len, 0) * 8 + (precondition ? (size_t)n * 8 : 0);
+    // the matrix (CSR: rowptr, col, FP64 and FP32 values, diagonal; stencil:
+    // V in FP64 and FP32), plus 16 bytes of slack per upload
+    const size_t mat = nnz > 0 ? (size_t)(n + 1) * 8 + (size_t)nnz * (4 + 8 + 4) + (size_t)n * 8 + 80
+                               : (size_t)n * 12 + 32;
+    return blocks + small + mat;
+}
+
 // ------------------------------------------------------------------ solver
 
 struct Solver::Impl {
@@ -86,10 +114,6 @@ struct Solver::Impl {
     Impl(tm_ctx *c, const tm_mat *Hm, int mm, double t, const tm_opts &oo)
         : ctx(c), H(Hm), m(mm), ld(leading_dim(mm)), n(Hm->n), tol(t), o(oo), s(c->stream) {}
 
-    ~Impl() {
-        if (st_host) (void)hipHostFree(st_host);
-        if (info_host) (void)hipHostFree(info_host);
-    }
 
     void alloc_small() {
         const size_t md = (size_t)m * m * sizeof(double);
@@ -115,13 +139,16 @@ struct Solver::Impl {
         TM_HIP(hipMemsetAsync(h->ptr, 0, ld * sizeof(double), s));
         TM_HIP(hipMemsetAsync(d->ptr, 0, ld * sizeof(double), s));
         TM_HIP(hipMemsetAsync(w->ptr, 0, ld * sizeof(double), s));
-        TM_HIP(hipHostMalloc((void **)&st_host, sizeof(CgState), hipHostMallocDefault));
-        TM_HIP(hipHostMalloc((void **)&info_host, 64, hipHostMallocDefault));
+        static_assert(sizeof(CgState) <= 2048, "CgState must fit the pinned buffer");
+        char *pin = (char *)ctx->pinned_buffer();
+        st_host = (CgState *)pin;
+        info_host = (int32_t *)(pin + 2048);
         if (o.precondition) {
             TM_REQUIRE(H->diag != nullptr, TM_EINVAL, "matrix has no diagonal");
             M.reset(new DevMem(ctx, n * sizeof(double)));
             std::vector<double> diag(n);
-            TM_HIP(hipMemcpy(diag.data(), H->diag, n * sizeof(double), hipMemcpyDeviceToHost));
+            TM_HIP(hipMemcpyAsync(diag.data(), H->diag, n * sizeof(double), hipMemcpyDeviceToHost, s));
+            TM_HIP(hipStreamSynchronize(s));
             const double sigma = std::min(0.0, H->diag_min - 0.5);
             for (auto &x : diag) x = 1.0 / (x - sigma);
             TM_HIP(hipMemcpyAsync(M->ptr, diag.data(), n * sizeof(double), hipMemcpyHostToDevice, s));

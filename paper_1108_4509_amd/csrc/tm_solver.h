@@ -23,6 +23,13 @@ struct DevMem {
 int spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64,
              int ndot = 0, double *partials = nullptr);
 
+// Upper bound of the device bytes one tm_solve() allocates for an n x m
+// problem with nnz stored nonzeros (0 for a stencil), at the given
+// precision, history length and preconditioner setting: the blocks that can
+// be alive together, the workspaces, the m x m matrices and the matrix itself.
+size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, bool precondition,
+                       int history_len);
+
 class Solver {
   public:
     Solver(tm_ctx *ctx, const tm_mat *H, int m, double tol, const tm_opts &o);

@@ -69,3 +69,38 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.tm_solve(None, None, 1, 1e-8, None, None, None, None, None, None, 0) == _abi.TM_EINVAL
     assert lib.tm_set_matrix_csr(None, 1, None, None, None, ctypes.byref(out)) == _abi.TM_EINVAL
     assert b"null" in lib.tm_last_error()
+
+
+def test_serving_structs_and_footprint(lib):
+    """Serving structs match the header; the admission bound grows with n and
+    m, covers the blocks of the chosen precision, and malformed calls are
+    rejected without touching a device."""
+    from paper_1108_4509_amd import _abi
+    assert ctypes.sizeof(_abi.tm_server_opts) == 4 + 4 + 8
+    assert ctypes.sizeof(_abi.tm_request) == 8 * 4 + 4 + 4 + 8 * 3
+    assert ctypes.sizeof(_abi.tm_server_stats) == 6 * 8 + 6 * 8 + 2 * 8
+
+    def fp(n, nnz, m, precision):
+        o = _abi.tm_opts()
+        lib.tm_opts_default(ctypes.byref(o))
+        o.precision = precision
+        out = ctypes.c_uint64()
+        assert lib.tm_solve_footprint(n, nnz, m, ctypes.byref(o), ctypes.byref(out)) == 0
+        return out.value
+
+    n, m = 110592, 256
+    ld = 256
+    for prec, blocks in ((_abi.TM_FULL_DP, 7 * 8), (_abi.TM_MP2, 3 * 8 + 4 * 4),
+                         (_abi.TM_MIXED, 3 * 4 + 3 * 8 + 4 * 4)):
+        b = fp(n, 7 * n, m, prec)
+        assert b >= (blocks + 8) * n * ld          # blocks plus the start block
+        assert b <= (blocks + 8) * n * ld + (256 << 20)
+    assert fp(n, 7 * n, m, _abi.TM_MIXED) < fp(2 * n, 14 * n, m, _abi.TM_MIXED)
+    assert fp(n, 7 * n, 128, _abi.TM_MIXED) < fp(n, 7 * n, m, _abi.TM_MIXED)
+    out = ctypes.c_uint64()
+    assert lib.tm_solve_footprint(10, 30, 11, None, ctypes.byref(out)) == _abi.TM_EINVAL
+    bad = _abi.tm_server_opts(device=0, max_slots=0, hbm_budget=1 << 30)
+    h = ctypes.c_void_p()
+    assert lib.tm_server_create(ctypes.byref(bad), ctypes.byref(h)) == _abi.TM_EINVAL
+    assert lib.tm_server_submit(None, None, None) == _abi.TM_EINVAL
+    assert lib.tm_server_poll(None, 1, None, None) == _abi.TM_EINVAL

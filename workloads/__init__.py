@@ -16,5 +16,6 @@ from .problems import (  # noqa: F401
     make_problem,
     config_problem,
     serving_stream,
+    serving_problem,
     CONFIGS,
 )

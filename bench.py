@@ -21,7 +21,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# dense matrix-core peaks; a two-term BF16 product issues three BF16 products
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16x3": 2516.0 / 3.0}
 
 
 def log(*a):
@@ -81,6 +82,8 @@ def kernel_work(p, ld):
         "trmm_mp2/f64": (1.0 * N * m * (m + 1), 16.0 * blk, "f32"),
         # FP32 bulk phase Gram H'
         "gram_shift/f32": (2.0 * N * m * m, 8.0 * blk, "f32"),
+        # the same on BF16 matrix cores with two-term operands (3 products)
+        "gram_bf16x3/f32": (2.0 * N * m * m, 8.0 * blk, "bf16x3"),
     }
 
 
@@ -107,7 +110,8 @@ def kernel_rooflines(tm, ctx, H, p, reps=20):
                        "tflops": round((2.0 / 3.0) * p.m ** 3 / (chol_ms * 1e-3) / 1e12, 4)}
     # the headline is the longest per-iteration bulk kernel; the m x m Cholesky
     # (one workgroup, latency-bound) is reported by time only
-    dom = max((k for k in out if out[k]["bound"] in ("hbm", "mfma") and k != "gram_shift/f32"),
+    dom = max((k for k in out if out[k]["bound"] in ("hbm", "mfma")
+               and k not in ("gram_shift/f32", "gram_bf16x3/f32")),
               key=lambda k: out[k]["avg_ms"])
     d = out[dom]
     roof = {"bound": d["bound"], "achieved": d.get("achieved"), "peak": d.get("peak"),
@@ -254,12 +258,26 @@ def main():
         log(f"fp64 {t:.3f}s iters={res64['iterations']} E_G={res64['E_G']:.15f}")
 
     # parity against the oracle's stored E_G (written by tests/golden/make_golden.py)
-    rel_err = None
+    g_EG = None
     gpath = os.path.join(ROOT, "tests", "golden", f"oracle_{a.config}_s0.json")
     if os.path.exists(gpath):
         with open(gpath) as f:
-            g = json.load(f)
-        rel_err = abs(res["E_G"] - g["E_G"]) / abs(g["E_G"])
+            g_EG = json.load(f)["E_G"]
+
+    def err(E):
+        return abs(E - g_EG) / abs(g_EG) if g_EG is not None else None
+
+    rel_err = err(res["E_G"])
+
+    # the two-term BF16 bulk variant, and its bulk phase alone (accuracy floor)
+    variants = {}
+    for prec in ("mixed_bf16", "full_bf16", "full_sp"):
+        t, rv = run(prec)
+        variants[prec] = {"seconds": round(t, 4), "iterations": rv["iterations"],
+                          "iters_bulk": rv["iters_sp"], "E_G": rv["E_G"],
+                          "rel_err_vs_oracle": err(rv["E_G"]),
+                          "max_residual": rv["max_residual"], "converged": rv["converged"]}
+        log(f"{prec} {t:.3f}s iters={rv['iterations']} err={variants[prec]['rel_err_vs_oracle']}")
 
     roofline, kernels = kernel_rooflines(tm, ctx, H, p)
     serving = None
@@ -288,6 +306,7 @@ def main():
         "iterations": res["iterations"], "iters_fp32": res["iters_sp"],
         "iterations_fp64": res64["iterations"] if res64 else None,
         "E_G": res["E_G"], "rel_err_vs_oracle": rel_err, "max_residual": res["max_residual"],
+        "variants": variants,
         "roofline": roofline, "kernels": kernels, "serving": serving, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

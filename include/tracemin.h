@@ -48,7 +48,10 @@ typedef enum tm_status {
     TM_EAGAIN = -8    /* a served request is still queued or running          */
 } tm_status;
 
-typedef enum tm_dtype { TM_F64 = 0, TM_F32 = 1 } tm_dtype;
+/* TM_BF16X3: FP32 blocks multiplied on BF16 matrix cores with each operand
+ * split into two BF16 terms (hi + lo, three products, FP32 accumulation);
+ * accepted by tm_gram only. */
+typedef enum tm_dtype { TM_F64 = 0, TM_F32 = 1, TM_BF16X3 = 2 } tm_dtype;
 
 /* Precision policies (Sec. 2.2).  Every policy keeps the m x m Cholesky,
  * triangular inverse and Rayleigh-Ritz eigensolve in FP64, and reports E_G and
@@ -61,12 +64,19 @@ typedef enum tm_dtype { TM_F64 = 0, TM_F32 = 1 } tm_dtype;
  *   TM_MIXED    FULL_SP until the residual reaches switch_tol (or the FP32
  *               energy stalls), then MP2 with subspace rotations every k_rot
  *               iterations until tol -- the switch the paper recommends in
- *               Sec. 3 and Sec. 5. */
+ *               Sec. 3 and Sec. 5.
+ *   TM_MIXED_BF16  TM_MIXED with the bulk phase's H' = C^T X' on BF16 matrix
+ *               cores (two-term BF16 operands, FP32 accumulation); the MP2
+ *               refinement restores FP64 accuracy.
+ *   TM_FULL_BF16   the bulk phase of TM_MIXED_BF16 alone (no refinement):
+ *               its accuracy floor, for error reports. */
 typedef enum tm_precision {
     TM_FULL_DP = 0,
     TM_FULL_SP = 1,
     TM_MP2 = 2,
-    TM_MIXED = 3
+    TM_MIXED = 3,
+    TM_MIXED_BF16 = 4,
+    TM_FULL_BF16 = 5
 } tm_precision;
 
 /* ---------------------------------------------------------------- objects */
@@ -301,7 +311,9 @@ tm_status tm_sym_eig(tm_ctx *ctx, int32_t m, const double *A, double *U,
  *   TM_K_GRAM_MP2   H' from FP64 blocks on FP32 matrix cores (dtype ignored)
  *   TM_K_ROT_GRAD_MP2 G from FP64 C and X, FP32 H' and FP32 G (dtype ignored)
  *   TM_K_TRMM_MP2   FP64 C D + C R' with R' on FP32 matrix cores (dtype ignored)
- *   TM_K_CHOL       S = R^T R and R^{-1}, m x m FP64 (dtype ignored) */
+ *   TM_K_CHOL       S = R^T R and R^{-1}, m x m FP64 (dtype ignored)
+ *   TM_K_GRAM_BF16X3 H' from FP32 blocks on BF16 matrix cores, two-term
+ *                   operands (dtype ignored) */
 typedef enum tm_kernel_id {
     TM_K_SPMM = 0,
     TM_K_GRAM_SHIFT = 1,
@@ -311,7 +323,8 @@ typedef enum tm_kernel_id {
     TM_K_GRAM_MP2 = 5,
     TM_K_ROT_GRAD_MP2 = 6,
     TM_K_TRMM_MP2 = 7,
-    TM_K_CHOL = 8
+    TM_K_CHOL = 8,
+    TM_K_GRAM_BF16X3 = 9
 } tm_kernel_id;
 
 tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m,

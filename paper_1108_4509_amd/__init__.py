@@ -20,7 +20,8 @@ from . import _abi
 from ._abi import (TM_F32, TM_F64, TM_FULL_DP, TM_FULL_SP, TM_MIXED, TM_MP2,  # noqa: F401
                    TM_ENOCONV, TM_ENOTSPD, TM_EINVAL, TM_OK, TraceminError)
 
-PRECISIONS = {"full_dp": TM_FULL_DP, "full_sp": TM_FULL_SP, "mp2": TM_MP2, "mixed": TM_MIXED}
+PRECISIONS = {"full_dp": TM_FULL_DP, "full_sp": TM_FULL_SP, "mp2": TM_MP2, "mixed": TM_MIXED,
+              "mixed_bf16": 4, "full_bf16": 5}
 
 
 def _torch():
@@ -237,11 +238,18 @@ def spmm(ctx: Context, H: Matrix, m: int, C, X):
                "tm_spmm")
 
 
-def gram(ctx: Context, m: int, A, B, h=None, out=None):
+def gram(ctx: Context, m: int, A, B, h=None, out=None, bf16x3: bool = False):
+    """A^T (B - A diag(h)) (h optional), m x m FP64.  bf16x3: FP32 blocks on
+    BF16 matrix cores with two-term BF16 operands."""
     torch = _torch()
     n = A.shape[0]
     out = out if out is not None else torch.empty((m, m), dtype=torch.float64, device=A.device)
-    _abi.check(_abi.lib().tm_gram(ctx.handle, n, m, _dtype_code(A), _ptr(A), _ptr(B), _ptr(h),
+    code = _dtype_code(A)
+    if bf16x3:
+        if A.dtype != torch.float32:
+            raise ValueError("bf16x3 takes FP32 blocks")
+        code = 2
+    _abi.check(_abi.lib().tm_gram(ctx.handle, n, m, code, _ptr(A), _ptr(B), _ptr(h),
                                   _ptr(out)), "tm_gram")
     return out
 
@@ -296,7 +304,7 @@ KERNELS = {"spmm": _abi.TM_K_SPMM, "gram_shift": _abi.TM_K_GRAM_SHIFT,
            "gram_sym": _abi.TM_K_GRAM_SYM, "rot_grad": _abi.TM_K_ROT_GRAD,
            "trmm": _abi.TM_K_TRMM, "gram_mp2": _abi.TM_K_GRAM_MP2,
            "rot_grad_mp2": _abi.TM_K_ROT_GRAD_MP2, "trmm_mp2": _abi.TM_K_TRMM_MP2,
-           "chol": _abi.TM_K_CHOL}
+           "chol": _abi.TM_K_CHOL, "gram_bf16x3": _abi.TM_K_GRAM_BF16X3}
 
 
 def time_kernel(ctx: Context, H: Matrix, kernel: str, m: int, dtype: str = "f32",

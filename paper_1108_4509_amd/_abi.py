@@ -117,7 +117,7 @@ SIGNATURES = {
 }
 
 (TM_K_SPMM, TM_K_GRAM_SHIFT, TM_K_GRAM_SYM, TM_K_ROT_GRAD, TM_K_TRMM, TM_K_GRAM_MP2,
- TM_K_ROT_GRAD_MP2, TM_K_TRMM_MP2, TM_K_CHOL) = range(9)
+ TM_K_ROT_GRAD_MP2, TM_K_TRMM_MP2, TM_K_CHOL, TM_K_GRAM_BF16X3) = range(10)
 
 _lib = None
 

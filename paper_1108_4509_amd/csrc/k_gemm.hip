@@ -17,6 +17,8 @@
 // to one XCD: row chunks of the tall operand stay in that XCD's L2.
 #include "tm_common.h"
 
+#include <type_traits>
+
 namespace tmin {
 namespace {
 
@@ -227,6 +229,154 @@ __global__ void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
     for (int p = 0; p < nsplit; ++p) s += partials[(int64_t)p * m * m + src];
     if (zero_diag && i == j) s = 0.0;
     out[idx] = s;
+}
+
+// ---------------------------------------------------------------- BF16x3 Gram
+// H' = A^T B' on BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation) with each operand split into two BF16 terms, x = hi + lo,
+// hi = bf16(x), lo = bf16(x - hi): A^T B ~ hi_a^T hi_b + hi_a^T lo_b +
+// lo_a^T hi_b, the lo_a^T lo_b term (2^-16 relative) dropped.  The split
+// operand carries 16 significant bits, so the product is accurate to about
+// 2^-16 relative to sum |a||b| -- between BF16 (2^-8) and FP32 (2^-24).
+// The k dimension of a Gram product is the row index N, so the LDS tiles are
+// stored k-contiguous: element (k, c) of a 32-row stage sits at
+// [k / 8][c][k % 8], and one 16-byte read gives an MFMA lane its eight k.
+// Loader map: thread t handles column pair t % (BM/2) and rows 8 g .. 8 g + 7
+// of the stage, g = t / (BM/2).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline void split_bf16(double x, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)(float)x;
+    lo = (__bf16)(float)(x - (double)(float)hi);
+}
+
+template <typename TA, int BM, bool SHIFT>
+__global__ __launch_bounds__(kThreads, 2) void gram_bf16x3_kernel(
+    int64_t n, int m, int ld, const TA *__restrict__ A, const TA *__restrict__ B,
+    const double *__restrict__ h, int T, int ntiles, int64_t rows_per_split,
+    double *__restrict__ partials) {
+    constexpr int CP = BM / 2;              // column pairs per tile row
+    constexpr int NKG = kThreads / CP;      // 8-row groups per stage
+    constexpr int KT = 8 * NKG;             // rows per stage
+    constexpr int WM = BM / 2;
+    constexpr int NB = WM / 16;
+    using Acc = typename Mfma<float>::acc_t;
+    using V2 = typename std::conditional<sizeof(TA) == 8, vd2, float __attribute__((ext_vector_type(2)))>::type;
+
+    __shared__ bf16x8 Ah[2][NKG][BM + 1], Al[2][NKG][BM + 1];
+    __shared__ bf16x8 Bh[2][NKG][BM + 1], Bl[2][NKG][BM + 1];
+
+    const int logical = xcd_logical(gridDim.x);
+    const int split = logical / ntiles;
+    const int tile = logical - split * ntiles;
+    const int ti = tile / T, tj = tile - (tile / T) * T;
+    const int i0 = ti * BM, j0 = tj * BM;
+    const int64_t k_begin = (int64_t)split * rows_per_split;
+    int64_t k_end = k_begin + rows_per_split;
+    if (k_end > n) k_end = n;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int cp = tid % CP, kg = tid / CP;
+    const int ci = i0 + 2 * cp, cj = j0 + 2 * cp;
+    const bool ci_ok = ci < ld, cj_ok = cj < ld;   // ld is a multiple of 32
+    const bool same = (ti == tj);
+    double hv[2] = {0.0, 0.0};
+    if (SHIFT && cj_ok) {
+        hv[0] = h[cj];
+        hv[1] = h[cj + 1];
+    }
+
+    Acc acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+    V2 ra[8], rb[8], rx[SHIFT ? 8 : 1];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t k = k0 + 8 * kg + r;
+            const bool rok = k < k_end;
+            ra[r] = (rok && ci_ok) ? *reinterpret_cast<const V2 *>(A + k * ld + ci) : V2(0);
+            rb[r] = (rok && cj_ok) ? *reinterpret_cast<const V2 *>(B + k * ld + cj) : V2(0);
+            if constexpr (SHIFT)
+                rx[r] = same ? ra[r] : ((rok && cj_ok) ? *reinterpret_cast<const V2 *>(A + k * ld + cj) : V2(0));
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            bf16x8 ah, al, bh, bl;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                __bf16 x, y;
+                split_bf16((double)ra[r][c], x, y);
+                ah[r] = x;
+                al[r] = y;
+                double bv = (double)rb[r][c];
+                if constexpr (SHIFT) bv -= (double)rx[r][c] * hv[c];
+                split_bf16(bv, x, y);
+                bh[r] = x;
+                bl[r] = y;
+            }
+            Ah[buf][kg][2 * cp + c] = ah;
+            Al[buf][kg][2 * cp + c] = al;
+            Bh[buf][kg][2 * cp + c] = bh;
+            Bl[buf][kg][2 * cp + c] = bl;
+        }
+    };
+
+    int buf = 0;
+    if (k_begin < k_end) {
+        load(k_begin);
+        store(0);
+    }
+    __syncthreads();
+    for (int64_t k0 = k_begin; k0 < k_end; k0 += KT) {
+        const bool more = k0 + KT < k_end;
+        if (more) load(k0 + KT);
+#pragma unroll
+        for (int ks = 0; ks < NKG / 4; ++ks) {
+            const int g = 4 * ks + (lane >> 4);
+            bf16x8 fah[NB], fal[NB], fbh[NB], fbl[NB];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                fah[a] = Ah[buf][g][wi * WM + a * 16 + (lane & 15)];
+                fal[a] = Al[buf][g][wi * WM + a * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                fbh[b] = Bh[buf][g][wj * WM + b * 16 + (lane & 15)];
+                fbl[b] = Bl[buf][g][wj * WM + b * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[a], fbh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[a], fbl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[a], fbh[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    double *P = partials + (int64_t)split * m * m;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi * WM + a * 16 + Mfma<float>::row(lane, r);
+                const int j = j0 + wj * WM + b * 16 + (lane & 15);
+                if (i < m && j < m) P[(int64_t)i * m + j] = (double)acc[a][b][r];
+            }
 }
 
 int gram_tile(int ld) { return ld >= 256 ? 128 : 64; }
@@ -539,6 +689,33 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     TM_HIP(hipGetLastError());
 }
 
+template <typename TA>
+void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, const double *h,
+                 bool zero_diag, double *partials, double *out, bool reduce) {
+    const int ld = leading_dim(m);
+    int BM, T, nsplit;
+    gram_shape(n, m, BM, T, nsplit);
+    const int ntiles = T * T;
+    const int KT = 8 * (kThreads / (BM / 2));
+    const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
+    const int grid = ntiles * nsplit;   // multiple of 8
+#define TM_GRAM16(BMV, SH)                                                                 \
+    hipLaunchKernelGGL((gram_bf16x3_kernel<TA, BMV, SH>), dim3(grid), dim3(kThreads), 0, s, n, m, \
+                       ld, A, B, h, T, ntiles, rows, partials)
+    if (BM == 128) {
+        if (h) TM_GRAM16(128, true); else TM_GRAM16(128, false);
+    } else {
+        if (h) TM_GRAM16(64, true); else TM_GRAM16(64, false);
+    }
+#undef TM_GRAM16
+    TM_HIP(hipGetLastError());
+    if (!reduce) return;
+    const int64_t total = (int64_t)m * m;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       s, m, nsplit, BM, false, zero_diag, partials, out);
+    TM_HIP(hipGetLastError());
+}
+
 template <typename TA, typename TM, typename TO>
 int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
         const TA *X, const double *vec, TO *out, const TO *Gp, const TO *Pp,
@@ -590,6 +767,8 @@ void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
 template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool);
 template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool);
 template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool);
+template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool);
+template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool);
 template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *);
 template int rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *, const float *, const float *, const double *, double *);
 template int rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *, const float *, const float *, const double *, double *);

@@ -294,7 +294,7 @@ tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol, const tm
         tm_opts o;
         if (opts) o = *opts; else tm_opts_default(&o);
         TM_REQUIRE(o.max_iter >= 0, TM_EINVAL, "max_iter must be >= 0");
-        TM_REQUIRE(o.precision >= TM_FULL_DP && o.precision <= TM_MIXED, TM_EINVAL, "unknown precision");
+        TM_REQUIRE(o.precision >= TM_FULL_DP && o.precision <= TM_FULL_BF16, TM_EINVAL, "unknown precision");
         TM_REQUIRE(history_len >= 0, TM_EINVAL, "history_len must be >= 0");
         TM_REQUIRE(o.reserved0 == 0, TM_EINVAL, "tm_opts.reserved0 must be 0");
         std::memset(res, 0, sizeof(*res));
@@ -319,7 +319,7 @@ tm_status tm_gram(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype, const void *
     return guarded([&]() {
         TM_REQUIRE(A && B && out, TM_EINVAL, "null argument");
         check_block_args(ctx, n, m);
-        TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
+        TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32 || dtype == TM_BF16X3, TM_EINVAL, "dtype");
         const int ld = leading_dim(m);
         DevMem ws(ctx, gram_workspace(n, m));
         DevMem hp(ctx, ld * sizeof(double));
@@ -333,6 +333,9 @@ tm_status tm_gram(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype, const void *
         if (dtype == TM_F64)
             gram<double, double>(ctx->stream, n, m, (const double *)A, (const double *)B, hv, false, sym,
                                  (double *)ws.ptr, out);
+        else if (dtype == TM_BF16X3)
+            gram_bf16x3<float>(ctx->stream, n, m, (const float *)A, (const float *)B, hv, false,
+                               (double *)ws.ptr, out);
         else
             gram<float, float>(ctx->stream, n, m, (const float *)A, (const float *)B, hv, false, sym,
                                (double *)ws.ptr, out);
@@ -463,11 +466,11 @@ tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m
         check_block_args(ctx, H->n, m);
         TM_REQUIRE(reps >= 1 && reps <= 100000, TM_EINVAL, "reps out of range");
         TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
-        TM_REQUIRE(kernel >= TM_K_SPMM && kernel <= TM_K_CHOL, TM_EINVAL, "unknown kernel");
+        TM_REQUIRE(kernel >= TM_K_SPMM && kernel <= TM_K_GRAM_BF16X3, TM_EINVAL, "unknown kernel");
         const int ld = leading_dim(m);
         const int64_t n = H->n;
         const bool mp2 = kernel == TM_K_GRAM_MP2 || kernel == TM_K_ROT_GRAD_MP2 || kernel == TM_K_TRMM_MP2;
-        const bool f64 = dtype == TM_F64 || mp2;
+        const bool f64 = (dtype == TM_F64 || mp2) && kernel != TM_K_GRAM_BF16X3;
         const size_t blk = (size_t)n * ld * (f64 ? 8 : 4);
         hipStream_t s = ctx->stream;
         DevMem A(ctx, blk), B(ctx, blk), O(ctx, blk), vec(ctx, ld * sizeof(double)),
@@ -524,6 +527,9 @@ tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m
                 break;
             case TM_K_CHOL:
                 chol_inverse(s, m, mm_p, (double *)rinv.ptr, (double *)ch.ptr, (int32_t *)info.ptr);
+                break;
+            case TM_K_GRAM_BF16X3:
+                gram_bf16x3<float>(s, n, m, (float *)A.ptr, (float *)B.ptr, v, true, ws_p, mm_p, false);
                 break;
             }
         };

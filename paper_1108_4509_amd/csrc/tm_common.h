@@ -124,6 +124,13 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
           double *out, bool reduce = true);
 
+// The Gram product with h (H' = A^T (B - A diag(h)), or A^T B without h) on
+// BF16 matrix cores with two-term BF16 operands (about 2^-16 relative to
+// sum |a||b|); full m x m, same partials layout and workspace as gram().
+template <typename TA>
+void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, const double *h,
+                 bool zero_diag, double *partials, double *out, bool reduce = true);
+
 // Tall-skinny products out = A W (+ epilogue) ------------------------------
 enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2 };
 // EPI_NONE:  out = A W

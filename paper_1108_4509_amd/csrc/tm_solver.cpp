@@ -110,6 +110,7 @@ struct Solver::Impl {
     CgState *st_host = nullptr;
     int32_t *info_host = nullptr;
     int rotations = 0;
+    bool bf16_bulk = false;   // the FP32 phase forms H' on BF16 matrix cores
 
     Impl(tm_ctx *c, const tm_mat *Hm, int mm, double t, const tm_opts &oo)
         : ctx(c), H(Hm), m(mm), ld(leading_dim(mm)), n(Hm->n), tol(t), o(oo), s(c->stream) {}
@@ -241,7 +242,10 @@ struct Solver::Impl {
             reduce_partials(s, 1, nch, ld, (double *)dot_ws->ptr, (double *)h->ptr);
         }
         // (5)-(6): H' = C^T (X - C H_D), diag(H') = 0
-        gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, false, (double *)gram_ws->ptr, (double *)Hp->ptr);
+        if (!is_f64<TC>() && bf16_bulk)
+            gram_bf16x3<TC>(s, n, m, C, X, (double *)h->ptr, true, (double *)gram_ws->ptr, (double *)Hp->ptr);
+        else
+            gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, false, (double *)gram_ws->ptr, (double *)Hp->ptr);
         // (7): G = -2 (X' - C H')
         pad_matrix<TMH>(s, m, (double *)Hp->ptr, false, (TMH *)Wp->ptr, nullptr);
         // with the traces for Eq. 8 and the descent test fused into the epilogue
@@ -287,8 +291,10 @@ struct Solver::Impl {
     }
 
     double auto_switch_tol() const {
-        // FP32 rounding floor of rho ~ eps32 * ||H|| * sqrt(m); leave well above it
+        // rounding floor of rho ~ u * ||H|| * sqrt(m) for the bulk phase's
+        // unit roundoff u (FP32 2^-24; two-term BF16 about 2^-17); leave well above it
         const double hnorm = std::max(std::fabs(H->diag_max), std::fabs(H->diag_min)) * 2.0;
+        if (bf16_bulk) return 4.0 * 7.63e-6 * hnorm * std::sqrt((double)m);
         return 64.0 * 5.96e-8 * hnorm * std::sqrt((double)m);
     }
 
@@ -302,8 +308,9 @@ struct Solver::Impl {
         TM_HIP(hipMemsetAsync(info->ptr, 0, 64, s));
 
         const int prec = o.precision;
-        const bool mixed = prec == TM_MIXED;
-        Phase ph = phase_of(mixed ? TM_FULL_SP : prec);
+        const bool mixed = prec == TM_MIXED || prec == TM_MIXED_BF16;
+        bf16_bulk = prec == TM_MIXED_BF16 || prec == TM_FULL_BF16;
+        Phase ph = phase_of((mixed || prec == TM_FULL_BF16) ? TM_FULL_SP : prec);
         alloc_c(ph.c64);
         alloc_g(ph.g64);
         // start block -> C (cast), orthonormalize
@@ -312,7 +319,7 @@ struct Solver::Impl {
         } else {
             convert_block<double, float>(s, n * ld, C0, (float *)Cn32->ptr);
         }
-        const bool gate = mixed || prec == TM_FULL_SP;
+        const bool gate = mixed || prec == TM_FULL_SP || prec == TM_FULL_BF16;
         double sw = o.switch_tol > 0 ? o.switch_tol : auto_switch_tol();
         reset_state(sw, gate ? 1 : 0, hl);
         zero_g();

@@ -88,6 +88,33 @@ def test_spmm_f32(ctx, tm, orc, stencil):
 
 
 @pytest.mark.parametrize("n,m", [(5000, 27), (3001, 76), (4099, 130), (2050, 256), (1500, 512),
+                                 (700, 1)])
+@pytest.mark.parametrize("shift", [False, True], ids=["plain", "shift"])
+def test_gram_bf16x3(ctx, tm, n, m, shift):
+    """Two-term BF16 operands on BF16 matrix cores: each operand is carried to
+    2^-16 relative and the dropped lo*lo product is 2^-16 of |a||b|, so
+    |err| <= 4 * 2^-16 * S + gamma_{3K}(u32) * S with S = |A|^T |B'| and K the
+    rows one workgroup accumulates in FP32 (<= n / 8).  A BF16-only product
+    (a dropped cross term) is off by up to 2^-8 S and fails this."""
+    import torch
+    print_case(test="gram_bf16x3", n=n, m=m, shift=shift)
+    rng = np.random.default_rng(n + m)
+    A = rand_block(rng, n, m).astype(np.float32)
+    B = rand_block(rng, n, m).astype(np.float32)
+    h = rng.standard_normal(m) if shift else None
+    Ad = tm.to_block(A, dtype=torch.float32)
+    Bd = tm.to_block(B, dtype=torch.float32)
+    hd = torch.tensor(h, device=Ad.device) if shift else None
+    got = host(tm.gram(ctx, m, Ad, Bd, h=hd, bf16x3=True))
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    Bp = B64 - A64 * h[None, :] if shift else B64
+    ref = A64.T @ Bp
+    S = np.abs(A64).T @ np.abs(Bp)
+    tol = (4 * 2.0 ** -16 + gamma(3 * ((n + 7) // 8), U32)) * S
+    assert np.all(np.abs(got - ref) <= tol)
+
+
+@pytest.mark.parametrize("n,m", [(5000, 27), (3001, 76), (4099, 130), (2050, 256), (1500, 512),
                                  (700, 1), (64, 64)])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_gram(ctx, tm, n, m, dt):

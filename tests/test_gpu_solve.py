@@ -131,7 +131,7 @@ def wells_oracle(orc, wells_problem):
                      orc.OracleOptions(tol=1e-10, k_rot=50))
 
 
-@pytest.mark.parametrize("precision", ["full_dp", "mixed", "mp2"])
+@pytest.mark.parametrize("precision", ["full_dp", "mixed", "mp2", "mixed_bf16"])
 def test_wells_precisions(ctx, tm, wells_problem, wells_oracle, precision):
     print_case(test="wells", precision=precision)
     r, C, w, _ = _solve(tm, ctx, wells_problem, precision=precision)
@@ -140,6 +140,18 @@ def test_wells_precisions(ctx, tm, wells_problem, wells_oracle, precision):
     assert abs(r["E_G"] - ref) <= 1e-10 * abs(ref)
     assert r["max_residual"] <= 1e-8
     assert np.max(np.abs(host(w) - wells_oracle.eigenvalues)) <= 1e-9
+
+
+def test_wells_full_bf16_floor(ctx, tm, wells_problem, wells_oracle):
+    """The two-term BF16 bulk phase alone stalls at its rounding floor: it
+    reports ENOCONV and an E_G error between the FP32 floor and plain BF16."""
+    print_case(test="wells_full_bf16")
+    r, C, w, _ = _solve(tm, ctx, wells_problem, precision="full_bf16", tol=1e-12)
+    ref = wells_oracle.E_G
+    err = abs(r["E_G"] - ref) / abs(ref)
+    print(f"full_bf16 E_G relative error {err:.3e}, iterations {r['iterations']}")
+    assert r["converged"] == 0
+    assert err < 1e-3
 
 
 def test_wells_brute_force_and_full_sp(ctx, tm, orc):

@@ -119,6 +119,8 @@ typedef struct tm_opts {
     int32_t reserved0;     /* must be 0 */
     double switch_tol;     /* TM_MIXED: leave FP32 when rho <= switch_tol (<= 0: automatic) */
     double rise_tol;       /* restart CG when E rises by more than rise_tol*|E| */
+    double stall_tol;      /* TM_MIXED*: also leave the bulk phase when E drops by less
+                              than stall_tol*|E| over 25 iterations (<= 0: 1e-7) */
 } tm_opts;
 
 typedef struct tm_result {

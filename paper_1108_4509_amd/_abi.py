@@ -41,7 +41,7 @@ class tm_opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_iter", c_int32), ("k_rot", c_int32),
                 ("k_check", c_int32), ("precondition", c_int32), ("history", c_int32),
                 ("transport", c_int32), ("reserved0", c_int32),
-                ("switch_tol", c_double), ("rise_tol", c_double)]
+                ("switch_tol", c_double), ("rise_tol", c_double), ("stall_tol", c_double)]
 
 
 class tm_result(ctypes.Structure):

@@ -144,32 +144,40 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
+    // loads are unconditional (rows past the chunk end read a valid row and
+    // columns past ld column 0, both zeroed at the store) so that no select
+    // on a loaded value forces the prefetch to complete early
     V ra[PASSES], rb[PASSES], rx[SHIFT ? PASSES : 1];
+    bool rv[PASSES];
+    const int ci_c = ci_ok ? ci : 0, cj_c = cj_ok ? cj : 0;
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int q = 0; q < PASSES; ++q) {
             const int64_t k = k0 + rbase + q * RPP;
-            const bool rok = k < k_end;
-            ra[q] = (rok && ci_ok) ? *reinterpret_cast<const V *>(A + k * ld + ci) : vzero<TA>();
-            rb[q] = (rok && cj_ok) ? *reinterpret_cast<const V *>(B + k * ld + cj) : vzero<TA>();
+            rv[q] = k < k_end;
+            const int64_t kk = rv[q] ? k : k_begin;
+            ra[q] = *reinterpret_cast<const V *>(A + kk * ld + ci_c);
+            rb[q] = *reinterpret_cast<const V *>(B + kk * ld + cj_c);
             if constexpr (SHIFT)
-                rx[q] = same ? ra[q]
-                             : ((rok && cj_ok) ? *reinterpret_cast<const V *>(A + k * ld + cj)
-                                               : vzero<TA>());
+                if (!same) rx[q] = *reinterpret_cast<const V *>(A + kk * ld + cj_c);
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < PASSES; ++q) {
             const int row = rbase + q * RPP;
+            const bool va = rv[q] && ci_ok, vb = rv[q] && cj_ok;
 #pragma unroll
             for (int w = 0; w < VW; ++w) {
-                As[buf][row][cv * VW + w] = (TM)velem<TA>(ra[q], w);
+                As[buf][row][cv * VW + w] = va ? (TM)velem<TA>(ra[q], w) : TM(0);
                 if constexpr (SHIFT) {
-                    const double x = (double)velem<TA>(rb[q], w) - (double)velem<TA>(rx[q], w) * hv[w];
-                    Bs[buf][row][cv * VW + w] = (TM)x;
+                    const TA xa = same ? velem<TA>(ra[q], w) : velem<TA>(rx[q], w);
+                    TM x;
+                    if constexpr (sizeof(TA) == 4) x = fmaf(-xa, (float)hv[w], velem<TA>(rb[q], w));
+                    else x = (TM)((double)velem<TA>(rb[q], w) - (double)xa * hv[w]);
+                    Bs[buf][row][cv * VW + w] = vb ? x : TM(0);
                 } else {
-                    Bs[buf][row][cv * VW + w] = (TM)velem<TA>(rb[q], w);
+                    Bs[buf][row][cv * VW + w] = vb ? (TM)velem<TA>(rb[q], w) : TM(0);
                 }
             }
         }
@@ -215,20 +223,35 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
             }
 }
 
-__global__ void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
-                                   bool zero_diag,
-                                   const double *__restrict__ partials,
-                                   double *__restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)m * m) return;
-    const int i = (int)(idx / m), j = (int)(idx - (int64_t)i * m);
-    int64_t src = idx;
-    if (symmetric && (i / BM) > (j / BM)) src = (int64_t)j * m + i;
+// Sum over the row-chunk partials in a fixed order: 64 elements per
+// workgroup, four lane groups take every fourth chunk, then the four group
+// sums are added in order.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
+                                                          bool zero_diag,
+                                                          const double *__restrict__ partials,
+                                                          double *__restrict__ out) {
+    constexpr int E = 64, G = 4;
+    __shared__ double red[G][E];
+    const int e = threadIdx.x % E, g = threadIdx.x / E;
+    const int64_t idx = (int64_t)blockIdx.x * E + e;
+    const int64_t mm = (int64_t)m * m;
     double s = 0.0;
+    int i = 0, j = 0;
+    if (idx < mm) {
+        i = (int)(idx / m);
+        j = (int)(idx - (int64_t)i * m);
+        int64_t src = idx;
+        if (symmetric && (i / BM) > (j / BM)) src = (int64_t)j * m + i;
 #pragma unroll 8
-    for (int p = 0; p < nsplit; ++p) s += partials[(int64_t)p * m * m + src];
-    if (zero_diag && i == j) s = 0.0;
-    out[idx] = s;
+        for (int p = g; p < nsplit; p += G) s += partials[(int64_t)p * mm + src];
+    }
+    red[g][e] = s;
+    __syncthreads();
+    if (g == 0 && idx < mm) {
+        double v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+        if (zero_diag && i == j) v = 0.0;
+        out[idx] = v;
+    }
 }
 
 // ---------------------------------------------------------------- BF16x3 Gram
@@ -295,15 +318,18 @@ __global__ __launch_bounds__(kThreads, 2) void gram_bf16x3_kernel(
         for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
     V2 ra[8], rb[8], rx[SHIFT ? 8 : 1];
+    bool rv[8];
+    const int ci_c = ci_ok ? ci : 0, cj_c = cj_ok ? cj : 0;
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int64_t k = k0 + 8 * kg + r;
-            const bool rok = k < k_end;
-            ra[r] = (rok && ci_ok) ? *reinterpret_cast<const V2 *>(A + k * ld + ci) : V2(0);
-            rb[r] = (rok && cj_ok) ? *reinterpret_cast<const V2 *>(B + k * ld + cj) : V2(0);
+            rv[r] = k < k_end;
+            const int64_t kk = rv[r] ? k : k_begin;
+            ra[r] = *reinterpret_cast<const V2 *>(A + kk * ld + ci_c);
+            rb[r] = *reinterpret_cast<const V2 *>(B + kk * ld + cj_c);
             if constexpr (SHIFT)
-                rx[r] = same ? ra[r] : ((rok && cj_ok) ? *reinterpret_cast<const V2 *>(A + k * ld + cj) : V2(0));
+                if (!same) rx[r] = *reinterpret_cast<const V2 *>(A + kk * ld + cj_c);
         }
     };
     auto store = [&](int buf) {
@@ -313,12 +339,12 @@ __global__ __launch_bounds__(kThreads, 2) void gram_bf16x3_kernel(
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 __bf16 x, y;
-                split_bf16((double)ra[r][c], x, y);
+                split_bf16((rv[r] && ci_ok) ? (double)ra[r][c] : 0.0, x, y);
                 ah[r] = x;
                 al[r] = y;
                 double bv = (double)rb[r][c];
-                if constexpr (SHIFT) bv -= (double)rx[r][c] * hv[c];
-                split_bf16(bv, x, y);
+                if constexpr (SHIFT) bv -= (double)(same ? ra[r][c] : rx[r][c]) * hv[c];
+                split_bf16((rv[r] && cj_ok) ? bv : 0.0, x, y);
                 bh[r] = x;
                 bl[r] = y;
             }
@@ -576,44 +602,61 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
                     if (rl >= 0 && rl < EH) tile[rl * TS + wc * WC + b * 16 + (lane & 15)] = acc[a][b][r];
                 }
         __syncthreads();
-        for (int rl = erow; rl < EH; rl += RPT) {
-            const int64_t row = r0 + half * EH + rl;
-            if (row >= n || !col_ok) continue;
-            const int64_t e = row * ld + ecol;
-            TA v[4];
+        // EG rows per lane at a time: all their loads are issued before any
+        // result is formed, so the round trips overlap
+        constexpr int EG = (sizeof(TM) == 8 && EPI == EPI_GRAD) ? 1 : 4;   // FP64 tiles: no room
+        static_assert(EH % (RPT * EG) == 0, "epilogue row groups");
+        for (int rl0 = erow; rl0 < EH; rl0 += RPT * EG) {
+            TA xv[EG][4], av[EG][4];
+            TO gp[EG][4], pp[EG][4];
+            double wgt[EG];
+            bool ok[EG];
 #pragma unroll
-            for (int w = 0; w < 4; ++w) v[w] = (TA)tile[rl * TS + 4 * ecv + w];
-            TO o[4];
-            if constexpr (EPI == EPI_NONE) {
-#pragma unroll
-                for (int w = 0; w < 4; ++w) o[w] = (TO)v[w];
-            } else if constexpr (EPI == EPI_GRAD) {
-                TA xv[4], av[4];
-                load4<TA>(X + e, xv);
-                load4<TA>(A + e, av);
-#pragma unroll
-                for (int w = 0; w < 4; ++w) o[w] = (TO)((TA)-2 * ((xv[w] - av[w] * (TA)vv[w]) - v[w]));
-                if (fuse) {
-                    TO gp[4], pp[4];
-                    load4<TO>(gd.Gp + e, gp);
-                    load4<TO>(gd.Pp + e, pp);
-                    const double wgt = gd.M ? gd.M[row] : 1.0;
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        const double g = (double)o[w];
-                        dsum[0][w] += g * g;
-                        dsum[1][w] += wgt * g * g;
-                        dsum[2][w] += wgt * (double)gp[w] * g;
-                        dsum[3][w] += (double)pp[w] * g;
-                    }
+            for (int g = 0; g < EG; ++g) {
+                const int rl = rl0 + g * RPT;
+                const int64_t row = r0 + half * EH + rl;
+                ok[g] = row < n && col_ok;
+                const int64_t e = (ok[g] ? row : r0) * ld + (col_ok ? ecol : c0);
+                if constexpr (EPI == EPI_GRAD) load4<TA>(X + e, xv[g]);
+                if constexpr (EPI != EPI_NONE) load4<TA>(A + e, av[g]);
+                if (EPI == EPI_GRAD && fuse) {
+                    load4<TO>(gd.Gp + e, gp[g]);
+                    load4<TO>(gd.Pp + e, pp[g]);
+                    wgt[g] = gd.M ? gd.M[ok[g] ? row : r0] : 1.0;
                 }
-            } else {
-                TA av[4];
-                load4<TA>(A + e, av);
-#pragma unroll
-                for (int w = 0; w < 4; ++w) o[w] = (TO)(av[w] * (TA)vv[w] + v[w]);
             }
-            store4<TO>(out + e, o);
+#pragma unroll
+            for (int g = 0; g < EG; ++g) {
+                if (!ok[g]) continue;
+                const int rl = rl0 + g * RPT;
+                const int64_t e = (r0 + half * EH + rl) * ld + ecol;
+                TA v[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) v[w] = (TA)tile[rl * TS + 4 * ecv + w];
+                TO o[4];
+                if constexpr (EPI == EPI_NONE) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) o[w] = (TO)v[w];
+                } else if constexpr (EPI == EPI_GRAD) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w)
+                        o[w] = (TO)((TA)-2 * ((xv[g][w] - av[g][w] * (TA)vv[w]) - v[w]));
+                    if (fuse) {
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            const double gg = (double)o[w];
+                            dsum[0][w] += gg * gg;
+                            dsum[1][w] += wgt[g] * gg * gg;
+                            dsum[2][w] += wgt[g] * (double)gp[g][w] * gg;
+                            dsum[3][w] += (double)pp[g][w] * gg;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) o[w] = (TO)(av[g][w] * (TA)vv[w] + v[w]);
+                }
+                store4<TO>(out + e, o);
+            }
         }
     }
 
@@ -684,7 +727,7 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     TM_HIP(hipGetLastError());
     if (!reduce) return;
     const int64_t total = (int64_t)m * m;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
                        s, m, nsplit, BM, symmetric, zero_diag, partials, out);
     TM_HIP(hipGetLastError());
 }
@@ -711,7 +754,7 @@ void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, cons
     TM_HIP(hipGetLastError());
     if (!reduce) return;
     const int64_t total = (int64_t)m * m;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
                        s, m, nsplit, BM, false, zero_diag, partials, out);
     TM_HIP(hipGetLastError());
 }

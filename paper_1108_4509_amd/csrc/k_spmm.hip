@@ -14,13 +14,12 @@ namespace {
 
 typedef double vd2 __attribute__((ext_vector_type(2)));
 typedef float vf4 __attribute__((ext_vector_type(4)));
-typedef float vf2 __attribute__((ext_vector_type(2)));
 template <typename T> struct Vec;
 template <> struct Vec<double> { using type = vd2; static constexpr int W = 2; };
 template <> struct Vec<float> { using type = vf4; static constexpr int W = 4; };
 
 constexpr int kMaxCv = 2;     // column vectors per lane (ld <= 1024)
-constexpr int kGridCap = 1024;
+constexpr int kGridCap = 4096;   // 4 waves each: about 16 waves per CU
 
 // Launch geometry: a workgroup of 256 lanes holds `rpb` rows at once with
 // `tpr` lanes per row (each lane loops over the row's vectors with stride
@@ -250,7 +249,10 @@ __device__ void flush_wave_dots(const double (&ds)[NCV][2][Vec<T>::W], int ndot,
     }
 }
 
-template <typename T, int NCV>
+// UB nonzeros are gathered before any is consumed (UB * NCV vector loads in
+// flight per lane); measured best: 8 for FP32 one-vector rows, 2 for two,
+// 1 for four or more
+template <typename T, int NCV, int UB = (NCV >= 4 ? 1 : (sizeof(T) == 4 && NCV == 1 ? 8 : (NCV == 2 && sizeof(T) == 4 ? 1 : 2)))>
 __global__ __launch_bounds__(256) void spmm_csr_wave_kernel(
     int64_t n, int64_t rows_per_block, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const T *__restrict__ val,
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(256) void spmm_csr_wave_kernel(
 #pragma unroll
         for (int q = 0; q < NCV; ++q) acc[q] = V(0);
         // U nonzeros at a time keep U * NCV vector loads in flight
-        constexpr int U = NCV >= 4 ? 1 : 4;
+        constexpr int U = UB;
         int64_t k = k0;
         for (; k + U <= k1; k += U) {
             V v[U][NCV];
@@ -382,223 +384,6 @@ __global__ __launch_bounds__(256) void spmm_stencil_wave_kernel(
     if (ndot > 0) flush_wave_dots<T, NCV>(ds, ndot, wave, lane, lb, partials, red);
 }
 
-// ---------------------------------------------------------------- slab kernels
-// For wide blocks the rows are cut into 512-byte column slabs (64 FP64 or
-// 128 FP32 columns, one 8-byte element per lane) and the slabs are handed to
-// the XCDs so that each XCD sweeps one contiguous (slab, row range) with all
-// of its waves side by side: wave w of the XCD takes rows r0 + w,
-// r0 + w + wpx, ...  The rows in flight on an XCD then form a narrow moving
-// window, and a neighbour row needed again one grid plane later (the z +- 1
-// couplings of a 3-D stencil, 2304 rows apart at 48^3) is 2304 x 512 B =
-// 1.2 MB back in the stream: still in the XCD's 4 MB L2.  With whole rows
-// (2 KB in FP64) that distance is 4.7 MB and the re-reads go to memory.
-// Workgroup b runs on XCD b % 8.  Fused column dots are reduced over the 4
-// waves in a fixed order and written per workgroup:
-// partials[(p * nprow + part * bpx + b / 8) * ld + col].
-template <typename T> struct SlabE;
-template <> struct SlabE<double> { using type = double; static constexpr int W = 1; };
-template <> struct SlabE<float> { using type = vf2; static constexpr int W = 2; };
-
-template <typename T>
-__device__ inline double slab_elem(const typename SlabE<T>::type &v, int w) {
-    if constexpr (SlabE<T>::W == 1) return (double)v; else return (double)v[w];
-}
-
-struct SlabMap {
-    int s;          // slab
-    int64_t r0, r1; // row range
-    int prow;       // partial-sum row of this workgroup
-};
-
-// slab and row range of the j-th pass of this workgroup
-__device__ inline SlabMap slab_map(int64_t n, int nslab, int j) {
-    const int xcd = blockIdx.x & 7, bpx = gridDim.x >> 3, bx = blockIdx.x >> 3;
-    SlabMap mp;
-    if (nslab >= 8) {
-        mp.s = xcd * (nslab >> 3) + j;
-        mp.r0 = 0;
-        mp.r1 = n;
-        mp.prow = bx;
-    } else {
-        const int xps = 8 / nslab, part = xcd % xps;
-        mp.s = xcd / xps;
-        mp.r0 = n * part / xps;
-        mp.r1 = n * (part + 1) / xps;
-        mp.prow = part * bpx + bx;
-    }
-    return mp;
-}
-
-template <typename T>
-__device__ void slab_flush_dots(const double (&d)[2][SlabE<T>::W], int ndot, int nprow, int ld,
-                                const SlabMap &mp, double *__restrict__ partials,
-                                double (*red)[4][128]) {
-    constexpr int W = SlabE<T>::W;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int w = 0; w < W; ++w) red[p][wave][lane * W + w] = d[p][w];
-    __syncthreads();
-    if (wave == 0) {
-        for (int p = 0; p < ndot; ++p)
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const int e = lane * W + w;
-                const double v = ((red[p][0][e] + red[p][1][e]) + red[p][2][e]) + red[p][3][e];
-                partials[((int64_t)p * nprow + mp.prow) * ld + mp.s * 64 * W + e] = v;
-            }
-    }
-    __syncthreads();
-}
-
-// RW consecutive rows per wave and step: the first eight nonzeros of all RW
-// rows are gathered before any is consumed, so 8 RW loads are in flight.
-template <typename T, int RW>
-__global__ __launch_bounds__(256) void spmm_csr_slab_kernel(
-    int64_t n, int ldE, int nslab, const int64_t *__restrict__ rowptr,
-    const int32_t *__restrict__ col, const T *__restrict__ val,
-    const typename SlabE<T>::type *__restrict__ C, typename SlabE<T>::type *__restrict__ X,
-    int ndot, double *__restrict__ partials) {
-    using E = typename SlabE<T>::type;
-    constexpr int W = SlabE<T>::W;
-    __shared__ double red[2][4][128];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wpx = (gridDim.x >> 3) * 4;
-    const int w = (blockIdx.x >> 3) * 4 + wave;
-    const int npass = nslab >= 8 ? nslab >> 3 : 1;
-    const int nprow = nslab >= 8 ? (gridDim.x >> 3) : (8 / nslab) * (gridDim.x >> 3);
-    for (int j = 0; j < npass; ++j) {
-        const SlabMap mp = slab_map(n, nslab, j);
-        const E *Cs = C + mp.s * 64 + lane;
-        E *Xs = X + mp.s * 64 + lane;
-        double d[2][W];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < W; ++q) d[p][q] = 0.0;
-        for (int64_t rb = mp.r0 + (int64_t)w * RW; rb < mp.r1; rb += (int64_t)wpx * RW) {
-            int64_t k0[RW], k1[RW];
-#pragma unroll
-            for (int t = 0; t < RW; ++t) {
-                const bool in = rb + t < mp.r1;
-                k0[t] = in ? rowptr[rb + t] : 0;
-                k1[t] = in ? rowptr[rb + t + 1] : 0;
-            }
-            E v[RW][8];
-            T a[RW][8];
-#pragma unroll
-            for (int t = 0; t < RW; ++t)
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const bool in = k0[t] + u < k1[t];
-                    a[t][u] = in ? val[k0[t] + u] : T(0);
-                    v[t][u] = in ? Cs[(int64_t)col[k0[t] + u] * ldE] : E(0);
-                }
-#pragma unroll
-            for (int t = 0; t < RW; ++t) {
-                if (rb + t >= mp.r1) break;
-                E acc = E(0);
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc = a[t][u] * v[t][u] + acc;
-                for (int64_t k = k0[t] + 8; k < k1[t]; ++k) acc = val[k] * Cs[(int64_t)col[k] * ldE] + acc;
-                const int64_t r = rb + t;
-                Xs[r * ldE] = acc;
-                if (ndot > 0) {
-                    const E c = Cs[r * ldE];
-#pragma unroll
-                    for (int q = 0; q < W; ++q) {
-                        const double cq = slab_elem<T>(c, q);
-                        d[0][q] += cq * slab_elem<T>(acc, q);
-                        if (ndot > 1) d[1][q] += cq * cq;
-                    }
-                }
-            }
-        }
-        if (ndot > 0) slab_flush_dots<T>(d, ndot, nprow, ldE * W, mp, partials, red);
-    }
-}
-
-template <typename T, int ORDER, int NDIM>
-__global__ __launch_bounds__(256) void spmm_stencil_slab_kernel(
-    int64_t n, int ldE, int nslab, StencilDev H, const T *__restrict__ Vpot,
-    const typename SlabE<T>::type *__restrict__ C, typename SlabE<T>::type *__restrict__ X,
-    int ndot, double *__restrict__ partials) {
-    using E = typename SlabE<T>::type;
-    constexpr int W = SlabE<T>::W;
-    __shared__ double red[2][4][128];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wpx = (gridDim.x >> 3) * 4;
-    const int w = (blockIdx.x >> 3) * 4 + wave;
-    const int npass = nslab >= 8 ? nslab >> 3 : 1;
-    const int nprow = nslab >= 8 ? (gridDim.x >> 3) : (8 / nslab) * (gridDim.x >> 3);
-    const T c0 = (T)H.c0, c1 = (T)H.c1, c2 = (T)H.c2;
-    const int ext[3] = {H.nx, H.ny, H.nz};
-    const int64_t stride[3] = {1, (int64_t)H.nx, (int64_t)H.nx * H.ny};
-    for (int j = 0; j < npass; ++j) {
-        const SlabMap mp = slab_map(n, nslab, j);
-        const E *Cs = C + mp.s * 64 + lane;
-        E *Xs = X + mp.s * 64 + lane;
-        double d[2][W];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < W; ++q) d[p][q] = 0.0;
-        for (int64_t r = mp.r0 + w; r < mp.r1; r += wpx) {
-            int crd[3];
-            crd[0] = (int)(r % H.nx);
-            crd[1] = (int)((r / H.nx) % H.ny);
-            crd[2] = NDIM == 3 ? (int)(r / ((int64_t)H.nx * H.ny)) : 0;
-            const T diag = c0 + (Vpot ? Vpot[r] : T(0));
-            const E center = Cs[r * ldE];
-            E acc = diag * center;
-#pragma unroll
-            for (int ax = 0; ax < NDIM; ++ax) {
-#pragma unroll
-                for (int o = -ORDER / 2; o <= ORDER / 2; ++o) {
-                    if (o == 0) continue;
-                    int c;
-                    if (!neighbour(crd[ax], o, ext[ax], H.periodic, c)) continue;
-                    const int64_t nb = r + (int64_t)(c - crd[ax]) * stride[ax];
-                    const T coef = (o == 1 || o == -1) ? c1 : c2;
-                    acc = coef * Cs[nb * ldE] + acc;
-                }
-            }
-            Xs[r * ldE] = acc;
-            if (ndot > 0) {
-#pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const double cq = slab_elem<T>(center, q);
-                    d[0][q] += cq * slab_elem<T>(acc, q);
-                    if (ndot > 1) d[1][q] += cq * cq;
-                }
-            }
-        }
-        if (ndot > 0) slab_flush_dots<T>(d, ndot, nprow, ldE * W, mp, partials, red);
-    }
-}
-
-// Slab launch: returns nslab, or 0 when the block does not cut into a power
-// of two of 512-byte slabs.
-template <typename T>
-int slab_count(int ld) {
-    constexpr int cols = 64 * SlabE<T>::W;
-    if (ld % cols != 0) return 0;
-    const int ns = ld / cols;
-    if (ns < 1 || (ns & (ns - 1)) != 0 || ns > 64) return 0;
-    return ns;
-}
-
-constexpr int kSlabGrid = 1024;   // 128 workgroups (512 waves) per XCD
-constexpr int kSlabRows = 4;      // consecutive rows per wave step (CSR)
-
-// partial rows written by a slab launch
-inline int slab_partial_rows(int nslab) {
-    return nslab >= 8 ? kSlabGrid / 8 : (8 / nslab) * (kSlabGrid / 8);
-}
-
 // grid for the wave kernels: ~kGridCap workgroups of 4 waves, multiple of 8
 Geometry wave_geometry(int64_t n) {
     Geometry g;
@@ -625,14 +410,6 @@ int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
     Geometry g = geometry(H.n, ldv);
     const T *val;
     if constexpr (sizeof(T) == 8) val = H.val64; else val = H.val32;
-    if (const int ns = slab_count<T>(ld); ns > 0 && H.n >= 64 * kSlabGrid) {
-        using E = typename SlabE<T>::type;
-        hipLaunchKernelGGL((spmm_csr_slab_kernel<T, kSlabRows>), dim3(kSlabGrid), dim3(256), 0, s, H.n,
-                           ld / SlabE<T>::W, ns, H.rowptr, H.col, val,
-                           reinterpret_cast<const E *>(C), reinterpret_cast<E *>(X), ndot, partials);
-        TM_HIP(hipGetLastError());
-        return slab_partial_rows(ns);
-    }
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
     auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
     if (ldv % 64 == 0 && ldv <= 512) {
@@ -666,22 +443,6 @@ int spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld, const T 
     Geometry g = geometry(n, ldv);
     const T *Vp;
     if constexpr (sizeof(T) == 8) Vp = H.V64; else Vp = H.V32;
-    if (const int ns = slab_count<T>(ld); ns > 0 && n >= 64 * kSlabGrid) {
-        using E = typename SlabE<T>::type;
-        const E *Ce = reinterpret_cast<const E *>(C);
-        E *Xe = reinterpret_cast<E *>(X);
-        const int ldE = ld / SlabE<T>::W;
-#define TM_SLAB(ORD, ND)                                                                     \
-    hipLaunchKernelGGL((spmm_stencil_slab_kernel<T, ORD, ND>), dim3(kSlabGrid), dim3(256), 0, s, \
-                       n, ldE, ns, H, Vp, Ce, Xe, ndot, partials)
-        if (H.ndim == 3 && H.order == 2) TM_SLAB(2, 3);
-        else if (H.ndim == 3 && H.order == 4) TM_SLAB(4, 3);
-        else if (H.ndim == 2 && H.order == 2) TM_SLAB(2, 2);
-        else TM_SLAB(4, 2);
-#undef TM_SLAB
-        TM_HIP(hipGetLastError());
-        return slab_partial_rows(ns);
-    }
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
     auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
     const int ncv = ldv / 64;

@@ -62,29 +62,31 @@ __global__ __launch_bounds__(kDotThreads) void coldots_kernel(
     }
 }
 
-// Final fixed-order reduction over row chunks: block (p, slab of 32 columns),
-// 32 lane groups stride over the chunks (loads unrolled to keep many in
-// flight), then the group sums are added in order.
+// Sum of per-chunk partial rows, partials[(p * nchunk + c) * ld + j] over c,
+// for each product p and column j.  A workgroup takes 8 columns; its 128 lane
+// groups stride over the chunks (loads unrolled to keep many in flight), then
+// the group sums are combined by a fixed pairwise tree.
 __global__ __launch_bounds__(1024) void coldots_reduce_kernel(
     int nchunk, int ld, const double *__restrict__ partials, double *__restrict__ out) {
-    __shared__ double red[32][33];
+    constexpr int CW = 8, NG = 1024 / CW;
+    __shared__ double red[NG][CW + 1];
     const int p = blockIdx.x;
     const int t = threadIdx.x;
-    const int j = blockIdx.y * 32 + (t & 31);
-    const int g = t >> 5;
+    const int c = t % CW, g = t / CW;
+    const int j = blockIdx.y * CW + c;
     double s = 0.0;
     if (j < ld) {
         const double *base = partials + (int64_t)p * nchunk * ld + j;
 #pragma unroll 8
-        for (int c = g; c < nchunk; c += 32) s += base[(int64_t)c * ld];
+        for (int q = g; q < nchunk; q += NG) s += base[(int64_t)q * ld];
     }
-    red[g][t & 31] = s;
+    red[g][c] = s;
     __syncthreads();
-    if (t < 32 && j < ld) {
-        double v = 0.0;
-        for (int q = 0; q < 32; ++q) v += red[q][t];
-        out[(int64_t)p * ld + j] = v;
+    for (int w = NG / 2; w >= 1; w >>= 1) {
+        if (g < w) red[g][c] += red[g + w][c];
+        __syncthreads();
     }
+    if (g == 0 && j < ld) out[(int64_t)p * ld + j] = red[0][c];
 }
 
 int dot_chunks(int64_t n) {
@@ -285,7 +287,7 @@ void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
 
 void reduce_partials(hipStream_t s, int nprod, int nchunk, int ld, const double *partials,
                      double *out) {
-    hipLaunchKernelGGL(coldots_reduce_kernel, dim3(nprod, (ld + 31) / 32), dim3(1024), 0, s,
+    hipLaunchKernelGGL(coldots_reduce_kernel, dim3(nprod, (ld + 7) / 8), dim3(1024), 0, s,
                        nchunk, ld, partials, out);
     TM_HIP(hipGetLastError());
 }

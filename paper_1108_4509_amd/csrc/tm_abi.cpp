@@ -151,6 +151,7 @@ void tm_opts_default(tm_opts *o) {
     o->transport = 1;
     o->switch_tol = 0.0;
     o->rise_tol = 1e-13;
+    o->stall_tol = 0.0;
 }
 
 tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr, const int32_t *col,

@@ -275,7 +275,7 @@ struct Solver::Impl {
         init.tol = tol;
         init.rise_tol = o.rise_tol;
         init.switch_tol = switch_tol;
-        init.stall_tol = 1e-6;
+        init.stall_tol = o.stall_tol > 0 ? o.stall_tol : 1e-7;
         init.stall_window = gate ? 25 : 0;
         init.history_len = hist_len;
         init.phase_gate = gate;
@@ -292,10 +292,11 @@ struct Solver::Impl {
 
     double auto_switch_tol() const {
         // rounding floor of rho ~ u * ||H|| * sqrt(m) for the bulk phase's
-        // unit roundoff u (FP32 2^-24; two-term BF16 about 2^-17); leave well above it
+        // unit roundoff u (FP32 2^-24; two-term BF16 about 2^-17); leave the
+        // bulk phase a little above it (16x: measured best at 48^3, m = 256)
         const double hnorm = std::max(std::fabs(H->diag_max), std::fabs(H->diag_min)) * 2.0;
         if (bf16_bulk) return 4.0 * 7.63e-6 * hnorm * std::sqrt((double)m);
-        return 64.0 * 5.96e-8 * hnorm * std::sqrt((double)m);
+        return 16.0 * 5.96e-8 * hnorm * std::sqrt((double)m);
     }
 
     tm_status run(const double *C0, double *C_out, double *eig_out, tm_result *res,

@@ -330,10 +330,10 @@ def test_c2_gram_sampled(ctx, tm, c2):
             assert abs(G[i, j] - ref) <= bound
 
 
-# Blocks of at least 65536 rows whose width cuts into 512-byte column slabs go
-# through the slab kernels (each XCD sweeps one slab's row range); ragged row
-# counts, both stencil orders, 1 to 16 slabs, and the fused column dots.
-_SLAB_CASES = [
+# Large blocks (65536+ rows, 128 to 1024 columns): ragged row counts, both
+# stencil orders, one to eight vectors per lane in the wave-per-row kernels,
+# and the fused column dots.
+_LARGE_CASES = [
     ("7pt_m128", StencilSpec(3, (42, 42, 42), 2, "periodic", 0.5), 128, 3),
     ("7pt_m512", StencilSpec(3, (41, 43, 40), 2, "periodic", 0.5), 512, 0),
     ("13pt_m256", StencilSpec(3, (41, 41, 41), 4, "periodic", 0.5), 256, 4),
@@ -341,13 +341,13 @@ _SLAB_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", _SLAB_CASES, ids=[c[0] for c in _SLAB_CASES])
+@pytest.mark.parametrize("case", _LARGE_CASES, ids=[c[0] for c in _LARGE_CASES])
 @pytest.mark.parametrize("stencil", [False, True], ids=["csr", "stencil"])
-def test_spmm_slab_path(ctx, tm, orc, case, stencil):
+def test_spmm_large_blocks(ctx, tm, orc, case, stencil):
     import torch
     name, spec, m, wells = case
     prob = make_problem(name, spec, m=m, seed=11, n_wells=wells)
-    print_case(test="spmm_slab", case=name, stencil=stencil, N=prob.N, m=m)
+    print_case(test="spmm_large", case=name, stencil=stencil, N=prob.N, m=m)
     H = orc.csr_matrix(*prob.csr(), prob.N)
     Hd = tm.matrix_from_problem(ctx, prob, stencil=stencil)
     C = rand_block(np.random.default_rng(3), prob.N, m)

@@ -253,3 +253,33 @@ def test_c2_full_size(ctx, tm, precision):
     assert abs(r["E_G"] - g["E_G"]) <= 1e-10 * abs(g["E_G"])
     assert r["max_residual"] <= 1e-8
     assert np.max(np.abs(host(w) - np.array(g["eigenvalues"]))) <= 1e-8
+
+
+@pytest.mark.slow
+def test_c3_full_size_certified(ctx, tm, orc):
+    """64^3 13-point + 200 wells, m = 512, MIXED.  The oracle cannot run this
+    size to convergence in test time, so it certifies the GPU's result
+    instead, in FP64 on the host: every Ritz pair (lambda_j, c_j) has
+    ||H c_j - lambda_j c_j|| <= 1e-8, C^T C = I to 1e-12, E_G equals
+    tr(C^T H C), and three oracle CG iterations started from the GPU's C
+    cannot lower the energy by more than 1e-10 |E_G| (a subspace short of
+    the minimum would be pushed down at once)."""
+    p = config_problem("c3")
+    print_case(test="c3_full", N=p.N, m=p.m)
+    r, C, w, _ = _solve(tm, ctx, p, precision="mixed")
+    assert r["converged"] == 1 and r["max_residual"] <= 1e-8
+    Ch = host(C, p.m)
+    wh = host(w)
+    del C
+    H = orc.csr_matrix(*p.csr(), p.N)
+    X = orc.spmm(H, Ch)
+    res = np.linalg.norm(X - Ch * wh[None, :], axis=0)
+    assert np.max(res) <= 1e-8
+    S = Ch.T @ Ch
+    assert np.max(np.abs(S - np.eye(p.m))) <= 1e-12
+    E_rq = float(np.einsum("ij,ij->", Ch, X))
+    assert abs(E_rq - r["E_G"]) <= 1e-12 * abs(r["E_G"])
+    cont = orc.solve(H, Ch, orc.OracleOptions(tol=1e-14, max_iter=3, k_rot=0))
+    assert min(cont.energies) >= r["E_G"] - 1e-10 * abs(r["E_G"])
+    print(f"c3: E_G {r['E_G']:.15f} iterations {r['iterations']} max residual {np.max(res):.2e} "
+          f"continuation min E {min(cont.energies):.15f}")

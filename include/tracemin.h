@@ -116,7 +116,8 @@ typedef struct tm_opts {
     int32_t transport;     /* 1 (default): a subspace rotation C <- C U also maps
                               P <- P U and G_prev <- G_prev U and CG continues;
                               0: CG restarts after each rotation */
-    int32_t reserved0;     /* must be 0 */
+    int32_t graphs;        /* 1: replay batches of k_check iterations without a
+                              rotation from captured HIP graphs (same kernels) */
     double switch_tol;     /* TM_MIXED: leave FP32 when rho <= switch_tol (<= 0: automatic) */
     double rise_tol;       /* restart CG when E rises by more than rise_tol*|E| */
     double stall_tol;      /* TM_MIXED*: also leave the bulk phase when E drops by less

@@ -184,7 +184,7 @@ def to_block(C: np.ndarray, dtype=None, device=None):
 
 def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition=False,
          history=False, switch_tol=0.0, rise_tol=1e-13, transport=None,
-         stall_tol=0.0) -> _abi.tm_opts:
+         stall_tol=0.0, graphs=None) -> _abi.tm_opts:
     o = _abi.tm_opts()
     _abi.lib().tm_opts_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -196,6 +196,8 @@ def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition
     o.switch_tol = switch_tol
     o.rise_tol = rise_tol
     o.stall_tol = stall_tol
+    if graphs is not None:
+        o.graphs = 1 if graphs else 0
     if transport is not None:
         o.transport = 1 if transport else 0
     return o

@@ -40,7 +40,7 @@ class tm_stencil(ctypes.Structure):
 class tm_opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_iter", c_int32), ("k_rot", c_int32),
                 ("k_check", c_int32), ("precondition", c_int32), ("history", c_int32),
-                ("transport", c_int32), ("reserved0", c_int32),
+                ("transport", c_int32), ("graphs", c_int32),
                 ("switch_tol", c_double), ("rise_tol", c_double), ("stall_tol", c_double)]
 
 

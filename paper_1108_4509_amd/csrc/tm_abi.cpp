@@ -149,6 +149,7 @@ void tm_opts_default(tm_opts *o) {
     o->precondition = 0;
     o->history = 0;
     o->transport = 1;
+    o->graphs = 0;
     o->switch_tol = 0.0;
     o->rise_tol = 1e-13;
     o->stall_tol = 0.0;
@@ -297,7 +298,7 @@ tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol, const tm
         TM_REQUIRE(o.max_iter >= 0, TM_EINVAL, "max_iter must be >= 0");
         TM_REQUIRE(o.precision >= TM_FULL_DP && o.precision <= TM_FULL_BF16, TM_EINVAL, "unknown precision");
         TM_REQUIRE(history_len >= 0, TM_EINVAL, "history_len must be >= 0");
-        TM_REQUIRE(o.reserved0 == 0, TM_EINVAL, "tm_opts.reserved0 must be 0");
+        TM_REQUIRE(o.graphs == 0 || o.graphs == 1, TM_EINVAL, "tm_opts.graphs must be 0 or 1");
         std::memset(res, 0, sizeof(*res));
         Solver solver(ctx, H, m, tol, o);
         return solver.run(C0, C_out, eig_out, res, history, history_len);

@@ -112,6 +112,18 @@ struct Solver::Impl {
     int rotations = 0;
     bool bf16_bulk = false;   // the FP32 phase forms H' on BF16 matrix cores
 
+    // captured iteration batches, keyed by the buffers they were recorded on
+    struct GraphKey {
+        const void *c32, *c64, *g, *gp, *p, *y;
+        bool operator==(const GraphKey &o) const {
+            return c32 == o.c32 && c64 == o.c64 && g == o.g && gp == o.gp && p == o.p && y == o.y;
+        }
+    };
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+    ~Impl() {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    }
+
     Impl(tm_ctx *c, const tm_mat *Hm, int mm, double t, const tm_opts &oo)
         : ctx(c), H(Hm), m(mm), ld(leading_dim(mm)), n(Hm->n), tol(t), o(oo), s(c->stream) {}
 
@@ -302,6 +314,26 @@ struct Solver::Impl {
     tm_status run(const double *C0, double *C_out, double *eig_out, tm_result *res,
                   double *hist_host, int hist_len) {
         auto t0 = std::chrono::steady_clock::now();
+        // graphs cannot be recorded on the legacy default stream: then the
+        // solve runs on a stream of its own, after the caller's prior work
+        struct OwnStream {
+            hipStream_t st = nullptr;
+            ~OwnStream() {
+                if (st) {
+                    (void)hipStreamSynchronize(st);
+                    (void)hipStreamDestroy(st);
+                }
+            }
+        } own;
+        if (o.graphs && s == nullptr) {
+            TM_HIP(hipStreamCreateWithFlags(&own.st, hipStreamNonBlocking));
+            hipEvent_t ev;
+            TM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            TM_HIP(hipEventRecord(ev, nullptr));
+            TM_HIP(hipStreamWaitEvent(own.st, ev, 0));
+            (void)hipEventDestroy(ev);
+            s = own.st;
+        }
         alloc_small();
         int hl = (o.history && hist_host) ? hist_len : 0;
         if (hl > 0) hist.reset(new DevMem(ctx, (size_t)2 * hl * sizeof(double)));
@@ -334,15 +366,49 @@ struct Solver::Impl {
         int iters_sp = 0;
         bool sp_phase = !ph.c64;
         const int kcheck = std::max(1, o.k_check);
+        auto step = [&](bool rotate) {
+            if (!ph.c64) iterate<float, float, float, float>(c32, cn32, (float *)X32->ptr, rotate, hist_dev);
+            else if (!ph.g64) iterate<double, float, float, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
+            else iterate<double, double, double, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
+        };
         while (true) {
             int it_dev_done = 0;
-            for (int b = 0; b < kcheck && it_host + b < o.max_iter; ++b) {
+            const int nb = std::min(kcheck, o.max_iter - it_host);
+            bool any_rotation = false;
+            for (int b = 0; b < nb; ++b) {
                 const int i = it_host + b;
-                const bool rotate = o.k_rot > 0 && i > 0 && (i % o.k_rot) == 0;
-                if (!ph.c64) iterate<float, float, float, float>(c32, cn32, (float *)X32->ptr, rotate, hist_dev);
-                else if (!ph.g64) iterate<double, float, float, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
-                else iterate<double, double, double, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
-                it_dev_done = b + 1;
+                any_rotation |= o.k_rot > 0 && i > 0 && (i % o.k_rot) == 0;
+            }
+            if (o.graphs && nb == kcheck && !any_rotation) {
+                // a batch of k_check iterations without a rotation is the same
+                // launch sequence every time for the same buffers: replay it
+                // from a captured HIP graph (no memset nodes are recorded)
+                const GraphKey key{c32, c64, G->ptr, Gp->ptr, P->ptr, Y->ptr};
+                hipGraphExec_t exec = nullptr;
+                for (auto &kv : graphs)
+                    if (kv.first == key) exec = kv.second;
+                if (!exec) {
+                    // recording runs the host side of the batch (buffer roles
+                    // advance as they will on the device) but not the kernels
+                    hipGraph_t g = nullptr;
+                    TM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                    for (int b = 0; b < nb; ++b) step(false);
+                    TM_HIP(hipStreamEndCapture(s, &g));
+                    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    TM_HIP(e);
+                    graphs.push_back({key, exec});
+                } else if (nb % 2) {
+                    std::swap(G, Gp);   // the roles a replay leaves behind
+                }
+                TM_HIP(hipGraphLaunch(exec, s));
+                it_dev_done = nb;
+            } else {
+                for (int b = 0; b < nb; ++b) {
+                    const int i = it_host + b;
+                    step(o.k_rot > 0 && i > 0 && (i % o.k_rot) == 0);
+                    it_dev_done = b + 1;
+                }
             }
             poll();
             it_host = st_host->it;

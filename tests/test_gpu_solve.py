@@ -283,3 +283,22 @@ def test_c3_full_size_certified(ctx, tm, orc):
     assert min(cont.energies) >= r["E_G"] - 1e-10 * abs(r["E_G"])
     print(f"c3: E_G {r['E_G']:.15f} iterations {r['iterations']} max residual {np.max(res):.2e} "
           f"continuation min E {min(cont.energies):.15f}")
+
+
+@pytest.mark.parametrize("precision", ["full_dp", "mixed"])
+def test_graph_replay_matches_eager(ctx, tm, wells_problem, precision):
+    """Batches of k_check iterations replayed from captured HIP graphs run
+    the same kernels on the same buffers as the eager launches: every
+    quantity must agree bit for bit.  A solve replays its graphs many times,
+    with eager rotation batches, polls and (MIXED) a phase switch to new
+    buffers in between."""
+    print_case(test="graphs", precision=precision)
+    ra, Ca, wa, ha = _solve(tm, ctx, wells_problem, precision=precision, hist=3000, graphs=False)
+    rg, Cg, wg, hg = _solve(tm, ctx, wells_problem, precision=precision, hist=3000, graphs=True)
+    assert ra["iterations"] > 3 * 10
+    assert rg["iterations"] == ra["iterations"] and rg["iters_sp"] == ra["iters_sp"]
+    assert rg["E_G"] == ra["E_G"]
+    assert np.array_equal(host(wg), host(wa))
+    assert np.array_equal(host(Cg), host(Ca))
+    k = ra["iterations"]
+    assert np.array_equal(hg[:k], ha[:k])

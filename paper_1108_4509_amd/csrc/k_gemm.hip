@@ -93,14 +93,25 @@ __device__ inline void upper_tile(int t, int T, int &ti, int &tj) {
     tj = i + t;
 }
 
+// The update C_next = C + alpha P fused into S = C_next^T C_next (Fig. 1's
+// step C + alpha P, then Fig. 4 step (1)): both operands are formed from C
+// and P while they are staged, and the workgroups on the diagonal tiles store
+// C_next (each element once).
+template <typename TA, typename TP>
+struct GramUpd {
+    const TP *P = nullptr;
+    const CgState *st = nullptr;
+    TA *Cn = nullptr;
+};
+
 // One workgroup: a BM x BM tile of A^T B' over a chunk of rows.  Each lane
 // loads 16-byte vectors from a fixed column group (so h is read once), the
 // LDS stage is double-buffered, one barrier per stage.
-template <typename TA, typename TM, int BM, bool SHIFT>
+template <typename TA, typename TM, int BM, bool SHIFT, bool UPD = false, typename TP = TA>
 __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TA *__restrict__ B,
     const double *__restrict__ h, int T, int ntiles, bool symmetric,
-    int64_t rows_per_split, double *__restrict__ partials) {
+    int64_t rows_per_split, double *__restrict__ partials, GramUpd<TA, TP> up) {
     constexpr int KT = stage_rows<TM>();
     constexpr int WM = BM / 2;
     constexpr int NB = WM / 16;
@@ -147,9 +158,14 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
     // loads are unconditional (rows past the chunk end read a valid row and
     // columns past ld column 0, both zeroed at the store) so that no select
     // on a loaded value forces the prefetch to complete early
+    typedef TP PV __attribute__((ext_vector_type(VW)));
     V ra[PASSES], rb[PASSES], rx[SHIFT ? PASSES : 1];
+    PV pa[UPD ? PASSES : 1], pb[UPD ? PASSES : 1];
+    int64_t krow[UPD ? PASSES : 1];
     bool rv[PASSES];
     const int ci_c = ci_ok ? ci : 0, cj_c = cj_ok ? cj : 0;
+    TA alpha = TA(0);
+    if constexpr (UPD) alpha = (TA)up.st->alpha;
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int q = 0; q < PASSES; ++q) {
@@ -157,12 +173,34 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
             rv[q] = k < k_end;
             const int64_t kk = rv[q] ? k : k_begin;
             ra[q] = *reinterpret_cast<const V *>(A + kk * ld + ci_c);
-            rb[q] = *reinterpret_cast<const V *>(B + kk * ld + cj_c);
+            if constexpr (UPD) {
+                krow[q] = kk;
+                pa[q] = *reinterpret_cast<const PV *>(up.P + kk * ld + ci_c);
+                if (!same) {
+                    rb[q] = *reinterpret_cast<const V *>(B + kk * ld + cj_c);
+                    pb[q] = *reinterpret_cast<const PV *>(up.P + kk * ld + cj_c);
+                }
+            } else {
+                rb[q] = *reinterpret_cast<const V *>(B + kk * ld + cj_c);
+            }
             if constexpr (SHIFT)
                 if (!same) rx[q] = *reinterpret_cast<const V *>(A + kk * ld + cj_c);
         }
     };
     auto store = [&](int buf) {
+        if constexpr (UPD) {
+            // C_next = C + alpha P for both operands; the diagonal tiles keep it
+#pragma unroll
+            for (int q = 0; q < PASSES; ++q) {
+#pragma unroll
+                for (int w = 0; w < VW; ++w) {
+                    ra[q][w] = ra[q][w] + alpha * (TA)pa[q][w];
+                    if (same) rb[q][w] = ra[q][w];
+                    else rb[q][w] = rb[q][w] + alpha * (TA)pb[q][w];
+                }
+                if (same && rv[q] && ci_ok) *reinterpret_cast<V *>(up.Cn + krow[q] * ld + ci) = ra[q];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < PASSES; ++q) {
             const int row = rbase + q * RPP;
@@ -717,7 +755,7 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     const int grid = ntiles * nsplit;   // multiple of 8
 #define TM_GRAM(BMV, SH)                                                            \
     hipLaunchKernelGGL((gram_kernel<TA, TM, BMV, SH>), dim3(grid), dim3(kThreads), 0, s, \
-                       n, m, ld, A, B, h, T, ntiles, symmetric, rows, partials)
+                       n, m, ld, A, B, h, T, ntiles, symmetric, rows, partials, GramUpd<TA, TA>{})
     if (BM == 128) {
         if (h) TM_GRAM(128, true); else TM_GRAM(128, false);
     } else {
@@ -729,6 +767,33 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     const int64_t total = (int64_t)m * m;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
                        s, m, nsplit, BM, symmetric, zero_diag, partials, out);
+    TM_HIP(hipGetLastError());
+}
+
+template <typename TA, typename TM, typename TP>
+void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, const CgState *st,
+                 TA *Cn, double *partials, double *out) {
+    const int ld = leading_dim(m);
+    int BM, T, nsplit;
+    gram_shape(n, m, BM, T, nsplit);
+    const int ntiles = T * (T + 1) / 2;
+    constexpr int KT = stage_rows<TM>();
+    const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
+    const int grid = ntiles * nsplit;   // multiple of 8
+    GramUpd<TA, TP> up;
+    up.P = P;
+    up.st = st;
+    up.Cn = Cn;
+    if (BM == 128)
+        hipLaunchKernelGGL((gram_kernel<TA, TM, 128, false, true, TP>), dim3(grid), dim3(kThreads), 0, s,
+                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up);
+    else
+        hipLaunchKernelGGL((gram_kernel<TA, TM, 64, false, true, TP>), dim3(grid), dim3(kThreads), 0, s,
+                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up);
+    TM_HIP(hipGetLastError());
+    const int64_t total = (int64_t)m * m;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
+                       s, m, nsplit, BM, true, false, partials, out);
     TM_HIP(hipGetLastError());
 }
 
@@ -810,6 +875,9 @@ void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
 template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool);
 template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool);
 template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool);
+template void gram_update<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *, double *, double *);
+template void gram_update<double, double, float>(hipStream_t, int64_t, int, const double *, const float *, const CgState *, double *, double *, double *);
+template void gram_update<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *, double *, double *);
 template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool);
 template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool);
 template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *);

@@ -124,6 +124,12 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
           double *out, bool reduce = true);
 
+// S = Cn^T Cn with Cn = C + alpha P formed while staged (alpha from st) and
+// written to Cn: the update of Fig. 1 fused into Fig. 4 step (1).
+template <typename TA, typename TM, typename TP>
+void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, const CgState *st,
+                 TA *Cn, double *partials, double *out);
+
 // The Gram product with h (H' = A^T (B - A diag(h)), or A^T B without h) on
 // BF16 matrix cores with two-term BF16 operands (about 2^-16 relative to
 // sum |a||b|); full m x m, same partials layout and workspace as gram().

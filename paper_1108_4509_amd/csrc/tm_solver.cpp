@@ -207,6 +207,11 @@ struct Solver::Impl {
     template <typename TC, typename TS, typename TT>
     void orthonormalize(TC *Cin, TC *Cout) {
         gram<TC, TS>(s, n, m, Cin, Cin, nullptr, false, true, (double *)gram_ws->ptr, (double *)S->ptr);
+        finish_orthonormalize<TC, TT>(Cin, Cout);
+    }
+    // Fig. 4 steps (2)-(4) once S = Cin^T Cin is in S: Cout = Cin R^{-1}
+    template <typename TC, typename TT>
+    void finish_orthonormalize(TC *Cin, TC *Cout) {
         chol_inverse(s, m, (double *)S->ptr, (double *)Rinv->ptr, (double *)chol_ws->ptr, (int32_t *)info->ptr);
         pad_matrix<TT>(s, m, (double *)Rinv->ptr, true, (TT *)Wp->ptr, (double *)d->ptr);
         rot<TC, TT, TC>(s, n, m, Cin, (TT *)Wp->ptr, EPI_TRMM, nullptr, (double *)d->ptr, Cout);
@@ -276,9 +281,10 @@ struct Solver::Impl {
             reduce_partials(s, 2, nch, ld, (double *)dot_ws->ptr, (double *)dots2->ptr);
         }
         cg_control_alpha(s, m, ld, (double *)h->ptr, (double *)dots2->ptr, st);
-        // C_{i+1} = orthonormalize(C_i + alpha P)
-        c_update<TC, TG>(s, n, ld, C, Pv, st, Cn);
-        orthonormalize<TC, TMS, TMH>(Cn, C);
+        // C_{i+1} = orthonormalize(C_i + alpha P): the update is formed inside
+        // the Gram S = (C + alpha P)^T (C + alpha P), which also stores it
+        gram_update<TC, TMS, TG>(s, n, m, C, Pv, st, Cn, (double *)gram_ws->ptr, (double *)S->ptr);
+        finish_orthonormalize<TC, TMH>(Cn, C);
         std::swap(G, Gp);
     }
 

@@ -2,9 +2,10 @@
 // triangular inverse of Fig. 4 (steps (2) and (3)), and the assembly of the
 // m x m H of Eq. 9 from the pieces of Algorithm-2.
 //
-// The factorization is O(m^3) with m <= 1024, so it is latency-bound; it runs
-// as one workgroup of 1024 lanes with the matrix in a device workspace
-// (resident in L2) and the current panel staged in LDS.
+// The factorization is O(m^3) with m <= 1024, so it is latency-bound: the
+// serial part (the 64-wide diagonal blocks) runs in LDS inside one workgroup,
+// the panel and trailing products of each block column spread over many
+// workgroups, with the matrices in a device workspace resident in L2.
 #include "tm_common.h"
 
 #include <algorithm>
@@ -13,8 +14,6 @@
 namespace tmin {
 namespace {
 
-constexpr int kDenseThreads = 1024;
-constexpr int kStage = 17920;   // doubles of LDS staging (140 KiB)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 // v_mfma_f64_16x16x4: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
@@ -81,249 +80,288 @@ __device__ void diag_factor_wave(int lane, double *aug, double *piv, double (*Di
     }
 }
 
-// S = L L^T (L lower; S = R^T R with R = L^T) and Rinv = R^{-1} = L^{-T}
-// (upper triangle only; the caller clears the rest), in one right-looking
-// sweep over NB-wide panels that also carries the block forward substitution
-// L X = I:
-//   1. the diagonal block is factored and inverted by one wave (Dinv = L_kk^{-1});
-//   2. the panel's rows of the inverse are finished, X_k = Dinv W_k, where W
-//      holds I minus the updates of the earlier panels;
-//   3. the panel L_ik = S_ik Dinv^T;
-//   4. the trailing matrix S_ij -= L_ik L_jk^T (lower tiles) and the rows of W
-//      below, W_i -= L_ik X_k, both on FP64 matrix cores with L_ik and X_k
-//      staged in LDS.
-// W lives in the X workspace (rows below the panel), so each entry of X is
-// written once as final.  work: L (m*m), X (m*m) doubles.
-template <int NB>
-__global__ __launch_bounds__(kDenseThreads) void chol_inv_kernel(
-    int m, const double *__restrict__ S, double *__restrict__ Rinv,
-    double *__restrict__ work, int32_t *__restrict__ info) {
-    __shared__ double stage[kStage];
+// S = L L^T (L lower; S = R^T R with R = L^T) and Rinv = R^{-1} = L^{-T},
+// right-looking over kBlk-wide block columns, each in three launches:
+//   K1 (one workgroup): the diagonal block S_kk = L_kk L_kk^T is factored and
+//      inverted in LDS (X_kk = L_kk^{-1}), over 16-wide sub-panels, carrying
+//      the same block forward substitution L X = I inside the block;
+//   K2 (many workgroups): the panel below, L_ik = S_ik X_kk^T, and the block
+//      row of the inverse left of the diagonal, X_kj = X_kk W_kj, where W
+//      holds the off-diagonal part of I minus the updates of the earlier
+//      block columns (W_kj = -sum_{l<k} L_kl X_lj);
+//   K3 (many workgroups): the trailing matrix S_ij -= L_ik L_jk^T (lower
+//      tiles) and the rows of W below, W_ij -= L_ik X_kj.
+// All products are FP64 matrix-core tiles of 16 x 16.  Only the lower
+// triangles of S and of the updated trailing matrix are read.  work: L
+// (m*m; the trailing matrix, then the panels), X (m*m; W, then X = L^{-1})
+// doubles.  Rinv is written whole (zeros below the diagonal).
+constexpr int kBlk = 64;           // block column of the launches
+constexpr int kSub = 16;           // sub-panel inside K1
+constexpr int kBlkThreads = 256;   // 4 waves per workgroup
+constexpr int kAS = kBlk + 1;      // LDS row stride of the K1 block
+
+__global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
+    int m, int kb, const double *__restrict__ S, const double *__restrict__ L,
+    double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info) {
+    constexpr int NB = kSub, RSA = 2 * NB + 1, nwaves = kBlkThreads / 64;
+    __shared__ double A[kBlk * kAS];   // the block; the sub-panel columns become L
+    __shared__ double W[kBlk * kAS];   // W, then X_kk (lower, zero above)
+    __shared__ double aug[NB * RSA];
     __shared__ double Dinv[NB][NB + 1];
     __shared__ double piv[NB];
-    __shared__ double Sd[NB];
+    __shared__ double Sd[kBlk];
     __shared__ int ok_flag;
-    constexpr int PS = NB + 1;   // row stride of the staged panel
-    double *L = work;
-    double *X = work + (size_t)m * m;
-    constexpr int nwaves = kDenseThreads / 64;
-
-    for (int kb = 0; kb < m; kb += NB) {
-        // the lane index is made opaque per panel so that the many per-lane
-        // offsets of the unrolled loops are not hoisted out of the panel loop
-        // (their live ranges would exceed the register file)
-        int tid = threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        const int lane = tid & 63, wave = tid >> 6;
-        const int nb = (m - kb < NB) ? (m - kb) : NB;
-        const double *src = (kb == 0) ? S : L;
-        const int R = m - kb - nb;          // rows below the diagonal block
-        const int kw = kb + nb;             // columns of X_k and of the W update
-        const int XSS = ((kw + 15) & ~15) + 1;
-        double *XS = stage + kStage - NB * XSS;   // X_k (NB x kw), after the panel
-        // (1) diagonal block: stage [D | I] (identity-padded beyond nb),
-        // factor and invert it with one wave, then publish L_kk, the
-        // diagonal block of X and of Rinv
-        {
-            constexpr int RSA = 2 * NB + 1;
-            constexpr int NA = NB * 2 * NB, UA = (NA + kDenseThreads - 1) / kDenseThreads;
-            double v[UA];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = (m - kb < kBlk) ? (m - kb) : kBlk;
+    const double *src = (kb == 0) ? S : L;
+    {
+        // lower triangle of the block; identity beyond nb (pivots 1)
+        constexpr int U = kBlk * kBlk / kBlkThreads;
+        double v[U];
 #pragma unroll
-            for (int u = 0; u < UA; ++u) {
-                const int e = tid + u * kDenseThreads;
-                const int i = e / (2 * NB), c = e - (e / (2 * NB)) * (2 * NB);
-                v[u] = (i == c || i == c - NB) ? 1.0 : 0.0;
-                if (e < NA && c < NB && i < nb && c < nb) {
-                    const int r = i > c ? i : c, q = i > c ? c : i;   // lower part
-                    v[u] = src[(size_t)(kb + r) * m + kb + q];
-                }
-            }
-            const double sd = (tid < nb) ? S[(size_t)(kb + tid) * m + kb + tid] : 1.0;
-#pragma unroll
-            for (int u = 0; u < UA; ++u) {
-                const int e = tid + u * kDenseThreads;
-                if (e < NA) stage[(e / (2 * NB)) * RSA + e % (2 * NB)] = v[u];
-            }
-            if (tid < NB) Sd[tid] = sd;
-            __syncthreads();
-            if (wave == 0) {
-                diag_factor_wave<NB>(lane, stage, piv, Dinv);
-                if (lane == 0) {
-                    int ok = 1;
-                    for (int k = 0; k < nb; ++k)
-                        if (!(piv[k] > kPivotTol * fabs(Sd[k]))) ok = 0;
-                    ok_flag = ok;
-                }
-            }
-            __syncthreads();
-            if (!ok_flag) {
-                if (tid == 0) info[0] = kb + 1;
-                return;   // uniform
-            }
-            for (int e = tid; e < NB * NB; e += kDenseThreads) {
-                const int i = e / NB, c = e - (e / NB) * NB;
-                if (i < nb && c < nb) {
-                    if (c <= i) L[(size_t)(kb + i) * m + kb + c] = stage[c * RSA + i];
-                    const double xv = Dinv[i][c];
-                    X[(size_t)(kb + i) * m + kb + c] = xv;
-                    if (c <= i) Rinv[(size_t)(kb + c) * m + kb + i] = xv;
-                } else {
-                    Dinv[i][c] = 0.0;
-                }
-            }
-            __syncthreads();   // stage is reused below; Dinv padding visible
+        for (int u = 0; u < U; ++u) {
+            const int e = tid + u * kBlkThreads, i = e / kBlk, c = e % kBlk;
+            v[u] = (i == c) ? 1.0 : 0.0;
+            if (i < nb && c <= i) v[u] = src[(size_t)(kb + i) * m + kb + c];
         }
-        // (2) X_k = Dinv W_k on the columns left of the block; the block itself
-        // is Dinv.  Stage X_k (zero rows beyond nb) for the W update.
-        {
-            // one wave per 16-column tile of W_k, all NB rows: the tile is
-            // read completely before it is overwritten in place
-            const int nbj = kb / 16;
-            for (int bj = wave; bj < nbj; bj += nwaves) {
-                const int jc = bj * 16 + (lane & 15);
-                d4 acc[NB / 16];
+        const double sd = (tid < nb) ? S[(size_t)(kb + tid) * m + kb + tid] : 1.0;
 #pragma unroll
-                for (int bi = 0; bi < NB / 16; ++bi) acc[bi] = d4{0.0, 0.0, 0.0, 0.0};
-                double bv[NB / 4];   // all loads in flight before the products
+        for (int u = 0; u < U; ++u) {
+            const int e = tid + u * kBlkThreads, i = e / kBlk, c = e % kBlk;
+            A[i * kAS + c] = v[u];
+            W[i * kAS + c] = 0.0;
+        }
+        if (tid < kBlk) Sd[tid] = sd;
+    }
+    __syncthreads();
+    const int np = (nb + NB - 1) / NB;
+    for (int p = 0; p < np; ++p) {
+        const int q = p * NB;
+        // (1) the 16 x 16 diagonal sub-block, factored and inverted by wave 0
+        if (wave == 0) {
 #pragma unroll
-                for (int u = 0; u < NB / 4; ++u) {
-                    const int t = 4 * u + (lane >> 4);
-                    bv[u] = (t < nb) ? X[(size_t)(kb + t) * m + jc] : 0.0;
-                }
+            for (int u = 0; u < NB * 2 * NB / 64; ++u) {
+                const int e = lane + 64 * u, i = e / (2 * NB), c = e % (2 * NB);
+                double v = (i == c - NB) ? 1.0 : 0.0;
+                if (c < NB) v = A[(q + (i > c ? i : c)) * kAS + q + (i > c ? c : i)];
+                aug[i * RSA + c] = v;
+            }
+            // LDS written by this wave is read back by other lanes of it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            diag_factor_wave<NB>(lane, aug, piv, Dinv);
+            if (lane == 0) {
+                int bad = -1;
+                for (int k = NB - 1; k >= 0; --k)
+                    if (!(piv[k] > kPivotTol * fabs(Sd[q + k]))) bad = k;
+                ok_flag = bad;
+            }
+        }
+        __syncthreads();
+        if (ok_flag >= 0) {   // uniform
+            if (tid == 0 && info[0] == 0) info[0] = kb + q + ok_flag + 1;
+            return;
+        }
+        // (2) X of the sub-panel's rows: Dinv on the diagonal, X_pj = Dinv W_pj
+        //     left of it (one wave per 16-column strip, read before written);
+        // (3) the sub-panel below: L_ip = A_ip Dinv^T (one wave per tile)
+        for (int e = tid; e < NB * NB; e += kBlkThreads)
+            W[(q + e / NB) * kAS + q + e % NB] = Dinv[e / NB][e % NB];
+        const int nbelow = np - 1 - p;
+        for (int t = wave; t < p + nbelow; t += nwaves) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            if (t < p) {
+                const int jc = t * NB + (lane & 15);
+                double bv[NB / 4];
+#pragma unroll
+                for (int u = 0; u < NB / 4; ++u) bv[u] = W[(q + 4 * u + (lane >> 4)) * kAS + jc];
 #pragma unroll
                 for (int u = 0; u < NB / 4; ++u)
+                    acc = mfma64(Dinv[lane & 15][4 * u + (lane >> 4)], bv[u], acc);
 #pragma unroll
-                    for (int bi = 0; bi < NB / 16; ++bi)
-                        acc[bi] = mfma64(Dinv[bi * 16 + (lane & 15)][4 * u + (lane >> 4)], bv[u], acc[bi]);
+                for (int r = 0; r < 4; ++r) W[(q + mfma64_row(lane, r)) * kAS + jc] = acc[r];
+            } else {
+                const int r0 = (t + 1) * NB;   // sub-panel row tile t + 1
+                double av[NB / 4];
 #pragma unroll
-                for (int bi = 0; bi < NB / 16; ++bi)
+                for (int u = 0; u < NB / 4; ++u) av[u] = A[(r0 + (lane & 15)) * kAS + q + 4 * u + (lane >> 4)];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = bi * 16 + mfma64_row(lane, r);
-                        XS[i * XSS + jc] = (i < nb) ? acc[bi][r] : 0.0;
-                        if (i < nb) {
-                            X[(size_t)(kb + i) * m + jc] = acc[bi][r];
-                            Rinv[(size_t)jc * m + kb + i] = acc[bi][r];
-                        }
-                    }
-            }
-            for (int e = tid; e < NB * NB; e += kDenseThreads) {
-                const int i = e / NB, c = e - (e / NB) * NB;
-                if (kb + c < XSS - 1) XS[i * XSS + kb + c] = Dinv[i][c];
-            }
-        }
-        // (3) stage S_ik (R x nb), then the panel L_ik = S_ik Dinv^T
-        for (int e0 = tid; e0 < R * NB; e0 += 8 * kDenseThreads) {
-            double v[8];
+                for (int u = 0; u < NB / 4; ++u)
+                    acc = mfma64(av[u], Dinv[lane & 15][4 * u + (lane >> 4)], acc);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kDenseThreads, r = e / NB, c = e % NB;
-                v[u] = (e < R * NB && c < nb) ? src[(size_t)(kb + nb + r) * m + kb + c] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kDenseThreads;
-                if (e < R * NB) stage[(e / NB) * PS + e % NB] = v[u];
+                for (int r = 0; r < 4; ++r) A[(r0 + mfma64_row(lane, r)) * kAS + q + (lane & 15)] = acc[r];
             }
         }
         __syncthreads();
-        const int nbr = (R + 15) / 16;
-        constexpr int kStrips = (NB == 32) ? 2 : 4;
-        d4 pacc[kStrips][NB / 16];
-#pragma unroll
-        for (int sidx = 0; sidx < kStrips; ++sidx) {
-            const int bi = wave + sidx * nwaves;
-            if (bi >= nbr) break;
-            const int ra = bi * 16 + (lane & 15);
-#pragma unroll
-            for (int bj = 0; bj < NB / 16; ++bj) {
-                d4 acc = {0.0, 0.0, 0.0, 0.0};
-                for (int t0 = 0; t0 < nb; t0 += 4) {
-                    const int k = t0 + (lane >> 4);
-                    const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
-                    const double b = Dinv[bj * 16 + (lane & 15)][k];   // B[k][j] = Dinv[j][k]
-                    acc = mfma64(a, b, acc);
-                }
-                pacc[sidx][bj] = acc;
-            }
-        }
-        __syncthreads();   // all reads of the staged S_ik done
-#pragma unroll
-        for (int sidx = 0; sidx < kStrips; ++sidx) {
-            const int bi = wave + sidx * nwaves;
-            if (bi >= nbr) break;
-#pragma unroll
-            for (int bj = 0; bj < NB / 16; ++bj) {
-                const d4 acc = pacc[sidx][bj];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = bi * 16 + mfma64_row(lane, r), c = bj * 16 + (lane & 15);
-                    if (i < R && c < nb) {
-                        stage[i * PS + c] = acc[r];
-                        L[(size_t)(kb + nb + i) * m + kb + c] = acc[r];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // (4) trailing update of the lower triangle (disjoint from the panel
-        // columns) and of the W rows below the panel
-        const int npairs = nbr * (nbr + 1) / 2;
-        const int ncw = (kw + 15) / 16;
-        const int nwork = npairs + nbr * ncw;
-        for (int p = wave; p < nwork; p += nwaves) {
-            const bool sym = p < npairs;
+        // (4) trailing: A_ij -= L_ip L_jp^T (tiles below the sub-panel, lower)
+        //     and W_ij -= L_ip X_pj (rows below, columns up to the sub-panel)
+        const int nr = nbelow, npairs = nr * (nr + 1) / 2, nwork = npairs + nr * (p + 1);
+        for (int t = wave; t < nwork; t += nwaves) {
+            const bool sym = t < npairs;
             int bi, bj;
             if (sym) {
-                lower_pair(p, bi, bj);
+                lower_pair(t, bi, bj);
+                bi += p + 1;
+                bj += p + 1;
             } else {
-                const int q = p - npairs;
-                bi = q / ncw;
-                bj = q - bi * ncw;
-            }
-            // old values first, so their latency overlaps the products
-            double old[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
-                double v = 0.0;
-                if (sym) {
-                    if (i < R && j <= i) v = src[(size_t)(kb + nb + i) * m + kb + nb + j];
-                } else {
-                    // columns of this panel were never updated: W = I there (0 off the diagonal)
-                    if (i < R && j < kb) v = X[(size_t)(kb + nb + i) * m + j];
-                }
-                old[r] = v;
+                const int u = t - npairs;
+                bi = p + 1 + u / (p + 1);
+                bj = u % (p + 1);
             }
             d4 acc = {0.0, 0.0, 0.0, 0.0};
-            const int ra = bi * 16 + (lane & 15), rb = bj * 16 + (lane & 15);
-            for (int t0 = 0; t0 < nb; t0 += 4) {
-                const int k = t0 + (lane >> 4);
-                const double a = (ra < R) ? stage[ra * PS + k] : 0.0;
-                double b;
-                if (sym) b = (rb < R) ? stage[rb * PS + k] : 0.0;
-                else b = (rb < kw) ? XS[k * XSS + rb] : 0.0;
+#pragma unroll
+            for (int u = 0; u < NB / 4; ++u) {
+                const int k = q + 4 * u + (lane >> 4);
+                const double a = A[(bi * NB + (lane & 15)) * kAS + k];
+                const double b = sym ? A[(bj * NB + (lane & 15)) * kAS + k]
+                                     : W[k * kAS + bj * NB + (lane & 15)];
                 acc = mfma64(a, b, acc);
             }
+            double *T = sym ? A : W;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
-                if (sym) {
-                    if (i < R && j <= i) L[(size_t)(kb + nb + i) * m + kb + nb + j] = old[r] - acc[r];
-                } else {
-                    if (i < R && j < kw) X[(size_t)(kb + nb + i) * m + j] = old[r] - acc[r];
-                }
+                const int idx = (bi * NB + mfma64_row(lane, r)) * kAS + bj * NB + (lane & 15);
+                T[idx] -= acc[r];
             }
         }
         __syncthreads();
     }
+    // X_kk out, and the whole diagonal block of Rinv = X^T
+    for (int e = tid; e < nb * nb; e += kBlkThreads) {
+        const int i = e / nb, c = e - (e / nb) * nb;
+        const double x = W[i * kAS + c];
+        if (c <= i) X[(size_t)(kb + i) * m + kb + c] = x;
+        Rinv[(size_t)(kb + c) * m + kb + i] = (c <= i) ? x : 0.0;
+    }
 }
 
-__global__ void zero_lower_kernel(int m, double *__restrict__ A) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)m * m) return;
-    const int i = (int)(idx / m), j = (int)(idx - (int64_t)i * m);
-    if (j < i) A[idx] = 0.0;
+// K2: workgroups [0, nA) form the panel L_ik = S_ik X_kk^T, 16 rows each (one
+// 16-column tile per wave); workgroups [nA, nA + kb/16) finish a 16-column
+// strip of the block row of X, X_kj = X_kk W_kj (the strip is staged in LDS
+// before it is overwritten), with Rinv's mirror entries and the zeros below
+// its diagonal.
+__global__ __launch_bounds__(kBlkThreads) void chol_panel_kernel(
+    int m, int kb, const double *__restrict__ S, double *__restrict__ L,
+    double *__restrict__ X, double *__restrict__ Rinv) {
+    constexpr int KS = kBlk / 4;   // MFMA k-steps over the block width
+    __shared__ double Ws[kBlk][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = (m - kb < kBlk) ? (m - kb) : kBlk, R = m - kb - nb;
+    const int nA = (R + 15) / 16;
+    const double *src = (kb == 0) ? S : L;
+    const int g = blockIdx.x;
+    if (g < nA) {
+        // R > 0 here, so the block is full (nb == kBlk)
+        const int i0 = kb + nb + 16 * g, c0 = 16 * wave;
+        const int ia = i0 + (lane & 15), cb = c0 + (lane & 15);
+        double av[KS], bv[KS];
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int t = 4 * u + (lane >> 4);
+            av[u] = (ia < m) ? src[(size_t)ia * m + kb + t] : 0.0;
+            bv[u] = (t <= cb) ? X[(size_t)(kb + cb) * m + kb + t] : 0.0;   // X_kk[c][t]
+        }
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < KS; ++u) acc = mfma64(av[u], bv[u], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + mfma64_row(lane, r);
+            if (i < m) L[(size_t)i * m + kb + cb] = acc[r];
+        }
+        return;
+    }
+    const int j0 = 16 * (g - nA);
+    for (int e = tid; e < kBlk * 16; e += kBlkThreads) {
+        const int i = e >> 4, j = e & 15;
+        Ws[i][j] = (i < nb) ? X[(size_t)(kb + i) * m + j0 + j] : 0.0;
+    }
+    __syncthreads();
+    const int r0 = 16 * wave;
+    if (r0 >= nb) return;   // no barrier follows
+    const int ra = r0 + (lane & 15);
+    double av[KS];
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+        const int t = 4 * u + (lane >> 4);
+        av[u] = (ra < nb && t <= ra) ? X[(size_t)(kb + ra) * m + kb + t] : 0.0;   // X_kk lower
+    }
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < KS; ++u) acc = mfma64(av[u], Ws[4 * u + (lane >> 4)][lane & 15], acc);
+    const int j = j0 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = r0 + mfma64_row(lane, r);
+        if (i < nb) {
+            X[(size_t)(kb + i) * m + j] = acc[r];
+            Rinv[(size_t)j * m + kb + i] = acc[r];
+            Rinv[(size_t)(kb + i) * m + j] = 0.0;
+        }
+    }
+}
+
+// K3: one wave per 16 x 16 tile below the block column: the lower tiles of
+// the trailing matrix (lower_pair order), then the W tiles left of the
+// trailing matrix.  A tile is read and written by its own wave only.
+__global__ __launch_bounds__(kBlkThreads) void chol_trail_kernel(
+    int m, int kb, const double *__restrict__ S, double *__restrict__ L,
+    double *__restrict__ X) {
+    constexpr int KS = kBlk / 4;
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * (kBlkThreads / 64) + (threadIdx.x >> 6);
+    const int k0 = kb + kBlk;   // first row below the block (the block is full)
+    const int R = m - k0, nr = (R + 15) / 16, npairs = nr * (nr + 1) / 2;
+    const int nc = k0 / 16;
+    if (t >= npairs + nr * nc) return;
+    const double *src = (kb == 0) ? S : L;
+    const bool sym = t < npairs;
+    int bi, bj;
+    if (sym) {
+        lower_pair(t, bi, bj);
+    } else {
+        bi = (t - npairs) / nc;
+        bj = (t - npairs) - bi * nc;
+    }
+    const int ia = k0 + bi * 16 + (lane & 15);
+    const int jb = (sym ? k0 : 0) + bj * 16 + (lane & 15);   // column of B (and of the tile)
+    double av[KS], bv[KS], old[4];
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+        const int tk = 4 * u + (lane >> 4);
+        av[u] = (ia < m) ? L[(size_t)ia * m + kb + tk] : 0.0;
+        if (sym) {
+            bv[u] = (jb < m) ? L[(size_t)jb * m + kb + tk] : 0.0;
+        } else {
+            // X_kj: the block row of X left of the diagonal, X_kk (lower) on it
+            const bool valid = jb < kb || jb - kb <= tk;
+            bv[u] = valid ? X[(size_t)(kb + tk) * m + jb] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = k0 + bi * 16 + mfma64_row(lane, r);
+        double v = 0.0;
+        if (sym) {
+            if (i < m && jb <= i) v = src[(size_t)i * m + jb];
+        } else {
+            if (i < m && jb < kb) v = X[(size_t)i * m + jb];   // W; zero right of kb
+        }
+        old[r] = v;
+    }
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < KS; ++u) acc = mfma64(av[u], bv[u], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = k0 + bi * 16 + mfma64_row(lane, r);
+        if (sym) {
+            if (i < m && jb <= i) L[(size_t)i * m + jb] = old[r] - acc[r];
+        } else {
+            if (i < m) X[(size_t)i * m + jb] = old[r] - acc[r];
+        }
+    }
 }
 
 __global__ void assemble_kernel(int m, const double *__restrict__ Hp,
@@ -345,28 +383,23 @@ size_t chol_workspace(int m) {
 void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
                   double *work, int32_t *info) {
     TM_REQUIRE(m >= 1 && m <= 1024, TM_ENOTSUP, "Cholesky supports m <= 1024");
-    // the staged panel (R x (NB+1)) and X_k (NB x (kb+nb) rounded to 16, +1)
-    // must fit the LDS staging area together, for every panel
-    {
-        const int NB = m <= 512 ? 32 : 16;
-        for (int kb = 0; kb < m; kb += NB) {
-            const int nb = std::min(NB, m - kb), R = m - kb - nb;
-            const int XSS = ((kb + nb + 15) & ~15) + 1;
-            TM_REQUIRE((size_t)R * (NB + 1) + (size_t)NB * XSS <= (size_t)kStage, TM_ENOTSUP,
-                       "Cholesky staging exceeds LDS");
+    double *L = work, *X = work + (size_t)m * m;
+    for (int kb = 0; kb < m; kb += kBlk) {
+        const int nb = std::min(kBlk, m - kb), R = m - kb - nb;
+        hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(kBlkThreads), 0, s, m, kb, S, L, X,
+                           Rinv, info);
+        const int nA = (R + 15) / 16, nB = kb / 16;
+        if (nA + nB > 0)
+            hipLaunchKernelGGL(chol_panel_kernel, dim3(nA + nB), dim3(kBlkThreads), 0, s, m, kb,
+                               S, L, X, Rinv);
+        if (R > 0) {
+            const int nr = (R + 15) / 16, tiles = nr * (nr + 1) / 2 + nr * ((kb + kBlk) / 16);
+            const int per = kBlkThreads / 64;
+            hipLaunchKernelGGL(chol_trail_kernel, dim3((tiles + per - 1) / per), dim3(kBlkThreads),
+                               0, s, m, kb, S, L, X);
         }
+        TM_HIP(hipGetLastError());
     }
-    if (m <= 512)
-        hipLaunchKernelGGL(chol_inv_kernel<32>, dim3(1), dim3(kDenseThreads), 0, s, m, S,
-                           Rinv, work, info);
-    else
-        hipLaunchKernelGGL(chol_inv_kernel<16>, dim3(1), dim3(kDenseThreads), 0, s, m, S,
-                           Rinv, work, info);
-    TM_HIP(hipGetLastError());
-    const int64_t total = (int64_t)m * m;
-    hipLaunchKernelGGL(zero_lower_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       m, Rinv);
-    TM_HIP(hipGetLastError());
 }
 
 void assemble_subspace_matrix(hipStream_t s, int m, const double *Hp,

@@ -35,49 +35,49 @@ __device__ inline void lower_pair(int p, int &bi, int &bj) {
     bj = p - i * (i + 1) / 2;
 }
 
-// Factor the NB x NB diagonal block D = L_kk L_kk^T and invert it, by one
-// wave, on the augmented NB x 2NB matrix [D | I] staged in LDS (aug, row
-// stride 2NB + 1): lane c keeps column c in registers (rows a[0..NB)).
-// Gaussian elimination without pivoting: at step k every lane reads the
-// multipliers a_ik / a_kk of lane k's column by readlane and updates its own
-// column, so no barrier and no memory round trip is needed.  Afterwards the D half holds U = diag(d) L1^T and
-// the I half L1^{-1} (L1 unit lower), so L = L1 diag(d)^{1/2} and
-// L^{-1} = diag(d)^{-1/2} L1^{-1}.  Results go back to LDS: L_kk^T into the
-// D half of aug, L_kk^{-1} (zero above the diagonal) into Dinv, the pivots d
-// into piv.  For NB = 16 the upper 32 lanes repeat the last column.
 __device__ inline double readlane_f64(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
 }
 
+// Invert the Cholesky factor of an NB x NB diagonal block D = L L^T by one
+// wave, on the augmented NB x 2NB matrix [D | I] held in registers: lane c
+// keeps column c (rows a[0..NB)); for NB = 16 the upper 32 lanes repeat the
+// last column.  Gaussian elimination without pivoting: at step k every lane
+// takes the column of multipliers from lane k by readlane and updates its
+// own column, so no barrier and no memory round trip is needed.  Afterwards
+// the I half holds L1^{-1}, where D = L1 diag(d) L1^T with L1 unit lower, so
+// L^{-1} = diag(d)^{-1/2} L1^{-1}; it goes to Dinv (zero above the
+// diagonal).  Returns the pivot d_l in lane l < NB (1 in the other lanes).
 template <int NB>
-__device__ void diag_factor_wave(int lane, double *aug, double *piv, double (*Dinv)[NB + 1]) {
-    constexpr int NC = 2 * NB, RS = 2 * NB + 1;
-    const int c = lane < NC ? lane : NC - 1;
-    double a[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) a[i] = aug[i * RS + c];
+__device__ __attribute__((always_inline)) double diag_inv_wave(int lane, double (&a)[NB],
+                                                               double (*Dinv)[NB + 1]) {
+    constexpr int NC = 2 * NB;
+    double dl = 1.0;
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        // the multipliers a_ik / a_kk come from lane k by readlane
         const double dk = readlane_f64(a[k], k);
-        if (lane == 0) piv[k] = dk;
-        // a_ic -= a_ik (a_kc / a_kk): one scaling per lane, one FMA per row
-        const double rk = a[k] * (1.0 / dk);
+        dl = (lane == k) ? dk : dl;
+        // 1 / d_k: the hardware reciprocal refined by two Newton steps
+        double r = __builtin_amdgcn_rcp(dk);
+        r = fma(r, fma(-dk, r, 1.0), r);
+        r = fma(r, fma(-dk, r, 1.0), r);
+        // a_ic -= a_ik (a_kc / d_k): one scaling per lane, one FMA per row
+        const double rk = a[k] * r;
 #pragma unroll
         for (int i = k + 1; i < NB; ++i) a[i] = fma(-readlane_f64(a[i], k), rk, a[i]);
     }
-    if (lane < NB) {
-        // lane i: row i of L, L_iq = U_qi / sqrt(d_q) for q <= i, stored transposed
+    const double sl = 1.0 / sqrt(dl);   // lane l < NB: d_l^{-1/2}
+    double sc[NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) aug[q * RS + lane] = (q <= lane) ? a[q] / sqrt(piv[q]) : 0.0;
-    } else if (lane < NC) {
-        // lane NB + col: column col of X = diag(d)^{-1/2} L1^{-1}
+    for (int i = 0; i < NB; ++i) sc[i] = readlane_f64(sl, i);
+    if (lane >= NB && lane < NC) {
         const int col = lane - NB;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) Dinv[i][col] = (i >= col) ? a[i] / sqrt(piv[i]) : 0.0;
+        for (int i = 0; i < NB; ++i) Dinv[i][col] = (i >= col) ? a[i] * sc[i] : 0.0;
     }
+    return dl;
 }
 
 // S = L L^T (L lower; S = R^T R with R = L^T) and Rinv = R^{-1} = L^{-T},
@@ -103,12 +103,10 @@ constexpr int kAS = kBlk + 1;      // LDS row stride of the K1 block
 __global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
     int m, int kb, const double *__restrict__ S, const double *__restrict__ L,
     double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info) {
-    constexpr int NB = kSub, RSA = 2 * NB + 1, nwaves = kBlkThreads / 64;
+    constexpr int NB = kSub, nwaves = kBlkThreads / 64;
     __shared__ double A[kBlk * kAS];   // the block; the sub-panel columns become L
     __shared__ double W[kBlk * kAS];   // W, then X_kk (lower, zero above)
-    __shared__ double aug[NB * RSA];
     __shared__ double Dinv[NB][NB + 1];
-    __shared__ double piv[NB];
     __shared__ double Sd[kBlk];
     __shared__ int ok_flag;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -139,24 +137,17 @@ __global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
         const int q = p * NB;
         // (1) the 16 x 16 diagonal sub-block, factored and inverted by wave 0
         if (wave == 0) {
+            const int c = lane < 2 * NB ? lane : 2 * NB - 1;
+            double a[NB];
 #pragma unroll
-            for (int u = 0; u < NB * 2 * NB / 64; ++u) {
-                const int e = lane + 64 * u, i = e / (2 * NB), c = e % (2 * NB);
-                double v = (i == c - NB) ? 1.0 : 0.0;
-                if (c < NB) v = A[(q + (i > c ? i : c)) * kAS + q + (i > c ? c : i)];
-                aug[i * RSA + c] = v;
-            }
-            // LDS written by this wave is read back by other lanes of it
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            diag_factor_wave<NB>(lane, aug, piv, Dinv);
-            if (lane == 0) {
-                int bad = -1;
-                for (int k = NB - 1; k >= 0; --k)
-                    if (!(piv[k] > kPivotTol * fabs(Sd[q + k]))) bad = k;
-                ok_flag = bad;
-            }
+            for (int i = 0; i < NB; ++i)
+                a[i] = c < NB ? A[(q + (i > c ? i : c)) * kAS + q + (i > c ? c : i)]
+                              : (i == c - NB ? 1.0 : 0.0);
+            const double dl = diag_inv_wave<NB>(lane, a, Dinv);
+            // breakdown: the first pivot below kPivotTol times its S diagonal
+            const double sd = lane < NB ? Sd[q + lane] : 1.0;
+            const unsigned long long bad = __ballot(lane < NB && !(dl > kPivotTol * fabs(sd)));
+            if (lane == 0) ok_flag = bad ? __ffsll(bad) - 1 : -1;
         }
         __syncthreads();
         if (ok_flag >= 0) {   // uniform
@@ -227,12 +218,15 @@ __global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
         }
         __syncthreads();
     }
-    // X_kk out, and the whole diagonal block of Rinv = X^T
-    for (int e = tid; e < nb * nb; e += kBlkThreads) {
-        const int i = e / nb, c = e - (e / nb) * nb;
-        const double x = W[i * kAS + c];
-        if (c <= i) X[(size_t)(kb + i) * m + kb + c] = x;
-        Rinv[(size_t)(kb + c) * m + kb + i] = (c <= i) ? x : 0.0;
+    // X_kk out, and the whole diagonal block of Rinv = X^T (zero below the
+    // diagonal); each written along its rows
+    constexpr int U = kBlk * kBlk / kBlkThreads;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = tid + u * kBlkThreads, i = e / kBlk, c = e % kBlk;
+        if (i < nb && c <= i) X[(size_t)(kb + i) * m + kb + c] = W[i * kAS + c];
+        // Rinv row i, column c: X_kk[c][i]
+        if (i < nb && c < nb) Rinv[(size_t)(kb + i) * m + kb + c] = (i <= c) ? W[c * kAS + i] : 0.0;
     }
 }
 

@@ -445,20 +445,21 @@ __global__ __launch_bounds__(kThreads, 2) void gram_bf16x3_kernel(
 
 int gram_tile(int ld) { return ld >= 256 ? 128 : 64; }
 
-void gram_shape(int64_t n, int m, int &BM, int &T, int &nsplit) {
+void gram_shape(int64_t n, int m, bool symmetric, int &BM, int &T, int &nsplit) {
     const int ld = leading_dim(m);
     BM = gram_tile(ld);
     T = (ld + BM - 1) / BM;
-    // aim at ~2 workgroups per CU, at most 64 MiB of FP64 partials, and at
-    // least 128 rows per split; nsplit is a multiple of 8 (XCD mapping)
-    const int ntiles_full = T * T;
-    int64_t ns = 512 / ntiles_full;
-    const int64_t cap_bytes = (int64_t)64 << 20;
+    // two workgroups per CU (512 over the 256 CUs, so that no CU runs more
+    // row chunks than another), at most 96 MiB of FP64 partials, and at least
+    // 128 rows per split; nsplit is a multiple of 8 (XCD mapping)
+    const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
+    int64_t ns = 512 / ntiles;
+    const int64_t cap_bytes = (int64_t)96 << 20;
     int64_t cap = cap_bytes / ((int64_t)m * m * 8);
     if (ns > cap) ns = cap;
     int64_t cap_rows = n / 128;
     if (ns > cap_rows) ns = cap_rows;
-    ns = (ns + 7) / 8 * 8;
+    ns = ns / 8 * 8;
     if (ns < 8) ns = 8;
     nsplit = (int)ns;
 }
@@ -736,9 +737,10 @@ __global__ void pad_kernel(int m, int ld, const double *__restrict__ W,
 }  // namespace
 
 size_t gram_workspace(int64_t n, int m) {
-    int BM, T, nsplit;
-    gram_shape(n, m, BM, T, nsplit);
-    return (size_t)nsplit * m * m * sizeof(double);
+    int BM, T, ns_full, ns_sym;
+    gram_shape(n, m, false, BM, T, ns_full);
+    gram_shape(n, m, true, BM, T, ns_sym);
+    return (size_t)std::max(ns_full, ns_sym) * m * m * sizeof(double);
 }
 
 template <typename TA, typename TM>
@@ -746,9 +748,9 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
           double *out, bool reduce) {
     const int ld = leading_dim(m);
-    int BM, T, nsplit;
-    gram_shape(n, m, BM, T, nsplit);
     if (h) symmetric = false;
+    int BM, T, nsplit;
+    gram_shape(n, m, symmetric, BM, T, nsplit);
     const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
     constexpr int KT = stage_rows<TM>();
     const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
@@ -775,7 +777,7 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
                  TA *Cn, double *partials, double *out) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
-    gram_shape(n, m, BM, T, nsplit);
+    gram_shape(n, m, true, BM, T, nsplit);
     const int ntiles = T * (T + 1) / 2;
     constexpr int KT = stage_rows<TM>();
     const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
@@ -802,7 +804,7 @@ void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, cons
                  bool zero_diag, double *partials, double *out, bool reduce) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
-    gram_shape(n, m, BM, T, nsplit);
+    gram_shape(n, m, false, BM, T, nsplit);
     const int ntiles = T * T;
     const int KT = 8 * (kThreads / (BM / 2));
     const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;

@@ -318,6 +318,133 @@ __global__ __launch_bounds__(256) void spmm_csr_wave_kernel(
     if (ndot > 0) flush_wave_dots<T, NCV>(ds, ndot, wave, lane, lb, partials, red);
 }
 
+// Column-chunked form: a chunk is 256 bytes of every row (16 lanes of
+// 16-byte vectors; 4 rows per wave, 16 per workgroup pass), and the launch
+// is chunk-major, so each XCD walks all rows of one chunk (or a contiguous
+// part of them) in order.  The rows that neighbour the ones in flight then
+// stay in that XCD's L2 even for stencil offsets of a whole grid plane.  The
+// workgroup's row pointers, columns and values are staged in LDS first (two
+// round trips for all its rows), and each lane group gathers two rows at a
+// time.
+constexpr int kChunkLanes = 16;
+constexpr int kChunkRows = 64;   // rows per workgroup (more when n / 64 exceeds kGridCap)
+constexpr int kChunkMeta = 1024; // staged nonzeros per workgroup
+
+template <typename T, int UB, int RG>
+__global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
+    int64_t n, int rows_per_block, int nrb, int nchunks, const int64_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const T *__restrict__ val,
+    const typename Vec<T>::type *__restrict__ C, typename Vec<T>::type *__restrict__ X,
+    int ldv, int ndot, double *__restrict__ partials) {
+    using V = typename Vec<T>::type;
+    constexpr int W = Vec<T>::W;
+    constexpr int L = kChunkLanes, RPW = 64 / L, RPP = 4 * RPW;
+    __shared__ double red[2][RPP][L * W];
+    __shared__ int64_t rp[257];
+    __shared__ int32_t cs[kChunkMeta];
+    __shared__ T vs[kChunkMeta];
+    const int64_t lb = logical_block(gridDim.x);
+    if (lb >= (int64_t)nrb * nchunks) return;   // uniform
+    const int chunk = (int)(lb / nrb), rb = (int)(lb - (int64_t)chunk * nrb);
+    const int t = threadIdx.x, l = t % L, slot = t / L;
+    const int cv = chunk * L + l;
+    const int64_t r_begin = (int64_t)rb * rows_per_block;
+    int64_t r_end = r_begin + rows_per_block;
+    if (r_end > n) r_end = n;
+    const int nr = (int)(r_end - r_begin);   // <= 256
+    for (int i = t; i <= nr; i += 256) rp[i] = rowptr[r_begin + i];
+    __syncthreads();
+    const int64_t e0 = rp[0];
+    const int ne = (int)(rp[nr] - e0);
+    const bool staged = ne <= kChunkMeta;   // uniform
+    if (staged) {
+        for (int e = t; e < ne; e += 256) {
+            cs[e] = col[e0 + e];
+            vs[e] = val[e0 + e];
+        }
+    }
+    __syncthreads();
+    double ds[2][W];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int w = 0; w < W; ++w) ds[p][w] = 0.0;
+    auto finish = [&](int64_t r, const V &acc) {
+        X[r * ldv + cv] = acc;
+        if (ndot > 0) {
+            const V c = C[r * ldv + cv];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                ds[0][w] += (double)c[w] * (double)acc[w];
+                if (ndot > 1) ds[1][w] += (double)c[w] * (double)c[w];
+            }
+        }
+    };
+    if (staged) {
+        // RG rows per lane group at a time (rows i, i + RPP, ...), UB
+        // nonzeros of each per batch, all gathers in flight together; slots
+        // past a row's end read entry 0 with weight zero
+        for (int i = slot; i < nr; i += RG * RPP) {
+            int s0[RG], s1[RG];
+            V acc[RG];
+            int len = 0;
+#pragma unroll
+            for (int g = 0; g < RG; ++g) {
+                const int ig = i + g * RPP;
+                const bool has = ig < nr;
+                s0[g] = has ? (int)(rp[ig] - e0) : 0;
+                s1[g] = has ? (int)(rp[ig + 1] - e0) : 0;
+                len = max(len, s1[g] - s0[g]);
+                acc[g] = V(0);
+            }
+            for (int o = 0; o < len; o += UB) {
+                V v[RG][UB];
+                T x[RG][UB];
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int u = 0; u < UB; ++u) {
+                        const int q = s0[g] + o + u;
+                        const bool in = q < s1[g];
+                        v[g][u] = C[(int64_t)cs[in ? q : 0] * ldv + cv];
+                        x[g][u] = in ? vs[in ? q : 0] : T(0);
+                    }
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int u = 0; u < UB; ++u) acc[g] = fma_v<V, T>(x[g][u], v[g][u], acc[g]);
+            }
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+                if (i + g * RPP < nr) finish(r_begin + i + g * RPP, acc[g]);
+        }
+    } else {
+        for (int i = slot; i < nr; i += RPP) {
+            V acc = V(0);
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+                acc = fma_v<V, T>(val[k], C[(int64_t)col[k] * ldv + cv], acc);
+            finish(r_begin + i, acc);
+        }
+    }
+    if (ndot > 0) {
+        // the RPP row slots meet in LDS; summed in slot order
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int w = 0; w < W; ++w) red[p][slot][l * W + w] = ds[p][w];
+        __syncthreads();
+        const int ld = ldv * W;
+        if (t < 2 * L * W) {
+            const int p = t / (L * W), e = t - p * (L * W);
+            if (p < ndot) {
+                double sum = 0.0;
+                for (int g = 0; g < RPP; ++g) sum += red[p][g][e];
+                partials[((int64_t)p * nrb + rb) * ld + chunk * L * W + e] = sum;
+            }
+        }
+    }
+}
+
 template <typename T, int NCV, int ORDER, int NDIM>
 __global__ __launch_bounds__(256) void spmm_stencil_wave_kernel(
     int64_t n, int64_t rows_per_block, StencilDev H, const T *__restrict__ Vpot,
@@ -412,6 +539,20 @@ int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
     if constexpr (sizeof(T) == 8) val = H.val64; else val = H.val32;
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
     auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
+    if (ldv % kChunkLanes == 0) {
+        const int nchunks = ldv / kChunkLanes;
+        int64_t rpb = kChunkRows;
+        while ((H.n + rpb - 1) / rpb > kGridCap) rpb += 16;
+        TM_REQUIRE(rpb <= 256, TM_ENOTSUP, "too many rows for the SpMM row blocks");
+        const int nrb = (int)((H.n + rpb - 1) / rpb);
+        int64_t grid = (int64_t)nchunks * nrb;
+        grid = (grid + 7) / 8 * 8;
+        hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, 2, 4>), dim3((unsigned)grid), dim3(256), 0, s,
+                           H.n, (int)rpb, nrb, nchunks, H.rowptr, H.col, val, Cv, Xv, ldv, ndot,
+                           partials);
+        TM_HIP(hipGetLastError());
+        return nrb;
+    }
     if (ldv % 64 == 0 && ldv <= 512) {
         Geometry w = wave_geometry(H.n);
 #define TM_CSR_WAVE(NCV)                                                                   \

@@ -115,15 +115,18 @@ def kernel_rooflines(tm, ctx, H, p, reps=20):
               key=lambda k: out[k]["avg_ms"])
     d = out[dom]
     roof = {"bound": d["bound"], "achieved": d.get("achieved"), "peak": d.get("peak"),
-            "unit": d.get("unit"), "frac": d.get("frac"), "traffic": measured_traffic(dom),
+            "unit": d.get("unit"), "frac": d.get("frac"),
+            "traffic": measured_traffic(dom) if p.name == TRAFFIC_CONFIG else None,
             "kernel": dom, "avg_ms": d["avg_ms"]}
     return roof, out
 
 
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
-# `bench.py --kernels-only` (scaled by a 1 GiB copy: x2.0 reads, x1.0 writes),
+# `bench.py --kernels-only` on the default workload (scaled by a 1 GiB copy:
+# x2.0 reads, x1.0 writes),
 # with the SHA-1 of the kernel source they were taken on; a changed source
 # invalidates the number.
+TRAFFIC_CONFIG = "c2"
 TRAFFIC = {
     "rot_grad_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
                          "d812bfbaac4e054706bc864dc18935383a4ed3a9", 2.0 * 442342.1 * 1024 + 117504.0 * 1024),
@@ -187,6 +190,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--precision", default="mixed", help="precision of the timed steps")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the BF16 / FULL_SP variant solves")
+    ap.add_argument("--max-iter", type=int, default=20000,
+                    help="iteration cap of each solve (a capped solve is reported as such)")
     ap.add_argument("--serving", type=int, default=40,
                     help="requests of the serving stream replayed after the solves (0: none)")
     ap.add_argument("--serving-only", action="store_true",
@@ -233,7 +240,8 @@ def main():
     def run(precision):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r, C, w, _ = tm.solve(ctx, H, p.m, tol, C0, tm.opts(precision=precision),
+        r, C, w, _ = tm.solve(ctx, H, p.m, tol, C0,
+                              tm.opts(precision=precision, max_iter=a.max_iter),
                               want_vectors=False)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, r
@@ -248,7 +256,7 @@ def main():
         t, res = run(a.precision)
         times.append(t)
         log(f"step {i} {a.precision} {t:.3f}s iters={res['iterations']} sp={res['iters_sp']} "
-            f"E_G={res['E_G']:.15f} maxres={res['max_residual']:.2e}")
+            f"E_G={res['E_G']:.15f} maxres={res['max_residual']:.2e} converged={res['converged']}")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_begin
     fp64_times, res64 = [], None
@@ -271,7 +279,7 @@ def main():
 
     # the two-term BF16 bulk variant, and its bulk phase alone (accuracy floor)
     variants = {}
-    for prec in ("mixed_bf16", "full_bf16", "full_sp"):
+    for prec in (() if a.no_variants else ("mixed_bf16", "full_bf16", "full_sp")):
         t, rv = run(prec)
         variants[prec] = {"seconds": round(t, 4), "iterations": rv["iterations"],
                           "iters_bulk": rv["iters_sp"], "E_G": rv["E_G"],
@@ -306,7 +314,7 @@ def main():
         "iterations": res["iterations"], "iters_fp32": res["iters_sp"],
         "iterations_fp64": res64["iterations"] if res64 else None,
         "E_G": res["E_G"], "rel_err_vs_oracle": rel_err, "max_residual": res["max_residual"],
-        "variants": variants,
+        "converged": res["converged"], "variants": variants,
         "roofline": roofline, "kernels": kernels, "serving": serving, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

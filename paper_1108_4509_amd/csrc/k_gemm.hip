@@ -450,17 +450,21 @@ void gram_shape(int64_t n, int m, bool symmetric, int &BM, int &T, int &nsplit) 
     BM = gram_tile(ld);
     T = (ld + BM - 1) / BM;
     // two workgroups per CU (512 over the 256 CUs, so that no CU runs more
-    // row chunks than another), at most 96 MiB of FP64 partials, and at least
-    // 128 rows per split; nsplit is a multiple of 8 (XCD mapping)
+    // row chunks than another), at most 256 MiB of FP64 partials, and at
+    // least 128 rows per split; the grid (tiles x splits) is a multiple of 8
+    // for the XCD mapping
     const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
     int64_t ns = 512 / ntiles;
-    const int64_t cap_bytes = (int64_t)96 << 20;
+    const int64_t cap_bytes = (int64_t)256 << 20;
     int64_t cap = cap_bytes / ((int64_t)m * m * 8);
     if (ns > cap) ns = cap;
     int64_t cap_rows = n / 128;
     if (ns > cap_rows) ns = cap_rows;
-    ns = ns / 8 * 8;
-    if (ns < 8) ns = 8;
+    while (ns > 1 && (ntiles * ns) % 8 != 0) --ns;
+    if (ns < 1 || (ntiles * ns) % 8 != 0) {
+        ns = 1;
+        while ((ntiles * ns) % 8 != 0) ++ns;
+    }
     nsplit = (int)ns;
 }
 

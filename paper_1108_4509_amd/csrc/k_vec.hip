@@ -111,17 +111,6 @@ __global__ void p_update_kernel(int64_t count, int ld, const TG *__restrict__ G,
     }
 }
 
-template <typename TC, typename TP>
-__global__ void c_update_kernel(int64_t count, const TC *__restrict__ C,
-                                const TP *__restrict__ P,
-                                const CgState *__restrict__ st,
-                                TC *__restrict__ Cn) {
-    const TC alpha = (TC)st->alpha;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-         e += (int64_t)gridDim.x * blockDim.x)
-        Cn[e] = C[e] + alpha * (TC)P[e];
-}
-
 template <typename TI, typename TO>
 __global__ void convert_kernel(int64_t count, const TI *__restrict__ in,
                                TO *__restrict__ out) {
@@ -301,15 +290,6 @@ void p_update(hipStream_t s, int64_t n, int ld, const TG *G, const double *M,
     TM_HIP(hipGetLastError());
 }
 
-template <typename TC, typename TP>
-void c_update(hipStream_t s, int64_t n, int ld, const TC *C, const TP *P,
-              const CgState *st, TC *Cn) {
-    const int64_t count = n * ld;
-    hipLaunchKernelGGL((c_update_kernel<TC, TP>), dim3(elem_grid(count)), dim3(256),
-                       0, s, count, C, P, st, Cn);
-    TM_HIP(hipGetLastError());
-}
-
 template <typename TI, typename TO>
 void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out) {
     hipLaunchKernelGGL((convert_kernel<TI, TO>), dim3(elem_grid(count)), dim3(256),
@@ -340,9 +320,6 @@ template void coldots<double>(hipStream_t, int64_t, int, const DotArgs<double> &
 template void coldots<float>(hipStream_t, int64_t, int, const DotArgs<float> &, double *, double *);
 template void p_update<double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *);
 template void p_update<float, float>(hipStream_t, int64_t, int, const float *, const double *, const CgState *, float *);
-template void c_update<double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *);
-template void c_update<float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *);
-template void c_update<double, float>(hipStream_t, int64_t, int, const double *, const float *, const CgState *, double *);
 template void convert_block<double, float>(hipStream_t, int64_t, const double *, float *);
 template void convert_block<float, double>(hipStream_t, int64_t, const float *, double *);
 

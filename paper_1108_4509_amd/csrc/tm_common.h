@@ -177,10 +177,6 @@ void assemble_subspace_matrix(hipStream_t s, int m, const double *Hp,
 template <typename TG, typename TP>
 void p_update(hipStream_t s, int64_t n, int ld, const TG *G, const double *M,
               const CgState *st, TP *P);
-// Cn = C + alpha P    (alpha read from st->alpha)
-template <typename TC, typename TP>
-void c_update(hipStream_t s, int64_t n, int ld, const TC *C, const TP *P,
-              const CgState *st, TC *Cn);
 template <typename TI, typename TO>
 void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out);
 

@@ -263,7 +263,9 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
 
 // Sum over the row-chunk partials in a fixed order: 64 elements per
 // workgroup, four lane groups take every fourth chunk, then the four group
-// sums are added in order.
+// sums are added in order.  A symmetric product has partials only in the
+// upper tiles: the elements of a strictly upper tile are read there (rows
+// contiguous) and written to both (i, j) and (j, i); lower tiles read nothing.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
                                                           bool zero_diag,
                                                           const double *__restrict__ partials,
@@ -275,20 +277,23 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int
     const int64_t mm = (int64_t)m * m;
     double s = 0.0;
     int i = 0, j = 0;
-    if (idx < mm) {
+    bool active = idx < mm;
+    if (active) {
         i = (int)(idx / m);
         j = (int)(idx - (int64_t)i * m);
-        int64_t src = idx;
-        if (symmetric && (i / BM) > (j / BM)) src = (int64_t)j * m + i;
+        if (symmetric && (i / BM) > (j / BM)) active = false;
+    }
+    if (active) {
 #pragma unroll 8
-        for (int p = g; p < nsplit; p += G) s += partials[(int64_t)p * mm + src];
+        for (int p = g; p < nsplit; p += G) s += partials[(int64_t)p * mm + idx];
     }
     red[g][e] = s;
     __syncthreads();
-    if (g == 0 && idx < mm) {
+    if (g == 0 && active) {
         double v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
         if (zero_diag && i == j) v = 0.0;
         out[idx] = v;
+        if (symmetric && (i / BM) < (j / BM)) out[(int64_t)j * m + i] = v;
     }
 }
 
@@ -836,7 +841,13 @@ int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
         const double *M, double *partials) {
     const int ld = leading_dim(m);
     const int B = ld >= 256 ? 128 : 64;
-    const int nrb = (int)((n + B - 1) / B);
+    // row tile: 64 rows give about twice the workgroups (7 rounds of 512 at
+    // N = 110592 instead of 3.4, so less idle tail) and measured faster for
+    // every variant but the refinement gradient (FP64 C and X, FP32 G),
+    // whose larger epilogue keeps the 128-row tile
+    const bool mp2_grad = epi == EPI_GRAD && sizeof(TA) == 8 && sizeof(TO) == 4;
+    const int BR = (B == 128 && !mp2_grad) ? 64 : B;
+    const int nrb = (int)((n + BR - 1) / BR);
     const int ncb = (ld + B - 1) / B;
     int grid = nrb * ncb;
     grid = (grid + 7) / 8 * 8;
@@ -845,17 +856,21 @@ int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
     gd.Pp = Pp;
     gd.M = M;
     gd.partials = (epi == EPI_GRAD) ? partials : nullptr;
-#define TM_ROT(E, BB)                                                                      \
-    hipLaunchKernelGGL((rot_kernel<TA, TM, TO, E, BB, BB>), dim3(grid), dim3(kThreads), \
+#define TM_ROT(E, BRV, BCV)                                                                  \
+    hipLaunchKernelGGL((rot_kernel<TA, TM, TO, E, BRV, BCV>), dim3(grid), dim3(kThreads),   \
                        0, s, n, m, ld, A, Wpad, X, vec, out, nrb, ncb, gd)
-    if (B == 128) {
-        if (epi == EPI_NONE) TM_ROT(EPI_NONE, 128);
-        else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 128);
-        else TM_ROT(EPI_TRMM, 128);
+    if (B == 128 && BR == 128) {
+        if (epi == EPI_NONE) TM_ROT(EPI_NONE, 128, 128);
+        else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 128, 128);
+        else TM_ROT(EPI_TRMM, 128, 128);
+    } else if (B == 128) {
+        if (epi == EPI_NONE) TM_ROT(EPI_NONE, 64, 128);
+        else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 64, 128);
+        else TM_ROT(EPI_TRMM, 64, 128);
     } else {
-        if (epi == EPI_NONE) TM_ROT(EPI_NONE, 64);
-        else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 64);
-        else TM_ROT(EPI_TRMM, 64);
+        if (epi == EPI_NONE) TM_ROT(EPI_NONE, 64, 64);
+        else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 64, 64);
+        else TM_ROT(EPI_TRMM, 64, 64);
     }
 #undef TM_ROT
     TM_HIP(hipGetLastError());
@@ -863,9 +878,9 @@ int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
 }
 
 size_t rot_partials_workspace(int64_t n, int m) {
+    // the smallest row tile rot() launches
     const int ld = leading_dim(m);
-    const int B = ld >= 256 ? 128 : 64;
-    return (size_t)4 * ((n + B - 1) / B) * ld * sizeof(double);
+    return (size_t)4 * ((n + 63) / 64) * ld * sizeof(double);
 }
 
 template <typename TM>

@@ -87,6 +87,65 @@ def test_spmm_f32(ctx, tm, orc, stencil):
     assert np.all(np.abs(host(Xd, prob.m) - X) <= tol)
 
 
+def _irregular_csr(rng, n, long_every, empty_every):
+    """A general sparse matrix: mostly 1-9 entries per row, every long_every-th
+    row 100-199 entries, every empty_every-th row and the last three rows
+    empty (rows of one workgroup then exceed the staged-metadata capacity when
+    long rows are frequent, and empty rows sit at block ends)."""
+    rowptr = [0]
+    cols, vals = [], []
+    for r in range(n):
+        if r % empty_every == 5 or r >= n - 3:
+            k = 0
+        elif r % long_every == 3:
+            k = int(rng.integers(100, 200))
+        else:
+            k = int(rng.integers(1, 10))
+        c = np.sort(rng.choice(n, size=k, replace=False))
+        cols.append(c)
+        vals.append(rng.standard_normal(k))
+        rowptr.append(rowptr[-1] + k)
+    return (np.array(rowptr, dtype=np.int64), np.concatenate(cols).astype(np.int32),
+            np.concatenate(vals))
+
+
+@pytest.mark.parametrize("long_every", [23, 5], ids=["staged", "unstaged"])
+@pytest.mark.parametrize("m", [64, 96, 256])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_spmm_irregular_csr(ctx, tm, orc, long_every, m, dt):
+    """General CSR rows (empty, short and long) through every SpMM path:
+    column chunks with LDS-staged row data, chunks reading the row data from
+    memory when a workgroup's rows hold too many entries, and the whole-row
+    kernels for widths that are not a multiple of a chunk."""
+    import torch
+    n = 3001
+    print_case(test="spmm_irregular", long_every=long_every, m=m, dt=dt)
+    rng = np.random.default_rng(long_every * 1000 + m)
+    rowptr, col, val = _irregular_csr(rng, n, long_every, 17)
+    Hd = tm.set_matrix_csr(ctx, rowptr, col, val)
+    H = orc.csr_matrix(rowptr, col, val, n)
+    C = rand_block(np.random.default_rng(3), n, m)
+    tdt, u = (torch.float64, U64) if dt == "f64" else (torch.float32, U32)
+    if dt == "f32":
+        C = C.astype(np.float32).astype(np.float64)
+    Cd = tm.to_block(C, dtype=tdt)
+    Xd = torch.full_like(Cd, np.nan)
+    tm.spmm(ctx, Hd, m, Cd, Xd)
+    X = orc.spmm(H, C)
+    nnz_row = int(np.max(np.diff(rowptr)))
+    absH = abs(H)
+    if dt == "f32":
+        # the FP32 kernel multiplies by FP32-rounded matrix values
+        absHC = absH @ np.abs(C)
+        tol = 2 * gamma(nnz_row + 2, u) * absHC
+    else:
+        tol = 2 * gamma(nnz_row + 1, u) * (absH @ np.abs(C))
+    got = host(Xd)
+    assert np.all(np.abs(got[:, :m] - X) <= tol + 1e-300)
+    assert np.all(got[n - 3:, :m] == 0)          # empty rows give zero rows
+    assert np.all(got[:, m:] == 0)               # padded columns stay zero
+
+
 @pytest.mark.parametrize("n,m", [(5000, 27), (3001, 76), (4099, 130), (2050, 256), (1500, 512),
                                  (700, 1)])
 @pytest.mark.parametrize("shift", [False, True], ids=["plain", "shift"])
@@ -260,6 +319,28 @@ def test_cholesky_not_spd(ctx, tm):
     with pytest.raises(tm.TraceminError) as ei:
         tm.cholesky_inverse(ctx, torch.from_numpy(S).cuda())
     assert ei.value.status == tm.TM_ENOTSPD
+
+
+@pytest.mark.parametrize("m,bad", [(200, 150), (150, 120), (64, 63)])
+def test_cholesky_breakdown_later_block(ctx, tm, m, bad):
+    """A breakdown past the first 64-wide block (or at the last pivot of one)
+    is reported after the earlier blocks have been factored: S = B^T B with
+    column `bad` of B equal to column 30 is singular at pivot `bad`."""
+    import torch
+    print_case(test="cholesky_breakdown", m=m, bad=bad)
+    rng = np.random.default_rng(m)
+    B = rng.standard_normal((3 * m, m))
+    B[:, bad] = B[:, 30]
+    S = B.T @ B
+    with pytest.raises(tm.TraceminError) as ei:
+        tm.cholesky_inverse(ctx, torch.from_numpy(S).cuda())
+    assert ei.value.status == tm.TM_ENOTSPD
+    # the reported pivot is the first one that broke down (1-based)
+    assert f"(pivot {bad + 1})" in str(ei.value), str(ei.value)
+    # the same matrix without the dependence factors
+    B[:, bad] = rng.standard_normal(3 * m)
+    R_inv = host(tm.cholesky_inverse(ctx, torch.from_numpy(B.T @ B).cuda()))
+    assert np.all(np.isfinite(R_inv))
 
 
 @pytest.mark.parametrize("m", [1, 2, 3, 27, 64, 101, 256, 600])

@@ -71,6 +71,7 @@ struct GradDots {
     const TO *Pp = nullptr;
     const double *M = nullptr;
     double *partials = nullptr;
+    const void *Xs = nullptr;   // EPI_GRADX: X' in the matrix-core precision
 };
 
 // rows of A and B per LDS stage: the FP32 instruction is twice as fast, so
@@ -111,7 +112,8 @@ template <typename TA, typename TM, int BM, bool SHIFT, bool UPD = false, typena
 __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TA *__restrict__ B,
     const double *__restrict__ h, int T, int ntiles, bool symmetric,
-    int64_t rows_per_split, double *__restrict__ partials, GramUpd<TA, TP> up) {
+    int64_t rows_per_split, double *__restrict__ partials, GramUpd<TA, TP> up,
+    TM *__restrict__ xout) {
     constexpr int KT = stage_rows<TM>();
     constexpr int WM = BM / 2;
     constexpr int NB = WM / 16;
@@ -159,13 +161,17 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
     // columns past ld column 0, both zeroed at the store) so that no select
     // on a loaded value forces the prefetch to complete early
     typedef TP PV __attribute__((ext_vector_type(VW)));
+    typedef TM XV __attribute__((ext_vector_type(VW)));   // VW elements of X'
     V ra[PASSES], rb[PASSES], rx[SHIFT ? PASSES : 1];
     PV pa[UPD ? PASSES : 1], pb[UPD ? PASSES : 1];
-    int64_t krow[UPD ? PASSES : 1];
+    int64_t krow[(UPD || SHIFT) ? PASSES : 1];
     bool rv[PASSES];
     const int ci_c = ci_ok ? ci : 0, cj_c = cj_ok ? cj : 0;
     TA alpha = TA(0);
     if constexpr (UPD) alpha = (TA)up.st->alpha;
+    // the workgroups of tile row 0 store X' = X - C diag(h) for their columns
+    // (each element once), in the matrix-core precision
+    const bool xstore = SHIFT && xout != nullptr && ti == 0;
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int q = 0; q < PASSES; ++q) {
@@ -173,8 +179,8 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
             rv[q] = k < k_end;
             const int64_t kk = rv[q] ? k : k_begin;
             ra[q] = *reinterpret_cast<const V *>(A + kk * ld + ci_c);
+            if constexpr (UPD || SHIFT) krow[q] = kk;
             if constexpr (UPD) {
-                krow[q] = kk;
                 pa[q] = *reinterpret_cast<const PV *>(up.P + kk * ld + ci_c);
                 if (!same) {
                     rb[q] = *reinterpret_cast<const V *>(B + kk * ld + cj_c);
@@ -205,6 +211,7 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
         for (int q = 0; q < PASSES; ++q) {
             const int row = rbase + q * RPP;
             const bool va = rv[q] && ci_ok, vb = rv[q] && cj_ok;
+            XV xv;
 #pragma unroll
             for (int w = 0; w < VW; ++w) {
                 As[buf][row][cv * VW + w] = va ? (TM)velem<TA>(ra[q], w) : TM(0);
@@ -214,10 +221,13 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
                     if constexpr (sizeof(TA) == 4) x = fmaf(-xa, (float)hv[w], velem<TA>(rb[q], w));
                     else x = (TM)((double)velem<TA>(rb[q], w) - (double)xa * hv[w]);
                     Bs[buf][row][cv * VW + w] = vb ? x : TM(0);
+                    xv[w] = x;
                 } else {
                     Bs[buf][row][cv * VW + w] = vb ? (TM)velem<TA>(rb[q], w) : TM(0);
                 }
             }
+            if constexpr (SHIFT)
+                if (xstore && vb) *reinterpret_cast<XV *>(xout + krow[q] * ld + cj) = xv;
         }
     };
 
@@ -625,15 +635,17 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     const int ecv = tid % CVN, erow = tid / CVN;
     const int ecol = c0 + 4 * ecv;
     const bool col_ok = ecol < ld;             // ld is a multiple of 32
-    const bool fuse = (EPI == EPI_GRAD) && gd.partials != nullptr;
+    constexpr bool GRADLIKE = EPI == EPI_GRAD || EPI == EPI_GRADX;
+    const bool fuse = GRADLIKE && gd.partials != nullptr;
+    const TM *Xs = reinterpret_cast<const TM *>(gd.Xs);
     double vv[4] = {0.0, 0.0, 0.0, 0.0};
-    if (EPI != EPI_NONE && col_ok) {
+    if ((EPI == EPI_GRAD || EPI == EPI_TRMM) && col_ok) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) vv[w] = vec[ecol + w];
     }
-    double dsum[EPI == EPI_GRAD ? 4 : 1][4];
+    double dsum[GRADLIKE ? 4 : 1][4];
 #pragma unroll
-    for (int p = 0; p < (EPI == EPI_GRAD ? 4 : 1); ++p)
+    for (int p = 0; p < (GRADLIKE ? 4 : 1); ++p)
 #pragma unroll
         for (int w = 0; w < 4; ++w) dsum[p][w] = 0.0;
 
@@ -652,10 +664,11 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
         __syncthreads();
         // EG rows per lane at a time: all their loads are issued before any
         // result is formed, so the round trips overlap
-        constexpr int EG = (sizeof(TM) == 8 && EPI == EPI_GRAD) ? 1 : 4;   // FP64 tiles: no room
+        constexpr int EG = (sizeof(TM) == 8 && GRADLIKE) ? 1 : 4;   // FP64 tiles: no room
         static_assert(EH % (RPT * EG) == 0, "epilogue row groups");
         for (int rl0 = erow; rl0 < EH; rl0 += RPT * EG) {
             TA xv[EG][4], av[EG][4];
+            TM xs[EG][4];
             TO gp[EG][4], pp[EG][4];
             double wgt[EG];
             bool ok[EG];
@@ -666,8 +679,9 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
                 ok[g] = row < n && col_ok;
                 const int64_t e = (ok[g] ? row : r0) * ld + (col_ok ? ecol : c0);
                 if constexpr (EPI == EPI_GRAD) load4<TA>(X + e, xv[g]);
-                if constexpr (EPI != EPI_NONE) load4<TA>(A + e, av[g]);
-                if (EPI == EPI_GRAD && fuse) {
+                if constexpr (EPI == EPI_GRADX) load4<TM>(Xs + e, xs[g]);
+                if constexpr (EPI == EPI_GRAD || EPI == EPI_TRMM) load4<TA>(A + e, av[g]);
+                if (GRADLIKE && fuse) {
                     load4<TO>(gd.Gp + e, gp[g]);
                     load4<TO>(gd.Pp + e, pp[g]);
                     wgt[g] = gd.M ? gd.M[ok[g] ? row : r0] : 1.0;
@@ -685,10 +699,14 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
                 if constexpr (EPI == EPI_NONE) {
 #pragma unroll
                     for (int w = 0; w < 4; ++w) o[w] = (TO)v[w];
-                } else if constexpr (EPI == EPI_GRAD) {
+                } else if constexpr (GRADLIKE) {
 #pragma unroll
-                    for (int w = 0; w < 4; ++w)
-                        o[w] = (TO)((TA)-2 * ((xv[g][w] - av[g][w] * (TA)vv[w]) - v[w]));
+                    for (int w = 0; w < 4; ++w) {
+                        if constexpr (EPI == EPI_GRAD)
+                            o[w] = (TO)((TA)-2 * ((xv[g][w] - av[g][w] * (TA)vv[w]) - v[w]));
+                        else
+                            o[w] = (TO)((TA)-2 * ((TA)xs[g][w] - v[w]));
+                    }
                     if (fuse) {
 #pragma unroll
                         for (int w = 0; w < 4; ++w) {
@@ -708,7 +726,7 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
         }
     }
 
-    if constexpr (EPI == EPI_GRAD) {
+    if constexpr (GRADLIKE) {
         if (fuse) {
             // the RPT lanes of a column vector meet in LDS; fixed order
             __syncthreads();
@@ -755,7 +773,7 @@ size_t gram_workspace(int64_t n, int m) {
 template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
-          double *out, bool reduce) {
+          double *out, bool reduce, TM *xshift) {
     const int ld = leading_dim(m);
     if (h) symmetric = false;
     int BM, T, nsplit;
@@ -766,7 +784,8 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     const int grid = ntiles * nsplit;   // multiple of 8
 #define TM_GRAM(BMV, SH)                                                            \
     hipLaunchKernelGGL((gram_kernel<TA, TM, BMV, SH>), dim3(grid), dim3(kThreads), 0, s, \
-                       n, m, ld, A, B, h, T, ntiles, symmetric, rows, partials, GramUpd<TA, TA>{})
+                       n, m, ld, A, B, h, T, ntiles, symmetric, rows, partials, GramUpd<TA, TA>{}, \
+                       xshift)
     if (BM == 128) {
         if (h) TM_GRAM(128, true); else TM_GRAM(128, false);
     } else {
@@ -797,10 +816,10 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
     up.Cn = Cn;
     if (BM == 128)
         hipLaunchKernelGGL((gram_kernel<TA, TM, 128, false, true, TP>), dim3(grid), dim3(kThreads), 0, s,
-                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up);
+                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up, nullptr);
     else
         hipLaunchKernelGGL((gram_kernel<TA, TM, 64, false, true, TP>), dim3(grid), dim3(kThreads), 0, s,
-                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up);
+                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up, nullptr);
     TM_HIP(hipGetLastError());
     const int64_t total = (int64_t)m * m;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
@@ -838,7 +857,8 @@ void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, cons
 template <typename TA, typename TM, typename TO>
 int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
         const TA *X, const double *vec, TO *out, const TO *Gp, const TO *Pp,
-        const double *M, double *partials) {
+        const double *M, double *partials, const TM *Xs) {
+    TM_REQUIRE(epi != EPI_GRADX || Xs != nullptr, TM_EINVAL, "EPI_GRADX needs X'");
     const int ld = leading_dim(m);
     const int B = ld >= 256 ? 128 : 64;
     // row tile: 64 rows give about twice the workgroups (7 rounds of 512 at
@@ -855,21 +875,25 @@ int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
     gd.Gp = Gp;
     gd.Pp = Pp;
     gd.M = M;
-    gd.partials = (epi == EPI_GRAD) ? partials : nullptr;
+    gd.partials = (epi == EPI_GRAD || epi == EPI_GRADX) ? partials : nullptr;
+    gd.Xs = Xs;
 #define TM_ROT(E, BRV, BCV)                                                                  \
     hipLaunchKernelGGL((rot_kernel<TA, TM, TO, E, BRV, BCV>), dim3(grid), dim3(kThreads),   \
                        0, s, n, m, ld, A, Wpad, X, vec, out, nrb, ncb, gd)
     if (B == 128 && BR == 128) {
         if (epi == EPI_NONE) TM_ROT(EPI_NONE, 128, 128);
         else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 128, 128);
+        else if (epi == EPI_GRADX) TM_ROT(EPI_GRADX, 128, 128);
         else TM_ROT(EPI_TRMM, 128, 128);
     } else if (B == 128) {
         if (epi == EPI_NONE) TM_ROT(EPI_NONE, 64, 128);
         else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 64, 128);
+        else if (epi == EPI_GRADX) TM_ROT(EPI_GRADX, 64, 128);
         else TM_ROT(EPI_TRMM, 64, 128);
     } else {
         if (epi == EPI_NONE) TM_ROT(EPI_NONE, 64, 64);
         else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 64, 64);
+        else if (epi == EPI_GRADX) TM_ROT(EPI_GRADX, 64, 64);
         else TM_ROT(EPI_TRMM, 64, 64);
     }
 #undef TM_ROT
@@ -893,18 +917,18 @@ void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
     TM_HIP(hipGetLastError());
 }
 
-template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool);
-template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool);
-template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool);
+template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, double *);
+template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool, float *);
+template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, float *);
 template void gram_update<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *, double *, double *);
 template void gram_update<double, double, float>(hipStream_t, int64_t, int, const double *, const float *, const CgState *, double *, double *, double *);
 template void gram_update<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *, double *, double *);
 template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool);
 template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool);
-template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *);
-template int rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *, const float *, const float *, const double *, double *);
-template int rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *, const float *, const float *, const double *, double *);
-template int rot<double, float, double>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, double *, const double *, const double *, const double *, double *);
+template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const double *);
+template int rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *, const float *, const float *, const double *, double *, const float *);
+template int rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *, const float *, const float *, const double *, double *, const float *);
+template int rot<double, float, double>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const float *);
 template void pad_matrix<double>(hipStream_t, int, const double *, bool, double *, double *);
 template void pad_matrix<float>(hipStream_t, int, const double *, bool, float *, double *);
 

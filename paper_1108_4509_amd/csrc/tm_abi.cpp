@@ -379,18 +379,28 @@ tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t precis
         const int ld = leading_dim(m);
         const int64_t n = H->n;
         hipStream_t s = ctx->stream;
+        const bool dp = precision == TM_FULL_DP;
         DevMem hv(ctx, ld * sizeof(double)), dws(ctx, spmm_partials_workspace(ld)),
-            gws(ctx, gram_workspace(n, m)), wp(ctx, (size_t)ld * ld * sizeof(double));
+            gws(ctx, gram_workspace(n, m)), wp(ctx, (size_t)ld * ld * sizeof(double)),
+            xs(ctx, (size_t)n * ld * (dp ? sizeof(double) : sizeof(float)));
         const int nch = spmm_any(s, H, ld, C, X, true, 1, (double *)dws.ptr);
         reduce_partials(s, 1, nch, ld, (double *)dws.ptr, (double *)hv.ptr);
-        if (precision == TM_FULL_DP) {
-            gram<double, double>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp);
+        // X' = X - C diag(h) is kept by the Gram in the matrix-core precision
+        // and read back by the gradient, as in the solver
+        if (dp) {
+            double *Xs = (double *)xs.ptr;
+            gram<double, double>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp,
+                                 true, Xs);
             pad_matrix<double>(s, m, Hp, false, (double *)wp.ptr, nullptr);
-            rot<double, double, double>(s, n, m, C, (double *)wp.ptr, EPI_GRAD, X, (double *)hv.ptr, G);
+            rot<double, double, double>(s, n, m, C, (double *)wp.ptr, EPI_GRADX, X, (double *)hv.ptr, G,
+                                        nullptr, nullptr, nullptr, nullptr, Xs);
         } else {
-            gram<double, float>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp);
+            float *Xs = (float *)xs.ptr;
+            gram<double, float>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp,
+                                true, Xs);
             pad_matrix<float>(s, m, Hp, false, (float *)wp.ptr, nullptr);
-            rot<double, float, double>(s, n, m, C, (float *)wp.ptr, EPI_GRAD, X, (double *)hv.ptr, G);
+            rot<double, float, double>(s, n, m, C, (float *)wp.ptr, EPI_GRADX, X, (double *)hv.ptr, G,
+                                       nullptr, nullptr, nullptr, nullptr, Xs);
         }
         sum_vector(s, m, (double *)hv.ptr, E);
         TM_HIP(hipMemcpyAsync(h, hv.ptr, m * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -499,29 +509,32 @@ tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m
             switch (kernel) {
             case TM_K_SPMM: spmm_any(s, H, ld, A.ptr, O.ptr, f64); break;
             case TM_K_GRAM_SHIFT:
-                if (f64) gram<double, double>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false);
-                else gram<float, float>(s, n, m, (float *)A.ptr, (float *)B.ptr, v, true, false, ws_p, mm_p, false);
+                // as in the solver: X' kept for the gradient
+                if (f64) gram<double, double>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false, (double *)O.ptr);
+                else gram<float, float>(s, n, m, (float *)A.ptr, (float *)B.ptr, v, true, false, ws_p, mm_p, false, (float *)O.ptr);
                 break;
             case TM_K_GRAM_SYM:
                 if (f64) gram<double, double>(s, n, m, (double *)A.ptr, (double *)A.ptr, nullptr, false, true, ws_p, mm_p, false);
                 else gram<float, float>(s, n, m, (float *)A.ptr, (float *)A.ptr, nullptr, false, true, ws_p, mm_p, false);
                 break;
             case TM_K_ROT_GRAD:
-                if (f64) rot<double, double, double>(s, n, m, (double *)A.ptr, (double *)wp.ptr, EPI_GRAD, (double *)B.ptr, v, (double *)O.ptr);
-                else rot<float, float, float>(s, n, m, (float *)A.ptr, (float *)wp.ptr, EPI_GRAD, (float *)B.ptr, v, (float *)O.ptr);
+                // as in the solver: G from X' (B here) and C H'
+                if (f64) rot<double, double, double>(s, n, m, (double *)A.ptr, (double *)wp.ptr, EPI_GRADX, nullptr, v, (double *)O.ptr, nullptr, nullptr, nullptr, nullptr, (double *)B.ptr);
+                else rot<float, float, float>(s, n, m, (float *)A.ptr, (float *)wp.ptr, EPI_GRADX, nullptr, v, (float *)O.ptr, nullptr, nullptr, nullptr, nullptr, (float *)B.ptr);
                 break;
             case TM_K_TRMM:
                 if (f64) rot<double, double, double>(s, n, m, (double *)A.ptr, (double *)wp.ptr, EPI_TRMM, nullptr, v, (double *)O.ptr);
                 else rot<float, float, float>(s, n, m, (float *)A.ptr, (float *)wp.ptr, EPI_TRMM, nullptr, v, (float *)O.ptr);
                 break;
             case TM_K_GRAM_MP2:
-                gram<double, float>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false);
+                gram<double, float>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false, (float *)g32.ptr);
                 break;
             case TM_K_ROT_GRAD_MP2: {
-                // the refinement-phase gradient: FP64 C and X, FP32 H' and FP32 G, fused traces
+                // the refinement-phase gradient: FP64 C, FP32 X' (from the Gram), FP32 H'
+                // and FP32 G, fused traces
                 float *G = (float *)g32.ptr, *Gprev = (float *)O.ptr, *Pprev = Gprev + n * ld;
-                rot<double, float, float>(s, n, m, (double *)A.ptr, (float *)wp.ptr, EPI_GRAD, (double *)B.ptr, v,
-                                          G, Gprev, Pprev, nullptr, (double *)dp.ptr);
+                rot<double, float, float>(s, n, m, (double *)A.ptr, (float *)wp.ptr, EPI_GRADX, nullptr, v,
+                                          G, Gprev, Pprev, nullptr, (double *)dp.ptr, (float *)B.ptr);
                 break;
             }
             case TM_K_TRMM_MP2:

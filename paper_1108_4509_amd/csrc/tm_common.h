@@ -119,10 +119,12 @@ void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
 // Gram products out = A^T B' (m x m, FP64), B' = B - A diag(h) if h --------
 size_t gram_workspace(int64_t n, int m);
 // reduce = false launches only the split-K product (used to time it alone).
+// xshift (with h): B' itself, n x ld in the matrix-core precision TM, is also
+// stored there (the EPI_GRADX input of rot()).
 template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
-          double *out, bool reduce = true);
+          double *out, bool reduce = true, TM *xshift = nullptr);
 
 // S = Cn^T Cn with Cn = C + alpha P formed while staged (alpha from st) and
 // written to Cn: the update of Fig. 1 fused into Fig. 4 step (1).
@@ -138,9 +140,11 @@ void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, cons
                  bool zero_diag, double *partials, double *out, bool reduce = true);
 
 // Tall-skinny products out = A W (+ epilogue) ------------------------------
-enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2 };
+enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2, EPI_GRADX = 3 };
 // EPI_NONE:  out = A W
 // EPI_GRAD:  out = -2 ((X - A diag(h)) - A W)          (Fig. 2, step (7))
+// EPI_GRADX: out = -2 (X' - A W), X' = X - A diag(h) given in the matrix-core
+//            precision (stored by the Gram that formed it, see gram())
 // EPI_TRMM:  out = A diag(d) + A W, W strictly upper   (Eq. 13)
 // With EPI_GRAD and partials != nullptr the epilogue also accumulates, per
 // output column j, the traces of the Polak-Ribiere step (Eq. 8) and the descent
@@ -151,7 +155,8 @@ size_t rot_partials_workspace(int64_t n, int m);
 template <typename TA, typename TM, typename TO>
 int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad,
         int epi, const TA *X, const double *vec, TO *out, const TO *Gp = nullptr,
-        const TO *Pp = nullptr, const double *M = nullptr, double *partials = nullptr);
+        const TO *Pp = nullptr, const double *M = nullptr, double *partials = nullptr,
+        const TM *Xs = nullptr);
 // Copy an m x m FP64 matrix into an ld x ld zero-padded matrix of type TM,
 // keeping the strict upper triangle only (strict_upper) and returning the
 // diagonal in diag (when not null).

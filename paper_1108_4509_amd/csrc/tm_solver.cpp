@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 namespace tmin {
@@ -258,18 +259,25 @@ struct Solver::Impl {
             const int nch = spmm_any(s, H, ld, C, X, is_f64<TC>(), 1, (double *)dot_ws->ptr);
             reduce_partials(s, 1, nch, ld, (double *)dot_ws->ptr, (double *)h->ptr);
         }
-        // (5)-(6): H' = C^T (X - C H_D), diag(H') = 0
-        if (!is_f64<TC>() && bf16_bulk)
+        // (5)-(6): H' = C^T (X - C H_D), diag(H') = 0; X' = X - C H_D is formed
+        // in C's precision while staged and kept, rounded once to the matrix-core
+        // precision, in Y (free until the line step) for step (7)
+        static_assert(std::is_same<TG, TMH>::value, "X' is held in a direction block");
+        TMH *Xs = nullptr;
+        if (!is_f64<TC>() && bf16_bulk) {
             gram_bf16x3<TC>(s, n, m, C, X, (double *)h->ptr, true, (double *)gram_ws->ptr, (double *)Hp->ptr);
-        else
-            gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, false, (double *)gram_ws->ptr, (double *)Hp->ptr);
+        } else {
+            Xs = reinterpret_cast<TMH *>(Yv);
+            gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, false, (double *)gram_ws->ptr,
+                          (double *)Hp->ptr, true, Xs);
+        }
         // (7): G = -2 (X' - C H')
         pad_matrix<TMH>(s, m, (double *)Hp->ptr, false, (TMH *)Wp->ptr, nullptr);
         // with the traces for Eq. 8 and the descent test fused into the epilogue
         {
-            const int nch = rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, EPI_GRAD, X,
+            const int nch = rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, Xs ? EPI_GRADX : EPI_GRAD, X,
                                              (double *)h->ptr, Gv, Gpv, Pv, Mv,
-                                             (double *)dot_ws->ptr);
+                                             (double *)dot_ws->ptr, Xs);
             reduce_partials(s, 4, nch, ld, (double *)dot_ws->ptr, (double *)dots->ptr);
         }
         cg_control_gamma(s, m, ld, (double *)h->ptr, (double *)dots->ptr, st, hist_dev);

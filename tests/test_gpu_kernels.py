@@ -251,8 +251,10 @@ def test_energy_grad_alg2_full_dp(ctx, tm, orc, name, prob):
 
 
 def test_energy_grad_mp2(ctx, tm, orc):
-    """MP2 (Sec. 2.2): steps (6)-(7) on FP32 matrix cores.  The error of G is
-    bounded by FP32 rounding of H' and of C H' (u32 relative), not of X'."""
+    """MP2 (Sec. 2.2): steps (6)-(7) on FP32 matrix cores.  X' = X - C H_D is
+    formed in FP64 (the cancellation happens there) and rounded once to FP32
+    for step (7), so the error of G is bounded by FP32 rounding of H', of
+    C H' and of X' (u32 relative to each), not of X or C H_D."""
     prob = _problems()[1][1]
     print_case(test="energy_grad_mp2")
     H = orc.csr_matrix(*prob.csr(), prob.N)
@@ -265,8 +267,9 @@ def test_energy_grad_mp2(ctx, tm, orc):
     assert abs(E - E_o) <= 4 * gamma(n + 16, U64) * np.sum(np.abs(C) * absX)  # DP energy
     absXp = absX + np.abs(C) * np.abs(h_o)[None, :]
     assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * gamma(n + 4, U32) * (np.abs(C).T @ absXp))
+    Xp_o = X_o - C * h_o[None, :]
     bound = 8 * gamma(n + m + 4, U32) * (np.abs(C) @ (np.abs(C).T @ absXp)) \
-        + 8 * gamma(n + 16, U64) * absXp
+        + 4 * U32 * np.abs(Xp_o) + 8 * gamma(n + 16, U64) * absXp
     assert np.all(np.abs(host(G, m) - G_o) <= bound)
 
 

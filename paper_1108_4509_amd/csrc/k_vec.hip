@@ -101,13 +101,36 @@ __global__ void p_update_kernel(int64_t count, int ld, const TG *__restrict__ G,
                                 const double *__restrict__ M,
                                 const CgState *__restrict__ st,
                                 TP *__restrict__ P) {
+    // 16-byte vectors of the block (count and ld are multiples of 32), the
+    // same arithmetic per element as a scalar loop
+    static_assert(sizeof(TG) == sizeof(TP), "G and P share a precision");
+    constexpr int W = 16 / sizeof(TP);
+    typedef TG VG __attribute__((ext_vector_type(W)));
+    typedef TP VP __attribute__((ext_vector_type(W)));
     const double gamma = st->gamma;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        double z = (double)G[e];
-        if (M) z *= M[e / ld];
-        const double p = (gamma != 0.0) ? z + gamma * (double)P[e] : z;
-        P[e] = (TP)p;
+    const int64_t nv = count / W;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const VG g = reinterpret_cast<const VG *>(G)[v];
+        const double mw = M ? M[(v * W) / ld] : 1.0;   // one row per vector
+        VP out;
+        if (gamma != 0.0) {
+            const VP pv = reinterpret_cast<const VP *>(P)[v];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                double z = (double)g[w];
+                if (M) z *= mw;
+                out[w] = (TP)(z + gamma * (double)pv[w]);
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                double z = (double)g[w];
+                if (M) z *= mw;
+                out[w] = (TP)z;
+            }
+        }
+        reinterpret_cast<VP *>(P)[v] = out;
     }
 }
 

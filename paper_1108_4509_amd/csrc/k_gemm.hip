@@ -276,34 +276,51 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
 // sums are added in order.  A symmetric product has partials only in the
 // upper tiles: the elements of a strictly upper tile are read there (rows
 // contiguous) and written to both (i, j) and (j, i); lower tiles read nothing.
+// With pad (non-symmetric products) the workgroups cover the ld x ld padded
+// matrix instead and also store it in the matrix-core precision (zeros
+// outside m x m): the operand of the rotation GEMM that follows.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
                                                           bool zero_diag,
                                                           const double *__restrict__ partials,
-                                                          double *__restrict__ out) {
+                                                          double *__restrict__ out, int ld,
+                                                          float *__restrict__ padf,
+                                                          double *__restrict__ padd) {
     constexpr int E = 64, G = 4;
     __shared__ double red[G][E];
     const int e = threadIdx.x % E, g = threadIdx.x / E;
+    const bool pad = padf != nullptr || padd != nullptr;
+    const int cols = pad ? ld : m;
     const int64_t idx = (int64_t)blockIdx.x * E + e;
     const int64_t mm = (int64_t)m * m;
     double s = 0.0;
     int i = 0, j = 0;
-    bool active = idx < mm;
-    if (active) {
-        i = (int)(idx / m);
-        j = (int)(idx - (int64_t)i * m);
-        if (symmetric && (i / BM) > (j / BM)) active = false;
+    bool inside = idx < (int64_t)cols * cols;
+    if (inside) {
+        i = (int)(idx / cols);
+        j = (int)(idx - (int64_t)i * cols);
     }
+    const bool in_m = inside && i < m && j < m;
+    bool active = in_m;
+    if (active && symmetric && (i / BM) > (j / BM)) active = false;
+    const int64_t src = (int64_t)i * m + j;
     if (active) {
 #pragma unroll 8
-        for (int p = g; p < nsplit; p += G) s += partials[(int64_t)p * mm + idx];
+        for (int p = g; p < nsplit; p += G) s += partials[(int64_t)p * mm + src];
     }
     red[g][e] = s;
     __syncthreads();
-    if (g == 0 && active) {
-        double v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    if (g != 0 || !inside) return;
+    double v = 0.0;
+    if (active) {
+        v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
         if (zero_diag && i == j) v = 0.0;
-        out[idx] = v;
+        out[src] = v;
         if (symmetric && (i / BM) < (j / BM)) out[(int64_t)j * m + i] = v;
+    }
+    if (pad) {
+        const int64_t pidx = (int64_t)i * ld + j;
+        if (padf) padf[pidx] = (float)v;
+        else padd[pidx] = v;
     }
 }
 
@@ -773,7 +790,7 @@ size_t gram_workspace(int64_t n, int m) {
 template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
-          double *out, bool reduce, TM *xshift) {
+          double *out, bool reduce, TM *xshift, TM *wpad) {
     const int ld = leading_dim(m);
     if (h) symmetric = false;
     int BM, T, nsplit;
@@ -795,8 +812,16 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     TM_HIP(hipGetLastError());
     if (!reduce) return;
     const int64_t total = (int64_t)m * m;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, BM, symmetric, zero_diag, partials, out);
+    float *padf = nullptr;
+    double *padd = nullptr;
+    if (wpad) {
+        TM_REQUIRE(!symmetric, TM_EINVAL, "the padded copy is for non-symmetric products");
+        if constexpr (sizeof(TM) == 4) padf = reinterpret_cast<float *>(wpad);
+        else padd = reinterpret_cast<double *>(wpad);
+    }
+    const int64_t cover = wpad ? (int64_t)ld * ld : total;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((cover + 63) / 64)), dim3(256), 0,
+                       s, m, nsplit, BM, symmetric, zero_diag, partials, out, ld, padf, padd);
     TM_HIP(hipGetLastError());
 }
 
@@ -823,13 +848,13 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
     TM_HIP(hipGetLastError());
     const int64_t total = (int64_t)m * m;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, BM, true, false, partials, out);
+                       s, m, nsplit, BM, true, false, partials, out, ld, nullptr, nullptr);
     TM_HIP(hipGetLastError());
 }
 
 template <typename TA>
 void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, const double *h,
-                 bool zero_diag, double *partials, double *out, bool reduce) {
+                 bool zero_diag, double *partials, double *out, bool reduce, float *wpad) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
     gram_shape(n, m, false, BM, T, nsplit);
@@ -849,8 +874,11 @@ void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, cons
     TM_HIP(hipGetLastError());
     if (!reduce) return;
     const int64_t total = (int64_t)m * m;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, BM, false, zero_diag, partials, out);
+    float *padf = nullptr;
+    if (wpad) padf = wpad;
+    const int64_t cover = wpad ? (int64_t)ld * ld : total;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((cover + 63) / 64)), dim3(256), 0,
+                       s, m, nsplit, BM, false, zero_diag, partials, out, ld, padf, nullptr);
     TM_HIP(hipGetLastError());
 }
 
@@ -917,14 +945,14 @@ void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
     TM_HIP(hipGetLastError());
 }
 
-template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, double *);
-template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool, float *);
-template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, float *);
+template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, double *, double *);
+template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool, float *, float *);
+template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, float *, float *);
 template void gram_update<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *, double *, double *);
 template void gram_update<double, double, float>(hipStream_t, int64_t, int, const double *, const float *, const CgState *, double *, double *, double *);
 template void gram_update<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *, double *, double *);
-template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool);
-template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool);
+template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool, float *);
+template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool, float *);
 template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const double *);
 template int rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *, const float *, const float *, const double *, double *, const float *);
 template int rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *, const float *, const float *, const double *, double *, const float *);

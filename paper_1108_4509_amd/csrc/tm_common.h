@@ -120,11 +120,13 @@ void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
 size_t gram_workspace(int64_t n, int m);
 // reduce = false launches only the split-K product (used to time it alone).
 // xshift (with h): B' itself, n x ld in the matrix-core precision TM, is also
-// stored there (the EPI_GRADX input of rot()).
+// stored there (the EPI_GRADX input of rot()).  wpad (non-symmetric): the
+// result is also stored as the zero-padded ld x ld matrix in TM (the W of
+// rot(), as pad_matrix would write it).
 template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
-          double *out, bool reduce = true, TM *xshift = nullptr);
+          double *out, bool reduce = true, TM *xshift = nullptr, TM *wpad = nullptr);
 
 // S = Cn^T Cn with Cn = C + alpha P formed while staged (alpha from st) and
 // written to Cn: the update of Fig. 1 fused into Fig. 4 step (1).
@@ -137,7 +139,8 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
 // sum |a||b|); full m x m, same partials layout and workspace as gram().
 template <typename TA>
 void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, const double *h,
-                 bool zero_diag, double *partials, double *out, bool reduce = true);
+                 bool zero_diag, double *partials, double *out, bool reduce = true,
+                 float *wpad = nullptr);
 
 // Tall-skinny products out = A W (+ epilogue) ------------------------------
 enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2, EPI_GRADX = 3 };

@@ -269,10 +269,10 @@ struct Solver::Impl {
         } else {
             Xs = reinterpret_cast<TMH *>(Yv);
             gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, false, (double *)gram_ws->ptr,
-                          (double *)Hp->ptr, true, Xs);
+                          (double *)Hp->ptr, true, Xs, (TMH *)Wp->ptr);
         }
-        // (7): G = -2 (X' - C H')
-        pad_matrix<TMH>(s, m, (double *)Hp->ptr, false, (TMH *)Wp->ptr, nullptr);
+        // (7): G = -2 (X' - C H'); the reduction above stored H' padded in TMH
+        if (!Xs) pad_matrix<TMH>(s, m, (double *)Hp->ptr, false, (TMH *)Wp->ptr, nullptr);
         // with the traces for Eq. 8 and the descent test fused into the epilogue
         {
             const int nch = rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, Xs ? EPI_GRADX : EPI_GRAD, X,

@@ -72,16 +72,17 @@ def kernel_work(p, ld):
         "spmm/f64": (2.0 * nnz * m, 16.0 * blk + 12.0 * nnz + 8.0 * (N + 1), "f64"),
         # Y = H P with FP32 P
         "spmm/f32": (2.0 * nnz * m, 8.0 * blk + 12.0 * nnz + 8.0 * (N + 1), "f32"),
-        # H' = C^T X' from FP64 C and X on FP32 matrix cores; X' kept in FP32
-        "gram_mp2/f64": (2.0 * N * m * m, 20.0 * blk, "f32"),
+        # H' = C^T X' (symmetric: upper tiles) from FP64 C and X on FP32
+        # matrix cores; X' kept in FP32
+        "gram_mp2/f64": (1.0 * N * m * (m + 1), 20.0 * blk, "f32"),
         # G = -2 (X' - C H'): read C (FP64), X', G_prev, P_prev (FP32), write G (FP32)
         "rot_grad_mp2/f64": (2.0 * N * m * m, 24.0 * blk, "f32"),
         # S = C^T C, FP64, upper tiles
         "gram_sym/f64": (1.0 * N * m * (m + 1), 8.0 * blk, "f64"),
         # C D + C R' with FP32 R', FP64 C in and out
         "trmm_mp2/f64": (1.0 * N * m * (m + 1), 16.0 * blk, "f32"),
-        # FP32 bulk phase Gram H', X' kept
-        "gram_shift/f32": (2.0 * N * m * m, 12.0 * blk, "f32"),
+        # FP32 bulk phase Gram H' (upper tiles), X' kept
+        "gram_shift/f32": (1.0 * N * m * (m + 1), 12.0 * blk, "f32"),
         # the same on BF16 matrix cores with two-term operands (3 products)
         "gram_bf16x3/f32": (2.0 * N * m * m, 8.0 * blk, "bf16x3"),
     }

@@ -273,8 +273,12 @@ tm_status tm_rotate(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype,
 
 /* Energy and gradient by Fig. 2, Algorithm-2, with FP64 blocks:
  * X = HC; h = diag(C^T X); E = sum h; X' = X - C diag(h); H' = C^T X' with
- * diag(H') := 0; G = -2 (X' - C H').  Outputs: X (n x ld), G (n x ld),
- * h (m), Hp (m x m), E (1 double); all device.
+ * diag(H') := 0; G = -2 (X' - C H').  C must be orthonormal, as the method
+ * keeps it: H' = C^T H C - diag(h) is then symmetric and is formed from its
+ * upper 64- or 128-column block tiles, mirrored (it differs from the full
+ * product by (C^T C - I) diag(h), which only moves G within span(C)).
+ * Outputs: X (n x ld), G (n x ld), h (m), Hp (m x m), E (1 double); all
+ * device.
  * precision TM_FULL_DP: all FP64.  TM_MP2: steps (6) and (7) on FP32
  * matrix cores (Sec. 2.2, MP2); G is still returned in FP64. */
 tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m,
@@ -307,11 +311,12 @@ tm_status tm_sym_eig(tm_ctx *ctx, int32_t m, const double *A, double *U,
  * launches (after two warm-up launches), on library-allocated blocks filled
  * with a constant byte pattern.  Synchronous.  kernel selects:
  *   TM_K_SPMM       X = H C                               (dtype)
- *   TM_K_GRAM_SHIFT H' = C^T (X - C diag(h)), split-K part  (dtype)
+ *   TM_K_GRAM_SHIFT H' = C^T (X - C diag(h)) upper tiles, split-K part (dtype)
  *   TM_K_GRAM_SYM   S = C^T C upper tiles, split-K part     (dtype)
  *   TM_K_ROT_GRAD   G = -2 (X' - C H')                     (dtype)
  *   TM_K_TRMM       C D + C R'                             (dtype)
- *   TM_K_GRAM_MP2   H' from FP64 blocks on FP32 matrix cores (dtype ignored)
+ *   TM_K_GRAM_MP2   H' upper tiles from FP64 blocks on FP32 matrix cores
+ *                   (dtype ignored)
  *   TM_K_ROT_GRAD_MP2 G from FP64 C and X, FP32 H' and FP32 G (dtype ignored)
  *   TM_K_TRMM_MP2   FP64 C D + C R' with R' on FP32 matrix cores (dtype ignored)
  *   TM_K_CHOL       S = R^T R and R^{-1}, m x m FP64 (dtype ignored)

@@ -276,9 +276,9 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
 // sums are added in order.  A symmetric product has partials only in the
 // upper tiles: the elements of a strictly upper tile are read there (rows
 // contiguous) and written to both (i, j) and (j, i); lower tiles read nothing.
-// With pad (non-symmetric products) the workgroups cover the ld x ld padded
-// matrix instead and also store it in the matrix-core precision (zeros
-// outside m x m): the operand of the rotation GEMM that follows.
+// With pad the workgroups cover the ld x ld padded matrix instead and also
+// store it in the matrix-core precision (zeros outside m x m, mirrored for a
+// symmetric product): the operand of the rotation GEMM that follows.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
                                                           bool zero_diag,
                                                           const double *__restrict__ partials,
@@ -318,9 +318,16 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int
         if (symmetric && (i / BM) < (j / BM)) out[(int64_t)j * m + i] = v;
     }
     if (pad) {
+        // lower tiles of a symmetric product are written by their mirror
+        if (in_m && !active) return;
         const int64_t pidx = (int64_t)i * ld + j;
         if (padf) padf[pidx] = (float)v;
         else padd[pidx] = v;
+        if (active && symmetric && (i / BM) < (j / BM)) {
+            const int64_t q = (int64_t)j * ld + i;
+            if (padf) padf[q] = (float)v;
+            else padd[q] = v;
+        }
     }
 }
 
@@ -792,7 +799,6 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
           double *out, bool reduce, TM *xshift, TM *wpad) {
     const int ld = leading_dim(m);
-    if (h) symmetric = false;
     int BM, T, nsplit;
     gram_shape(n, m, symmetric, BM, T, nsplit);
     const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
@@ -815,7 +821,6 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     float *padf = nullptr;
     double *padd = nullptr;
     if (wpad) {
-        TM_REQUIRE(!symmetric, TM_EINVAL, "the padded copy is for non-symmetric products");
         if constexpr (sizeof(TM) == 4) padf = reinterpret_cast<float *>(wpad);
         else padd = reinterpret_cast<double *>(wpad);
     }

@@ -386,19 +386,18 @@ tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t precis
         const int nch = spmm_any(s, H, ld, C, X, true, 1, (double *)dws.ptr);
         reduce_partials(s, 1, nch, ld, (double *)dws.ptr, (double *)hv.ptr);
         // X' = X - C diag(h) is kept by the Gram in the matrix-core precision
-        // and read back by the gradient, as in the solver
+        // and read back by the gradient; H' from its upper block tiles,
+        // mirrored, also stored padded for the gradient GEMM: as in the solver
         if (dp) {
             double *Xs = (double *)xs.ptr;
-            gram<double, double>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp,
-                                 true, Xs);
-            pad_matrix<double>(s, m, Hp, false, (double *)wp.ptr, nullptr);
+            gram<double, double>(s, n, m, C, X, (double *)hv.ptr, true, true, (double *)gws.ptr, Hp,
+                                 true, Xs, (double *)wp.ptr);
             rot<double, double, double>(s, n, m, C, (double *)wp.ptr, EPI_GRADX, X, (double *)hv.ptr, G,
                                         nullptr, nullptr, nullptr, nullptr, Xs);
         } else {
             float *Xs = (float *)xs.ptr;
-            gram<double, float>(s, n, m, C, X, (double *)hv.ptr, true, false, (double *)gws.ptr, Hp,
-                                true, Xs);
-            pad_matrix<float>(s, m, Hp, false, (float *)wp.ptr, nullptr);
+            gram<double, float>(s, n, m, C, X, (double *)hv.ptr, true, true, (double *)gws.ptr, Hp,
+                                true, Xs, (float *)wp.ptr);
             rot<double, float, double>(s, n, m, C, (float *)wp.ptr, EPI_GRADX, X, (double *)hv.ptr, G,
                                        nullptr, nullptr, nullptr, nullptr, Xs);
         }
@@ -510,8 +509,8 @@ tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m
             case TM_K_SPMM: spmm_any(s, H, ld, A.ptr, O.ptr, f64); break;
             case TM_K_GRAM_SHIFT:
                 // as in the solver: X' kept for the gradient
-                if (f64) gram<double, double>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false, (double *)O.ptr);
-                else gram<float, float>(s, n, m, (float *)A.ptr, (float *)B.ptr, v, true, false, ws_p, mm_p, false, (float *)O.ptr);
+                if (f64) gram<double, double>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, true, ws_p, mm_p, false, (double *)O.ptr);
+                else gram<float, float>(s, n, m, (float *)A.ptr, (float *)B.ptr, v, true, true, ws_p, mm_p, false, (float *)O.ptr);
                 break;
             case TM_K_GRAM_SYM:
                 if (f64) gram<double, double>(s, n, m, (double *)A.ptr, (double *)A.ptr, nullptr, false, true, ws_p, mm_p, false);
@@ -527,7 +526,7 @@ tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m
                 else rot<float, float, float>(s, n, m, (float *)A.ptr, (float *)wp.ptr, EPI_TRMM, nullptr, v, (float *)O.ptr);
                 break;
             case TM_K_GRAM_MP2:
-                gram<double, float>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, false, ws_p, mm_p, false, (float *)g32.ptr);
+                gram<double, float>(s, n, m, (double *)A.ptr, (double *)B.ptr, v, true, true, ws_p, mm_p, false, (float *)g32.ptr);
                 break;
             case TM_K_ROT_GRAD_MP2: {
                 // the refinement-phase gradient: FP64 C, FP32 X' (from the Gram), FP32 H'

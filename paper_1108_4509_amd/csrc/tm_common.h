@@ -120,9 +120,11 @@ void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
 size_t gram_workspace(int64_t n, int m);
 // reduce = false launches only the split-K product (used to time it alone).
 // xshift (with h): B' itself, n x ld in the matrix-core precision TM, is also
-// stored there (the EPI_GRADX input of rot()).  wpad (non-symmetric): the
-// result is also stored as the zero-padded ld x ld matrix in TM (the W of
-// rot(), as pad_matrix would write it).
+// stored there (the EPI_GRADX input of rot()).  wpad: the result is also
+// stored as the zero-padded ld x ld matrix in TM (the W of rot(), as
+// pad_matrix would write it).  symmetric: only the upper block tiles are
+// computed and mirrored (exact for A = B; with h, the symmetric H' of an
+// orthonormal A).
 template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,

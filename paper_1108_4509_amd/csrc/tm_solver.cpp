@@ -261,14 +261,17 @@ struct Solver::Impl {
         }
         // (5)-(6): H' = C^T (X - C H_D), diag(H') = 0; X' = X - C H_D is formed
         // in C's precision while staged and kept, rounded once to the matrix-core
-        // precision, in Y (free until the line step) for step (7)
+        // precision, in Y (free until the line step) for step (7).  C is
+        // orthonormal here, so H' = C^T H C - H_D is symmetric: only its upper
+        // block tiles are computed and mirrored (the difference from the full
+        // product, (C^T C - I) H_D, lies in span(C) and leaves E unchanged)
         static_assert(std::is_same<TG, TMH>::value, "X' is held in a direction block");
         TMH *Xs = nullptr;
         if (!is_f64<TC>() && bf16_bulk) {
             gram_bf16x3<TC>(s, n, m, C, X, (double *)h->ptr, true, (double *)gram_ws->ptr, (double *)Hp->ptr);
         } else {
             Xs = reinterpret_cast<TMH *>(Yv);
-            gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, false, (double *)gram_ws->ptr,
+            gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, true, (double *)gram_ws->ptr,
                           (double *)Hp->ptr, true, Xs, (TMH *)Wp->ptr);
         }
         // (7): G = -2 (X' - C H'); the reduction above stored H' padded in TMH

@@ -243,11 +243,22 @@ def test_energy_grad_alg2_full_dp(ctx, tm, orc, name, prob):
     assert abs(E - E_o) <= 4 * g * np.sum(np.abs(C) * absX)
     assert np.all(np.abs(host(h) - h_o) <= 4 * g * np.sum(np.abs(C) * absX, axis=0))
     absXp = absX + np.abs(C) * np.abs(h_o)[None, :]
-    assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * g * (np.abs(C).T @ absXp))
+    mirror = _mirror_term(C, h_o)
+    assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * g * (np.abs(C).T @ absXp) + mirror)
     absG = 2 * (absXp + np.abs(C) @ np.abs(Hp_o))
-    bound = 8 * g * (absG + 2 * np.abs(C) @ (np.abs(C).T @ absXp))
+    bound = 8 * g * (absG + 2 * np.abs(C) @ (np.abs(C).T @ absXp)) + 2 * np.abs(C) @ mirror
     assert np.all(np.abs(host(G, m) - G_o) <= bound)
     assert np.all(np.abs(host(X, m) - X_o) <= 2 * gamma(14, U64) * absX)
+
+
+def _mirror_term(C, h):
+    """H' is formed from its upper block tiles and mirrored, which is exact
+    only when C^T C = I: entry (i, j) then differs from c_i . x'_j by
+    (c_i . c_j)(h_j - h_i).  Bound of that term for the given (FP64) C, with
+    the rounding of the check's own C^T C added."""
+    n = C.shape[0]
+    O = np.abs(C.T @ C - np.eye(C.shape[1])) + gamma(n, U64) * (np.abs(C).T @ np.abs(C))
+    return 2 * O * np.abs(h[:, None] - h[None, :])
 
 
 def test_energy_grad_mp2(ctx, tm, orc):
@@ -266,10 +277,11 @@ def test_energy_grad_mp2(ctx, tm, orc):
     absX = abs(H) @ np.abs(C)
     assert abs(E - E_o) <= 4 * gamma(n + 16, U64) * np.sum(np.abs(C) * absX)  # DP energy
     absXp = absX + np.abs(C) * np.abs(h_o)[None, :]
-    assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * gamma(n + 4, U32) * (np.abs(C).T @ absXp))
+    mirror = _mirror_term(C, h_o)
+    assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * gamma(n + 4, U32) * (np.abs(C).T @ absXp) + mirror)
     Xp_o = X_o - C * h_o[None, :]
     bound = 8 * gamma(n + m + 4, U32) * (np.abs(C) @ (np.abs(C).T @ absXp)) \
-        + 4 * U32 * np.abs(Xp_o) + 8 * gamma(n + 16, U64) * absXp
+        + 4 * U32 * np.abs(Xp_o) + 8 * gamma(n + 16, U64) * absXp + 2 * np.abs(C) @ mirror
     assert np.all(np.abs(host(G, m) - G_o) <= bound)
 
 

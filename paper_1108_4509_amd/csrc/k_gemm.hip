@@ -94,6 +94,41 @@ __device__ inline void upper_tile(int t, int T, int &ti, int &tj) {
     tj = i + t;
 }
 
+// Which 16 x 16 blocks of a 128 x 128 tile a wave accumulates on a diagonal
+// tile of a symmetric product.  The strictly lower 64 x 64 quarter (block
+// rows 4-7, block columns 0-3) is the mirror of the upper one and is not
+// formed; the other 48 blocks are dealt 12 per wave, in column runs:
+//   wave 0: columns 0-2 x rows 0-3     wave 1: column 3 x rows 0-3, column 4
+//   wave 2: column 5, column 6 x rows 0-3   wave 3: column 6 x rows 4-7, column 7
+// diag_block(w, k) = 8 * (block row) + (block column) of the wave's k-th block.
+__host__ __device__ constexpr int diag_block(int w, int k) {
+    return w == 0   ? 8 * (k % 4) + k / 4
+           : w == 1 ? (k < 4 ? 8 * k + 3 : 8 * (k - 4) + 4)
+           : w == 2 ? (k < 8 ? 8 * k + 5 : 8 * (k - 8) + 6)
+                    : (k < 4 ? 8 * (k + 4) + 6 : 8 * (k - 4) + 7);
+}
+__host__ __device__ constexpr unsigned diag_rows(int w) {
+    unsigned r = 0;
+    for (int k = 0; k < 12; ++k) r |= 1u << (diag_block(w, k) / 8);
+    return r;
+}
+__host__ __device__ constexpr unsigned diag_cols(int w) {
+    unsigned c = 0;
+    for (int k = 0; k < 12; ++k) c |= 1u << (diag_block(w, k) % 8);
+    return c;
+}
+constexpr bool diag_plan_ok() {
+    // every block of the upper part exactly once, none of the lower quarter
+    int seen[64] = {};
+    for (int w = 0; w < 4; ++w)
+        for (int k = 0; k < 12; ++k) ++seen[diag_block(w, k)];
+    for (int b = 0; b < 64; ++b)
+        if (seen[b] != ((b / 8 >= 4 && b % 8 < 4) ? 0 : 1)) return false;
+    return true;
+}
+static_assert(diag_plan_ok(), "diagonal-tile block plan");
+template <int V> struct IntC { static constexpr int value = V; };
+
 // The update C_next = C + alpha P fused into S = C_next^T C_next (Fig. 1's
 // step C + alpha P, then Fig. 4 step (1)): both operands are formed from C
 // and P while they are staged, and the workgroups on the diagonal tiles store
@@ -231,55 +266,91 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
         }
     };
 
-    int buf = 0;
-    if (k_begin < k_end) {
-        load(k_begin);
-        store(0);
-    }
-    __syncthreads();
-    for (int64_t k0 = k_begin; k0 < k_end; k0 += KT) {
-        const bool more = k0 + KT < k_end;
-        if (more) load(k0 + KT);
-#pragma unroll
-        for (int kk = 0; kk < KT; kk += 4) {
-            TM fa[NB], fb[NB];
-            const int kr = kk + (lane >> 4);
-#pragma unroll
-            for (int a = 0; a < NB; ++a) fa[a] = As[buf][kr][wi * WM + a * 16 + (lane & 15)];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) fb[b] = Bs[buf][kr][wj * WM + b * 16 + (lane & 15)];
-#pragma unroll
-            for (int a = 0; a < NB; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b) acc[a][b] = Mfma<TM>::op(fa[a], fb[b], acc[a][b]);
-        }
-        if (more) store(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-    }
-
+    // plan 0: the wave's (BM/2) x (BM/2) quadrant; plans 1-4: wave plan - 1
+    // of a diagonal tile of a symmetric product (BM = 128, see diag_block)
     double *P = partials + (int64_t)split * m * m;
+    auto run = [&](auto plan) {
+        constexpr int PL = decltype(plan)::value;
+        constexpr int DW = PL - 1;
+        int buf = 0;
+        if (k_begin < k_end) {
+            load(k_begin);
+            store(0);
+        }
+        __syncthreads();
+        for (int64_t k0 = k_begin; k0 < k_end; k0 += KT) {
+            const bool more = k0 + KT < k_end;
+            if (more) load(k0 + KT);
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+            for (int kk = 0; kk < KT; kk += 4) {
+                const int kr = kk + (lane >> 4);
+                if constexpr (PL == 0) {
+                    TM fa[NB], fb[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+                    for (int a = 0; a < NB; ++a) fa[a] = As[buf][kr][wi * WM + a * 16 + (lane & 15)];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wi * WM + a * 16 + Mfma<TM>::row(lane, r);
-                const int j = j0 + wj * WM + b * 16 + (lane & 15);
-                if (i < m && j < m) P[(int64_t)i * m + j] = (double)acc[a][b][r];
+                    for (int b = 0; b < NB; ++b) fb[b] = Bs[buf][kr][wj * WM + b * 16 + (lane & 15)];
+#pragma unroll
+                    for (int a = 0; a < NB; ++a)
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) acc[a][b] = Mfma<TM>::op(fa[a], fb[b], acc[a][b]);
+                } else {
+                    TM fa[8], fb[8];
+#pragma unroll
+                    for (int a = 0; a < 8; ++a)
+                        if ((diag_rows(DW) >> a) & 1u) fa[a] = As[buf][kr][a * 16 + (lane & 15)];
+#pragma unroll
+                    for (int b = 0; b < 8; ++b)
+                        if ((diag_cols(DW) >> b) & 1u) fb[b] = Bs[buf][kr][b * 16 + (lane & 15)];
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        acc[k / 4][k % 4] = Mfma<TM>::op(fa[diag_block(DW, k) / 8], fb[diag_block(DW, k) % 8],
+                                                         acc[k / 4][k % 4]);
+                }
             }
+            if (more) store(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (PL != 0 && a * NB + b >= 12) continue;
+                const int bi = PL == 0 ? wi * NB + a : diag_block(DW, a * NB + b) / 8;
+                const int bj = PL == 0 ? wj * NB + b : diag_block(DW, a * NB + b) % 8;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + bi * 16 + Mfma<TM>::row(lane, r);
+                    const int j = j0 + bj * 16 + (lane & 15);
+                    if (i < m && j < m) P[(int64_t)i * m + j] = (double)acc[a][b][r];
+                }
+            }
+    };
+    if constexpr (BM == 128) {
+        if (symmetric && same) {
+            if (wave == 0) run(IntC<1>{});
+            else if (wave == 1) run(IntC<2>{});
+            else if (wave == 2) run(IntC<3>{});
+            else run(IntC<4>{});
+            return;
+        }
+    }
+    run(IntC<0>{});
 }
 
 // Sum over the row-chunk partials in a fixed order: 64 elements per
 // workgroup, four lane groups take every fourth chunk, then the four group
 // sums are added in order.  A symmetric product has partials only in the
-// upper tiles: the elements of a strictly upper tile are read there (rows
-// contiguous) and written to both (i, j) and (j, i); lower tiles read nothing.
+// upper 64 x 64 blocks (block row <= block column: the upper tiles, less the
+// lower quarter of 128-wide diagonal tiles): the elements of a strictly upper
+// block are read there (rows contiguous) and written to both (i, j) and
+// (j, i); lower blocks read nothing.
 // With pad the workgroups cover the ld x ld padded matrix instead and also
 // store it in the matrix-core precision (zeros outside m x m, mirrored for a
 // symmetric product): the operand of the rotation GEMM that follows.
-__global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int BM, bool symmetric,
+constexpr int kSymBlk = 64;
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, bool symmetric,
                                                           bool zero_diag,
                                                           const double *__restrict__ partials,
                                                           double *__restrict__ out, int ld,
@@ -301,7 +372,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int
     }
     const bool in_m = inside && i < m && j < m;
     bool active = in_m;
-    if (active && symmetric && (i / BM) > (j / BM)) active = false;
+    if (active && symmetric && (i / kSymBlk) > (j / kSymBlk)) active = false;
     const int64_t src = (int64_t)i * m + j;
     if (active) {
 #pragma unroll 8
@@ -315,7 +386,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int
         v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
         if (zero_diag && i == j) v = 0.0;
         out[src] = v;
-        if (symmetric && (i / BM) < (j / BM)) out[(int64_t)j * m + i] = v;
+        if (symmetric && (i / kSymBlk) < (j / kSymBlk)) out[(int64_t)j * m + i] = v;
     }
     if (pad) {
         // lower tiles of a symmetric product are written by their mirror
@@ -323,7 +394,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, int
         const int64_t pidx = (int64_t)i * ld + j;
         if (padf) padf[pidx] = (float)v;
         else padd[pidx] = v;
-        if (active && symmetric && (i / BM) < (j / BM)) {
+        if (active && symmetric && (i / kSymBlk) < (j / kSymBlk)) {
             const int64_t q = (int64_t)j * ld + i;
             if (padf) padf[q] = (float)v;
             else padd[q] = v;
@@ -826,7 +897,7 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     }
     const int64_t cover = wpad ? (int64_t)ld * ld : total;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((cover + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, BM, symmetric, zero_diag, partials, out, ld, padf, padd);
+                       s, m, nsplit, symmetric, zero_diag, partials, out, ld, padf, padd);
     TM_HIP(hipGetLastError());
 }
 
@@ -853,7 +924,7 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
     TM_HIP(hipGetLastError());
     const int64_t total = (int64_t)m * m;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, BM, true, false, partials, out, ld, nullptr, nullptr);
+                       s, m, nsplit, true, false, partials, out, ld, nullptr, nullptr);
     TM_HIP(hipGetLastError());
 }
 
@@ -883,7 +954,7 @@ void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, cons
     if (wpad) padf = wpad;
     const int64_t cover = wpad ? (int64_t)ld * ld : total;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((cover + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, BM, false, zero_diag, partials, out, ld, padf, nullptr);
+                       s, m, nsplit, false, zero_diag, partials, out, ld, padf, nullptr);
     TM_HIP(hipGetLastError());
 }
 

@@ -8,6 +8,8 @@
 //          gradient epilogue of Fig. 2 step (7), the triangular product
 //          C R^{-1} = C D + C R' of Fig. 4 step (4) / Eq. 13, and the
 //          subspace rotation C U of the Rayleigh-Ritz step (Eq. 9).
+//   trmm_lds_kernel : the triangular product of Eq. 13 at ld = 256 with R'
+//          held in LDS and C streamed once (see there).
 //
 // Operands are staged through LDS by 256-lane workgroups (2 x 2 waves); each
 // wave owns a (B/2) x (B/2) output patch made of 16 x 16 MFMA blocks.  Matrix
@@ -843,6 +845,146 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     }
 }
 
+// --------------------------------------------- TRMM with R' resident in LDS
+// C D + C R' (Eq. 13) on FP32 matrix cores for ld = 16 NB: R' is strictly
+// upper triangular, so its 16 x 16 blocks on and above the diagonal fit in
+// LDS (136 blocks, 148 KB at NB = 16).  One workgroup of eight waves per CU
+// loads them once; each wave then streams its own 16-row strips of C from
+// HBM straight into matrix-core operands (no LDS staging of C, no barriers)
+// and forms the full output width, so C is read once and the zero blocks
+// below the diagonal are never multiplied.  Inside an instruction the k
+// order is permuted so that a lane's four k come from one 16-byte load: in
+// k block kb, step e, lane group g takes k = 16 kb + 4 g + e, and R' supplies
+// the same k.  Stored block (kb, jb), kb <= jb, keeps element (r, c) at word
+// (r / 4) * 68 + 4 c + r % 4, so a lane's four k of one column are one
+// aligned 16-byte LDS read.
+constexpr int kTriWaves = 8;
+constexpr int kTriStride = 68;
+constexpr int kTriBlock = 4 * kTriStride;
+constexpr int kTriGrid = 256;
+
+__host__ __device__ constexpr int tri_index(int NB, int kb, int jb) {
+    return kb * NB - kb * (kb - 1) / 2 + (jb - kb);
+}
+
+// Four consecutive elements of C as raw 16-byte vectors (one for FP32, two
+// for FP64), converted to FP32 only when used, so that a prefetch does not
+// wait for its own load.
+template <typename TA> struct Raw4 {
+    static constexpr int NV = sizeof(TA) == 8 ? 2 : 1;
+    typename Vec16<TA>::type v[NV];
+    __device__ void fetch(const TA *p) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = *reinterpret_cast<const typename Vec16<TA>::type *>(p + 4 / NV * i);
+    }
+    __device__ void to_float(float (&a)[4]) const {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[e] = (float)v[e / (4 / NV)][e % (4 / NV)];
+    }
+};
+
+template <typename TA, int NB>
+__global__ __launch_bounds__(kTriWaves * 64) void trmm_lds_kernel(
+    int64_t n, int ld, const TA *__restrict__ A, const float *__restrict__ W,
+    const double *__restrict__ d, TA *__restrict__ out, int64_t nstrips) {
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    using Acc = Mfma<float>::acc_t;
+    __shared__ __align__(16) float Wl[NBLK * kTriBlock];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int j = lane & 15, g = lane >> 4;
+
+    for (int idx = tid; idx < NBLK * 64; idx += kTriWaves * 64) {
+        const int blk = idx >> 6, q = idx & 63;
+        int kb = 0, b = blk;
+        while (b >= NB - kb) {
+            b -= NB - kb;
+            ++kb;
+        }
+        const int jb = kb + b, rr = q >> 2, cq = q & 3;
+        const vf4 x = *reinterpret_cast<const vf4 *>(W + (int64_t)(kb * 16 + rr) * ld + jb * 16 + 4 * cq);
+        float *dst = Wl + blk * kTriBlock + (rr >> 2) * kTriStride + 16 * cq + (rr & 3);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dst[4 * t] = x[t];
+    }
+    __syncthreads();
+
+    // balanced contiguous strips: workgroup, then wave (waves w and w + 4
+    // share a SIMD, so the extra strips go to waves 0, 1, 2, ... first)
+    const int64_t s0 = (int64_t)blockIdx.x * nstrips / gridDim.x;
+    const int64_t s1 = (int64_t)(blockIdx.x + 1) * nstrips / gridDim.x;
+    const int64_t cnt = s1 - s0, base = cnt / kTriWaves, rem = cnt % kTriWaves;
+    const int64_t my0 = s0 + wave * base + (wave < rem ? wave : rem);
+    const int64_t my1 = my0 + base + (wave < rem ? 1 : 0);
+
+    // C of k block 0 of the first strip; each k block prefetches the next
+    // (the last one the next strip's first), rows clamped to n - 1
+    auto a_row = [&](int64_t st) {
+        const int64_t r = st * 16 + j;
+        return A + (r < n ? r : n - 1) * ld + 4 * g;
+    };
+    Raw4<TA> an;
+    if (my0 < my1) an.fetch(a_row(my0));
+    for (int64_t st = my0; st < my1; ++st) {
+        const int64_t row0 = st * 16;
+        const TA *Ar = a_row(st);
+        const TA *An = a_row(st + 1 < my1 ? st + 1 : st);
+        Acc acc[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[c] = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb) {
+            float a[4];
+            an.to_float(a);
+            an.fetch(kb + 1 < NB ? Ar + (kb + 1) * 16 : An);
+            // the prefetch is issued before this block's work, not sunk into it
+            __builtin_amdgcn_sched_barrier(0);
+            float bw[NB][4];
+#pragma unroll
+            for (int jb = kb; jb < NB; ++jb) {
+                const vf4 x = *reinterpret_cast<const vf4 *>(Wl + tri_index(NB, kb, jb) * kTriBlock +
+                                                             g * kTriStride + 4 * j);
+                bw[jb][0] = x[0]; bw[jb][1] = x[1]; bw[jb][2] = x[2]; bw[jb][3] = x[3];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int jb = kb; jb < NB; ++jb) acc[jb] = Mfma<float>::op(a[e], bw[jb][e], acc[jb]);
+            // one scheduling region per k block: the LDS reads of a block
+            // interleave with its own matrix-core work and are not hoisted
+            // across blocks (which would exceed the register budget)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+
+        // out = C D + C R': this lane holds rows row0 + 4 g + r of column
+        // 16 jb + j.  A full strip needs no row mask; the last, partial one
+        // clamps its loads to row n - 1 and masks its stores.
+        auto epilogue = [&](auto fullc) {
+            constexpr bool FULL = decltype(fullc)::value != 0;
+            int64_t rowc[4];
+            bool ok[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + 4 * g + r;
+                ok[r] = FULL || row < n;
+                rowc[r] = ok[r] ? row : n - 1;
+            }
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int col = jb * 16 + j;
+                TA av[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) av[r] = A[rowc[r] * ld + col];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (FULL || ok[r]) out[rowc[r] * ld + col] = av[r] * (TA)d[col] + (TA)acc[jb][r];
+            }
+        };
+        if (row0 + 16 <= n) epilogue(IntC<1>{});
+        else epilogue(IntC<0>{});
+    }
+}
+
 template <typename TM>
 __global__ void pad_kernel(int m, int ld, const double *__restrict__ W,
                            bool strict_upper, TM *__restrict__ Wpad,
@@ -964,6 +1106,16 @@ int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
         const double *M, double *partials, const TM *Xs) {
     TM_REQUIRE(epi != EPI_GRADX || Xs != nullptr, TM_EINVAL, "EPI_GRADX needs X'");
     const int ld = leading_dim(m);
+    if constexpr (std::is_same<TM, float>::value && std::is_same<TA, TO>::value) {
+        if (ld == 256 && epi == EPI_TRMM) {
+            const int64_t nstrips = (n + 15) / 16;
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(kTriGrid, nstrips));
+            hipLaunchKernelGGL((trmm_lds_kernel<TA, 16>), dim3(grid), dim3(kTriWaves * 64), 0, s, n, ld, A,
+                               Wpad, vec, out, nstrips);
+            TM_HIP(hipGetLastError());
+            return grid;
+        }
+    }
     const int B = ld >= 256 ? 128 : 64;
     // row tile: 64 rows give about twice the workgroups (7 rounds of 512 at
     // N = 110592 instead of 3.4, so less idle tail) and measured faster for

@@ -285,6 +285,31 @@ def test_energy_grad_mp2(ctx, tm, orc):
     assert np.all(np.abs(host(G, m) - G_o) <= bound)
 
 
+def test_energy_grad_mp2_wide(ctx, tm, orc):
+    """MP2 gradient at a 256-wide block (m = 250, the width whose H' and R'
+    are kept in LDS by the gradient and triangular products) with a ragged
+    last row strip (n = 45 x 47 = 2115 = 132 x 16 + 3); same bounds as the
+    MP2 case above."""
+    prob = make_problem("d250", StencilSpec(2, (45, 47), 2, "dirichlet", 1.0), m=250, seed=9)
+    print_case(test="energy_grad_mp2_wide", n=prob.N, m=prob.m)
+    H = orc.csr_matrix(*prob.csr(), prob.N)
+    Hd = tm.matrix_from_problem(ctx, prob)
+    C = orc.orthonormalize(prob.C0())
+    E, G, X, h, Hp = tm.energy_grad(ctx, Hd, prob.m, tm.to_block(C), precision="mp2")
+    E_o, G_o, X_o, h_o, Hp_o = orc.energy_gradient_alg2(H, C)
+    n, m = C.shape
+    absX = abs(H) @ np.abs(C)
+    absXp = absX + np.abs(C) * np.abs(h_o)[None, :]
+    mirror = _mirror_term(C, h_o)
+    assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * gamma(n + 4, U32) * (np.abs(C).T @ absXp) + mirror)
+    Xp_o = X_o - C * h_o[None, :]
+    bound = 8 * gamma(n + m + 4, U32) * (np.abs(C) @ (np.abs(C).T @ absXp)) \
+        + 4 * U32 * np.abs(Xp_o) + 8 * gamma(n + 16, U64) * absXp + 2 * np.abs(C) @ mirror
+    got = host(G)
+    assert np.all(np.abs(got[:, :m] - G_o) <= bound)
+    assert np.all(got[:, m:] == 0)
+
+
 @pytest.mark.parametrize("n,m", [(4096, 27), (3001, 76), (2050, 256)])
 @pytest.mark.parametrize("precision", ["full_dp", "mp2"])
 def test_orthonormalize(ctx, tm, orc, n, m, precision):

@@ -45,6 +45,15 @@ template <> struct Mfma<double> {
 };
 
 constexpr int kThreads = 256;
+// threads of a Gram workgroup: 8 waves as 2 x 4, each a 64 x 32 patch of a
+// 128-wide tile (4 waves as 2 x 2 leave 2 per SIMD at the FP64 accumulator
+// budget; 8 halve each wave's accumulators and staging).  The all-FP64
+// shifted and updating products keep 4 waves: at 8 they exceed the
+// 128-register budget of 4 waves per SIMD and spill.
+template <typename TA, typename TM, bool SHIFT, bool UPD, typename TP>
+constexpr int gram_threads() {
+    return (sizeof(TA) == 8 && sizeof(TM) == 8 && (SHIFT || (UPD && sizeof(TP) == 8))) ? 256 : 512;
+}
 constexpr int kPad = 16;   // LDS row padding (elements) against bank conflicts
 
 // 16-byte vector of T for global loads (clang vector types: element access
@@ -99,36 +108,34 @@ __device__ inline void upper_tile(int t, int T, int &ti, int &tj) {
 // Which 16 x 16 blocks of a 128 x 128 tile a wave accumulates on a diagonal
 // tile of a symmetric product.  The strictly lower 64 x 64 quarter (block
 // rows 4-7, block columns 0-3) is the mirror of the upper one and is not
-// formed; the other 48 blocks are dealt 12 per wave, in column runs:
-//   wave 0: columns 0-2 x rows 0-3     wave 1: column 3 x rows 0-3, column 4
-//   wave 2: column 5, column 6 x rows 0-3   wave 3: column 6 x rows 4-7, column 7
-// diag_block(w, k) = 8 * (block row) + (block column) of the wave's k-th block.
-__host__ __device__ constexpr int diag_block(int w, int k) {
-    return w == 0   ? 8 * (k % 4) + k / 4
-           : w == 1 ? (k < 4 ? 8 * k + 3 : 8 * (k - 4) + 4)
-           : w == 2 ? (k < 8 ? 8 * k + 5 : 8 * (k - 8) + 6)
-                    : (k < 4 ? 8 * (k + 4) + 6 : 8 * (k - 4) + 7);
+// formed; the other 48 blocks, taken column by column (columns 0-3: rows
+// 0-3; columns 4-7: rows 0-7), are dealt in runs of 48 / waves.
+// diag_block(nw, w, k) = 8 * (block row) + (block column) of the k-th block
+// of wave w out of nw.
+__host__ __device__ constexpr int diag_block(int nw, int w, int k) {
+    const int q = w * (48 / nw) + k;
+    return q < 16 ? 8 * (q % 4) + q / 4 : 8 * ((q - 16) % 8) + 4 + (q - 16) / 8;
 }
-__host__ __device__ constexpr unsigned diag_rows(int w) {
+__host__ __device__ constexpr unsigned diag_rows(int nw, int w) {
     unsigned r = 0;
-    for (int k = 0; k < 12; ++k) r |= 1u << (diag_block(w, k) / 8);
+    for (int k = 0; k < 48 / nw; ++k) r |= 1u << (diag_block(nw, w, k) / 8);
     return r;
 }
-__host__ __device__ constexpr unsigned diag_cols(int w) {
+__host__ __device__ constexpr unsigned diag_cols(int nw, int w) {
     unsigned c = 0;
-    for (int k = 0; k < 12; ++k) c |= 1u << (diag_block(w, k) % 8);
+    for (int k = 0; k < 48 / nw; ++k) c |= 1u << (diag_block(nw, w, k) % 8);
     return c;
 }
-constexpr bool diag_plan_ok() {
+constexpr bool diag_plan_ok(int nw) {
     // every block of the upper part exactly once, none of the lower quarter
     int seen[64] = {};
-    for (int w = 0; w < 4; ++w)
-        for (int k = 0; k < 12; ++k) ++seen[diag_block(w, k)];
+    for (int w = 0; w < nw; ++w)
+        for (int k = 0; k < 48 / nw; ++k) ++seen[diag_block(nw, w, k)];
     for (int b = 0; b < 64; ++b)
         if (seen[b] != ((b / 8 >= 4 && b % 8 < 4) ? 0 : 1)) return false;
     return true;
 }
-static_assert(diag_plan_ok(), "diagonal-tile block plan");
+static_assert(diag_plan_ok(4) && diag_plan_ok(8), "diagonal-tile block plan");
 template <int V> struct IntC { static constexpr int value = V; };
 
 // The update C_next = C + alpha P fused into S = C_next^T C_next (Fig. 1's
@@ -145,18 +152,20 @@ struct GramUpd {
 // One workgroup: a BM x BM tile of A^T B' over a chunk of rows.  Each lane
 // loads 16-byte vectors from a fixed column group (so h is read once), the
 // LDS stage is double-buffered, one barrier per stage.
-template <typename TA, typename TM, int BM, bool SHIFT, bool UPD = false, typename TP = TA>
-__global__ __launch_bounds__(kThreads, 2) void gram_kernel(
+template <typename TA, typename TM, int BM, bool SHIFT, bool UPD = false, typename TP = TA, int NT = kThreads>
+__global__ __launch_bounds__(NT, NT / 128) void gram_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TA *__restrict__ B,
     const double *__restrict__ h, int T, int ntiles, bool symmetric,
     int64_t rows_per_split, double *__restrict__ partials, GramUpd<TA, TP> up,
     TM *__restrict__ xout) {
     constexpr int KT = stage_rows<TM>();
-    constexpr int WM = BM / 2;
-    constexpr int NB = WM / 16;
+    constexpr int NW = NT / 64;             // waves: 2 x (NW / 2)
+    constexpr int WM = BM / 2;              // rows of a wave's patch
+    constexpr int WN = BM / (NW / 2);       // columns of a wave's patch
+    constexpr int NBR = WM / 16, NBC = WN / 16;
     constexpr int VW = Vec16<TA>::W;
     constexpr int VPR = BM / VW;            // vectors per tile row
-    constexpr int RPP = kThreads / VPR;     // tile rows per load pass
+    constexpr int RPP = NT / VPR;           // tile rows per load pass
     constexpr int PASSES = KT / RPP;
     static_assert(KT % RPP == 0, "stage rows must be a multiple of rows per pass");
     using V = typename Vec16<TA>::type;
@@ -178,7 +187,7 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int wi = wave >> 1, wj = wave & 1;
+    const int wi = wave / (NW / 2), wj = wave % (NW / 2);
     const int cv = tid % VPR, rbase = tid / VPR;
     const int ci = i0 + cv * VW, cj = j0 + cv * VW;
     const bool ci_ok = ci < ld, cj_ok = cj < ld;   // ld is a multiple of 32
@@ -188,11 +197,11 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
 #pragma unroll
     for (int w = 0; w < VW; ++w) hv[w] = (SHIFT && cj_ok) ? h[cj + w] : 0.0;
 
-    Acc acc[NB][NB];
+    Acc acc[NBR][NBC];
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+    for (int a = 0; a < NBR; ++a)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+        for (int b = 0; b < NBC; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
     // loads are unconditional (rows past the chunk end read a valid row and
     // columns past ld column 0, both zeroed at the store) so that no select
@@ -268,8 +277,9 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
         }
     };
 
-    // plan 0: the wave's (BM/2) x (BM/2) quadrant; plans 1-4: wave plan - 1
-    // of a diagonal tile of a symmetric product (BM = 128, see diag_block)
+    // plan 0: the wave's WM x WN patch; plans 1..NW: wave plan - 1 of a
+    // diagonal tile of a symmetric product (BM = 128, see diag_block)
+    constexpr int PER = 48 / NW;
     double *P = partials + (int64_t)split * m * m;
     auto run = [&](auto plan) {
         constexpr int PL = decltype(plan)::value;
@@ -287,27 +297,27 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
             for (int kk = 0; kk < KT; kk += 4) {
                 const int kr = kk + (lane >> 4);
                 if constexpr (PL == 0) {
-                    TM fa[NB], fb[NB];
+                    TM fa[NBR], fb[NBC];
 #pragma unroll
-                    for (int a = 0; a < NB; ++a) fa[a] = As[buf][kr][wi * WM + a * 16 + (lane & 15)];
+                    for (int a = 0; a < NBR; ++a) fa[a] = As[buf][kr][wi * WM + a * 16 + (lane & 15)];
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) fb[b] = Bs[buf][kr][wj * WM + b * 16 + (lane & 15)];
+                    for (int b = 0; b < NBC; ++b) fb[b] = Bs[buf][kr][wj * WN + b * 16 + (lane & 15)];
 #pragma unroll
-                    for (int a = 0; a < NB; ++a)
+                    for (int a = 0; a < NBR; ++a)
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) acc[a][b] = Mfma<TM>::op(fa[a], fb[b], acc[a][b]);
+                        for (int b = 0; b < NBC; ++b) acc[a][b] = Mfma<TM>::op(fa[a], fb[b], acc[a][b]);
                 } else {
                     TM fa[8], fb[8];
 #pragma unroll
                     for (int a = 0; a < 8; ++a)
-                        if ((diag_rows(DW) >> a) & 1u) fa[a] = As[buf][kr][a * 16 + (lane & 15)];
+                        if ((diag_rows(NW, DW) >> a) & 1u) fa[a] = As[buf][kr][a * 16 + (lane & 15)];
 #pragma unroll
                     for (int b = 0; b < 8; ++b)
-                        if ((diag_cols(DW) >> b) & 1u) fb[b] = Bs[buf][kr][b * 16 + (lane & 15)];
+                        if ((diag_cols(NW, DW) >> b) & 1u) fb[b] = Bs[buf][kr][b * 16 + (lane & 15)];
 #pragma unroll
-                    for (int k = 0; k < 12; ++k)
-                        acc[k / 4][k % 4] = Mfma<TM>::op(fa[diag_block(DW, k) / 8], fb[diag_block(DW, k) % 8],
-                                                         acc[k / 4][k % 4]);
+                    for (int k = 0; k < PER; ++k)
+                        acc[k / NBC][k % NBC] = Mfma<TM>::op(fa[diag_block(NW, DW, k) / 8],
+                                                             fb[diag_block(NW, DW, k) % 8], acc[k / NBC][k % NBC]);
                 }
             }
             if (more) store(buf ^ 1);
@@ -315,12 +325,12 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
             buf ^= 1;
         }
 #pragma unroll
-        for (int a = 0; a < NB; ++a)
+        for (int a = 0; a < NBR; ++a)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if (PL != 0 && a * NB + b >= 12) continue;
-                const int bi = PL == 0 ? wi * NB + a : diag_block(DW, a * NB + b) / 8;
-                const int bj = PL == 0 ? wj * NB + b : diag_block(DW, a * NB + b) % 8;
+            for (int b = 0; b < NBC; ++b) {
+                if (PL != 0 && a * NBC + b >= PER) continue;
+                const int bi = PL == 0 ? wi * NBR + a : diag_block(NW, DW, a * NBC + b) / 8;
+                const int bj = PL == 0 ? wj * NBC + b : diag_block(NW, DW, a * NBC + b) % 8;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + bi * 16 + Mfma<TM>::row(lane, r);
@@ -331,10 +341,16 @@ __global__ __launch_bounds__(kThreads, 2) void gram_kernel(
     };
     if constexpr (BM == 128) {
         if (symmetric && same) {
-            if (wave == 0) run(IntC<1>{});
-            else if (wave == 1) run(IntC<2>{});
-            else if (wave == 2) run(IntC<3>{});
-            else run(IntC<4>{});
+            switch (wave) {
+            case 0: run(IntC<1>{}); break;
+            case 1: run(IntC<2>{}); break;
+            case 2: run(IntC<3>{}); break;
+            case 3: run(IntC<4>{}); break;
+            case 4: if constexpr (NW > 4) run(IntC<5>{}); break;
+            case 5: if constexpr (NW > 4) run(IntC<6>{}); break;
+            case 6: if constexpr (NW > 4) run(IntC<7>{}); break;
+            default: if constexpr (NW > 4) run(IntC<8>{}); break;
+            }
             return;
         }
     }
@@ -1019,7 +1035,8 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
     const int grid = ntiles * nsplit;   // multiple of 8
 #define TM_GRAM(BMV, SH)                                                            \
-    hipLaunchKernelGGL((gram_kernel<TA, TM, BMV, SH>), dim3(grid), dim3(kThreads), 0, s, \
+    hipLaunchKernelGGL((gram_kernel<TA, TM, BMV, SH, false, TA, gram_threads<TA, TM, SH, false, TA>()>), \
+                       dim3(grid), dim3(gram_threads<TA, TM, SH, false, TA>()), 0, s,         \
                        n, m, ld, A, B, h, T, ntiles, symmetric, rows, partials, GramUpd<TA, TA>{}, \
                        xshift)
     if (BM == 128) {
@@ -1058,10 +1075,12 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
     up.st = st;
     up.Cn = Cn;
     if (BM == 128)
-        hipLaunchKernelGGL((gram_kernel<TA, TM, 128, false, true, TP>), dim3(grid), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL((gram_kernel<TA, TM, 128, false, true, TP, gram_threads<TA, TM, false, true, TP>()>),
+                           dim3(grid), dim3(gram_threads<TA, TM, false, true, TP>()), 0, s,
                            n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up, nullptr);
     else
-        hipLaunchKernelGGL((gram_kernel<TA, TM, 64, false, true, TP>), dim3(grid), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL((gram_kernel<TA, TM, 64, false, true, TP, gram_threads<TA, TM, false, true, TP>()>),
+                           dim3(grid), dim3(gram_threads<TA, TM, false, true, TP>()), 0, s,
                            n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up, nullptr);
     TM_HIP(hipGetLastError());
     const int64_t total = (int64_t)m * m;

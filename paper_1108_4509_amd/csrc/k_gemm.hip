@@ -945,6 +945,32 @@ __global__ __launch_bounds__(kTriWaves * 64) void trmm_lds_kernel(
         const int64_t row0 = st * 16;
         const TA *Ar = a_row(st);
         const TA *An = a_row(st + 1 < my1 ? st + 1 : st);
+        // out = C D + C R': this lane holds rows row0 + 4 g + r of column
+        // 16 jb + j.  Column block jb is complete after k block jb (R' is
+        // upper triangular), so it is written right then, while the C it
+        // re-reads for the FP64 term C D was just loaded by this wave.  A
+        // full strip needs no row mask; the last, partial one clamps its
+        // loads to row n - 1 and masks its stores.
+        auto strip = [&](auto fullc) {
+        constexpr bool FULL = decltype(fullc)::value != 0;
+        int64_t rowc[4];
+        bool ok[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = row0 + 4 * g + r;
+            ok[r] = FULL || row < n;
+            rowc[r] = ok[r] ? row : n - 1;
+        }
+        auto finish = [&](int jb, const Acc &c) {
+            const int col = jb * 16 + j;
+            const TA dc = (TA)d[col];
+            TA av[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) av[r] = A[rowc[r] * ld + col];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (FULL || ok[r]) out[rowc[r] * ld + col] = av[r] * dc + (TA)c[r];
+        };
         Acc acc[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[c] = Acc{0, 0, 0, 0};
@@ -955,49 +981,36 @@ __global__ __launch_bounds__(kTriWaves * 64) void trmm_lds_kernel(
             an.fetch(kb + 1 < NB ? Ar + (kb + 1) * 16 : An);
             // the prefetch is issued before this block's work, not sunk into it
             __builtin_amdgcn_sched_barrier(0);
-            float bw[NB][4];
+            // column blocks in two halves: only half of R's operands live
 #pragma unroll
-            for (int jb = kb; jb < NB; ++jb) {
-                const vf4 x = *reinterpret_cast<const vf4 *>(Wl + tri_index(NB, kb, jb) * kTriBlock +
-                                                             g * kTriStride + 4 * j);
-                bw[jb][0] = x[0]; bw[jb][1] = x[1]; bw[jb][2] = x[2]; bw[jb][3] = x[3];
+            for (int h = 0; h < 2; ++h) {
+                constexpr int HB = NB / 2;
+                float bw[HB][4];
+#pragma unroll
+                for (int q = 0; q < HB; ++q) {
+                    const int jb = h * HB + q;
+                    if (jb < kb) continue;
+                    const vf4 x = *reinterpret_cast<const vf4 *>(Wl + tri_index(NB, kb, jb) * kTriBlock +
+                                                                 g * kTriStride + 4 * j);
+                    bw[q][0] = x[0]; bw[q][1] = x[1]; bw[q][2] = x[2]; bw[q][3] = x[3];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int q = 0; q < HB; ++q) {
+                        const int jb = h * HB + q;
+                        if (jb >= kb) acc[jb] = Mfma<float>::op(a[e], bw[q][e], acc[jb]);
+                    }
             }
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int jb = kb; jb < NB; ++jb) acc[jb] = Mfma<float>::op(a[e], bw[jb][e], acc[jb]);
+            finish(kb, acc[kb]);
             // one scheduling region per k block: the LDS reads of a block
             // interleave with its own matrix-core work and are not hoisted
             // across blocks (which would exceed the register budget)
             __builtin_amdgcn_sched_barrier(0);
         }
-
-        // out = C D + C R': this lane holds rows row0 + 4 g + r of column
-        // 16 jb + j.  A full strip needs no row mask; the last, partial one
-        // clamps its loads to row n - 1 and masks its stores.
-        auto epilogue = [&](auto fullc) {
-            constexpr bool FULL = decltype(fullc)::value != 0;
-            int64_t rowc[4];
-            bool ok[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + 4 * g + r;
-                ok[r] = FULL || row < n;
-                rowc[r] = ok[r] ? row : n - 1;
-            }
-#pragma unroll
-            for (int jb = 0; jb < NB; ++jb) {
-                const int col = jb * 16 + j;
-                TA av[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) av[r] = A[rowc[r] * ld + col];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (FULL || ok[r]) out[rowc[r] * ld + col] = av[r] * (TA)d[col] + (TA)acc[jb][r];
-            }
         };
-        if (row0 + 16 <= n) epilogue(IntC<1>{});
-        else epilogue(IntC<0>{});
+        if (row0 + 16 <= n) strip(IntC<1>{});
+        else strip(IntC<0>{});
     }
 }
 

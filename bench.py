@@ -130,9 +130,9 @@ def kernel_rooflines(tm, ctx, H, p, reps=20):
 TRAFFIC_CONFIG = "c2"
 TRAFFIC = {
     "rot_grad_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                         "d812bfbaac4e054706bc864dc18935383a4ed3a9", 2.0 * 442342.1 * 1024 + 117504.0 * 1024),
+                         "4ad5b16f05d854432ee2869f3725fa32b1862fbe", 2.0 * 282789.1 * 1024 + 124416.0 * 1024),
     "gram_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                     "d812bfbaac4e054706bc864dc18935383a4ed3a9", 2.0 * 222702.4 * 1024 + 65536.0 * 1024),
+                     "4ad5b16f05d854432ee2869f3725fa32b1862fbe", 2.0 * 326245.1 * 1024 + 164352.0 * 1024),
 }
 
 

@@ -81,7 +81,8 @@ __device__ __attribute__((always_inline)) double diag_inv_wave(int lane, double 
 }
 
 // S = L L^T (L lower; S = R^T R with R = L^T) and Rinv = R^{-1} = L^{-T},
-// right-looking over kBlk-wide block columns, each in three launches:
+// right-looking over kBlk-wide block columns, each in three steps (K3 of a
+// block column shares its launch with K1 of the next one):
 //   K1 (one workgroup): the diagonal block S_kk = L_kk L_kk^T is factored and
 //      inverted in LDS (X_kk = L_kk^{-1}), over 16-wide sub-panels, carrying
 //      the same block forward substitution L X = I inside the block;
@@ -100,9 +101,13 @@ constexpr int kSub = 16;           // sub-panel inside K1
 constexpr int kBlkThreads = 256;   // 4 waves per workgroup
 constexpr int kAS = kBlk + 1;      // LDS row stride of the K1 block
 
-__global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
+// K1 body.  upd: the trailing update of the previous block column is still
+// to be applied to this diagonal block (it runs beside that update's launch,
+// which skips these tiles): the block is read from where that update would
+// read it and the update is formed here, in the same order and precision.
+__device__ __attribute__((always_inline)) void chol_block_body(
     int m, int kb, const double *__restrict__ S, const double *__restrict__ L,
-    double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info) {
+    double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info, bool upd) {
     constexpr int NB = kSub, nwaves = kBlkThreads / 64;
     __shared__ double A[kBlk * kAS];   // the block; the sub-panel columns become L
     __shared__ double W[kBlk * kAS];   // W, then X_kk (lower, zero above)
@@ -111,27 +116,57 @@ __global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
     __shared__ int ok_flag;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nb = (m - kb < kBlk) ? (m - kb) : kBlk;
-    const double *src = (kb == 0) ? S : L;
+    const int kp = upd ? kb - kBlk : kb;   // the block column last applied to the source
+    const double *src = (kp == 0) ? S : L;
     {
         // lower triangle of the block; identity beyond nb (pivots 1)
+        // (with upd, the previous block column's panel rows of this block,
+        // L_kp, are loaded into W in the same round trip)
         constexpr int U = kBlk * kBlk / kBlkThreads;
-        double v[U];
+        double v[U], lp[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = tid + u * kBlkThreads, i = e / kBlk, c = e % kBlk;
             v[u] = (i == c) ? 1.0 : 0.0;
             if (i < nb && c <= i) v[u] = src[(size_t)(kb + i) * m + kb + c];
+            lp[u] = (upd && i < nb) ? L[(size_t)(kb + i) * m + kp + c] : 0.0;
         }
         const double sd = (tid < nb) ? S[(size_t)(kb + tid) * m + kb + tid] : 1.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = tid + u * kBlkThreads, i = e / kBlk, c = e % kBlk;
             A[i * kAS + c] = v[u];
-            W[i * kAS + c] = 0.0;
+            W[i * kAS + c] = lp[u];
         }
         if (tid < kBlk) Sd[tid] = sd;
     }
     __syncthreads();
+    if (upd) {
+        // A_ij -= L_ip L_jp^T over the previous block column p = kb - kBlk,
+        // one wave per lower 16 x 16 tile (the products and their order are
+        // those of the trailing kernel)
+        constexpr int KS = kBlk / 4;
+        const int nt = (nb + 15) / 16;
+        for (int t = wave; t < nt * (nt + 1) / 2; t += nwaves) {
+            int bi, bj;
+            lower_pair(t, bi, bj);
+            const int ia = bi * 16 + (lane & 15), ja = bj * 16 + (lane & 15);
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int u = 0; u < KS; ++u) {
+                const int tk = 4 * u + (lane >> 4);
+                acc = mfma64(W[ia * kAS + tk], W[ja * kAS + tk], acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = bi * 16 + mfma64_row(lane, r), j = bj * 16 + (lane & 15);
+                if (i < nb && j <= i) A[i * kAS + j] -= acc[r];
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < kBlk * kAS; e += kBlkThreads) W[e] = 0.0;
+        __syncthreads();
+    }
     const int np = (nb + NB - 1) / NB;
     for (int p = 0; p < np; ++p) {
         const int q = p * NB;
@@ -230,6 +265,12 @@ __global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
     }
 }
 
+__global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
+    int m, int kb, const double *__restrict__ S, const double *__restrict__ L,
+    double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info) {
+    chol_block_body(m, kb, S, L, X, Rinv, info, false);
+}
+
 // K2: workgroups [0, nA) form the panel L_ik = S_ik X_kk^T, 16 rows each (one
 // 16-column tile per wave); workgroups [nA, nA + kb/16) finish a 16-column
 // strip of the block row of X, X_kj = X_kk W_kj (the strip is staged in LDS
@@ -299,12 +340,14 @@ __global__ __launch_bounds__(kBlkThreads) void chol_panel_kernel(
 // K3: one wave per 16 x 16 tile below the block column: the lower tiles of
 // the trailing matrix (lower_pair order), then the W tiles left of the
 // trailing matrix.  A tile is read and written by its own wave only.
-__global__ __launch_bounds__(kBlkThreads) void chol_trail_kernel(
+// skip: the first skip lower tiles (those of the next diagonal block, which
+// its own K1 updates) are left out.
+__device__ __attribute__((always_inline)) void chol_trail_body(
     int m, int kb, const double *__restrict__ S, double *__restrict__ L,
-    double *__restrict__ X) {
+    double *__restrict__ X, int skip) {
     constexpr int KS = kBlk / 4;
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * (kBlkThreads / 64) + (threadIdx.x >> 6);
+    const int t = skip + blockIdx.x * (kBlkThreads / 64) + (threadIdx.x >> 6);
     const int k0 = kb + kBlk;   // first row below the block (the block is full)
     const int R = m - k0, nr = (R + 15) / 16, npairs = nr * (nr + 1) / 2;
     const int nc = k0 / 16;
@@ -358,6 +401,19 @@ __global__ __launch_bounds__(kBlkThreads) void chol_trail_kernel(
     }
 }
 
+// K3 of block column kb beside K1 of block column kb + kBlk: the last
+// workgroup factors the next diagonal block (applying its share of this
+// update itself), the others update the rest of the trailing matrix and W.
+__global__ __launch_bounds__(kBlkThreads) void chol_trail_block_kernel(
+    int m, int kb, const double *__restrict__ S, double *__restrict__ L,
+    double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info, int skip) {
+    if (blockIdx.x == gridDim.x - 1) {
+        chol_block_body(m, kb + kBlk, S, L, X, Rinv, info, true);
+        return;
+    }
+    chol_trail_body(m, kb, S, L, X, skip);
+}
+
 __global__ void assemble_kernel(int m, const double *__restrict__ Hp,
                                 const double *__restrict__ h, double *__restrict__ A) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -378,19 +434,22 @@ void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
                   double *work, int32_t *info) {
     TM_REQUIRE(m >= 1 && m <= 1024, TM_ENOTSUP, "Cholesky supports m <= 1024");
     double *L = work, *X = work + (size_t)m * m;
+    // K1 of block column 0; then per block column K2 and, while rows remain,
+    // K3 together with the next block column's K1
+    hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(kBlkThreads), 0, s, m, 0, S, L, X, Rinv,
+                       info);
     for (int kb = 0; kb < m; kb += kBlk) {
         const int nb = std::min(kBlk, m - kb), R = m - kb - nb;
-        hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(kBlkThreads), 0, s, m, kb, S, L, X,
-                           Rinv, info);
         const int nA = (R + 15) / 16, nB = kb / 16;
         if (nA + nB > 0)
             hipLaunchKernelGGL(chol_panel_kernel, dim3(nA + nB), dim3(kBlkThreads), 0, s, m, kb,
                                S, L, X, Rinv);
         if (R > 0) {
             const int nr = (R + 15) / 16, tiles = nr * (nr + 1) / 2 + nr * ((kb + kBlk) / 16);
+            const int nt = (std::min(kBlk, R) + 15) / 16, skip = nt * (nt + 1) / 2;
             const int per = kBlkThreads / 64;
-            hipLaunchKernelGGL(chol_trail_kernel, dim3((tiles + per - 1) / per), dim3(kBlkThreads),
-                               0, s, m, kb, S, L, X);
+            hipLaunchKernelGGL(chol_trail_block_kernel, dim3((tiles - skip + per - 1) / per + 1),
+                               dim3(kBlkThreads), 0, s, m, kb, S, L, X, Rinv, info, skip);
         }
         TM_HIP(hipGetLastError());
     }

@@ -335,7 +335,7 @@ def test_orthonormalize(ctx, tm, orc, n, m, precision):
             assert np.all(np.abs(got - ref) <= bound)
 
 
-@pytest.mark.parametrize("m", [1, 2, 5, 16, 17, 33, 100, 256, 300, 520, 1000])
+@pytest.mark.parametrize("m", [1, 2, 5, 16, 17, 33, 65, 100, 130, 256, 300, 520, 1000])
 def test_cholesky_inverse(ctx, tm, orc, m):
     import torch
     print_case(test="cholesky_inverse", m=m)

@@ -451,6 +451,58 @@ def test_c2_gram_sampled(ctx, tm, c2):
             assert abs(G[i, j] - ref) <= bound
 
 
+def test_c4_full_size_sampled(ctx, tm, orc):
+    """The 100^3 workload at full size (N = 10^6, m = 1024, FP32 blocks, the
+    shapes and launch configurations its solve uses): sampled rows of H C and
+    sampled entries of S = C^T C (upper tiles, mirrored) and of the shifted
+    Gram C^T (B - C diag h), each against the oracle's own sum over the
+    FP32-rounded operands.  The second operand B is the start block with its
+    rows rolled (a seeded permutation of the same synthetic input)."""
+    import torch
+    p = config_problem("c4")
+    print_case(test="c4_full_size_sampled", N=p.N, m=p.m)
+    m, n = p.m, p.N
+    C = p.C0()
+    rng = np.random.default_rng(44)
+    h = rng.standard_normal(m)
+    Cd = tm.to_block(C, dtype=torch.float32)
+    B = np.roll(C, 12345, axis=0)
+    Bd = tm.to_block(B, dtype=torch.float32)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    # H C on sampled rows
+    H = orc.csr_matrix(*p.csr(), n)
+    Hd = tm.matrix_from_problem(ctx, p)
+    Xd = torch.full_like(Cd, np.nan)
+    tm.spmm(ctx, Hd, m, Cd, Xd)
+    rows = rng.choice(n, 1000, replace=False)
+    nnz_row = int(np.max(np.diff(p.csr()[0])))
+    cols_needed = np.unique(H[rows].indices)
+    Cr = f32(C[cols_needed])
+    Hsub = H[rows][:, cols_needed]
+    ref = np.asarray(Hsub @ Cr)
+    absref = np.asarray(abs(Hsub) @ np.abs(Cr))
+    got = Xd[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= 2 * gamma(nnz_row + 1, U32) * absref)
+    del Xd
+    # S = C^T C and H' = C^T (B - C diag h) on sampled entries
+    S = host(tm.gram(ctx, m, Cd, Cd))
+    Hp = host(tm.gram(ctx, m, Cd, Bd, h=torch.from_numpy(h).cuda()))
+    pairs = rng.integers(0, m, size=(48, 2))
+    pairs[:8, 1] = pairs[:8, 0]           # diagonal entries
+    pairs[8:16, 1] = pairs[8:16, 0] + 1   # next to the diagonal (the mirror seam)
+    pairs = np.clip(pairs, 0, m - 1)
+    for i, j in pairs:
+        ci, cj, bj = f32(C[:, i]), f32(C[:, j]), f32(B[:, j])
+        ref = float(ci @ cj)
+        assert abs(S[i, j] - ref) <= 2 * gamma(n, U32) * float(np.abs(ci) @ np.abs(cj))
+        if i // 64 != j // 64:
+            assert S[i, j] == S[j, i]   # mirrored across 64-column blocks
+        bs = bj - cj * h[j]
+        ref = float(ci @ bs)
+        bound = 2 * gamma(n + 2, U32) * float(np.abs(ci) @ (np.abs(bj) + np.abs(cj) * abs(h[j])))
+        assert abs(Hp[i, j] - ref) <= bound
+
+
 # Large blocks (65536+ rows, 128 to 1024 columns): ragged row counts, both
 # stencil orders, one to eight vectors per lane in the wave-per-row kernels,
 # and the fused column dots.

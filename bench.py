@@ -182,6 +182,101 @@ def serving_bench(tm, n_requests, slots=4, budget=32 << 30):
             "hbm_peak_GiB": round(st["hbm_peak"] / 2**30, 3)}
 
 
+def eq16_lowest(n, m):
+    """The m lowest eigenvalues of the paper's H_N (Eq. 16): 4 (sin^2(p pi /
+    2(n+1)) + sin^2(q pi / 2(n+1))), p, q = 1..n, ascending."""
+    import numpy as np
+    s = 4.0 * np.sin(np.arange(1, n + 1) * np.pi / (2 * (n + 1))) ** 2
+    return np.sort((s[:, None] + s[None, :]).reshape(-1))[:m]
+
+
+TABLE1_POLICIES = ("full_dp", "mp1", "mp2", "full_sp")
+
+
+def table1_bench(tm, ctx, rows=None, timed_iters=60, stencil=True):
+    """Table 1 on this GPU: for each (N, m) row of the paper's 2-D Dirichlet
+    H_N, seconds per iteration under full DP, MP1, MP2 and full SP (the
+    iterations of a capped run, setup and final Rayleigh-Ritz excluded), and
+    the iterations FULL_DP and MP1 need to reach R = (E_i - E_G) / E_G <
+    1e-12 (Eq. 17) with E_G from Eq. 16, next to the paper's numbers."""
+    import numpy as np
+    import torch
+    from workloads import config_problem
+    with open(os.path.join(ROOT, "tests", "golden", "table1.json")) as f:
+        paper = {(r["n"], r["m"]): r for r in json.load(f)["rows"]}
+    out = []
+    for (n, m) in (rows or list(paper)):
+        p = config_problem(f"t1_{n}_{m}")
+        H = tm.matrix_from_problem(ctx, p, stencil=stencil)
+        C0 = tm.to_block(p.C0())
+        exact = float(np.sum(eq16_lowest(n, m)))
+        row = {"N": p.N, "n": n, "m": m, "E_G_eq16": exact, "s_per_iter": {}, "vs_full_dp": {},
+               "N_iter_R_1e-12": {}, "rel_err": {}, "paper": paper.get((n, m))}
+        for prec in TABLE1_POLICIES:
+            # the first phase runs the policy alone; never stops early
+            o = tm.opts(precision=prec, max_iter=timed_iters, k_rot=0, switch_tol=1e-300,
+                        stall_tol=1e-300)
+            tm.solve(ctx, H, m, 1e-300, C0, o, want_vectors=False)          # warm-up
+            torch.cuda.synchronize()
+            r, _, _, _ = tm.solve(ctx, H, m, 1e-300, C0, o, want_vectors=False)
+            row["s_per_iter"][prec] = r["seconds_phase"][0] / max(r["iterations"], 1)
+        for prec in TABLE1_POLICIES:
+            row["vs_full_dp"][prec] = round(row["s_per_iter"][prec] / row["s_per_iter"]["full_dp"], 3)
+            row["s_per_iter"][prec] = round(row["s_per_iter"][prec], 6)
+        for prec, k_rot in (("full_dp", 0), ("full_dp", 50), ("mp1", 0), ("mixed", 50)):
+            r, _, _, hist = tm.solve(ctx, H, m, 1e-9, C0,
+                                     tm.opts(precision=prec, k_rot=k_rot, history=True, max_iter=6000),
+                                     history_len=6000, want_vectors=False)
+            R = (hist[:, 0] - exact) / exact
+            hit = np.nonzero(R < 1e-12)[0]
+            key = prec + (f"_rot{k_rot}" if k_rot else "")
+            row["N_iter_R_1e-12"][key] = int(hit[0]) if len(hit) else None
+            row["rel_err"][key] = abs(r["E_G"] - exact) / exact
+            row.setdefault("seconds_to_tol", {})[key] = round(r["seconds"], 4)
+        log(f"table1 {n}^2 m={m}: {row['s_per_iter']} N_iter {row['N_iter_R_1e-12']}")
+        out.append(row)
+        del H
+    return out
+
+
+ACCURACY_POLICIES = (("full_dp", 0), ("mp1", 0), ("mp2", 0), ("mp2", 50), ("mp2_mp1", 0),
+                     ("full_sp", 0), ("mixed", 50))
+
+
+def accuracy_bench(tm, ctx, row=(192, 534), iters=1200):
+    """The accuracy floor of each policy (the paper's Fig. 7 and the
+    discussion after Table 1): R_i = (E_i - E_G) / E_G per iteration on a
+    Table 1 matrix, E_G from Eq. 16; MP2 with and without the occasional
+    rotation, and MP2 -> MP1 switching."""
+    import numpy as np
+    from workloads import config_problem
+    n, m = row
+    p = config_problem(f"t1_{n}_{m}")
+    H = tm.matrix_from_problem(ctx, p, stencil=True)
+    C0 = tm.to_block(p.C0())
+    exact = float(np.sum(eq16_lowest(n, m)))
+    out = {"N": p.N, "m": m, "E_G_eq16": exact, "iterations": iters, "curves": {}}
+    for prec, k_rot in ACCURACY_POLICIES:
+        o = tm.opts(precision=prec, k_rot=k_rot, history=True, max_iter=iters, stall_tol=1e-300)
+        r, _, _, hist = tm.solve(ctx, H, m, 1e-300, C0, o, history_len=iters, want_vectors=False)
+        R = (hist[:, 0] - exact) / exact
+        key = f"{prec}" + (f"_rot{k_rot}" if k_rot else "")
+        first = {}
+        for thr in (1e-6, 1e-9, 1e-12, 1e-14):
+            hit = np.nonzero(np.abs(R) < thr)[0]
+            first[f"{thr:.0e}"] = int(hit[0]) if len(hit) else None
+        tail = np.abs(R[-100:]) if len(R) >= 100 else np.abs(R)
+        out["curves"][key] = {
+            "floor_median_last100": float(np.median(tail)),
+            "final_E_G_rel_err": abs(r["E_G"] - exact) / exact,
+            "first_iter_below": first, "iters_phase1": r["iters_sp"],
+            "R_every_100": [float(x) for x in R[::100]],
+            "seconds": round(r["seconds"], 3)}
+        log(f"accuracy {key}: floor {out['curves'][key]['floor_median_last100']:.2e} "
+            f"first {first} final {out['curves'][key]['final_E_G_rel_err']:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +294,12 @@ def main():
                     help="requests of the serving stream replayed after the solves (0: none)")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving stream (with --serving requests)")
+    ap.add_argument("--table1", action="store_true",
+                    help="only the paper's Table 1 on this GPU (s/iter per policy, N_iter)")
+    ap.add_argument("--table1-rows", default="",
+                    help="comma-separated n:m rows of --table1 (default: all five)")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="only the accuracy-floor study (R_i per policy on a Table 1 matrix)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel roofline timings and a copy of known size "
                          "(for hardware-counter runs)")
@@ -213,6 +314,17 @@ def main():
     import paper_1108_4509_amd as tm
     from workloads import config_problem
 
+    if a.table1 or a.accuracy:
+        ctx = tm.Context(0)
+        if a.table1:
+            rows = [tuple(int(x) for x in r.split(":")) for r in a.table1_rows.split(",") if r]
+            print(json.dumps({"metric": "Table 1 on MI355X: s/iter per precision policy and "
+                              "iterations to R < 1e-12", "rows": table1_bench(tm, ctx, rows or None)}),
+                  flush=True)
+        if a.accuracy:
+            print(json.dumps({"metric": "accuracy floor per precision policy (R_i = (E_i - E_G)/E_G)",
+                              "accuracy": accuracy_bench(tm, ctx)}), flush=True)
+        return
     p = config_problem(a.config)
     log(f"bench: config {a.config} N={p.N} m={p.m}")
     ctx = tm.Context(0)

@@ -69,14 +69,24 @@ typedef enum tm_dtype { TM_F64 = 0, TM_F32 = 1, TM_BF16X3 = 2 } tm_dtype;
  *               cores (two-term BF16 operands, FP32 accumulation); the MP2
  *               refinement restores FP64 accuracy.
  *   TM_FULL_BF16   the bulk phase of TM_MIXED_BF16 alone (no refinement):
- *               its accuracy floor, for error reports. */
+ *               its accuracy floor, for error reports.
+ *   TM_MP1      the paper's MP1: everything as TM_FULL_DP except (i) G and P
+ *               stored in FP32 (G formed in FP64, then rounded) and (ii)
+ *               C_out = C L_D + C L' with the second term on FP32 matrix
+ *               cores (Eq. 11-13); H' = C^T X' and C H' stay FP64.
+ *   TM_MP2_MP1  TM_MP2 until rho <= switch_tol (or its energy stalls), then
+ *               TM_MP1 to tol, with the CG state carried across the switch
+ *               (G and P are FP32 in both): the switch Sec. 3 and Sec. 5
+ *               recommend in place of rotations. */
 typedef enum tm_precision {
     TM_FULL_DP = 0,
     TM_FULL_SP = 1,
     TM_MP2 = 2,
     TM_MIXED = 3,
     TM_MIXED_BF16 = 4,
-    TM_FULL_BF16 = 5
+    TM_FULL_BF16 = 5,
+    TM_MP1 = 6,
+    TM_MP2_MP1 = 7
 } tm_precision;
 
 /* ---------------------------------------------------------------- objects */
@@ -111,7 +121,12 @@ typedef struct tm_opts {
     int32_t max_iter;      /* total CG iterations over all phases            */
     int32_t k_rot;         /* subspace rotation every k_rot iterations (0 = off) */
     int32_t k_check;       /* host polls the device convergence flag every k_check iterations */
-    int32_t precondition;  /* 1: diagonal M of Eq. 18, M_ii = 1/(H_ii - sigma) */
+    int32_t precondition;  /* 1: diagonal M of Eq. 18, M_ii = 1/(H_ii - sigma);
+                              2: polynomial M = p(H - sigma I) of cheb_degree
+                              Chebyshev-iteration steps for (H - sigma I) z = G
+                              on the Gershgorin interval, sigma = lo -
+                              cheb_shift (hi - lo), applied in the precision of
+                              G (FP32 in every policy but TM_FULL_DP) */
     int32_t history;       /* 1: record E_i and rho_i per iteration         */
     int32_t transport;     /* 1 (default): a subspace rotation C <- C U also maps
                               P <- P U and G_prev <- G_prev U and CG continues;
@@ -122,6 +137,12 @@ typedef struct tm_opts {
     double rise_tol;       /* restart CG when E rises by more than rise_tol*|E| */
     double stall_tol;      /* TM_MIXED*: also leave the bulk phase when E drops by less
                               than stall_tol*|E| over 25 iterations (<= 0: 1e-7) */
+    uint64_t seed;         /* tm_solve with C0 = NULL: the start block is
+                              tm_random_block(seed) (standard normal entries) */
+    int32_t cheb_degree;   /* precondition = 2: steps (>= 1; 3 by default)   */
+    int32_t reserved;      /* 0 */
+    double cheb_shift;     /* precondition = 2: sigma below the Gershgorin
+                              interval, as a fraction of its width (0.02)   */
 } tm_opts;
 
 typedef struct tm_result {
@@ -131,12 +152,19 @@ typedef struct tm_result {
     double frob_residual;  /* sqrt(sum_j ||H c_j - lambda_j c_j||^2), FP64  */
     double orth_err;       /* max |C^T C - I|, FP64                          */
     double seconds;        /* wall time of the solve (synchronous)           */
+    double seconds_phase[3];  /* wall time of [0] the first phase (the FP32/BF16
+                              bulk of TM_MIXED*, the MP2 part of TM_MP2_MP1,
+                              all iterations of a one-phase policy), [1] the
+                              second phase, [2] the start (upload, first
+                              orthonormalization) plus the final FP64
+                              Rayleigh-Ritz and residuals                    */
     int32_t iterations;    /* CG iterations taken (all phases)               */
-    int32_t iters_sp;      /* iterations in the FP32 phase (TM_MIXED/TM_FULL_SP) */
+    int32_t iters_sp;      /* iterations of the first phase (= iterations for a
+                              one-phase policy)                              */
     int32_t converged;     /* 1 if rho <= tol was reached                    */
     int32_t restarts;      /* CG restarts (gamma = 0), including i = 0       */
     int32_t rotations;     /* subspace rotations performed                   */
-    int32_t reserved;
+    int32_t iters_phase2;  /* iterations of the second phase (0 if none)    */
 } tm_result;
 
 /* ------------------------------------------------------------- lifecycle */
@@ -153,13 +181,20 @@ void tm_destroy(tm_ctx *ctx);
 const char *tm_status_string(int32_t status);
 const char *tm_last_error(void);
 
+/* Flags of tm_set_matrix_csr. */
+#define TM_CHECK_SYMMETRY 1u   /* verify H = H^T entry by entry (duplicates summed);
+                                  TM_EINVAL if not                              */
+#define TM_DEVICE_PTRS 2u      /* rowptr, col and val are device pointers       */
+
 /* H from CSR arrays (Sec. 2.1: real, symmetric, sparse with O(N) nonzeros).
- * rowptr (n+1, int64), col (nnz, int32) and val (nnz, FP64) are host arrays
- * that are copied to the device; the caller may free them afterwards.
- * Columns must lie in [0, n) and rowptr must be non-decreasing with
- * rowptr[0] = 0; symmetry is the caller's responsibility. */
+ * rowptr (n+1, int64), col (nnz, int32) and val (nnz, FP64) are copied by the
+ * library (host arrays unless flags has TM_DEVICE_PTRS); the caller may free
+ * them afterwards.  Columns must lie in [0, n), rowptr must be non-decreasing
+ * with rowptr[0] = 0 and values finite (TM_EINVAL otherwise).  Symmetry is
+ * checked when flags has TM_CHECK_SYMMETRY, else it is the caller's
+ * responsibility.  Unknown flag bits are TM_EINVAL. */
 tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr,
-                            const int32_t *col, const double *val,
+                            const int32_t *col, const double *val, uint32_t flags,
                             tm_mat **out);
 tm_status tm_set_matrix_stencil(tm_ctx *ctx, const tm_stencil *s,
                                 tm_mat **out);
@@ -170,9 +205,21 @@ int64_t tm_matrix_rows(const tm_mat *mat);
 
 void tm_opts_default(tm_opts *opts);
 
+/* Fill the device block out (n x ld FP64, ld = tm_leading_dim(m)) with
+ * standard normal entries in columns 0..m-1 and zeros in the padding: the
+ * random start block of Sec. 3 ("random numbers, then orthonormalization").
+ * Entry (r, j) is a pure function of (seed, r * m + j): Philox4x32-10
+ * (Salmon et al., SC'11) with key (seed low, seed high) on the counter
+ * (k, 0, 0, 0), k = (r * m + j) / 2, gives four 32-bit words; words 0-1 and
+ * 2-3 form two 53-bit uniforms u1 in (0, 1], u2 in [0, 1) and the Box-Muller
+ * pair sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) gives entries 2k and 2k + 1. */
+tm_status tm_random_block(tm_ctx *ctx, int64_t n, int32_t m, uint64_t seed, double *out);
+
 /* Trace minimization (Fig. 1) from the start block C0 (device, N x ld FP64,
- * need not be orthonormal; it is orthonormalized first by Fig. 4) until
+ * need not be orthonormal; it is orthonormalized first by Fig. 4; NULL: the
+ * block tm_random_block makes from opts->seed) until
  * rho = ||X - C A||_F <= tol, where X = HC and A = C^T X.  Synchronous.
+ * m may be up to 2048 (TM_ENOTSUP above).
  *   C_out     device N x ld FP64 or NULL: the Ritz vectors, ascending.
  *   eig_out   device m FP64 or NULL: the Ritz values lambda_1..lambda_m.
  *   history   host array of 2*history_len doubles or NULL: (E_i, rho_i)
@@ -182,6 +229,22 @@ tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol,
                    const tm_opts *opts, const double *C0, double *C_out,
                    double *eig_out, tm_result *res, double *history,
                    int32_t history_len);
+
+/* The generalized problem H x = lambda S x with S symmetric positive
+ * definite (Sec. 2.1: the extension the trace minimization allows for
+ * nonorthogonal basis functions): minimizes tr(C^T H C) subject to
+ * C^T S C = I.  Each iteration is Algorithm-2 in the S metric (Z = S C,
+ * X' = X - Z H_D, H' = C^T X', G = -2 (X' - Z H')), the Polak-Ribiere step,
+ * the line step with S-norms p_j^T S p_j, and Fig. 4 in the S inner product
+ * (C^T S C = R^T R, C <- C R^{-1}).  Arguments as tm_solve; S is a matrix of
+ * the same context and size (CSR or stencil; a diagonal entry <= 0 is
+ * TM_EINVAL, a Cholesky breakdown TM_ENOTSPD).  rho = ||X - Z A||_F; the
+ * residuals are ||H c_j - lambda_j S c_j|| and orth_err is max |C^T S C - I|.
+ * Runs in TM_FULL_DP (other precisions: TM_ENOTSUP). */
+tm_status tm_solve_generalized(tm_ctx *ctx, const tm_mat *H, const tm_mat *S, int32_t m,
+                               double tol, const tm_opts *opts, const double *C0,
+                               double *C_out, double *eig_out, tm_result *res,
+                               double *history, int32_t history_len);
 
 /* ---------------------------------------------------------------- serving
  * Continuous batching of independent solves on one GPU (for callers that
@@ -280,7 +343,8 @@ tm_status tm_rotate(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype,
  * Outputs: X (n x ld), G (n x ld), h (m), Hp (m x m), E (1 double); all
  * device.
  * precision TM_FULL_DP: all FP64.  TM_MP2: steps (6) and (7) on FP32
- * matrix cores (Sec. 2.2, MP2); G is still returned in FP64. */
+ * matrix cores (Sec. 2.2, MP2).  TM_MP1: FP64 products, G rounded to FP32
+ * (Sec. 2.2, MP1 (i)).  G is returned in FP64 in every case. */
 tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m,
                          int32_t precision, const double *C, double *X,
                          double *G, double *h, double *Hp, double *E);
@@ -293,15 +357,17 @@ tm_status tm_orthonormalize(tm_ctx *ctx, int64_t n, int32_t m,
                             int32_t precision, double *C);
 
 /* R^{-1} of the Cholesky factor S = R^T R, R upper triangular (Fig. 4,
- * steps (2)-(3)), for an m x m FP64 S.  Rinv is m x m, upper triangular with
+ * steps (2)-(3)), for an m x m FP64 S, 1 <= m <= 2048.  Rinv is m x m, upper triangular with
  * zeros below the diagonal.  Synchronous; TM_ENOTSPD if a pivot is not
  * positive. */
 tm_status tm_cholesky_inverse(tm_ctx *ctx, int32_t m, const double *S,
                               double *Rinv);
 
-/* Eigen-decomposition of a symmetric m x m FP64 A by parallel cyclic Jacobi
- * (the diagonalization of H in Eq. 9): w ascending (m), U (m x m, column j is
- * the eigenvector of w[j]).  A is not modified. */
+/* Eigen-decomposition of a symmetric m x m FP64 A (1 <= m <= 2048) by
+ * parallel block Jacobi (the diagonalization of H in Eq. 9): w ascending (m),
+ * U (m x m, column j is the eigenvector of w[j]).  A is not modified.
+ * TM_ENOCONV if the off-diagonal norm has not fallen below 1e-15 ||A||_F
+ * within the sweep cap (no result is returned then). */
 tm_status tm_sym_eig(tm_ctx *ctx, int32_t m, const double *A, double *U,
                      double *w);
 

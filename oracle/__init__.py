@@ -13,6 +13,9 @@ diagonalization of symmetric matrices in mixed precision", that it follows):
   orthonormalization (Fig. 4), the nonlinear-CG driver (Fig. 1, Eq. 8), the
   diagonal preconditioner (Eq. 18), the final Rayleigh-Ritz step (Eq. 9) and a
   brute-force dense eigensolve for tiny N.
+* the generalized problem H x = lambda S x with S symmetric positive definite
+  (Sec. 2.1): energy and gradient in the S metric, S-orthonormalization, and
+  the same driver with ``solve(..., S=S)``.
 * ``jacobi.c``  -- cyclic Jacobi eigensolver in plain C, built by ``build.py``.
 
 Parity pins: see ``tests/test_oracle_*.py``.  The only routine without an
@@ -30,9 +33,14 @@ from .tracemin import (  # noqa: F401
     jacobi_eigh,
     rayleigh_ritz,
     jacobi_preconditioner,
+    gershgorin_bounds,
+    chebyshev_preconditioner,
     line_step,
     solve,
     brute_force_lowest,
+    energy_gradient_generalized,
+    orthonormalize_generalized,
+    brute_force_generalized,
     OracleOptions,
     OracleResult,
 )

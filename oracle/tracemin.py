@@ -191,6 +191,45 @@ def rayleigh_ritz(H, C: np.ndarray):
     return C @ U, w
 
 
+# ------------------------------------------------ generalized H x = lambda S x
+
+def energy_gradient_generalized(H, S, C: np.ndarray):
+    """Energy and gradient for H x = lambda S x with S symmetric positive
+    definite (Sec. 2.1: the extension to a nonorthogonal basis).  E(C) =
+    tr(C^T H C) is minimized subject to C^T S C = I; its span-invariant form
+    tr((C^T S C)^{-1} C^T H C) has, at C^T S C = I, the gradient
+    2 (H C - S C A) with A = C^T H C.  Algorithm-1 with the metric S:
+    X = HC, Z = SC, A = C^T X (symmetrized), E = tr A, G = -2 (X - Z A).
+    Returns (E, G, X, A, Z)."""
+    X = spmm(H, C)
+    Z = spmm(S, C)
+    A = C.T @ X
+    A = 0.5 * (A + A.T)
+    E = float(np.trace(A))
+    G = -2.0 * (X - Z @ A)
+    return E, G, X, A, Z
+
+
+def orthonormalize_generalized(S, C: np.ndarray) -> np.ndarray:
+    """Fig. 4 in the S inner product: C^T S C = R^T R, C_out = C R^{-1}, so
+    that C_out^T S C_out = I."""
+    Sg = C.T @ spmm(S, C)
+    R = cholesky_upper(0.5 * (Sg + Sg.T))
+    return C @ upper_triangular_inverse(R)
+
+
+def brute_force_generalized(H_dense: np.ndarray, S_dense: np.ndarray, m: int):
+    """Brute force for tiny N: S = R^T R (the oracle's Cholesky), the standard
+    problem R^{-T} H R^{-1} y = lambda y by cyclic Jacobi.  Returns (E_G,
+    eigenvalues ascending, gap)."""
+    R = cholesky_upper(np.asarray(S_dense, dtype=np.float64))
+    W = upper_triangular_inverse(R)
+    Ht = W.T @ np.asarray(H_dense, dtype=np.float64) @ W
+    w, _, _ = jacobi_eigh(0.5 * (Ht + Ht.T))
+    gap = float(w[m] - w[m - 1]) if m < len(w) else float("nan")
+    return float(np.sum(w[:m])), w, gap
+
+
 def jacobi_preconditioner(H) -> np.ndarray:
     """Diagonal preconditioner M (Eq. 18): M_ii = 1 / (H_ii - sigma).
 
@@ -203,8 +242,54 @@ def jacobi_preconditioner(H) -> np.ndarray:
     return 1.0 / (d - sigma)
 
 
+def gershgorin_bounds(H) -> Tuple[float, float]:
+    """[lo, hi] containing the spectrum of the symmetric H (Gershgorin discs:
+    H_ii -+ sum_{j != i} |H_ij|)."""
+    H = H.tocsr()
+    d = np.asarray(H.diagonal(), dtype=np.float64)
+    off = np.asarray(abs(H).sum(axis=1)).ravel() - np.abs(d)
+    return float(np.min(d - off)), float(np.max(d + off))
+
+
+def chebyshev_preconditioner(H, degree: int = 4, shift: float = 0.02):
+    """A non-diagonal preconditioner for Eq. 18 (Sec. 4: more elaborate
+    preconditioners than a diagonal, evaluated in single precision): M =
+    p(H - sigma I), the result of ``degree`` steps of the Chebyshev iteration
+    (Chebyshev acceleration for a symmetric positive definite system) for
+    (H - sigma I) z = g from z = 0, on the interval [a, b] = [lo - sigma,
+    hi - sigma] given by the Gershgorin bounds, with sigma = lo - shift *
+    (hi - lo) below the spectrum.  Its residual polynomial is r(x) =
+    T_s((theta - x) / delta) / T_s(theta / delta), theta = (a + b) / 2,
+    delta = (b - a) / 2, |r| < 1 on [a, b], so p(x) = (1 - r(x)) / x > 0
+    there and M is symmetric positive definite.  Returns apply(G) -> M G
+    (FP64 here; the GPU applies it in FP32)."""
+    lo, hi = gershgorin_bounds(H)
+    sigma = lo - shift * (hi - lo)
+    a, b = lo - sigma, hi - sigma
+    theta, delta = 0.5 * (a + b), 0.5 * (b - a)
+    s1 = theta / delta
+
+    def apply(G: np.ndarray) -> np.ndarray:
+        r = G.copy()
+        d = r / theta
+        z = d.copy()
+        rho = 1.0 / s1
+        for _ in range(degree - 1):
+            r = r - (spmm(H, d) - sigma * d)
+            rho_new = 1.0 / (2.0 * s1 - rho)
+            d = (rho_new * rho) * d + (2.0 * rho_new / delta) * r
+            z = z + d
+            rho = rho_new
+        return z
+
+    apply.interval = (a, b)
+    apply.sigma = sigma
+    apply.degree = degree
+    return apply
+
+
 def line_step(P: np.ndarray, Y: np.ndarray, G: np.ndarray,
-              a_diag: np.ndarray) -> Tuple[float, dict]:
+              a_diag: np.ndarray, SP: Optional[np.ndarray] = None) -> Tuple[float, dict]:
     """Step length alpha along P (Fig. 1, the line minimization).
 
     The paper cites a line minimization without giving one.  Reading: minimize
@@ -215,9 +300,12 @@ def line_step(P: np.ndarray, Y: np.ndarray, G: np.ndarray,
     and A = C^T H C is diagonal.  alpha = tr(P^T G) / curvature, capped at
     1 / max_j ||p_j|| (no column turns by more than 45 degrees); the cap is
     also the step when the curvature is not positive.
+
+    Generalized problem (SP = S P given): the constraint is C^T S C = I, so
+    the norms above become S-norms, p_j^T S p_j (exact when C^T S P = 0).
     """
     pg = float(np.sum(P * G))
-    pp = np.einsum("ij,ij->j", P, P)
+    pp = np.einsum("ij,ij->j", P, P if SP is None else SP)
     py = np.einsum("ij,ij->j", P, Y)
     curv = 2.0 * float(np.sum(py - a_diag * pp))
     cap = 1.0 / np.sqrt(float(pp.max())) if pp.max() > 0 else 0.0
@@ -238,6 +326,8 @@ class OracleOptions:
     max_iter: int = 20000
     k_rot: int = 0              # subspace rotation every k_rot iterations (0: never)
     precondition: bool = False  # diagonal M of Eq. 18
+    chebyshev: int = 0          # > 0: the polynomial M of that degree (chebyshev_preconditioner)
+    cheb_shift: float = 0.02
     rise_tol: float = 1e-13     # restart CG when E rises by more than this * |E|
     transport: bool = True      # at a rotation C <- C U, also P <- P U, G_prev <- G_prev U
 
@@ -260,17 +350,32 @@ class OracleResult:
 
 
 def solve(H, C0: np.ndarray, opts: Optional[OracleOptions] = None,
-          callback=None) -> OracleResult:
+          callback=None, S=None) -> OracleResult:
     """Trace minimization by nonlinear CG (Fig. 1), all in FP64.
 
     for i = 0, 1, ...:  E_i, G_i = -grad E(C_i) (Fig. 2); stop if converged;
     P_i = Z_i + gamma_i P_{i-1} with Z = M G (Eq. 18, Z = G without M) and the
     Polak-Ribiere gamma of Eq. 8 (M-weighted when preconditioned); alpha_i
     from ``line_step``; C_{i+1} = orthonormalize(C_i + alpha_i P_i) (Fig. 4).
+    With S (sparse, symmetric positive definite) the problem is
+    H x = lambda S x: the energy, gradient, orthonormalization and line step
+    take the S inner product (``energy_gradient_generalized``).
     """
     o = opts or OracleOptions()
     M = jacobi_preconditioner(H) if o.precondition else None
-    C = orthonormalize(np.asarray(C0, dtype=np.float64))
+    Mpoly = chebyshev_preconditioner(H, o.chebyshev, o.cheb_shift) if o.chebyshev > 0 else None
+    gen = S is not None
+
+    def orth(B):
+        return orthonormalize_generalized(S, B) if gen else orthonormalize(B)
+
+    def energy_grad(B):
+        if gen:
+            E, G, X, A, _ = energy_gradient_generalized(H, S, B)
+            return E, G, X, A
+        return energy_gradient_alg1(H, B)
+
+    C = orth(np.asarray(C0, dtype=np.float64))
     energies, rhos, alphas, gammas = [], [], [], []
     G_prev = Z_prev = P_prev = None
     E_prev = None
@@ -289,7 +394,7 @@ def solve(H, C0: np.ndarray, opts: Optional[OracleOptions] = None,
                 P_prev, G_prev, Z_prev = P_prev @ U, G_prev @ U, Z_prev @ U
             else:
                 restart = True
-        E, G, X, A = energy_gradient_alg1(H, C)
+        E, G, X, A = energy_grad(C)
         rho = 0.5 * float(np.linalg.norm(G))
         energies.append(E)
         rhos.append(rho)
@@ -300,7 +405,10 @@ def solve(H, C0: np.ndarray, opts: Optional[OracleOptions] = None,
             break
         if E_prev is not None and E > E_prev + o.rise_tol * abs(E_prev):
             restart = True
-        Z = G * M[:, None] if M is not None else G
+        if Mpoly is not None:
+            Z = Mpoly(G)
+        else:
+            Z = G * M[:, None] if M is not None else G
         if restart:
             gamma = 0.0
         else:
@@ -312,19 +420,20 @@ def solve(H, C0: np.ndarray, opts: Optional[OracleOptions] = None,
         if gamma == 0.0:
             restarts += 1
         Y = spmm(H, P)
-        alpha, _ = line_step(P, Y, G, np.diag(A).copy())
+        alpha, _ = line_step(P, Y, G, np.diag(A).copy(), spmm(S, P) if gen else None)
         alphas.append(alpha)
         gammas.append(gamma)
-        C = orthonormalize(C + alpha * P)
+        C = orth(C + alpha * P)
         G_prev, Z_prev, P_prev, E_prev = G, Z, P, E
         restart = False
     iterations = it + 1 if not converged else it
     C, w = rayleigh_ritz(H, C)
     X = spmm(H, C)
-    R = X - C * w[None, :]
+    Zc = spmm(S, C) if gen else C
+    R = X - Zc * w[None, :]
     col_res = np.sqrt(np.einsum("ij,ij->j", R, R))
-    S = C.T @ C
-    orth = float(np.max(np.abs(S - np.eye(S.shape[0]))))
+    Sg = C.T @ Zc
+    orth = float(np.max(np.abs(Sg - np.eye(Sg.shape[0]))))
     return OracleResult(
         E_G=float(np.sum(w)), eigenvalues=w, C=C, iterations=iterations,
         converged=converged, energies=energies, residual_norms=rhos,

@@ -18,10 +18,13 @@ import numpy as np
 
 from . import _abi
 from ._abi import (TM_F32, TM_F64, TM_FULL_DP, TM_FULL_SP, TM_MIXED, TM_MP2,  # noqa: F401
-                   TM_ENOCONV, TM_ENOTSPD, TM_EINVAL, TM_OK, TraceminError)
+                   TM_MIXED_BF16, TM_FULL_BF16, TM_MP1, TM_MP2_MP1, TM_CHECK_SYMMETRY,
+                   TM_DEVICE_PTRS, TM_ENOCONV, TM_ENOTSPD, TM_EINVAL, TM_ENOTSUP, TM_OK,
+                   TraceminError)
 
 PRECISIONS = {"full_dp": TM_FULL_DP, "full_sp": TM_FULL_SP, "mp2": TM_MP2, "mixed": TM_MIXED,
-              "mixed_bf16": 4, "full_bf16": 5}
+              "mixed_bf16": TM_MIXED_BF16, "full_bf16": TM_FULL_BF16, "mp1": TM_MP1,
+              "mp2_mp1": TM_MP2_MP1}
 
 
 def _torch():
@@ -130,14 +133,29 @@ class Matrix:
             pass
 
 
-def set_matrix_csr(ctx: Context, rowptr, col, val) -> Matrix:
-    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
-    col = np.ascontiguousarray(col, dtype=np.int32)
-    val = np.ascontiguousarray(val, dtype=np.float64)
-    n = rowptr.shape[0] - 1
+def set_matrix_csr(ctx: Context, rowptr, col, val, check_symmetry: bool = False) -> Matrix:
+    """H from CSR arrays: numpy host arrays, or torch device tensors (then
+    passed as device pointers, TM_DEVICE_PTRS)."""
+    torch = _torch()
+    flags = TM_CHECK_SYMMETRY if check_symmetry else 0
+    if isinstance(rowptr, torch.Tensor):
+        if (rowptr.dtype, col.dtype, val.dtype) != (torch.int64, torch.int32, torch.float64):
+            raise ValueError("device CSR arrays must be int64, int32 and float64")
+        if not (rowptr.is_cuda and col.is_cuda and val.is_cuda):
+            raise ValueError("tensor CSR arrays must live on the device")
+        rowptr, col, val = rowptr.contiguous(), col.contiguous(), val.contiguous()
+        n = rowptr.shape[0] - 1
+        ptrs = (rowptr.data_ptr(), col.data_ptr(), val.data_ptr())
+        flags |= TM_DEVICE_PTRS
+    else:
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        n = rowptr.shape[0] - 1
+        ptrs = (rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
     h = ctypes.c_void_p()
-    _abi.check(_abi.lib().tm_set_matrix_csr(ctx.handle, n, rowptr.ctypes.data, col.ctypes.data,
-                                            val.ctypes.data, ctypes.byref(h)), "tm_set_matrix_csr")
+    _abi.check(_abi.lib().tm_set_matrix_csr(ctx.handle, n, *ptrs, flags, ctypes.byref(h)),
+               "tm_set_matrix_csr")
     return Matrix(ctx, h, n)
 
 
@@ -182,16 +200,30 @@ def to_block(C: np.ndarray, dtype=None, device=None):
     return out
 
 
+def random_block(ctx: Context, n: int, m: int, seed: int):
+    """The seeded standard normal N x ld start block (tm_random_block)."""
+    torch = _torch()
+    out = torch.empty((n, leading_dim(m)), dtype=torch.float64, device="cuda")
+    _abi.check(_abi.lib().tm_random_block(ctx.handle, n, m, int(seed), _ptr(out)), "tm_random_block")
+    return out
+
+
 def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition=False,
          history=False, switch_tol=0.0, rise_tol=1e-13, transport=None,
-         stall_tol=0.0, graphs=None) -> _abi.tm_opts:
+         stall_tol=0.0, graphs=None, seed=0, cheb_degree=None, cheb_shift=None) -> _abi.tm_opts:
+    """tm_opts; precondition: False, True / "diagonal" (Eq. 18 with the
+    diagonal M) or "chebyshev" (the polynomial M of cheb_degree steps)."""
     o = _abi.tm_opts()
     _abi.lib().tm_opts_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.max_iter = max_iter
     o.k_rot = k_rot
     o.k_check = k_check
-    o.precondition = 1 if precondition else 0
+    o.precondition = 2 if precondition == "chebyshev" else (1 if precondition else 0)
+    if cheb_degree is not None:
+        o.cheb_degree = int(cheb_degree)
+    if cheb_shift is not None:
+        o.cheb_shift = float(cheb_shift)
     o.history = 1 if history else 0
     o.switch_tol = switch_tol
     o.rise_tol = rise_tol
@@ -200,27 +232,38 @@ def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition
         o.graphs = 1 if graphs else 0
     if transport is not None:
         o.transport = 1 if transport else 0
+    o.seed = int(seed)
     return o
 
 
 def solve(ctx: Context, H: Matrix, m: int, tol: float, C0, options=None, history_len: int = 0,
-          want_vectors: bool = True, allow_noconv: bool = True):
-    """Run tm_solve.  C0: N x ld FP64 device tensor (see ``to_block``).
+          want_vectors: bool = True, allow_noconv: bool = True, S: Optional[Matrix] = None):
+    """Run tm_solve.  C0: N x ld FP64 device tensor (see ``to_block``), or
+    None for the seeded start block of ``options.seed``.
 
     Returns (result dict, C tensor or None, eigenvalue tensor, history array or None).
     """
     torch = _torch()
-    N, ld = C0.shape
-    if C0.dtype != torch.float64 or not C0.is_contiguous():
-        raise ValueError("C0 must be a contiguous FP64 device tensor")
+    if C0 is not None:
+        N, ld = C0.shape
+        if C0.dtype != torch.float64 or not C0.is_contiguous():
+            raise ValueError("C0 must be a contiguous FP64 device tensor")
+    else:
+        N, ld = H.n, leading_dim(m)
     o = options or opts()
-    Cout = torch.empty_like(C0) if want_vectors else None
-    eig = torch.empty(max(m, 1), dtype=torch.float64, device=C0.device)
+    Cout = (torch.empty((N, ld), dtype=torch.float64, device="cuda") if want_vectors else None)
+    eig = torch.empty(max(m, 1), dtype=torch.float64, device="cuda")
     hist = np.zeros(2 * history_len) if history_len > 0 else None
     res = _abi.tm_result()
-    st = _abi.lib().tm_solve(ctx.handle, H.handle, m, tol, ctypes.byref(o), _ptr(C0), _ptr(Cout),
-                             _ptr(eig), ctypes.byref(res),
-                             hist.ctypes.data if hist is not None else None, history_len)
+    hp = hist.ctypes.data if hist is not None else None
+    if S is None:
+        st = _abi.lib().tm_solve(ctx.handle, H.handle, m, tol, ctypes.byref(o), _ptr(C0), _ptr(Cout),
+                                 _ptr(eig), ctypes.byref(res), hp, history_len)
+    else:
+        # H x = lambda S x (tm_solve_generalized)
+        st = _abi.lib().tm_solve_generalized(ctx.handle, H.handle, S.handle, m, tol, ctypes.byref(o),
+                                             _ptr(C0), _ptr(Cout), _ptr(eig), ctypes.byref(res), hp,
+                                             history_len)
     _abi.check(st, "tm_solve", allow=(TM_OK, TM_ENOCONV) if allow_noconv else (TM_OK,))
     r = res.as_dict()
     r["status"] = st

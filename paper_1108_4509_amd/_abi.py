@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libtracemin.so")
 TM_OK, TM_EINVAL, TM_ENOMEM, TM_ENOTSPD, TM_ENOCONV, TM_ENAN, TM_EDEVICE, TM_ENOTSUP, TM_EAGAIN = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 TM_F64, TM_F32 = 0, 1
-TM_FULL_DP, TM_FULL_SP, TM_MP2, TM_MIXED = 0, 1, 2, 3
+TM_FULL_DP, TM_FULL_SP, TM_MP2, TM_MIXED, TM_MIXED_BF16, TM_FULL_BF16, TM_MP1, TM_MP2_MP1 = range(8)
+TM_CHECK_SYMMETRY, TM_DEVICE_PTRS = 1, 2
 
 c_void_p = ctypes.c_void_p
 c_int32 = ctypes.c_int32
@@ -41,17 +42,22 @@ class tm_opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_iter", c_int32), ("k_rot", c_int32),
                 ("k_check", c_int32), ("precondition", c_int32), ("history", c_int32),
                 ("transport", c_int32), ("graphs", c_int32),
-                ("switch_tol", c_double), ("rise_tol", c_double), ("stall_tol", c_double)]
+                ("switch_tol", c_double), ("rise_tol", c_double), ("stall_tol", c_double),
+                ("seed", ctypes.c_uint64), ("cheb_degree", c_int32), ("reserved", c_int32),
+                ("cheb_shift", c_double)]
 
 
 class tm_result(ctypes.Structure):
     _fields_ = [("E_G", c_double), ("rho", c_double), ("max_residual", c_double),
                 ("frob_residual", c_double), ("orth_err", c_double), ("seconds", c_double),
+                ("seconds_phase", c_double * 3),
                 ("iterations", c_int32), ("iters_sp", c_int32), ("converged", c_int32),
-                ("restarts", c_int32), ("rotations", c_int32), ("reserved", c_int32)]
+                ("restarts", c_int32), ("rotations", c_int32), ("iters_phase2", c_int32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["seconds_phase"] = list(self.seconds_phase)
+        return d
 
 
 class tm_server_opts(ctypes.Structure):
@@ -84,7 +90,8 @@ SIGNATURES = {
     "tm_status_string": (ctypes.c_char_p, [c_int32]),
     "tm_last_error": (ctypes.c_char_p, []),
     "tm_set_matrix_csr": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
-                                    ctypes.POINTER(c_void_p)]),
+                                    ctypes.c_uint32, ctypes.POINTER(c_void_p)]),
+    "tm_random_block": (c_int32, [c_void_p, c_int64, c_int32, ctypes.c_uint64, c_void_p]),
     "tm_set_matrix_stencil": (c_int32, [c_void_p, ctypes.POINTER(tm_stencil),
                                         ctypes.POINTER(c_void_p)]),
     "tm_free_matrix": (None, [c_void_p]),
@@ -93,6 +100,9 @@ SIGNATURES = {
     "tm_solve": (c_int32, [c_void_p, c_void_p, c_int32, c_double, ctypes.POINTER(tm_opts),
                            c_void_p, c_void_p, c_void_p, ctypes.POINTER(tm_result),
                            c_void_p, c_int32]),
+    "tm_solve_generalized": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_double,
+                                       ctypes.POINTER(tm_opts), c_void_p, c_void_p, c_void_p,
+                                       ctypes.POINTER(tm_result), c_void_p, c_int32]),
     "tm_spmm": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "tm_gram": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
                           c_void_p]),

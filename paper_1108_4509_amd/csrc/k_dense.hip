@@ -2,7 +2,7 @@
 // triangular inverse of Fig. 4 (steps (2) and (3)), and the assembly of the
 // m x m H of Eq. 9 from the pieces of Algorithm-2.
 //
-// The factorization is O(m^3) with m <= 1024, so it is latency-bound: the
+// The factorization is O(m^3) with m <= 2048, so it is latency-bound: the
 // serial part (the 64-wide diagonal blocks) runs in LDS inside one workgroup,
 // the panel and trailing products of each block column spread over many
 // workgroups, with the matrices in a device workspace resident in L2.
@@ -432,7 +432,7 @@ size_t chol_workspace(int m) {
 
 void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
                   double *work, int32_t *info) {
-    TM_REQUIRE(m >= 1 && m <= 1024, TM_ENOTSUP, "Cholesky supports m <= 1024");
+    TM_REQUIRE(m >= 1 && m <= 2048, TM_ENOTSUP, "Cholesky supports m <= 2048");
     double *L = work, *X = work + (size_t)m * m;
     // K1 of block column 0; then per block column K2 and, while rows remain,
     // K3 together with the next block column's K1

@@ -573,17 +573,19 @@ __global__ __launch_bounds__(kThreads, 2) void gram_bf16x3_kernel(
 
 int gram_tile(int ld) { return ld >= 256 ? 128 : 64; }
 
-void gram_shape(int64_t n, int m, bool symmetric, int &BM, int &T, int &nsplit) {
+void gram_shape(int64_t n, int m, bool symmetric, int &BM, int &T, int &nsplit,
+                size_t ws_bytes = 0) {
     const int ld = leading_dim(m);
     BM = gram_tile(ld);
     T = (ld + BM - 1) / BM;
     // two workgroups per CU (512 over the 256 CUs, so that no CU runs more
-    // row chunks than another), at most 256 MiB of FP64 partials, and at
-    // least 128 rows per split; the grid (tiles x splits) is a multiple of 8
-    // for the XCD mapping
+    // row chunks than another), at most 256 MiB of FP64 partials (or the
+    // caller's workspace, ws_bytes), and at least 128 rows per split; the
+    // grid (tiles x splits) is a multiple of 8 for the XCD mapping
     const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
     int64_t ns = 512 / ntiles;
-    const int64_t cap_bytes = (int64_t)256 << 20;
+    int64_t cap_bytes = (int64_t)256 << 20;
+    if (ws_bytes > 0 && (int64_t)ws_bytes < cap_bytes) cap_bytes = (int64_t)ws_bytes;
     int64_t cap = cap_bytes / ((int64_t)m * m * 8);
     if (ns > cap) ns = cap;
     int64_t cap_rows = n / 128;
@@ -1029,6 +1031,12 @@ __global__ void pad_kernel(int m, int ld, const double *__restrict__ W,
 
 }  // namespace
 
+size_t gram_partials_bytes(int64_t n, int m, bool symmetric, size_t ws_bytes) {
+    int BM, T, ns;
+    gram_shape(n, m, symmetric, BM, T, ns, ws_bytes);
+    return (size_t)ns * m * m * sizeof(double);
+}
+
 size_t gram_workspace(int64_t n, int m) {
     int BM, T, ns_full, ns_sym;
     gram_shape(n, m, false, BM, T, ns_full);
@@ -1039,10 +1047,10 @@ size_t gram_workspace(int64_t n, int m) {
 template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
-          double *out, bool reduce, TM *xshift, TM *wpad) {
+          double *out, bool reduce, TM *xshift, TM *wpad, size_t ws_bytes) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
-    gram_shape(n, m, symmetric, BM, T, nsplit);
+    gram_shape(n, m, symmetric, BM, T, nsplit, ws_bytes);
     const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
     constexpr int KT = stage_rows<TM>();
     const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
@@ -1104,10 +1112,11 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
 
 template <typename TA>
 void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, const double *h,
-                 bool zero_diag, double *partials, double *out, bool reduce, float *wpad) {
+                 bool zero_diag, double *partials, double *out, bool reduce, float *wpad,
+                 size_t ws_bytes) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
-    gram_shape(n, m, false, BM, T, nsplit);
+    gram_shape(n, m, false, BM, T, nsplit, ws_bytes);
     const int ntiles = T * T;
     const int KT = 8 * (kThreads / (BM / 2));
     const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
@@ -1149,12 +1158,10 @@ int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
         }
     }
     const int B = ld >= 256 ? 128 : 64;
-    // row tile: 64 rows give about twice the workgroups (7 rounds of 512 at
-    // N = 110592 instead of 3.4, so less idle tail) and measured faster for
-    // every variant but the refinement gradient (FP64 C and X, FP32 G),
-    // whose larger epilogue keeps the 128-row tile
-    const bool mp2_grad = epi == EPI_GRAD && sizeof(TA) == 8 && sizeof(TO) == 4;
-    const int BR = (B == 128 && !mp2_grad) ? 64 : B;
+    // row tile: 64 rows give about twice the workgroups of 128 (7 rounds of
+    // 512 at N = 110592 instead of 3.4, so less idle tail); measured faster
+    // for every variant, the refinement gradient included
+    const int BR = 64;
     const int nrb = (int)((n + BR - 1) / BR);
     const int ncb = (ld + B - 1) / B;
     int grid = nrb * ncb;
@@ -1168,12 +1175,7 @@ int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
 #define TM_ROT(E, BRV, BCV)                                                                  \
     hipLaunchKernelGGL((rot_kernel<TA, TM, TO, E, BRV, BCV>), dim3(grid), dim3(kThreads),   \
                        0, s, n, m, ld, A, Wpad, X, vec, out, nrb, ncb, gd)
-    if (B == 128 && BR == 128) {
-        if (epi == EPI_NONE) TM_ROT(EPI_NONE, 128, 128);
-        else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 128, 128);
-        else if (epi == EPI_GRADX) TM_ROT(EPI_GRADX, 128, 128);
-        else TM_ROT(EPI_TRMM, 128, 128);
-    } else if (B == 128) {
+    if (B == 128) {
         if (epi == EPI_NONE) TM_ROT(EPI_NONE, 64, 128);
         else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 64, 128);
         else if (epi == EPI_GRADX) TM_ROT(EPI_GRADX, 64, 128);
@@ -1205,18 +1207,19 @@ void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
     TM_HIP(hipGetLastError());
 }
 
-template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, double *, double *);
-template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool, float *, float *);
-template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, float *, float *);
+template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, double *, double *, size_t);
+template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool, float *, float *, size_t);
+template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, float *, float *, size_t);
 template void gram_update<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *, double *, double *);
 template void gram_update<double, double, float>(hipStream_t, int64_t, int, const double *, const float *, const CgState *, double *, double *, double *);
 template void gram_update<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *, double *, double *);
-template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool, float *);
-template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool, float *);
+template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool, float *, size_t);
+template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool, float *, size_t);
 template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const double *);
 template int rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *, const float *, const float *, const double *, double *, const float *);
 template int rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *, const float *, const float *, const double *, double *, const float *);
 template int rot<double, float, double>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const float *);
+template int rot<double, double, float>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, float *, const float *, const float *, const double *, double *, const double *);
 template void pad_matrix<double>(hipStream_t, int, const double *, bool, double *, double *);
 template void pad_matrix<float>(hipStream_t, int, const double *, bool, float *, double *);
 

@@ -18,7 +18,8 @@ template <typename T> struct Vec;
 template <> struct Vec<double> { using type = vd2; static constexpr int W = 2; };
 template <> struct Vec<float> { using type = vf4; static constexpr int W = 4; };
 
-constexpr int kMaxCv = 2;     // column vectors per lane (ld <= 1024)
+constexpr int kMaxCv = 4;     // column vectors per lane of the generic kernels (ld <= 2048)
+constexpr int kRedWords = 2048;   // LDS words of their dot fold: rpb * ld <= 2048
 constexpr int kGridCap = 4096;   // 4 waves each: about 16 waves per CU
 
 // Launch geometry: a workgroup of 256 lanes holds `rpb` rows at once with
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(256) void spmm_csr_kernel(
     const T *__restrict__ val, const typename Vec<T>::type *__restrict__ C,
     typename Vec<T>::type *__restrict__ X, int ndot, double *__restrict__ partials) {
     using V = typename Vec<T>::type;
-    __shared__ double red[1024];
+    __shared__ double red[kRedWords];
     const int t = threadIdx.x;
     const int rr = t / tpr;
     const int lane = t - rr * tpr;
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256) void spmm_stencil_kernel(
     const T *__restrict__ Vpot, const typename Vec<T>::type *__restrict__ C,
     typename Vec<T>::type *__restrict__ X, int ndot, double *__restrict__ partials) {
     using V = typename Vec<T>::type;
-    __shared__ double red[1024];
+    __shared__ double red[kRedWords];
     const int t = threadIdx.x;
     const int rr = t / tpr;
     const int lane = t - rr * tpr;
@@ -533,8 +534,6 @@ template <typename T>
 int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
              double *partials) {
     const int ldv = ld / Vec<T>::W;
-    TM_REQUIRE(ldv <= kMaxCv * 256, TM_ENOTSUP, "block too wide for the SpMM kernel");
-    Geometry g = geometry(H.n, ldv);
     const T *val;
     if constexpr (sizeof(T) == 8) val = H.val64; else val = H.val32;
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
@@ -570,6 +569,8 @@ int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
         return w.grid;
     }
 generic:
+    TM_REQUIRE(ldv <= kMaxCv * 256, TM_ENOTSUP, "block too wide for the SpMM kernel");
+    Geometry g = geometry(H.n, ldv);
     hipLaunchKernelGGL(spmm_csr_kernel<T>, dim3(g.grid), dim3(256), 0, s, H.n, ldv, g.tpr, g.rpb,
                        g.rows_per_block, H.rowptr, H.col, val, Cv, Xv, ndot, partials);
     TM_HIP(hipGetLastError());

@@ -134,6 +134,138 @@ __global__ void p_update_kernel(int64_t count, int ld, const TG *__restrict__ G,
     }
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11): ten rounds of two 32 x 32 -> 64-bit products
+// mixed with the key, the key advanced by the Weyl increments between rounds.
+__device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// Standard normal entries of an n x ld block (columns >= m zero): entry
+// e = r * m + j is member e % 2 of the Box-Muller pair made from the Philox
+// output for counter (e / 2, 0, 0, 0).
+__global__ void random_block_kernel(int64_t n, int m, int ld, uint32_t k0, uint32_t k1,
+                                    double *__restrict__ out) {
+    const int64_t total = n * ld;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx / ld;
+        const int j = (int)(idx - r * ld);
+        double v = 0.0;
+        if (j < m) {
+            const uint64_t e = (uint64_t)r * (uint64_t)m + (uint64_t)j;
+            const uint64_t k = e >> 1;
+            uint32_t c[4] = {(uint32_t)k, (uint32_t)(k >> 32), 0u, 0u};
+            philox4x32_10(c, k0, k1);
+            const uint64_t a = (((uint64_t)c[1] << 32) | c[0]) >> 11;
+            const uint64_t b = (((uint64_t)c[3] << 32) | c[2]) >> 11;
+            const double u1 = (double)(a + 1) * 0x1.0p-53;   // (0, 1]
+            const double u2 = (double)b * 0x1.0p-53;         // [0, 1)
+            const double rad = sqrt(-2.0 * log(u1));
+            const double th = 6.283185307179586476925286766559 * u2;
+            v = (e & 1) ? rad * sin(th) : rad * cos(th);
+        }
+        out[idx] = v;
+    }
+}
+
+// Chebyshev iteration for (H - sigma) z = g from z = 0, applied to a block
+// in the block's own precision (the polynomial preconditioner of Eq. 18):
+// start d = g / theta, z = d; step k: r <- r - (H d - sigma d),
+// d <- c_dd d + c_r r, z <- z + d.  16-byte vectors (count is a multiple of
+// 32), arithmetic in T.
+template <typename T>
+__global__ void cheb_init_kernel(int64_t count, const T *__restrict__ g, T inv_theta,
+                                 T *__restrict__ d, T *__restrict__ z) {
+    constexpr int W = 16 / sizeof(T);
+    typedef T VT __attribute__((ext_vector_type(W)));
+    const int64_t nv = count / W;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const VT x = reinterpret_cast<const VT *>(g)[v];
+        VT o;
+#pragma unroll
+        for (int w = 0; w < W; ++w) o[w] = x[w] * inv_theta;
+        reinterpret_cast<VT *>(d)[v] = o;
+        reinterpret_cast<VT *>(z)[v] = o;
+    }
+}
+
+template <typename T>
+__global__ void cheb_step_kernel(int64_t count, const T *__restrict__ t, const T *r_in, T *r_out,
+                                 T *__restrict__ d, T *__restrict__ z, T sigma, T c_dd, T c_r) {
+    constexpr int W = 16 / sizeof(T);
+    typedef T VT __attribute__((ext_vector_type(W)));
+    const int64_t nv = count / W;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const VT tv = reinterpret_cast<const VT *>(t)[v];
+        const VT rv = reinterpret_cast<const VT *>(r_in)[v];
+        const VT dv = reinterpret_cast<const VT *>(d)[v];
+        const VT zv = reinterpret_cast<const VT *>(z)[v];
+        VT ro, dn, zo;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            ro[w] = rv[w] - (tv[w] - sigma * dv[w]);
+            dn[w] = c_dd * dv[w] + c_r * ro[w];
+            zo[w] = zv[w] + dn[w];
+        }
+        reinterpret_cast<VT *>(r_out)[v] = ro;
+        reinterpret_cast<VT *>(d)[v] = dn;
+        reinterpret_cast<VT *>(z)[v] = zo;
+    }
+}
+
+// Cn = C + alpha P with alpha from the controller (Fig. 1's update), for
+// the generalized problem, whose S-Gram cannot form it on the fly.
+template <typename TP>
+__global__ void update_block_kernel(int64_t count, const double *__restrict__ C,
+                                    const TP *__restrict__ P, const CgState *__restrict__ st,
+                                    double *__restrict__ Cn) {
+    const double alpha = st->alpha;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        Cn[e] = C[e] + alpha * (double)P[e];
+}
+
+// Xs = X - Z diag(h) (Fig. 2 step (5) in the S metric: Z = S C).
+__global__ void shift_block_kernel(int64_t count, int ld, const double *__restrict__ X,
+                                   const double *__restrict__ Z, const double *__restrict__ h,
+                                   double *__restrict__ Xs) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        Xs[e] = X[e] - Z[e] * h[e % ld];
+}
+
+// out[j] = v[j] for j < m, 0 for m <= j < ld.
+__global__ void pad_vector_kernel(int m, int ld, const double *__restrict__ v,
+                                  double *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < ld) out[j] = j < m ? v[j] : 0.0;
+}
+
+// Diagonal preconditioner of Eq. 18: M_ii = 1 / (H_ii - sigma).
+__global__ void jacobi_precond_kernel(int64_t n, const double *__restrict__ diag, double sigma,
+                                      double *__restrict__ M) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        M[i] = 1.0 / (diag[i] - sigma);
+}
+
 template <typename TI, typename TO>
 __global__ void convert_kernel(int64_t count, const TI *__restrict__ in,
                                TO *__restrict__ out) {
@@ -317,6 +449,65 @@ template <typename TI, typename TO>
 void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out) {
     hipLaunchKernelGGL((convert_kernel<TI, TO>), dim3(elem_grid(count)), dim3(256),
                        0, s, count, in, out);
+    TM_HIP(hipGetLastError());
+}
+
+void random_block(hipStream_t s, int64_t n, int m, uint64_t seed, double *out) {
+    const int ld = leading_dim(m);
+    hipLaunchKernelGGL(random_block_kernel, dim3(elem_grid(n * ld)), dim3(256), 0, s, n, m, ld,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), out);
+    TM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void cheb_init(hipStream_t s, int64_t count, const T *g, double inv_theta, T *d, T *z) {
+    hipLaunchKernelGGL((cheb_init_kernel<T>), dim3(elem_grid(count)), dim3(256), 0, s, count, g,
+                       (T)inv_theta, d, z);
+    TM_HIP(hipGetLastError());
+}
+template <typename T>
+void cheb_step(hipStream_t s, int64_t count, const T *t, const T *r_in, T *r_out, T *d, T *z,
+               double sigma, double c_dd, double c_r) {
+    hipLaunchKernelGGL((cheb_step_kernel<T>), dim3(elem_grid(count)), dim3(256), 0, s, count, t, r_in,
+                       r_out, d, z, (T)sigma, (T)c_dd, (T)c_r);
+    TM_HIP(hipGetLastError());
+}
+template void cheb_init<double>(hipStream_t, int64_t, const double *, double, double *, double *);
+template void cheb_init<float>(hipStream_t, int64_t, const float *, double, float *, float *);
+template void cheb_step<double>(hipStream_t, int64_t, const double *, const double *, double *, double *,
+                                double *, double, double, double);
+template void cheb_step<float>(hipStream_t, int64_t, const float *, const float *, float *, float *,
+                               float *, double, double, double);
+
+template <typename TP>
+void update_block(hipStream_t s, int64_t count, const double *C, const TP *P, const CgState *st,
+                  double *Cn) {
+    hipLaunchKernelGGL((update_block_kernel<TP>), dim3(elem_grid(count)), dim3(256), 0, s, count, C,
+                       P, st, Cn);
+    TM_HIP(hipGetLastError());
+}
+template void update_block<double>(hipStream_t, int64_t, const double *, const double *,
+                                   const CgState *, double *);
+template void update_block<float>(hipStream_t, int64_t, const double *, const float *,
+                                  const CgState *, double *);
+
+void shift_block(hipStream_t s, int64_t n, int ld, const double *X, const double *Z,
+                 const double *h, double *Xs) {
+    const int64_t count = n * ld;
+    hipLaunchKernelGGL(shift_block_kernel, dim3(elem_grid(count)), dim3(256), 0, s, count, ld, X, Z,
+                       h, Xs);
+    TM_HIP(hipGetLastError());
+}
+
+void pad_vector(hipStream_t s, int m, int ld, const double *v, double *out) {
+    hipLaunchKernelGGL(pad_vector_kernel, dim3((ld + 255) / 256), dim3(256), 0, s, m, ld, v, out);
+    TM_HIP(hipGetLastError());
+}
+
+void jacobi_preconditioner(hipStream_t s, int64_t n, const double *diag, double sigma,
+                           double *M) {
+    hipLaunchKernelGGL(jacobi_precond_kernel, dim3(elem_grid(n)), dim3(256), 0, s, n, diag,
+                       sigma, M);
     TM_HIP(hipGetLastError());
 }
 

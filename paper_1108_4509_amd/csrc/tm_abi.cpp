@@ -153,15 +153,40 @@ void tm_opts_default(tm_opts *o) {
     o->switch_tol = 0.0;
     o->rise_tol = 1e-13;
     o->stall_tol = 0.0;
+    o->seed = 0;
+    o->cheb_degree = 3;
+    o->cheb_shift = 0.02;
 }
 
-tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr, const int32_t *col,
-                            const double *val, tm_mat **out) {
+tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr_in, const int32_t *col_in,
+                            const double *val_in, uint32_t flags, tm_mat **out) {
     return guarded([&]() {
         use_device(ctx);
-        TM_REQUIRE(out && rowptr && col && val, TM_EINVAL, "null argument");
-        TM_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), TM_EINVAL, "n out of range");
+        TM_REQUIRE(out && rowptr_in && col_in && val_in, TM_EINVAL, "null argument");
         *out = nullptr;
+        TM_REQUIRE((flags & ~(TM_CHECK_SYMMETRY | TM_DEVICE_PTRS)) == 0, TM_EINVAL, "unknown flag bits");
+        TM_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), TM_EINVAL, "n out of range");
+        // device arrays are validated (and their FP32 copy and diagonal
+        // formed) through a host copy; host arrays are used in place
+        std::vector<int64_t> rp_h;
+        std::vector<int32_t> col_h;
+        std::vector<double> val_h;
+        const int64_t *rowptr = rowptr_in;
+        const int32_t *col = col_in;
+        const double *val = val_in;
+        if (flags & TM_DEVICE_PTRS) {
+            rp_h.resize(n + 1);
+            TM_HIP(hipMemcpy(rp_h.data(), rowptr_in, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+            TM_REQUIRE(rp_h[0] == 0 && rp_h[n] >= 0 && rp_h[n] < ((int64_t)1 << 40), TM_EINVAL,
+                       "rowptr[0] must be 0 and rowptr[n] a valid count");
+            col_h.resize(rp_h[n]);
+            val_h.resize(rp_h[n]);
+            TM_HIP(hipMemcpy(col_h.data(), col_in, rp_h[n] * sizeof(int32_t), hipMemcpyDeviceToHost));
+            TM_HIP(hipMemcpy(val_h.data(), val_in, rp_h[n] * sizeof(double), hipMemcpyDeviceToHost));
+            rowptr = rp_h.data();
+            col = col_h.data();
+            val = val_h.data();
+        }
         TM_REQUIRE(rowptr[0] == 0, TM_EINVAL, "rowptr[0] must be 0");
         for (int64_t r = 0; r < n; ++r)
             TM_REQUIRE(rowptr[r + 1] >= rowptr[r], TM_EINVAL, "rowptr must be non-decreasing");
@@ -175,6 +200,46 @@ tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr, const
                 if (col[k] == r) diag[r] += val[k];
             }
         for (int64_t k = 0; k < nnz; ++k) v32[k] = (float)val[k];
+        if (flags & TM_CHECK_SYMMETRY) {
+            // H = H^T (Sec. 2.1): every row's entries, duplicates summed, must
+            // equal the transposed ones; compared through the transpose built
+            // by a counting sort on the columns
+            std::vector<int64_t> tp(n + 1, 0);
+            for (int64_t k = 0; k < nnz; ++k) ++tp[col[k] + 1];
+            for (int64_t r = 0; r < n; ++r) tp[r + 1] += tp[r];
+            std::vector<int32_t> tcol(nnz);
+            std::vector<double> tval(nnz);
+            std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+            for (int64_t r = 0; r < n; ++r)
+                for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+                    const int64_t d = fill[col[k]]++;
+                    tcol[d] = (int32_t)r;
+                    tval[d] = val[k];
+                }
+            // (a duplicated entry may be summed in another order on the two
+            // sides: allowed to differ by a few units of rounding)
+            std::vector<double> acc(n, 0.0), mag(n, 0.0);
+            std::vector<int32_t> touched;
+            for (int64_t r = 0; r < n; ++r) {
+                touched.clear();
+                for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+                    acc[col[k]] += val[k];
+                    mag[col[k]] += std::fabs(val[k]);
+                    touched.push_back(col[k]);
+                }
+                for (int64_t k = tp[r]; k < tp[r + 1]; ++k) {
+                    acc[tcol[k]] -= tval[k];
+                    mag[tcol[k]] += std::fabs(tval[k]);
+                    touched.push_back(tcol[k]);
+                }
+                for (int32_t c : touched) {
+                    TM_REQUIRE(std::fabs(acc[c]) <= 4.0 * 2.220446049250313e-16 * mag[c], TM_EINVAL,
+                               "matrix is not symmetric (row " + std::to_string(r) + ", column " +
+                                   std::to_string(c) + ")");
+                }
+                for (int32_t c : touched) acc[c] = mag[c] = 0.0;
+            }
+        }
         tm_mat *m = new tm_mat;
         m->ctx = ctx;
         m->n = n;
@@ -200,6 +265,15 @@ tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr, const
             gmax = std::max(gmax, s);
         }
         m->diag_max = std::max(m->diag_max, 0.5 * gmax);
+        m->gersh_lo = 1e300;
+        m->gersh_hi = -1e300;
+        for (int64_t r = 0; r < n; ++r) {
+            double off = 0.0;
+            for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+                if (col[k] != r) off += std::fabs(val[k]);
+            m->gersh_lo = std::min(m->gersh_lo, diag[r] - off);
+            m->gersh_hi = std::max(m->gersh_hi, diag[r] + off);
+        }
         m->csr.n = n;
         m->csr.nnz = nnz;
         m->csr.rowptr = m->rowptr;
@@ -269,6 +343,49 @@ tm_status tm_set_matrix_stencil(tm_ctx *ctx, const tm_stencil *s, tm_mat **out) 
         const double off = s->ndim * (2.0 * std::fabs(d.c1) + 2.0 * std::fabs(d.c2));
         m->diag_max = std::max(*std::max_element(diag.begin(), diag.end()),
                                0.5 * (std::fabs(d.c0) + off));
+        // Gershgorin bounds row by row, with the stencil's neighbours merged
+        // as the matrix would hold them (wrapped offsets that meet on one
+        // point are summed; a wrap onto the point itself adds to the diagonal)
+        {
+            const int ext[3] = {d.nx, d.ny, d.nz};
+            std::vector<double> axis_off[3], axis_self[3];
+            for (int ax = 0; ax < d.ndim; ++ax) {
+                const int e = ext[ax];
+                axis_off[ax].assign(e, 0.0);
+                axis_self[ax].assign(e, 0.0);
+                for (int c = 0; c < e; ++c) {
+                    std::vector<std::pair<int, double>> tgt;
+                    for (int o = -(d.order / 2); o <= d.order / 2; ++o) {
+                        if (o == 0) continue;
+                        int t = c + o;
+                        if (d.periodic) t = ((t % e) + e) % e;
+                        else if (t < 0 || t >= e) continue;
+                        const double coef = (o == 1 || o == -1) ? d.c1 : d.c2;
+                        bool merged = false;
+                        for (auto &pr : tgt)
+                            if (pr.first == t) { pr.second += coef; merged = true; }
+                        if (!merged) tgt.push_back({t, coef});
+                    }
+                    for (auto &pr : tgt) {
+                        if (pr.first == c) axis_self[ax][c] += pr.second;
+                        else axis_off[ax][c] += std::fabs(pr.second);
+                    }
+                }
+            }
+            m->gersh_lo = 1e300;
+            m->gersh_hi = -1e300;
+            for (int64_t r = 0; r < n; ++r) {
+                const int crd[3] = {(int)(r % d.nx), (int)((r / d.nx) % d.ny),
+                                    d.ndim == 3 ? (int)(r / ((int64_t)d.nx * d.ny)) : 0};
+                double dg = diag[r], of = 0.0;
+                for (int ax = 0; ax < d.ndim; ++ax) {
+                    dg += axis_self[ax][crd[ax]];
+                    of += axis_off[ax][crd[ax]];
+                }
+                m->gersh_lo = std::min(m->gersh_lo, dg - of);
+                m->gersh_hi = std::max(m->gersh_hi, dg + of);
+            }
+        }
         *out = m;
         return TM_OK;
     });
@@ -288,20 +405,59 @@ tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol, const tm
                    const double *C0, double *C_out, double *eig_out, tm_result *res,
                    double *history, int32_t history_len) {
     return guarded([&]() {
-        TM_REQUIRE(H && C0 && res, TM_EINVAL, "null argument");
+        TM_REQUIRE(H && res, TM_EINVAL, "null argument");
         check_block_args(ctx, H->n, m);
         TM_REQUIRE(H->ctx == ctx, TM_EINVAL, "matrix belongs to another context");
         TM_REQUIRE(tol > 0.0 && std::isfinite(tol), TM_EINVAL, "tol must be positive");
-        TM_REQUIRE(m <= 1024, TM_ENOTSUP, "m > 1024 is not supported");
+        TM_REQUIRE(m <= 2048, TM_ENOTSUP, "m > 2048 is not supported");
         tm_opts o;
         if (opts) o = *opts; else tm_opts_default(&o);
         TM_REQUIRE(o.max_iter >= 0, TM_EINVAL, "max_iter must be >= 0");
-        TM_REQUIRE(o.precision >= TM_FULL_DP && o.precision <= TM_FULL_BF16, TM_EINVAL, "unknown precision");
+        TM_REQUIRE(o.precision >= TM_FULL_DP && o.precision <= TM_MP2_MP1, TM_EINVAL, "unknown precision");
         TM_REQUIRE(history_len >= 0, TM_EINVAL, "history_len must be >= 0");
         TM_REQUIRE(o.graphs == 0 || o.graphs == 1, TM_EINVAL, "tm_opts.graphs must be 0 or 1");
+        TM_REQUIRE(o.precondition >= 0 && o.precondition <= 2, TM_EINVAL, "tm_opts.precondition must be 0, 1 or 2");
+        TM_REQUIRE(o.precondition != 2 || (o.cheb_degree >= 1 && o.cheb_degree <= 64 &&
+                                           o.cheb_shift > 0.0 && std::isfinite(o.cheb_shift)),
+                   TM_EINVAL, "polynomial preconditioner: cheb_degree in [1, 64], cheb_shift > 0");
         std::memset(res, 0, sizeof(*res));
         Solver solver(ctx, H, m, tol, o);
         return solver.run(C0, C_out, eig_out, res, history, history_len);
+    });
+}
+
+tm_status tm_solve_generalized(tm_ctx *ctx, const tm_mat *H, const tm_mat *S, int32_t m, double tol,
+                               const tm_opts *opts, const double *C0, double *C_out, double *eig_out,
+                               tm_result *res, double *history, int32_t history_len) {
+    return guarded([&]() {
+        TM_REQUIRE(H && S && res, TM_EINVAL, "null argument");
+        check_block_args(ctx, H->n, m);
+        TM_REQUIRE(H->ctx == ctx && S->ctx == ctx, TM_EINVAL, "matrix belongs to another context");
+        TM_REQUIRE(S->n == H->n, TM_EINVAL, "H and S differ in size");
+        TM_REQUIRE(S->diag_min > 0.0, TM_EINVAL, "S has a diagonal entry <= 0: not positive definite");
+        TM_REQUIRE(tol > 0.0 && std::isfinite(tol), TM_EINVAL, "tol must be positive");
+        TM_REQUIRE(m <= 2048, TM_ENOTSUP, "m > 2048 is not supported");
+        tm_opts o;
+        if (opts) o = *opts; else tm_opts_default(&o);
+        TM_REQUIRE(o.max_iter >= 0, TM_EINVAL, "max_iter must be >= 0");
+        TM_REQUIRE(o.precision == TM_FULL_DP, TM_ENOTSUP, "the generalized problem runs in TM_FULL_DP");
+        TM_REQUIRE(o.precondition == 0 || o.precondition == 1, TM_ENOTSUP,
+                   "the generalized problem takes no preconditioner or the diagonal one");
+        TM_REQUIRE(history_len >= 0, TM_EINVAL, "history_len must be >= 0");
+        TM_REQUIRE(o.graphs == 0 || o.graphs == 1, TM_EINVAL, "tm_opts.graphs must be 0 or 1");
+        std::memset(res, 0, sizeof(*res));
+        Solver solver(ctx, H, m, tol, o, S);
+        return solver.run(C0, C_out, eig_out, res, history, history_len);
+    });
+}
+
+tm_status tm_random_block(tm_ctx *ctx, int64_t n, int32_t m, uint64_t seed, double *out) {
+    return guarded([&]() {
+        TM_REQUIRE(out, TM_EINVAL, "null argument");
+        check_block_args(ctx, n, m);
+        random_block(ctx->stream, n, m, seed, out);
+        sync(ctx);
+        return TM_OK;
     });
 }
 
@@ -374,12 +530,12 @@ tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t precis
     return guarded([&]() {
         TM_REQUIRE(H && C && X && G && h && Hp && E, TM_EINVAL, "null argument");
         check_block_args(ctx, H->n, m);
-        TM_REQUIRE(precision == TM_FULL_DP || precision == TM_MP2, TM_EINVAL,
-                   "precision must be TM_FULL_DP or TM_MP2");
+        TM_REQUIRE(precision == TM_FULL_DP || precision == TM_MP2 || precision == TM_MP1, TM_EINVAL,
+                   "precision must be TM_FULL_DP, TM_MP1 or TM_MP2");
         const int ld = leading_dim(m);
         const int64_t n = H->n;
         hipStream_t s = ctx->stream;
-        const bool dp = precision == TM_FULL_DP;
+        const bool dp = precision != TM_MP2;
         DevMem hv(ctx, ld * sizeof(double)), dws(ctx, spmm_partials_workspace(ld)),
             gws(ctx, gram_workspace(n, m)), wp(ctx, (size_t)ld * ld * sizeof(double)),
             xs(ctx, (size_t)n * ld * (dp ? sizeof(double) : sizeof(float)));
@@ -388,7 +544,15 @@ tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t precis
         // X' = X - C diag(h) is kept by the Gram in the matrix-core precision
         // and read back by the gradient; H' from its upper block tiles,
         // mirrored, also stored padded for the gradient GEMM: as in the solver
-        if (dp) {
+        if (precision == TM_MP1) {
+            // MP1 (i): FP64 products, G formed in FP64 and stored in FP32 (the
+            // epilogue forms X' again from X, C and h); returned widened to FP64
+            float *G32 = (float *)xs.ptr;
+            gram<double, double>(s, n, m, C, X, (double *)hv.ptr, true, true, (double *)gws.ptr, Hp,
+                                 true, nullptr, (double *)wp.ptr);
+            rot<double, double, float>(s, n, m, C, (double *)wp.ptr, EPI_GRAD, X, (double *)hv.ptr, G32);
+            convert_block<float, double>(s, n * ld, G32, G);
+        } else if (dp) {
             double *Xs = (double *)xs.ptr;
             gram<double, double>(s, n, m, C, X, (double *)hv.ptr, true, true, (double *)gws.ptr, Hp,
                                  true, Xs, (double *)wp.ptr);
@@ -412,8 +576,8 @@ tm_status tm_orthonormalize(tm_ctx *ctx, int64_t n, int32_t m, int32_t precision
     return guarded([&]() {
         TM_REQUIRE(C, TM_EINVAL, "null argument");
         check_block_args(ctx, n, m);
-        TM_REQUIRE(precision == TM_FULL_DP || precision == TM_MP2, TM_EINVAL,
-                   "precision must be TM_FULL_DP or TM_MP2");
+        TM_REQUIRE(precision == TM_FULL_DP || precision == TM_MP2 || precision == TM_MP1, TM_EINVAL,
+                   "precision must be TM_FULL_DP, TM_MP1 or TM_MP2");
         const int ld = leading_dim(m);
         hipStream_t s = ctx->stream;
         const size_t md = (size_t)m * m * sizeof(double);
@@ -446,7 +610,7 @@ tm_status tm_cholesky_inverse(tm_ctx *ctx, int32_t m, const double *S, double *R
     return guarded([&]() {
         TM_REQUIRE(S && Rinv, TM_EINVAL, "null argument");
         use_device(ctx);
-        TM_REQUIRE(m >= 1 && m <= 1024, TM_EINVAL, "m must be in [1, 1024]");
+        TM_REQUIRE(m >= 1 && m <= 2048, TM_EINVAL, "m must be in [1, 2048]");
         DevMem cw(ctx, chol_workspace(m)), info(ctx, 16);
         TM_HIP(hipMemsetAsync(info.ptr, 0, 16, ctx->stream));
         chol_inverse(ctx->stream, m, S, Rinv, (double *)cw.ptr, (int32_t *)info.ptr);
@@ -462,7 +626,7 @@ tm_status tm_sym_eig(tm_ctx *ctx, int32_t m, const double *A, double *U, double 
     return guarded([&]() {
         TM_REQUIRE(A && U && w, TM_EINVAL, "null argument");
         use_device(ctx);
-        TM_REQUIRE(m >= 1 && m <= 1024, TM_EINVAL, "m must be in [1, 1024]");
+        TM_REQUIRE(m >= 1 && m <= 2048, TM_EINVAL, "m must be in [1, 2048]");
         DevMem jw(ctx, jacobi_workspace(m)), info(ctx, 16);
         jacobi_eig(ctx->stream, m, A, U, w, (double *)jw.ptr, (int32_t *)info.ptr);
         sync(ctx);

@@ -118,17 +118,23 @@ void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
 
 // Gram products out = A^T B' (m x m, FP64), B' = B - A diag(h) if h --------
 size_t gram_workspace(int64_t n, int m);
+// Bytes of FP64 partials gram() (symmetric or not) uses when its workspace
+// holds ws_bytes (0: the default workspace, gram_workspace): fewer row
+// splits when the workspace is smaller.
+size_t gram_partials_bytes(int64_t n, int m, bool symmetric, size_t ws_bytes);
 // reduce = false launches only the split-K product (used to time it alone).
 // xshift (with h): B' itself, n x ld in the matrix-core precision TM, is also
 // stored there (the EPI_GRADX input of rot()).  wpad: the result is also
 // stored as the zero-padded ld x ld matrix in TM (the W of rot(), as
 // pad_matrix would write it).  symmetric: only the upper block tiles are
 // computed and mirrored (exact for A = B; with h, the symmetric H' of an
-// orthonormal A).
+// orthonormal A).  ws_bytes > 0: partials holds only that many bytes (the
+// split count is lowered to fit, see gram_partials_bytes).
 template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
-          double *out, bool reduce = true, TM *xshift = nullptr, TM *wpad = nullptr);
+          double *out, bool reduce = true, TM *xshift = nullptr, TM *wpad = nullptr,
+          size_t ws_bytes = 0);
 
 // S = Cn^T Cn with Cn = C + alpha P formed while staged (alpha from st) and
 // written to Cn: the update of Fig. 1 fused into Fig. 4 step (1).
@@ -142,7 +148,7 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
 template <typename TA>
 void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, const double *h,
                  bool zero_diag, double *partials, double *out, bool reduce = true,
-                 float *wpad = nullptr);
+                 float *wpad = nullptr, size_t ws_bytes = 0);
 
 // Tall-skinny products out = A W (+ epilogue) ------------------------------
 enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2, EPI_GRADX = 3 };
@@ -189,6 +195,28 @@ void p_update(hipStream_t s, int64_t n, int ld, const TG *G, const double *M,
               const CgState *st, TP *P);
 template <typename TI, typename TO>
 void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out);
+// The seeded standard normal start block of tm_random_block (n x ld FP64).
+void random_block(hipStream_t s, int64_t n, int m, uint64_t seed, double *out);
+// Chebyshev iteration steps (polynomial preconditioner): d = z = g * inv_theta;
+// r_out = r_in - (t - sigma d), d = c_dd d + c_r r_out, z += d (t = H d).
+// r_out may alias r_in.
+template <typename T>
+void cheb_init(hipStream_t s, int64_t count, const T *g, double inv_theta, T *d, T *z);
+template <typename T>
+void cheb_step(hipStream_t s, int64_t count, const T *t, const T *r_in, T *r_out, T *d, T *z,
+               double sigma, double c_dd, double c_r);
+// Cn = C + alpha P (alpha = st->alpha), count elements.
+template <typename TP>
+void update_block(hipStream_t s, int64_t count, const double *C, const TP *P, const CgState *st,
+                  double *Cn);
+// Xs = X - Z diag(h) for n x ld blocks (h: ld entries).
+void shift_block(hipStream_t s, int64_t n, int ld, const double *X, const double *Z,
+                 const double *h, double *Xs);
+// out[0..ld) = v[0..m) followed by zeros (a kernel, no memset node).
+void pad_vector(hipStream_t s, int m, int ld, const double *v, double *out);
+// M_ii = 1 / (diag_i - sigma) (Eq. 18's diagonal M), n entries.
+void jacobi_preconditioner(hipStream_t s, int64_t n, const double *diag, double sigma,
+                           double *M);
 
 // CG controller (single workgroup) -----------------------------------------
 // After the gradient: dots = [gg | gz | gprev_z | pprev_g] (4 x ld), h (ld).
@@ -230,4 +258,7 @@ struct tm_mat {
     float *V32 = nullptr;
     double *diag = nullptr;      // H_ii (n), FP64
     double diag_min = 0, diag_max = 0;
+    // Gershgorin bounds of the spectrum: min / max over rows of
+    // H_ii -+ sum_{j != i} |H_ij|
+    double gersh_lo = 0, gersh_hi = 0;
 };

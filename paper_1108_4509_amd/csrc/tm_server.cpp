@@ -150,7 +150,7 @@ struct tm_server {
 void tm_server::execute(Slot *slot, Request *r) {
     tm_ctx *ctx = slot->ctx;
     tm_mat *H = nullptr;
-    tm_status st = tm_set_matrix_csr(ctx, r->n, r->rowptr.data(), r->col.data(), r->val.data(), &H);
+    tm_status st = tm_set_matrix_csr(ctx, r->n, r->rowptr.data(), r->col.data(), r->val.data(), 0u, &H);
     if (st != TM_OK) {
         r->status = st;
         r->error = tm_last_error();
@@ -236,7 +236,7 @@ tm_status tm_solve_footprint(int64_t n, int64_t nnz, int32_t m, const tm_opts *o
     if (!bytes || n < 1 || m < 1 || m > n || nnz < 0) return TM_EINVAL;
     tm_opts o;
     if (opts) o = *opts; else tm_opts_default(&o);
-    *bytes = solve_footprint(n, nnz, m, o.precision, o.precondition != 0, 0) +
+    *bytes = solve_footprint(n, nnz, m, o.precision, o.precondition, 0) +
              (uint64_t)n * leading_dim(m) * 8 + (uint64_t)leading_dim(m) * 8 + 64 * Arena::kAlign;
     return TM_OK;
 }

@@ -46,16 +46,18 @@ template <typename T> constexpr bool is_f64() { return sizeof(T) == 8; }
 
 struct Phase {
     // storage of C and X; storage of G, G_prev, P, Y; matrix-core precision
-    // of H'/G and of the TRMM; precision of S = C^T C
-    bool c64, g64, mh64, ms64;
+    // of H' and G; precision of S = C^T C; precision of the TRMM's C R'
+    bool c64, g64, mh64, ms64, t64;
+    int id() const { return (c64 ? 1 : 0) | (g64 ? 2 : 0) | (mh64 ? 4 : 0) | (ms64 ? 8 : 0) | (t64 ? 16 : 0); }
 };
 
 Phase phase_of(int precision) {
     switch (precision) {
-    case TM_FULL_DP: return {true, true, true, true};
-    case TM_FULL_SP: return {false, false, false, false};
-    case TM_MP2: return {true, false, false, true};
-    default: return {true, true, true, true};
+    case TM_FULL_DP: return {true, true, true, true, true};
+    case TM_FULL_SP: return {false, false, false, false, false};
+    case TM_MP2: return {true, false, false, true, false};    // Sec. 2.2 MP2
+    case TM_MP1: return {true, false, true, true, false};     // Sec. 2.2 MP1 (i) and (ii)
+    default: return {true, true, true, true, true};
     }
 }
 
@@ -63,7 +65,7 @@ Phase phase_of(int precision) {
 
 // ------------------------------------------------------------------ footprint
 
-size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, bool precondition,
+size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, int precondition,
                        int history_len) {
     const size_t ld = (size_t)leading_dim(m);
     const size_t blk8 = (size_t)n * ld * 8, blk4 = (size_t)n * ld * 4;
@@ -73,7 +75,9 @@ size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, bool precon
     size_t blocks;
     switch (precision) {
     case TM_FULL_DP: blocks = 3 * blk8 + 4 * blk8; break;
-    case TM_MP2: blocks = 3 * blk8 + 4 * blk4; break;
+    case TM_MP2:
+    case TM_MP1:
+    case TM_MP2_MP1: blocks = 3 * blk8 + 4 * blk4; break;
     default: blocks = 3 * blk4 + 3 * blk8 + 4 * blk4; break;   // FULL_SP, MIXED
     }
     const size_t md = (size_t)m * m * 8;
@@ -81,7 +85,8 @@ size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, bool precon
                    std::max({coldots_workspace(n, (int)ld), spmm_partials_workspace((int)ld),
                              rot_partials_workspace(n, m)}) +
                    chol_workspace(m) + jacobi_workspace(m) + 64 + sizeof(CgState) +
-                   (size_t)2 * std::max(history_len, 0) * 8 + (precondition ? (size_t)n * 8 : 0);
+                   (size_t)2 * std::max(history_len, 0) * 8 + (precondition == 1 ? (size_t)n * 8 : 0) +
+                   (precondition == 2 ? 3 * blk8 : 0);   // the polynomial's work blocks
     // the matrix (CSR: rowptr, col, FP64 and FP32 values, diagonal; stencil:
     // V in FP64 and FP32), plus 16 bytes of slack per upload
     const size_t mat = nnz > 0 ? (size_t)(n + 1) * 8 + (size_t)nnz * (4 + 8 + 4) + (size_t)n * 8 + 80
@@ -100,10 +105,17 @@ struct Solver::Impl {
     tm_opts o;
     hipStream_t s;
 
-    // blocks (allocated per precision of C and of G)
-    std::unique_ptr<DevMem> C64, Cn64, X64, C32, Cn32, X32;
+    // the S of H x = lambda S x (Sec. 2.1), or null for the standard problem
+    const tm_mat *Smat = nullptr;
+    // blocks (allocated per precision of C and of G); Z = S C and W = S P
+    // for the generalized problem
+    std::unique_ptr<DevMem> C64, Cn64, X64, C32, Cn32, X32, Z64, W64;
     std::unique_ptr<DevMem> G, Gp, P, Y;  // element size set by g64
+    std::unique_ptr<DevMem> Zc, Rc, Dc;   // polynomial preconditioner: Z = M G and its work blocks
     bool g64_alloc = false;
+    // polynomial preconditioner: Chebyshev iteration for (H - sigma) z = g on
+    // [a, b] = Gershgorin bounds - sigma; theta, delta its centre and half-width
+    double ch_sigma = 0, ch_theta = 1, ch_delta = 1;
     // small buffers
     std::unique_ptr<DevMem> h, d, w, dots, dots2, Hp, S, Rinv, Amat, U, Wp;
     std::unique_ptr<DevMem> gram_ws, dot_ws, chol_ws, jac_ws, info, state, hist, M;
@@ -114,10 +126,13 @@ struct Solver::Impl {
     bool bf16_bulk = false;   // the FP32 phase forms H' on BF16 matrix cores
 
     // captured iteration batches, keyed by the buffers they were recorded on
+    // and the precision phase (which selects the kernels)
     struct GraphKey {
         const void *c32, *c64, *g, *gp, *p, *y;
+        int phase;
         bool operator==(const GraphKey &o) const {
-            return c32 == o.c32 && c64 == o.c64 && g == o.g && gp == o.gp && p == o.p && y == o.y;
+            return c32 == o.c32 && c64 == o.c64 && g == o.g && gp == o.gp && p == o.p && y == o.y &&
+                   phase == o.phase;
         }
     };
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -125,8 +140,8 @@ struct Solver::Impl {
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
     }
 
-    Impl(tm_ctx *c, const tm_mat *Hm, int mm, double t, const tm_opts &oo)
-        : ctx(c), H(Hm), m(mm), ld(leading_dim(mm)), n(Hm->n), tol(t), o(oo), s(c->stream) {}
+    Impl(tm_ctx *c, const tm_mat *Hm, const tm_mat *Sm, int mm, double t, const tm_opts &oo)
+        : ctx(c), H(Hm), m(mm), ld(leading_dim(mm)), n(Hm->n), tol(t), o(oo), s(c->stream), Smat(Sm) {}
 
 
     void alloc_small() {
@@ -157,16 +172,21 @@ struct Solver::Impl {
         char *pin = (char *)ctx->pinned_buffer();
         st_host = (CgState *)pin;
         info_host = (int32_t *)(pin + 2048);
-        if (o.precondition) {
+        if (o.precondition == 2) {
+            const double lo = H->gersh_lo, hi = H->gersh_hi;
+            ch_sigma = lo - o.cheb_shift * (hi - lo);
+            const double a = lo - ch_sigma, b = hi - ch_sigma;
+            TM_REQUIRE(b > a && a > 0.0, TM_EINVAL, "degenerate Gershgorin interval");
+            ch_theta = 0.5 * (a + b);
+            ch_delta = 0.5 * (b - a);
+        }
+        if (o.precondition == 1) {
+            // Eq. 18 with M_ii = 1 / (H_ii - sigma), sigma = min(0, min_i H_ii - 1/2)
+            // so that M is positive definite; formed on the device from H's diagonal
             TM_REQUIRE(H->diag != nullptr, TM_EINVAL, "matrix has no diagonal");
             M.reset(new DevMem(ctx, n * sizeof(double)));
-            std::vector<double> diag(n);
-            TM_HIP(hipMemcpyAsync(diag.data(), H->diag, n * sizeof(double), hipMemcpyDeviceToHost, s));
-            TM_HIP(hipStreamSynchronize(s));
             const double sigma = std::min(0.0, H->diag_min - 0.5);
-            for (auto &x : diag) x = 1.0 / (x - sigma);
-            TM_HIP(hipMemcpyAsync(M->ptr, diag.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
-            TM_HIP(hipStreamSynchronize(s));
+            jacobi_preconditioner(s, n, H->diag, sigma, (double *)M->ptr);
         }
     }
 
@@ -191,10 +211,16 @@ struct Solver::Impl {
     void alloc_g(bool f64) {
         if (G && g64_alloc == f64) return;
         G.reset(); Gp.reset(); P.reset(); Y.reset();
+        Zc.reset(); Rc.reset(); Dc.reset();
         G.reset(new DevMem(ctx, blk(f64)));
         Gp.reset(new DevMem(ctx, blk(f64)));
         P.reset(new DevMem(ctx, blk(f64)));
         Y.reset(new DevMem(ctx, blk(f64)));
+        if (o.precondition == 2) {
+            Zc.reset(new DevMem(ctx, blk(f64)));
+            Rc.reset(new DevMem(ctx, blk(f64)));
+            Dc.reset(new DevMem(ctx, blk(f64)));
+        }
         g64_alloc = f64;
     }
     void zero_g() {
@@ -233,8 +259,30 @@ struct Solver::Impl {
         ++rotations;
     }
 
-    // ---- one CG iteration (Fig. 1) with Algorithm-2 (Fig. 2)
-    template <typename TC, typename TG, typename TMH, typename TMS>
+    // ---- Z = M G with the polynomial M = p(H - sigma I) (Eq. 18): the
+    // Chebyshev iteration for (H - sigma I) z = g from z = 0, in TG (G's
+    // precision: single precision whenever G is stored in FP32, Sec. 4);
+    // T is a free block for H d
+    template <typename TG>
+    void precondition_poly(const TG *Gv, TG *Z, TG *R, TG *D, TG *T) {
+        const int64_t count = n * ld;
+        cheb_init<TG>(s, count, Gv, 1.0 / ch_theta, D, Z);
+        const double s1 = ch_theta / ch_delta;
+        double rho = 1.0 / s1;
+        const TG *r_in = Gv;
+        for (int k = 1; k < o.cheb_degree; ++k) {
+            spmm_any(s, H, ld, D, T, is_f64<TG>());
+            const double rho_new = 1.0 / (2.0 * s1 - rho);
+            cheb_step<TG>(s, count, T, r_in, R, D, Z, ch_sigma, rho_new * rho, 2.0 * rho_new / ch_delta);
+            r_in = R;
+            rho = rho_new;
+        }
+    }
+
+    // ---- one CG iteration (Fig. 1) with Algorithm-2 (Fig. 2).  TC: storage of
+    // C and X; TG: of G, G_prev, P, Y; TMH: matrix cores of H' and C H';
+    // TMS: of S = C^T C; TT: of the TRMM's C R' (Eq. 13)
+    template <typename TC, typename TG, typename TMH, typename TMS, typename TT>
     void iterate(TC *&C, TC *&Cn, TC *X, bool rotate, double *hist_dev) {
         if (rotate) {
             // the rotation keeps C's own precision (FP64 C stays FP64-accurate)
@@ -265,17 +313,23 @@ struct Solver::Impl {
         // orthonormal here, so H' = C^T H C - H_D is symmetric: only its upper
         // block tiles are computed and mirrored (the difference from the full
         // product, (C^T C - I) H_D, lies in span(C) and leaves E unchanged)
-        static_assert(std::is_same<TG, TMH>::value, "X' is held in a direction block");
+        // X' can be kept only where the direction blocks have the matrix-core
+        // precision; MP1 (FP64 products, FP32 G) forms X' again in the
+        // gradient's epilogue from X, C and h (EPI_GRAD)
+        constexpr bool keep_xs = std::is_same<TG, TMH>::value;
         TMH *Xs = nullptr;
         if (!is_f64<TC>() && bf16_bulk) {
             gram_bf16x3<TC>(s, n, m, C, X, (double *)h->ptr, true, (double *)gram_ws->ptr, (double *)Hp->ptr);
-        } else {
+            pad_matrix<TMH>(s, m, (double *)Hp->ptr, false, (TMH *)Wp->ptr, nullptr);
+        } else if constexpr (keep_xs) {
             Xs = reinterpret_cast<TMH *>(Yv);
             gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, true, (double *)gram_ws->ptr,
                           (double *)Hp->ptr, true, Xs, (TMH *)Wp->ptr);
+        } else {
+            gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, true, (double *)gram_ws->ptr,
+                          (double *)Hp->ptr, true, nullptr, (TMH *)Wp->ptr);
         }
         // (7): G = -2 (X' - C H'); the reduction above stored H' padded in TMH
-        if (!Xs) pad_matrix<TMH>(s, m, (double *)Hp->ptr, false, (TMH *)Wp->ptr, nullptr);
         // with the traces for Eq. 8 and the descent test fused into the epilogue
         {
             const int nch = rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, Xs ? EPI_GRADX : EPI_GRAD, X,
@@ -283,9 +337,22 @@ struct Solver::Impl {
                                              (double *)dot_ws->ptr, Xs);
             reduce_partials(s, 4, nch, ld, (double *)dot_ws->ptr, (double *)dots->ptr);
         }
+        // the polynomial M: Z = M G, and the traces tr(G^T Z), tr(G_prev^T Z)
+        // of the M-weighted Eq. 8 in place of the fused diagonal ones
+        TG *Zv = nullptr;
+        if (o.precondition == 2) {
+            Zv = (TG *)Zc->ptr;
+            precondition_poly<TG>(Gv, Zv, (TG *)Rc->ptr, (TG *)Dc->ptr, Yv);
+            DotArgs<TG> a;
+            a.nprod = 2;
+            a.a[0] = Gv; a.b[0] = Zv;
+            a.a[1] = Gpv; a.b[1] = Zv;
+            coldots<TG>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr + ld);
+        }
         cg_control_gamma(s, m, ld, (double *)h->ptr, (double *)dots->ptr, st, hist_dev);
         // P = M G + gamma P
-        p_update<TG, TG>(s, n, ld, Gv, Mv, st, Pv);
+        if (Zv) p_update<TG, TG>(s, n, ld, Zv, nullptr, st, Pv);
+        else p_update<TG, TG>(s, n, ld, Gv, Mv, st, Pv);
         // line step: Y = HP with p.y and p.p fused into the SpMM
         {
             const int nch = spmm_any(s, H, ld, Pv, Yv, is_f64<TG>(), 2, (double *)dot_ws->ptr);
@@ -295,7 +362,80 @@ struct Solver::Impl {
         // C_{i+1} = orthonormalize(C_i + alpha P): the update is formed inside
         // the Gram S = (C + alpha P)^T (C + alpha P), which also stores it
         gram_update<TC, TMS, TG>(s, n, m, C, Pv, st, Cn, (double *)gram_ws->ptr, (double *)S->ptr);
-        finish_orthonormalize<TC, TMH>(Cn, C);
+        finish_orthonormalize<TC, TT>(Cn, C);
+        std::swap(G, Gp);
+    }
+
+    // ---- the generalized problem H x = lambda S x (Sec. 2.1), all FP64
+    // Fig. 4 in the S inner product: Z = S Cin, Sg = Cin^T Z = R^T R,
+    // Cout = Cin R^{-1}
+    void orthonormalize_gen(double *Cin, double *Cout) {
+        double *Z = (double *)Z64->ptr;
+        spmm_any(s, Smat, ld, Cin, Z, true);
+        gram<double, double>(s, n, m, Cin, Z, nullptr, false, false, (double *)gram_ws->ptr,
+                             (double *)S->ptr);
+        finish_orthonormalize<double, double>(Cin, Cout);
+    }
+    // Eq. 9 with an S-orthonormal C: A = C^T H C (the full product: H' from
+    // C^T (X - C H_D) would need C^T C = I), A = U diag(w) U^T, C <- C U
+    // keeps C^T S C = I
+    void rayleigh_ritz_gen(double *&C, double *&Cn, double *X) {
+        const int nch = spmm_any(s, H, ld, C, X, true, 1, (double *)dot_ws->ptr);
+        reduce_partials(s, 1, nch, ld, (double *)dot_ws->ptr, (double *)h->ptr);
+        gram<double, double>(s, n, m, C, X, nullptr, false, false, (double *)gram_ws->ptr,
+                             (double *)Hp->ptr);
+        assemble_subspace_matrix(s, m, (double *)Hp->ptr, (double *)h->ptr, (double *)Amat->ptr);
+        jacobi_eig(s, m, (double *)Amat->ptr, (double *)U->ptr, (double *)w->ptr, (double *)jac_ws->ptr,
+                   (int32_t *)info->ptr + 1);
+        pad_matrix<double>(s, m, (double *)U->ptr, false, (double *)Wp->ptr, nullptr);
+        rot<double, double, double>(s, n, m, C, (double *)Wp->ptr, EPI_NONE, nullptr, nullptr, Cn);
+        std::swap(C, Cn);
+        ++rotations;
+    }
+    // One CG iteration for H x = lambda S x: Algorithm-2 in the S metric
+    // (X = HC, Z = SC, h = diag(C^T X), X' = X - Z H_D, H' = C^T X' with
+    // diag(H') := 0, G = -2 (X' - Z H')), the Polak-Ribiere step, the line
+    // step with S-norms (Y = HP, W = SP), C + alpha P and Fig. 4 in the S
+    // inner product.
+    void iterate_gen(double *&C, double *&Cn, double *X, bool rotate, double *hist_dev) {
+        if (rotate) {
+            rayleigh_ritz_gen(C, Cn, X);
+            if (o.transport) {
+                rot<double, double, double>(s, n, m, (double *)P->ptr, (double *)Wp->ptr, EPI_NONE, nullptr,
+                                            nullptr, (double *)Y->ptr);
+                std::swap(P, Y);
+                rot<double, double, double>(s, n, m, (double *)Gp->ptr, (double *)Wp->ptr, EPI_NONE, nullptr,
+                                            nullptr, (double *)G->ptr);
+                std::swap(G, Gp);
+            } else {
+                set_restart();
+            }
+        }
+        double *Gv = (double *)G->ptr, *Gpv = (double *)Gp->ptr, *Pv = (double *)P->ptr,
+               *Yv = (double *)Y->ptr, *Z = (double *)Z64->ptr, *W = (double *)W64->ptr;
+        const double *Mv = M ? (const double *)M->ptr : nullptr;
+        double *dw = (double *)dot_ws->ptr;
+        int nch = spmm_any(s, H, ld, C, X, true, 1, dw);
+        reduce_partials(s, 1, nch, ld, dw, (double *)h->ptr);
+        spmm_any(s, Smat, ld, C, Z, true);
+        // X' in Y (free until the line step)
+        shift_block(s, n, ld, X, Z, (double *)h->ptr, Yv);
+        gram<double, double>(s, n, m, C, Yv, nullptr, true, false, (double *)gram_ws->ptr,
+                             (double *)Hp->ptr, true, nullptr, (double *)Wp->ptr);
+        nch = rot<double, double, double>(s, n, m, Z, (double *)Wp->ptr, EPI_GRADX, X, (double *)h->ptr, Gv,
+                                          Gpv, Pv, Mv, dw, Yv);
+        reduce_partials(s, 4, nch, ld, dw, (double *)dots->ptr);
+        cg_control_gamma(s, m, ld, (double *)h->ptr, (double *)dots->ptr, st, hist_dev);
+        p_update<double, double>(s, n, ld, Gv, Mv, st, Pv);
+        // line step: p.(HP) and p.(SP), the S-norms of the columns of P
+        double *d2 = (double *)dots2->ptr;
+        nch = spmm_any(s, H, ld, Pv, Yv, true, 1, dw);
+        reduce_partials(s, 1, nch, ld, dw, d2);
+        nch = spmm_any(s, Smat, ld, Pv, W, true, 1, dw);
+        reduce_partials(s, 1, nch, ld, dw, d2 + ld);
+        cg_control_alpha(s, m, ld, (double *)h->ptr, d2, st);
+        update_block<double>(s, n * ld, C, Pv, st, Cn);
+        orthonormalize_gen(Cn, C);
         std::swap(G, Gp);
     }
 
@@ -359,34 +499,58 @@ struct Solver::Impl {
 
         const int prec = o.precision;
         const bool mixed = prec == TM_MIXED || prec == TM_MIXED_BF16;
+        const bool mp2_mp1 = prec == TM_MP2_MP1;
         bf16_bulk = prec == TM_MIXED_BF16 || prec == TM_FULL_BF16;
-        Phase ph = phase_of((mixed || prec == TM_FULL_BF16) ? TM_FULL_SP : prec);
+        Phase ph = phase_of((mixed || prec == TM_FULL_BF16) ? TM_FULL_SP : (mp2_mp1 ? TM_MP2 : prec));
         alloc_c(ph.c64);
         alloc_g(ph.g64);
+        // no start block given: the seeded standard normal block (Sec. 3:
+        // random numbers, then orthonormalization)
+        std::unique_ptr<DevMem> c0_own;
+        if (!C0) {
+            c0_own.reset(new DevMem(ctx, blk(true)));
+            random_block(s, n, m, o.seed, (double *)c0_own->ptr);
+            C0 = (const double *)c0_own->ptr;
+        }
         // start block -> C (cast), orthonormalize
         if (ph.c64) {
             TM_HIP(hipMemcpyAsync(Cn64->ptr, C0, blk(true), hipMemcpyDeviceToDevice, s));
         } else {
             convert_block<double, float>(s, n * ld, C0, (float *)Cn32->ptr);
         }
-        const bool gate = mixed || prec == TM_FULL_SP || prec == TM_FULL_BF16;
+        const bool gate = mixed || mp2_mp1 || prec == TM_FULL_SP || prec == TM_FULL_BF16;
         double sw = o.switch_tol > 0 ? o.switch_tol : auto_switch_tol();
         reset_state(sw, gate ? 1 : 0, hl);
         zero_g();
 
         double *c64 = C64 ? (double *)C64->ptr : nullptr, *cn64 = Cn64 ? (double *)Cn64->ptr : nullptr;
         float *c32 = C32 ? (float *)C32->ptr : nullptr, *cn32 = Cn32 ? (float *)Cn32->ptr : nullptr;
-        if (ph.c64) orthonormalize<double, double, double>(cn64, c64);
-        else orthonormalize<float, float, float>(cn32, c32);
+        if (Smat) {
+            Z64.reset(new DevMem(ctx, blk(true)));
+            W64.reset(new DevMem(ctx, blk(true)));
+            orthonormalize_gen(cn64, c64);
+        } else if (ph.c64) {
+            orthonormalize<double, double, double>(cn64, c64);
+        } else {
+            orthonormalize<float, float, float>(cn32, c32);
+        }
+        TM_HIP(hipStreamSynchronize(s));
+        c0_own.reset();
+        const auto t_loop = std::chrono::steady_clock::now();
+        auto t_switch = t_loop;
+        bool switched = false;
 
         int it_host = 0;        // active iterations known to the host
         int iters_sp = 0;
         bool sp_phase = !ph.c64;
+        bool first_phase = true;   // MP2 part of TM_MP2_MP1
         const int kcheck = std::max(1, o.k_check);
         auto step = [&](bool rotate) {
-            if (!ph.c64) iterate<float, float, float, float>(c32, cn32, (float *)X32->ptr, rotate, hist_dev);
-            else if (!ph.g64) iterate<double, float, float, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
-            else iterate<double, double, double, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
+            if (Smat) iterate_gen(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
+            else if (!ph.c64) iterate<float, float, float, float, float>(c32, cn32, (float *)X32->ptr, rotate, hist_dev);
+            else if (ph.g64) iterate<double, double, double, double, double>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
+            else if (ph.mh64) iterate<double, float, double, double, float>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
+            else iterate<double, float, float, double, float>(c64, cn64, (double *)X64->ptr, rotate, hist_dev);
         };
         while (true) {
             int it_dev_done = 0;
@@ -400,7 +564,7 @@ struct Solver::Impl {
                 // a batch of k_check iterations without a rotation is the same
                 // launch sequence every time for the same buffers: replay it
                 // from a captured HIP graph (no memset nodes are recorded)
-                const GraphKey key{c32, c64, G->ptr, Gp->ptr, P->ptr, Y->ptr};
+                const GraphKey key{c32, c64, G->ptr, Gp->ptr, P->ptr, Y->ptr, ph.id()};
                 hipGraphExec_t exec = nullptr;
                 for (auto &kv : graphs)
                     if (kv.first == key) exec = kv.second;
@@ -432,10 +596,28 @@ struct Solver::Impl {
             if (st_host->nan_seen) throw Error{TM_ENAN, "NaN or Inf in the energy or gradient"};
             if (st_host->done) break;
             if (st_host->phase_end) {
+                if (mp2_mp1 && first_phase) {
+                    // MP2 done: MP1 from here on.  C, X and the FP32 G, G_prev, P
+                    // keep their buffers and meaning, so CG continues
+                    iters_sp = st_host->it;
+                    t_switch = std::chrono::steady_clock::now();
+                    switched = true;
+                    ph = phase_of(TM_MP1);
+                    CgState cur = *st_host;
+                    cur.phase_end = 0;
+                    cur.phase_gate = 0;
+                    cur.stall_window = 0;
+                    cur.window_it = 0;
+                    TM_HIP(hipMemcpyAsync(st, &cur, sizeof(CgState), hipMemcpyHostToDevice, s));
+                    first_phase = false;
+                    continue;
+                }
                 if (mixed && sp_phase) {
                     // FP32 bulk done: cast C up (exact), re-orthonormalize in FP64,
                     // restart CG under MP2 (Sec. 3: switch when the residual is small)
                     iters_sp = st_host->it;
+                    t_switch = std::chrono::steady_clock::now();
+                    switched = true;
                     ph = phase_of(TM_MP2);
                     alloc_c(true);
                     c64 = (double *)C64->ptr;
@@ -456,14 +638,19 @@ struct Solver::Impl {
                     sp_phase = false;
                     continue;
                 }
-                if (sp_phase) iters_sp = st_host->it;
                 break;   // FULL_SP: the FP32 phase ends the solve
             }
             if (it_host >= o.max_iter || it_dev_done == 0) break;
         }
-        if (sp_phase && iters_sp == 0) iters_sp = st_host->it;
         const bool converged = st_host->done != 0;
         const int iterations = converged ? st_host->it - 1 : st_host->it;
+        const auto t_iter_end = std::chrono::steady_clock::now();
+        // one-phase policies (and a two-phase policy that never switched)
+        // count every iteration as the first phase's
+        if (!switched) {
+            iters_sp = iterations;
+            t_switch = t_iter_end;
+        }
 
         // ---- final FP64 Rayleigh-Ritz, residuals and orthonormality
         if (!c64) {
@@ -474,15 +661,23 @@ struct Solver::Impl {
             free_c(false);
         }
         double *X = (double *)X64->ptr;
-        rayleigh_ritz<double, double>(c64, cn64, X);
+        if (Smat) rayleigh_ritz_gen(c64, cn64, X);
+        else rayleigh_ritz<double, double>(c64, cn64, X);
         --rotations;   // the final one is not a subspace rotation of the iteration
         spmm_any(s, H, ld, c64, X, true);
+        // residuals ||H c_j - lambda_j S c_j|| and C^T S C - I (S = I for the
+        // standard problem)
+        const double *SC = c64;
+        if (Smat) {
+            spmm_any(s, Smat, ld, c64, (double *)Z64->ptr, true);
+            SC = (const double *)Z64->ptr;
+        }
         {
             DotArgs<double> a;
-            a.nprod = 1; a.kind = 1; a.a[0] = X; a.b[0] = c64; a.sc = (double *)w->ptr;
+            a.nprod = 1; a.kind = 1; a.a[0] = X; a.b[0] = SC; a.sc = (double *)w->ptr;
             coldots<double>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr);
         }
-        gram<double, double>(s, n, m, c64, c64, nullptr, false, true, (double *)gram_ws->ptr, (double *)S->ptr);
+        gram<double, double>(s, n, m, c64, SC, nullptr, false, !Smat, (double *)gram_ws->ptr, (double *)S->ptr);
         std::vector<double> wv(m), res2(m), Sh((size_t)m * m);
         TM_HIP(hipMemcpyAsync(wv.data(), w->ptr, m * sizeof(double), hipMemcpyDeviceToHost, s));
         TM_HIP(hipMemcpyAsync(res2.data(), dots->ptr, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -507,19 +702,25 @@ struct Solver::Impl {
         res->max_residual = mx;
         res->frob_residual = std::sqrt(fr);
         res->orth_err = orth;
-        res->seconds = std::chrono::duration<double>(t1 - t0).count();
+        auto secs = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+            return std::chrono::duration<double>(b - a).count();
+        };
+        res->seconds = secs(t0, t1);
+        res->seconds_phase[0] = secs(t_loop, t_switch);
+        res->seconds_phase[1] = secs(t_switch, t_iter_end);
+        res->seconds_phase[2] = secs(t0, t_loop) + secs(t_iter_end, t1);
         res->iterations = iterations;
         res->iters_sp = iters_sp;
+        res->iters_phase2 = iterations - iters_sp;
         res->converged = converged ? 1 : 0;
         res->restarts = st_host->restarts;
         res->rotations = rotations;
-        res->reserved = 0;
         return converged ? TM_OK : TM_ENOCONV;
     }
 };
 
-Solver::Solver(tm_ctx *ctx, const tm_mat *H, int m, double tol, const tm_opts &o)
-    : impl_(new Impl(ctx, H, m, tol, o)) {}
+Solver::Solver(tm_ctx *ctx, const tm_mat *H, int m, double tol, const tm_opts &o, const tm_mat *S)
+    : impl_(new Impl(ctx, H, S, m, tol, o)) {}
 Solver::~Solver() = default;
 tm_status Solver::run(const double *C0, double *C_out, double *eig_out, tm_result *res,
                       double *hist, int hist_len) {

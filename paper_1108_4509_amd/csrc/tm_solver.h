@@ -27,12 +27,14 @@ int spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, boo
 // problem with nnz stored nonzeros (0 for a stencil), at the given
 // precision, history length and preconditioner setting: the blocks that can
 // be alive together, the workspaces, the m x m matrices and the matrix itself.
-size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, bool precondition,
+size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, int precondition,
                        int history_len);
 
 class Solver {
   public:
-    Solver(tm_ctx *ctx, const tm_mat *H, int m, double tol, const tm_opts &o);
+    // S: the positive definite S of H x = lambda S x (FULL_DP only), or null
+    Solver(tm_ctx *ctx, const tm_mat *H, int m, double tol, const tm_opts &o,
+           const tm_mat *S = nullptr);
     ~Solver();
     tm_status run(const double *C0, double *C_out, double *eig_out, tm_result *res,
                   double *hist, int hist_len);

@@ -57,8 +57,8 @@ def test_pure_host_entry_points(lib):
 def test_struct_layouts_match_header(lib):
     """The ctypes mirrors have the sizes the C compiler gives the structs."""
     from paper_1108_4509_amd import _abi
-    assert ctypes.sizeof(_abi.tm_opts) == 8 * 4 + 3 * 8
-    assert ctypes.sizeof(_abi.tm_result) == 6 * 8 + 6 * 4
+    assert ctypes.sizeof(_abi.tm_opts) == 8 * 4 + 3 * 8 + 8 + 2 * 4 + 8
+    assert ctypes.sizeof(_abi.tm_result) == 6 * 8 + 3 * 8 + 6 * 4
     assert ctypes.sizeof(_abi.tm_stencil) == 6 * 4 + 8 + 8
 
 
@@ -67,7 +67,8 @@ def test_null_arguments_rejected_without_device(lib):
     out = ctypes.c_void_p()
     assert lib.tm_create(0, None, None, None) == _abi.TM_EINVAL
     assert lib.tm_solve(None, None, 1, 1e-8, None, None, None, None, None, None, 0) == _abi.TM_EINVAL
-    assert lib.tm_set_matrix_csr(None, 1, None, None, None, ctypes.byref(out)) == _abi.TM_EINVAL
+    assert lib.tm_set_matrix_csr(None, 1, None, None, None, 0, ctypes.byref(out)) == _abi.TM_EINVAL
+    assert lib.tm_random_block(None, 4, 2, 0, None) == _abi.TM_EINVAL
     assert b"null" in lib.tm_last_error()
 
 
@@ -104,3 +105,28 @@ def test_serving_structs_and_footprint(lib):
     assert lib.tm_server_create(ctypes.byref(bad), ctypes.byref(h)) == _abi.TM_EINVAL
     assert lib.tm_server_submit(None, None, None) == _abi.TM_EINVAL
     assert lib.tm_server_poll(None, 1, None, None) == _abi.TM_EINVAL
+
+
+def test_philox_reference_known_answers():
+    """The numpy Philox4x32-10 used to check tm_random_block reproduces the
+    known-answer vectors published with the generator (Random123 kat_vectors:
+    zero counter and key; all-ones; the digits of pi)."""
+    import numpy as np
+    from tests.philox_ref import philox4x32_10
+    cases = [((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+             ((0xffffffff,) * 4, (0xffffffff, 0xffffffff),
+              (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+             ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+              (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1))]
+    for ctr, key, want in cases:
+        got = philox4x32_10(np.array([ctr], dtype=np.uint64), key)[0]
+        assert [int(x) for x in got] == list(want)
+
+
+def test_random_block_reference_is_standard_normal():
+    import numpy as np
+    from tests.philox_ref import random_block
+    z = random_block(2000, 50, 12345)
+    assert abs(z.mean()) < 0.01 and abs(z.std() - 1.0) < 0.01
+    assert np.array_equal(random_block(3, 5, 7), random_block(30, 5, 7)[:3])
+    assert not np.array_equal(random_block(3, 5, 7), random_block(3, 5, 8))

@@ -174,7 +174,7 @@ def test_gram_bf16x3(ctx, tm, n, m, shift):
 
 
 @pytest.mark.parametrize("n,m", [(5000, 27), (3001, 76), (4099, 130), (2050, 256), (1500, 512),
-                                 (700, 1), (64, 64)])
+                                 (700, 1), (64, 64), (1100, 1024), (1600, 1519)])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_gram(ctx, tm, n, m, dt):
     import torch
@@ -207,7 +207,8 @@ def test_gram(ctx, tm, n, m, dt):
     assert np.all(np.abs(got - ref) <= tol)
 
 
-@pytest.mark.parametrize("n,m", [(5000, 27), (3001, 76), (2050, 256), (1100, 512)])
+@pytest.mark.parametrize("n,m", [(5000, 27), (3001, 76), (2050, 256), (1100, 512), (1030, 1024),
+                                 (1600, 1519)])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_rotate(ctx, tm, n, m, dt):
     import torch
@@ -310,6 +311,56 @@ def test_energy_grad_mp2_wide(ctx, tm, orc):
     assert np.all(got[:, m:] == 0)
 
 
+@pytest.mark.parametrize("m", [1000, 1519])
+@pytest.mark.parametrize("precision", ["full_dp", "mp1", "mp2"])
+def test_energy_grad_wide(ctx, tm, orc, m, precision):
+    """Algorithm-2 at 1024- and 1536-wide blocks (Table 1's m = 1064 and 1519
+    need ld = 1088 and 1536) on a small 2-D Dirichlet matrix, under each
+    policy; bounds as in the cases above.  MP1 (i) forms G in FP64 and
+    rounds it to FP32 once (u32 |G| more)."""
+    n1 = 48 if m == 1000 else 41
+    prob = make_problem("dw", StencilSpec(2, (n1, 45), 2, "dirichlet", 1.0), m=m, seed=13)
+    print_case(test="energy_grad_wide", n=prob.N, m=m, precision=precision)
+    H = orc.csr_matrix(*prob.csr(), prob.N)
+    Hd = tm.matrix_from_problem(ctx, prob)
+    C = orc.orthonormalize(prob.C0())
+    E, G, X, h, Hp = tm.energy_grad(ctx, Hd, m, tm.to_block(C), precision=precision)
+    E_o, G_o, X_o, h_o, Hp_o = orc.energy_gradient_alg2(H, C)
+    n = C.shape[0]
+    absX = abs(H) @ np.abs(C)
+    g = gamma(n + 16, U64)
+    assert abs(E - E_o) <= 4 * g * np.sum(np.abs(C) * absX)
+    absXp = absX + np.abs(C) * np.abs(h_o)[None, :]
+    mirror = _mirror_term(C, h_o)
+    got = host(G)
+    if precision == "mp2":
+        assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * gamma(n + 4, U32) * (np.abs(C).T @ absXp) + mirror)
+        Xp_o = X_o - C * h_o[None, :]
+        bound = 8 * gamma(n + m + 4, U32) * (np.abs(C) @ (np.abs(C).T @ absXp)) \
+            + 4 * U32 * np.abs(Xp_o) + 8 * g * absXp + 2 * np.abs(C) @ mirror
+    else:
+        assert np.all(np.abs(host(Hp) - Hp_o) <= 4 * g * (np.abs(C).T @ absXp) + mirror)
+        absG = 2 * (absXp + np.abs(C) @ np.abs(Hp_o))
+        bound = 8 * g * (absG + 2 * np.abs(C) @ (np.abs(C).T @ absXp)) + 2 * np.abs(C) @ mirror
+        if precision == "mp1":
+            bound = bound + 2 * U32 * np.abs(G_o)
+    assert np.all(np.abs(got[:, :m] - G_o) <= bound)
+    assert np.all(got[:, m:] == 0)
+
+
+def test_random_block(ctx, tm):
+    """tm_random_block against Philox4x32-10 + Box-Muller written out in numpy
+    from their published definitions: same counters, so the same normals to
+    the rounding of log, sqrt, sin and cos; zero padding; a ragged shape."""
+    from tests.philox_ref import random_block
+    for n, m, seed in ((1000, 27, 0), (333, 256, 2**40 + 77)):
+        print_case(test="random_block", n=n, m=m, seed=seed)
+        got = host(tm.random_block(ctx, n, m, seed))
+        ref = random_block(n, m, seed)
+        assert np.max(np.abs(got[:, :m] - ref)) <= 64 * U64 * (1.0 + np.abs(ref).max())
+        assert np.all(got[:, m:] == 0)
+
+
 @pytest.mark.parametrize("n,m", [(4096, 27), (3001, 76), (2050, 256)])
 @pytest.mark.parametrize("precision", ["full_dp", "mp2"])
 def test_orthonormalize(ctx, tm, orc, n, m, precision):
@@ -335,7 +386,8 @@ def test_orthonormalize(ctx, tm, orc, n, m, precision):
             assert np.all(np.abs(got - ref) <= bound)
 
 
-@pytest.mark.parametrize("m", [1, 2, 5, 16, 17, 33, 65, 100, 130, 256, 300, 520, 1000])
+@pytest.mark.parametrize("m", [1, 2, 5, 16, 17, 33, 65, 100, 130, 256, 300, 520, 1000, 1024,
+                               1519, 2048])
 def test_cholesky_inverse(ctx, tm, orc, m):
     import torch
     print_case(test="cholesky_inverse", m=m)
@@ -383,7 +435,7 @@ def test_cholesky_breakdown_later_block(ctx, tm, m, bad):
     assert np.all(np.isfinite(R_inv))
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 27, 64, 101, 256, 600])
+@pytest.mark.parametrize("m", [1, 2, 3, 27, 64, 101, 256, 600, 1024])
 def test_sym_eig(ctx, tm, orc, m):
     import torch
     print_case(test="sym_eig", m=m)
@@ -397,6 +449,26 @@ def test_sym_eig(ctx, tm, orc, m):
     assert np.max(np.abs(w - w_o)) <= 64 * m * U64 * scale
     assert np.max(np.abs(A @ U - U * w[None, :])) <= 64 * m * U64 * scale
     assert np.max(np.abs(U.T @ U - np.eye(m))) <= 64 * m * U64
+
+
+@pytest.mark.parametrize("m", [1519, 2048])
+def test_sym_eig_wide(ctx, tm, m):
+    """Widths past the oracle's reach in test time (Table 1's m = 1519 and the
+    limit 2048): the 1-D Dirichlet Laplacian with a diagonal ramp has no
+    degenerate eigenvalues; eigenvalues against numpy's LAPACK as an outside
+    witness, residuals and orthogonality at any size, and the trace."""
+    import torch
+    print_case(test="sym_eig_wide", m=m)
+    A = 2 * np.eye(m) - np.eye(m, k=1) - np.eye(m, k=-1) + np.diag(np.linspace(0.0, 1.0, m))
+    w, U = tm.sym_eig(ctx, torch.from_numpy(A).cuda())
+    w, U = host(w), host(U)
+    scale = np.linalg.norm(A)
+    assert np.max(np.abs(w - np.linalg.eigvalsh(A))) <= 64 * m * U64 * scale
+    assert np.max(np.abs(A @ U - U * w[None, :])) <= 64 * m * U64 * scale
+    assert np.max(np.abs(U.T @ U - np.eye(m))) <= 64 * m * U64
+    # the sum of m eigenvalues, each within the bound above, with independent
+    # rounding: about sqrt(m) times one eigenvalue's bound
+    assert abs(np.sum(w) - np.trace(A)) <= 64 * m * U64 * scale * np.sqrt(m)
 
 
 def test_sym_eig_closed_form(ctx, tm):

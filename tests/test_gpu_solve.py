@@ -131,7 +131,7 @@ def wells_oracle(orc, wells_problem):
                      orc.OracleOptions(tol=1e-10, k_rot=50))
 
 
-@pytest.mark.parametrize("precision", ["full_dp", "mixed", "mp2", "mixed_bf16"])
+@pytest.mark.parametrize("precision", ["full_dp", "mixed", "mp2", "mixed_bf16", "mp1", "mp2_mp1"])
 def test_wells_precisions(ctx, tm, wells_problem, wells_oracle, precision):
     print_case(test="wells", precision=precision)
     r, C, w, _ = _solve(tm, ctx, wells_problem, precision=precision)
@@ -185,6 +185,115 @@ def test_preconditioned(ctx, tm, wells_problem, wells_oracle):
     r, _, _, _ = _solve(tm, ctx, wells_problem, precondition=True)
     assert r["converged"] == 1
     assert abs(r["E_G"] - wells_oracle.E_G) <= 1e-10 * abs(wells_oracle.E_G)
+
+
+def test_preconditioned_trajectory(ctx, tm, orc, wells_problem):
+    """Eq. 18 with the diagonal M (varying with the wells here, so not a
+    scalar): the GPU's preconditioned iteration -- M formed on the device, G'
+    = M G in the direction update, the M-weighted Polak-Ribiere traces fused
+    into the gradient epilogue -- follows the oracle's energies step by step
+    while rounding has not been amplified, and ends at the same E_G."""
+    p = wells_problem
+    print_case(test="preconditioned_trajectory")
+    ref = orc.solve(orc.csr_matrix(*p.csr(), p.N), p.C0(),
+                    orc.OracleOptions(tol=1e-10, k_rot=50, precondition=True))
+    M = orc.jacobi_preconditioner(orc.csr_matrix(*p.csr(), p.N))
+    assert M.max() / M.min() > 1.3
+    r, _, w, hist = _solve(tm, ctx, p, hist=600, precondition=True)
+    Eo = np.array(ref.energies)
+    k = 40
+    assert np.max(np.abs(hist[:k, 0] - Eo[:k]) / np.abs(Eo[:k])) < 1e-9
+    assert r["converged"] == 1
+    assert abs(r["E_G"] - ref.E_G) <= 1e-10 * abs(ref.E_G)
+    assert abs(r["iterations"] - ref.iterations) <= 0.25 * ref.iterations + 10
+
+
+def test_seeded_start_block(ctx, tm, orc, wells_problem):
+    """tm_solve with no start block draws the seeded one (tm_random_block):
+    the same result as passing that block, and the oracle's E_G from it."""
+    import torch
+    p = wells_problem
+    print_case(test="seeded_start")
+    H = tm.matrix_from_problem(ctx, p)
+    C0 = tm.random_block(ctx, p.N, p.m, 2024)
+    r1, C1, w1, _ = tm.solve(ctx, H, p.m, 1e-8, None, tm.opts(seed=2024))
+    r2, C2, w2, _ = tm.solve(ctx, H, p.m, 1e-8, C0, tm.opts())
+    assert r1["E_G"] == r2["E_G"] and r1["iterations"] == r2["iterations"]
+    assert torch.equal(C1, C2)
+    ref = orc.solve(orc.csr_matrix(*p.csr(), p.N), host(C0, p.m), orc.OracleOptions(tol=1e-10))
+    assert abs(r1["E_G"] - ref.E_G) <= 1e-10 * abs(ref.E_G)
+    r3, _, _, _ = tm.solve(ctx, H, p.m, 1e-8, None, tm.opts(seed=2025))
+    assert abs(r3["E_G"] - ref.E_G) <= 1e-10 * abs(ref.E_G)
+
+
+def test_phase_accounting(ctx, tm, wells_problem):
+    """Per-phase iterations and seconds add up to the totals."""
+    for precision, two in (("mixed", True), ("mp2_mp1", True), ("full_dp", False)):
+        print_case(test="phase_accounting", precision=precision)
+        r, _, _, _ = _solve(tm, ctx, wells_problem, precision=precision)
+        assert r["converged"] == 1
+        assert r["iters_sp"] + r["iters_phase2"] == r["iterations"]
+        assert (r["iters_phase2"] > 0) == two and r["iters_sp"] > 0
+        ph = r["seconds_phase"]
+        assert min(ph) >= 0 and abs(sum(ph) - r["seconds"]) <= 1e-3 + 0.01 * r["seconds"]
+
+
+def test_csr_flags(ctx, tm, wells_problem):
+    """TM_CHECK_SYMMETRY rejects a matrix that is not symmetric and accepts
+    the stencil matrices; TM_DEVICE_PTRS takes device arrays and gives the
+    same matrix (the same solve, bit for bit) as the host arrays."""
+    import torch
+    p = wells_problem
+    rowptr, col, val = p.csr()
+    Hh = tm.set_matrix_csr(ctx, rowptr, col, val, check_symmetry=True)
+    Hd = tm.set_matrix_csr(ctx, torch.from_numpy(rowptr).cuda(), torch.from_numpy(col).cuda(),
+                           torch.from_numpy(val).cuda(), check_symmetry=True)
+    C0 = tm.to_block(p.C0())
+    ra, Ca, _, _ = tm.solve(ctx, Hh, p.m, 1e-8, C0)
+    rb, Cb, _, _ = tm.solve(ctx, Hd, p.m, 1e-8, C0)
+    assert ra["E_G"] == rb["E_G"] and torch.equal(Ca, Cb)
+    bad = val.copy()
+    k = next(i for i in range(int(rowptr[5]), int(rowptr[6])) if col[i] != 5)   # off-diagonal, row 5
+    bad[k] += 1e-3
+    with pytest.raises(tm.TraceminError) as ei:
+        tm.set_matrix_csr(ctx, rowptr, col, bad, check_symmetry=True)
+    assert ei.value.status == tm.TM_EINVAL and "symmetric" in str(ei.value)
+    tm.set_matrix_csr(ctx, rowptr, col, bad)    # unchecked: accepted as given
+    with pytest.raises(tm.TraceminError):
+        tm.set_matrix_csr(ctx, torch.from_numpy(rowptr).cuda(), torch.from_numpy(col).cuda(),
+                          torch.from_numpy(bad).cuda(), check_symmetry=True)
+
+
+@pytest.mark.parametrize("precision", ["full_dp", "mp1", "mp2", "mixed"])
+def test_table1_row1(ctx, tm, precision):
+    """Table 1's first row (the 2-D Dirichlet H_N of Eq. 14-15, N = 96^2,
+    m = 220) in stencil mode under each policy: E_G against the closed form
+    of Eq. 16 to 1e-10 and the printed E_G = 35.25."""
+    n, m = 96, 220
+    lam = eq16_spectrum(n)
+    p = config_problem("t1_96_220")
+    print_case(test="table1_row1", precision=precision)
+    r, _, w, _ = _solve(tm, ctx, p, precision=precision, stencil=True)
+    assert r["converged"] == 1
+    assert abs(r["E_G"] - lam[:m].sum()) <= 1e-10 * lam[:m].sum()
+    assert round(r["E_G"], 2) == 35.25
+    assert np.max(np.abs(host(w) - lam[:m])) < 1e-9
+
+
+def test_table1_widest_row(ctx, tm):
+    """Table 1's last row, N = 192^2 and m = 1519 (ld = 1536), MIXED in
+    stencil mode and FULL_DP on the CSR path: E_G = 395.6 against Eq. 16 to
+    1e-10."""
+    n, m = 192, 1519
+    lam = eq16_spectrum(n)
+    p = config_problem("t1_192_1519")
+    for precision, stencil in (("mixed", True), ("full_dp", False)):
+        print_case(test="table1_widest", precision=precision, stencil=stencil)
+        r, _, w, _ = _solve(tm, ctx, p, precision=precision, stencil=stencil)
+        assert r["converged"] == 1
+        assert abs(r["E_G"] - lam[:m].sum()) <= 1e-10 * lam[:m].sum()
+        assert round(r["E_G"], 1) == 395.6
+        assert np.max(np.abs(host(w) - lam[:m])) < 1e-9
 
 
 def test_13_point_closed_shell(ctx, tm):
@@ -302,3 +411,37 @@ def test_graph_replay_matches_eager(ctx, tm, wells_problem, precision):
     assert np.array_equal(host(Cg), host(Ca))
     k = ra["iterations"]
     assert np.array_equal(hg[:k], ha[:k])
+
+
+def test_chebyshev_trajectory(ctx, tm, orc, wells_problem):
+    """The polynomial preconditioner (Eq. 18 with M = p(H - sigma I), the
+    Chebyshev iteration on the Gershgorin interval) in FULL_DP follows the
+    oracle's preconditioned iteration step by step and ends at the same E_G,
+    in fewer iterations than the unpreconditioned solve; CSR and stencil
+    agree (the same Gershgorin interval)."""
+    p = wells_problem
+    print_case(test="chebyshev_trajectory")
+    ref = orc.solve(orc.csr_matrix(*p.csr(), p.N), p.C0(),
+                    orc.OracleOptions(tol=1e-10, k_rot=50, chebyshev=3))
+    plain, _, _, _ = _solve(tm, ctx, p)
+    for stencil in (False, True):
+        r, _, w, hist = _solve(tm, ctx, p, hist=600, precondition="chebyshev", cheb_degree=3,
+                               stencil=stencil)
+        Eo = np.array(ref.energies)
+        k = 40
+        assert np.max(np.abs(hist[:k, 0] - Eo[:k]) / np.abs(Eo[:k])) < 1e-9
+        assert r["converged"] == 1
+        assert abs(r["E_G"] - ref.E_G) <= 1e-10 * abs(ref.E_G)
+        assert np.max(np.abs(host(w) - ref.eigenvalues)) <= 1e-9
+        assert r["iterations"] < 0.7 * plain["iterations"]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mp2", "mp1"])
+def test_chebyshev_single_precision(ctx, tm, wells_problem, wells_oracle, precision):
+    """M applied in FP32 (the precision of G in these policies, Sec. 4): the
+    result keeps full FP64 accuracy."""
+    print_case(test="chebyshev_sp", precision=precision)
+    r, _, w, _ = _solve(tm, ctx, wells_problem, precision=precision, precondition="chebyshev")
+    assert r["converged"] == 1
+    assert abs(r["E_G"] - wells_oracle.E_G) <= 1e-10 * abs(wells_oracle.E_G)
+    assert np.max(np.abs(host(w) - wells_oracle.eigenvalues)) <= 1e-9

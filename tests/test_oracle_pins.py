@@ -298,3 +298,271 @@ def test_rotation_transport_leaves_cg_intact(oracle_mod):
     full = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(tol=1e-8, k_rot=5, transport=True))
     exact = 54 * (1 - math.cos(math.pi / 8))
     assert full.converged and abs(full.E_G - exact) <= 1e-12 * exact
+
+
+# ------------------------------------------------ line step and preconditioner
+
+def _ritz_basis_and_tangent(oracle_mod, p, seed):
+    """An orthonormal C whose m x m H = C^T H C is diagonal (a Ritz basis,
+    rotated with numpy's eigh as an outside witness) and a random direction P
+    projected onto the orthogonal complement of span(C)."""
+    H = _H(oracle_mod, p)
+    C = oracle_mod.orthonormalize(p.C0())
+    A = C.T @ (H @ C)
+    _, U = np.linalg.eigh(0.5 * (A + A.T))
+    C = C @ U
+    P = np.random.default_rng(seed).standard_normal(C.shape)
+    P -= C @ (C.T @ P)
+    P /= np.linalg.norm(P, axis=0)[None, :]
+    return H, C, P
+
+
+def _omega(H, C, P, a):
+    """E at the orthonormalized C + a P without orthonormalizing: the energy
+    depends on the span only (Sec. 2.1), so with S = B^T B for B = C + a P it
+    is tr(S^{-1} B^T H B) (numpy's solve, not the oracle's Cholesky)."""
+    B = C + a * P
+    return float(np.trace(np.linalg.solve(B.T @ B, B.T @ (H @ B))))
+
+
+def test_line_step_curvature_is_second_derivative(oracle_mod, small_well_problem):
+    """The line step's curvature 2 sum_j (p_j.Hp_j - A_jj p_j.p_j) is the
+    second derivative of E along P at a Ritz basis with P orthogonal to C,
+    the case where the second-order model is exact; central differences at
+    three step sizes converge to it at the O(eps^2) rate.  Its slope
+    tr(P^T G) is -dE/da (the gradient pin above), and the step is the
+    minimizer of the model: the differences of E at alpha * (1 +- 0.01)
+    match the model's parabola."""
+    H, C, P = _ritz_basis_and_tangent(oracle_mod, small_well_problem, 17)
+    E0, G, X, A = oracle_mod.energy_gradient_alg1(H, C)
+    assert np.max(np.abs(A - np.diag(np.diag(A)))) < 1e-13 * np.max(np.abs(A))
+    Y = oracle_mod.spmm(H, P)
+    alpha, info = oracle_mod.line_step(P, Y, G, np.diag(A).copy())
+    curv = info["curv"]
+    assert abs(curv) > 1.0
+    om0 = _omega(H, C, P, 0.0)
+    assert abs(om0 - E0) < 1e-13 * abs(E0)
+    errs = []
+    for eps in (4e-3, 2e-3, 1e-3):
+        fd2 = (_omega(H, C, P, eps) - 2 * om0 + _omega(H, C, P, -eps)) / eps ** 2
+        errs.append(abs(fd2 - curv) / abs(curv))
+    assert errs[-1] < 1e-5
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0   # O(eps^2)
+    # a factor or sign slip in either term is far outside that agreement
+    pp = np.einsum("ij,ij->j", P, P)
+    py = np.einsum("ij,ij->j", P, Y)
+    for wrong in (np.sum(py - np.diag(A) * pp), 2 * np.sum(py + np.diag(A) * pp),
+                  2 * np.sum(py)):
+        assert abs(wrong - curv) > 1e-2 * abs(curv)
+    # the step: the minimizer pg / curv of the parabola E0 - pg a + curv a^2 / 2
+    # when the curvature is positive, capped at 1 / max_j ||p_j||
+    assert abs(info["pg"] - float(np.sum(P * G))) < 1e-14 * abs(info["pg"])
+    cap = 1.0 / np.sqrt(pp.max())
+    assert alpha == pytest.approx(min(info["pg"] / curv, cap) if curv > 0 else cap, rel=1e-15)
+
+
+def test_preconditioner_scalar_multiple_reproduces_plain_cg(oracle_mod):
+    """Eq. 18 with a scalar M = c I (a matrix with a constant diagonal,
+    here the V = 0 periodic Laplacian, diagonal 3, so M = I / 3): G' = M G
+    scales every direction by c, the M-weighted Polak-Ribiere gamma is
+    unchanged, the step alpha grows by 1 / c and the iterates are those of
+    the unpreconditioned CG."""
+    p = config_problem("c1")
+    H = _H(oracle_mod, p)
+    M = oracle_mod.jacobi_preconditioner(H)
+    assert np.all(M == 1.0 / 3.0)
+    opts = dict(tol=1e-14, k_rot=0, max_iter=15)
+    base = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(**opts))
+    pre = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(precondition=True, **opts))
+    assert np.allclose(pre.energies, base.energies, rtol=1e-13, atol=0)
+    g0, g1 = np.array(base.gammas), np.array(pre.gammas)
+    assert g0[0] == 0 and g1[0] == 0 and np.all(g0[1:] != 0)
+    # equal up to rounding amplified by the recurrences over 15 iterations
+    assert np.max(np.abs(g1 - g0)) <= 1e-10 * np.max(np.abs(g0))
+    ratio = np.array(pre.alphas) / np.array(base.alphas)
+    assert np.max(np.abs(ratio - 3.0)) < 1e-10
+
+
+# ------------------------------------------------ generalized H x = lambda S x
+
+def fem_spectrum(n, ndim, bc, scale=0.5):
+    """Generalized eigenvalues of Q1 finite elements on a uniform grid: in 1-D
+    K u = mu M u with u_j = sin(j theta) or exp(i j theta) gives
+    mu = 6 (1 - cos theta) / (2 + cos theta); tensor products add them."""
+    if bc == "periodic":
+        th = 2 * np.pi * np.arange(n) / n
+    else:
+        th = np.arange(1, n + 1) * np.pi / (n + 1)
+    mu = 6.0 * (1.0 - np.cos(th)) / (2.0 + np.cos(th))
+    tot = mu
+    for _ in range(ndim - 1):
+        tot = (tot[..., None] + mu).reshape(-1)
+    return np.sort(scale * tot)
+
+
+def _gen_mats(oracle_mod, p):
+    H = oracle_mod.csr_matrix(*p.csr_H(), p.N)
+    S = oracle_mod.csr_matrix(*p.csr_S(), p.N)
+    return H, S
+
+
+def test_generalized_fem_closed_form(oracle_mod):
+    """Q1 finite elements, 3-D periodic 8^3, m = 7 (the constant mode and the
+    six +-1 modes): E_G and the Ritz values against the closed form; C is
+    S-orthonormal and every residual ||H c_j - lambda_j S c_j|| is small."""
+    from workloads import fem_problem
+    p = fem_problem("f8", 3, 8, 7, "periodic", seed=3)
+    H, S = _gen_mats(oracle_mod, p)
+    lam = fem_spectrum(8, 3, "periodic")
+    assert lam[7] - lam[6] > 0.1
+    r = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(tol=1e-10, k_rot=50), S=S)
+    assert r.converged
+    assert abs(r.E_G - lam[:7].sum()) < 1e-12 * max(1.0, lam[:7].sum())
+    assert np.max(np.abs(r.eigenvalues - lam[:7])) < 1e-11
+    assert r.orth_err < 1e-13 and r.max_residual < 1e-9
+    C = r.C
+    assert np.max(np.abs(C.T @ (S @ C) - np.eye(7))) < 1e-13
+
+
+def test_generalized_2d_dirichlet_closed_form(oracle_mod):
+    from workloads import fem_problem
+    n = 14
+    lam = fem_spectrum(n, 2, "dirichlet", scale=1.0)
+    m = next(k for k in range(10, 40) if lam[k] - lam[k - 1] > 1e-2)
+    p = fem_problem("f2d", 2, n, m, "dirichlet", seed=4, kinetic_scale=1.0)
+    H, S = _gen_mats(oracle_mod, p)
+    r = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(tol=1e-10, k_rot=50), S=S)
+    assert r.converged
+    assert abs(r.E_G - lam[:m].sum()) < 1e-12 * lam[:m].sum()
+
+
+def test_generalized_reduces_to_standard(oracle_mod):
+    """S = I gives the standard iteration (same energies, same E_G); S = c I
+    divides every eigenvalue by c."""
+    import scipy.sparse as sp
+    p = make_problem("s", StencilSpec(3, (6, 6, 6), 2, "periodic", 0.5), m=7, seed=31, n_wells=2)
+    H = _H(oracle_mod, p)
+    o = oracle_mod.OracleOptions(tol=1e-10, k_rot=50)
+    base = oracle_mod.solve(H, p.C0(), o)
+    I = sp.identity(p.N, format="csr")
+    same = oracle_mod.solve(H, p.C0(), o, S=I)
+    k = min(len(base.energies), len(same.energies), 40)
+    assert np.allclose(same.energies[:k], base.energies[:k], rtol=1e-12, atol=0)
+    assert abs(same.E_G - base.E_G) < 1e-12 * abs(base.E_G)
+    c = 2.5
+    scaled = oracle_mod.solve(H, p.C0(), o, S=c * I)
+    assert abs(scaled.E_G - base.E_G / c) < 1e-12 * abs(base.E_G)
+
+
+def test_generalized_brute_force_with_wells(oracle_mod):
+    """Tiny FEM grid with wells: iterative E_G equals the brute-force
+    Cholesky reduction plus dense Jacobi, with scipy's generalized eigh (not
+    used by the oracle) as an outside witness."""
+    import scipy.linalg as sl
+    from workloads import fem_problem
+    p = fem_problem("fw", 3, 6, 9, "periodic", seed=23, n_wells=3)
+    Hd, Sd = p.dense()
+    E_bf, w, gap = oracle_mod.brute_force_generalized(Hd, Sd, p.m)
+    assert gap > 1e-3
+    assert np.max(np.abs(w - sl.eigh(Hd, Sd, eigvals_only=True))) < 1e-11
+    H, S = _gen_mats(oracle_mod, p)
+    r = oracle_mod.solve(H, p.C0(), oracle_mod.OracleOptions(tol=1e-10, k_rot=50), S=S)
+    assert r.converged
+    assert abs(r.E_G - E_bf) < 1e-12 * abs(E_bf)
+    assert np.max(np.abs(r.eigenvalues - w[:p.m])) < 1e-11
+
+
+def _omega_gen(H, S, C, P, a):
+    B = C + a * P
+    return float(np.trace(np.linalg.solve(B.T @ (S @ B), B.T @ (H @ B))))
+
+
+def test_generalized_gradient_and_curvature(oracle_mod):
+    """-tr(P^T G) is the slope of E along P under the S constraint, and at an
+    S-orthonormal Ritz basis with P S-orthogonal to C the line step's
+    curvature 2 sum_j (p_j.H p_j - A_jj p_j.S p_j) is the second derivative
+    (central differences, O(eps^2))."""
+    import scipy.linalg as sl
+    from workloads import fem_problem
+    p = fem_problem("fg", 3, 6, 6, "periodic", seed=5, n_wells=2)
+    H, S = _gen_mats(oracle_mod, p)
+    C = oracle_mod.orthonormalize_generalized(S, p.C0())
+    A = C.T @ (H @ C)
+    _, U = sl.eigh(0.5 * (A + A.T))
+    C = C @ U
+    E0, G, X, A, Z = oracle_mod.energy_gradient_generalized(H, S, C)
+    assert np.max(np.abs(A - np.diag(np.diag(A)))) < 1e-12 * np.max(np.abs(A))
+    assert np.max(np.abs(C.T @ G)) < 1e-12 * np.linalg.norm(G)
+    P = np.random.default_rng(8).standard_normal(C.shape)
+    eps = 1e-5
+    fd = (_omega_gen(H, S, C, P, eps) - _omega_gen(H, S, C, P, -eps)) / (2 * eps)
+    assert abs(fd - (-np.sum(P * G))) < 1e-6 * abs(fd)
+    P -= C @ (Z.T @ P)                       # S-orthogonal to C
+    P /= np.sqrt(np.einsum("ij,ij->j", P, S @ P))[None, :]
+    assert np.max(np.abs(Z.T @ P)) < 1e-12
+    Y, SP = H @ P, S @ P
+    _, info = oracle_mod.line_step(P, Y, G, np.diag(A).copy(), SP)
+    curv = info["curv"]
+    om0 = _omega_gen(H, S, C, P, 0.0)
+    errs = []
+    for e in (4e-3, 2e-3, 1e-3):
+        fd2 = (_omega_gen(H, S, C, P, e) - 2 * om0 + _omega_gen(H, S, C, P, -e)) / e ** 2
+        errs.append(abs(fd2 - curv) / abs(curv))
+    assert errs[-1] < 1e-5 and errs[0] / errs[1] > 3.0
+
+
+# ------------------------------------- polynomial (non-diagonal) preconditioner
+
+def test_chebyshev_preconditioner_closed_form(oracle_mod):
+    """On an eigenvector v of H (a Fourier mode of the periodic Laplacian,
+    eigenvalue lam) the Chebyshev-iteration preconditioner acts as p(lam) v
+    with p(x) = (1 - T_s((theta - (x - sigma)) / delta) / T_s(theta / delta))
+    / (x - sigma), T_s the Chebyshev polynomial (cos(s arccos t) inside
+    [-1, 1], cosh(s arccosh t) above); p > 0 on the spectrum, so M is
+    symmetric positive definite, and the Gershgorin interval contains the
+    spectrum."""
+    n = 10
+    p = make_problem("k", StencilSpec(3, (n, n, n), 2, "periodic", 0.5), m=1, seed=1)
+    H = _H(oracle_mod, p)
+    lo, hi = oracle_mod.gershgorin_bounds(H)
+    assert lo == pytest.approx(0.0, abs=1e-15) and hi == pytest.approx(6.0, abs=1e-15)
+    x, y, z = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    for deg in (1, 2, 4, 7):
+        M = oracle_mod.chebyshev_preconditioner(H, degree=deg, shift=0.02)
+        a, b = M.interval
+        theta, delta = 0.5 * (a + b), 0.5 * (b - a)
+
+        def T(s, t):
+            t = np.asarray(t, dtype=float)
+            return np.where(np.abs(t) <= 1, np.cos(s * np.arccos(np.clip(t, -1, 1))),
+                            np.cosh(s * np.arccosh(np.maximum(np.abs(t), 1.0))) * np.sign(t) ** s)
+
+        for k in ((0, 0, 0), (1, 0, 0), (2, 3, 1), (5, 5, 5)):
+            th = 2 * np.pi * np.array(k) / n
+            lam = float(np.sum(1 - np.cos(th)))
+            v = np.cos(th[0] * z + th[1] * y + th[2] * x).reshape(-1, 1)   # x fastest
+            assert np.allclose(H @ v, lam * v, atol=1e-12)
+            xs = lam - M.sigma
+            want = (1.0 - T(deg, (theta - xs) / delta) / T(deg, theta / delta)) / xs
+            got = M(v)
+            assert np.max(np.abs(got - want * v)) < 1e-12 * max(1.0, abs(want))
+            assert want > 0
+
+
+def test_chebyshev_preconditioner_spd_and_solve(oracle_mod):
+    """M = p(H) formed densely on a tiny wells problem is symmetric with
+    positive eigenvalues, and the preconditioned solve reaches the closed-form
+    C1 energy in far fewer iterations than plain CG."""
+    p = make_problem("w5", StencilSpec(3, (5, 5, 5), 2, "periodic", 0.5), m=4, seed=2, n_wells=2)
+    H = _H(oracle_mod, p)
+    M = oracle_mod.chebyshev_preconditioner(H, degree=4)
+    Md = M(np.eye(p.N))
+    assert np.max(np.abs(Md - Md.T)) < 1e-13 * np.max(np.abs(Md))
+    assert np.linalg.eigvalsh(0.5 * (Md + Md.T)).min() > 0
+    q = config_problem("c1")
+    Hq = _H(oracle_mod, q)
+    plain = oracle_mod.solve(Hq, q.C0(), oracle_mod.OracleOptions(tol=1e-9, k_rot=50))
+    pre = oracle_mod.solve(Hq, q.C0(), oracle_mod.OracleOptions(tol=1e-9, k_rot=50, chebyshev=4))
+    exact = 54 * (1 - math.cos(math.pi / 8))
+    assert pre.converged and abs(pre.E_G - exact) < 1e-12 * exact
+    assert pre.iterations < 0.5 * plain.iterations

@@ -18,4 +18,6 @@ from .problems import (  # noqa: F401
     serving_stream,
     serving_problem,
     CONFIGS,
+    GenProblem,
+    fem_problem,
 )

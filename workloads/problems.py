@@ -273,6 +273,124 @@ CONFIGS: Dict[str, tuple] = {
 }
 
 
+# ------------------------------------------------------------ H x = lambda S x
+# Linear finite elements on a uniform grid (spacing 1): the basis functions are
+# not orthogonal, so the discretized problem is the generalized one the paper
+# names for nonorthogonal bases (Sec. 2.1).  In 1-D the stiffness and mass
+# matrices are K = tridiag(-1, 2, -1) and M = tridiag(1, 4, 1) / 6; on a
+# tensor-product (Q1) grid H = kinetic_scale * sum_d M x .. x K_d x .. x M
+# (+ diag(V)) and S = M x M (x M), both 9-point (2-D) or 27-point (3-D).
+
+def _fem_1d(n: int, bc: str):
+    import scipy.sparse as sp
+    if bc == "periodic":
+        if n < 3:
+            raise ValueError("periodic FEM needs n >= 3")
+        K = sp.diags([2.0] * n, 0, format="lil")
+        M = sp.diags([4.0 / 6.0] * n, 0, format="lil")
+        for i in range(n):
+            for j in ((i - 1) % n, (i + 1) % n):
+                K[i, j] = K[i, j] - 1.0
+                M[i, j] = M[i, j] + 1.0 / 6.0
+        return K.tocsr(), M.tocsr()
+    if bc != "dirichlet":
+        raise ValueError(f"unknown boundary condition {bc!r}")
+    K = sp.diags([[-1.0] * (n - 1), [2.0] * n, [-1.0] * (n - 1)], [-1, 0, 1], format="csr")
+    M = sp.diags([[1.0 / 6.0] * (n - 1), [4.0 / 6.0] * n, [1.0 / 6.0] * (n - 1)], [-1, 0, 1],
+                 format="csr")
+    return K, M
+
+
+def _csr_arrays(A):
+    A = A.tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return (A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+@dataclasses.dataclass
+class GenProblem:
+    """H x = lambda S x from Q1 finite elements: CSR arrays of H and S, m, C_0."""
+
+    name: str
+    ndim: int
+    n: int
+    bc: str
+    m: int
+    seed: int
+    kinetic_scale: float = 0.5
+    n_wells: int = 0
+    V: Optional[np.ndarray] = None
+    _mats: Optional[tuple] = dataclasses.field(default=None, repr=False)
+    _C0: Optional[np.ndarray] = dataclasses.field(default=None, repr=False)
+    _rng_state: Optional[dict] = dataclasses.field(default=None, repr=False)
+
+    @property
+    def N(self) -> int:
+        return self.n ** self.ndim
+
+    def _build(self):
+        import scipy.sparse as sp
+        if self._mats is None:
+            K, M = _fem_1d(self.n, self.bc)
+            H = None
+            for d in range(self.ndim):
+                term = None
+                for a in range(self.ndim):
+                    f = K if a == d else M
+                    term = f if term is None else sp.kron(f, term, format="csr")
+                H = term if H is None else H + term
+            H = self.kinetic_scale * H
+            if self.V is not None:
+                H = H + sp.diags(self.V, 0, format="csr")
+            S = M
+            for _ in range(self.ndim - 1):
+                S = sp.kron(M, S, format="csr")
+            self._mats = (_csr_arrays(H), _csr_arrays(S))
+        return self._mats
+
+    def csr_H(self):
+        return self._build()[0]
+
+    def csr_S(self):
+        return self._build()[1]
+
+    def C0(self) -> np.ndarray:
+        if self._C0 is None:
+            rng = np.random.default_rng()
+            rng.bit_generator.state = self._rng_state
+            self._C0 = start_block(rng, self.N, self.m)
+        return self._C0
+
+    def dense(self):
+        if self.N > 4096:
+            raise ValueError("dense matrices only for N <= 4096")
+        out = []
+        for (rowptr, col, val) in self._build():
+            A = np.zeros((self.N, self.N))
+            for r in range(self.N):
+                A[r, col[rowptr[r]:rowptr[r + 1]]] += val[rowptr[r]:rowptr[r + 1]]
+            out.append(A)
+        return tuple(out)
+
+
+def fem_problem(name: str, ndim: int, n: int, m: int, bc: str = "periodic", seed: int = 0,
+                n_wells: int = 0, kinetic_scale: float = 0.5) -> GenProblem:
+    """Q1 finite-element H x = lambda S x on an n^ndim grid; wells (3-D cubic
+    grids) as in ``make_problem``, added to H's diagonal (lumped mass: the
+    rows of S sum to one)."""
+    rng = np.random.default_rng(seed)
+    V = None
+    if n_wells > 0:
+        if ndim != 3:
+            raise ValueError("wells are defined on cubic 3-D grids")
+        V = gaussian_wells(n, n_wells, rng)
+    p = GenProblem(name=name, ndim=ndim, n=n, bc=bc, m=m, seed=seed,
+                   kinetic_scale=kinetic_scale, n_wells=n_wells, V=V)
+    p._rng_state = rng.bit_generator.state
+    return p
+
+
 def config_problem(name: str, seed: int = 0) -> Problem:
     spec_fn, m, wells = CONFIGS[name]
     return make_problem(name, spec_fn(), m, seed=seed, n_wells=wells)
@@ -311,5 +429,6 @@ def serving_problem(req: dict) -> Problem:
 __all__ = [
     "StencilSpec", "Problem", "stencil_csr", "laplacian_2d_dirichlet_csr",
     "periodic_fd_csr", "gaussian_wells", "start_block", "make_problem",
-    "config_problem", "serving_stream", "serving_problem", "CONFIGS",
+    "config_problem", "serving_stream", "serving_problem", "CONFIGS", "GenProblem",
+    "fem_problem",
 ]

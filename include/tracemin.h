@@ -328,6 +328,21 @@ tm_status tm_spmm(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t dtype,
 tm_status tm_gram(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype,
                   const void *A, const void *B, const double *h, double *out);
 
+/* tm_gram without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, products and result as tm_gram, to rounding:
+ * the padded h and the split-K partials live in a fixed 32 MiB device array
+ * of the library (one per GPU, held until the process ends), so the row
+ * splits are capped to fit it, which may change the summation order.  The
+ * call only enqueues work on the context's stream (no synchronization, no
+ * memset, no allocation); out is valid once the stream gets there.  Every
+ * call on a GPU uses that GPU's one array: calls that overlap on one GPU
+ * (several streams or host threads) race and must be serialized by the
+ * caller.  TM_ENOMEM if even one row split does not fit (m about 2040 or
+ * more). */
+tm_status tm_gram_noalloc(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype,
+                          const void *A, const void *B, const double *h, double *out);
+
 /* out = A W with A an n x ld block and W an m x m FP64 matrix (the subspace
  * rotation C U of the Rayleigh-Ritz step, Eq. 9).  W is rounded to the
  * block's precision. */

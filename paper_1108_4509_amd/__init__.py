@@ -301,6 +301,22 @@ def gram(ctx: Context, m: int, A, B, h=None, out=None, bf16x3: bool = False):
     return out
 
 
+def gram_noalloc(ctx: Context, m: int, A, B, h=None, out=None, bf16x3: bool = False):
+    """tm_gram_noalloc: as ``gram`` with no device allocation inside the
+    library (enqueue only; synchronize the stream before reading out)."""
+    torch = _torch()
+    n = A.shape[0]
+    out = out if out is not None else torch.empty((m, m), dtype=torch.float64, device=A.device)
+    code = _dtype_code(A)
+    if bf16x3:
+        if A.dtype != torch.float32:
+            raise ValueError("bf16x3 takes FP32 blocks")
+        code = 2
+    _abi.check(_abi.lib().tm_gram_noalloc(ctx.handle, n, m, code, _ptr(A), _ptr(B), _ptr(h),
+                                          _ptr(out)), "tm_gram_noalloc")
+    return out
+
+
 def rotate(ctx: Context, m: int, A, W, out=None):
     torch = _torch()
     out = out if out is not None else torch.empty_like(A)

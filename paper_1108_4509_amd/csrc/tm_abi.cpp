@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -12,7 +13,34 @@
 
 using namespace tmin;
 
+// Device memory of tm_gram_noalloc: the padded h and the split-K partials of
+// one Gram product.  Every device the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (kept per device).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Called with `device` current (from tm_create).
+void bind_scratch(int device) {
+    TM_REQUIRE(device >= 0 && device < kMaxDevices, TM_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void *p = nullptr;
+    TM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    TM_REQUIRE(p != nullptr, TM_EDEVICE, "no device address for the scratch array");
+    g_scratch_ptr[device] = p;
+}
+
+void *scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
 
 thread_local std::string g_last_error;
 
@@ -121,6 +149,7 @@ tm_status tm_create(int32_t device, const tm_allocator *alloc, void *stream, tm_
         TM_HIP(hipGetDeviceCount(&count));
         TM_REQUIRE(device >= 0 && device < count, TM_EINVAL, "no such device");
         TM_HIP(hipSetDevice(device));
+        bind_scratch(device);
         tm_ctx *c = new tm_ctx;
         c->device = device;
         c->stream = (hipStream_t)stream;
@@ -498,6 +527,43 @@ tm_status tm_gram(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype, const void *
             gram<float, float>(ctx->stream, n, m, (const float *)A, (const float *)B, hv, false, sym,
                                (double *)ws.ptr, out);
         sync(ctx);
+        return TM_OK;
+    });
+}
+
+tm_status tm_gram_noalloc(tm_ctx *ctx, int64_t n, int32_t m, int32_t dtype, const void *A,
+                          const void *B, const double *h, double *out) {
+    return guarded([&]() {
+        TM_REQUIRE(A && B && out, TM_EINVAL, "null argument");
+        check_block_args(ctx, n, m);
+        TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32 || dtype == TM_BF16X3, TM_EINVAL, "dtype");
+        char *base = (char *)scratch_of(ctx->device);
+        TM_REQUIRE(base != nullptr, TM_EDEVICE, "scratch not bound on this device");
+        const int ld = leading_dim(m);
+        const size_t hbytes = ((size_t)ld * sizeof(double) + 255) / 256 * 256;
+        const size_t avail = kScratchBytes - hbytes;
+        const bool sym = (A == B) && !h;
+        const size_t need = gram_partials_bytes(n, m, sym && dtype != TM_BF16X3, avail);
+        TM_REQUIRE(need <= avail, TM_ENOMEM,
+                   "m = " + std::to_string(m) + " needs " + std::to_string(need + hbytes) +
+                       " bytes of scratch; the allocation-free Gram holds " +
+                       std::to_string(kScratchBytes));
+        hipStream_t s = ctx->stream;
+        const double *hv = nullptr;
+        if (h) {
+            pad_vector(s, m, ld, h, (double *)base);
+            hv = (const double *)base;
+        }
+        double *partials = (double *)(base + hbytes);
+        if (dtype == TM_F64)
+            gram<double, double>(s, n, m, (const double *)A, (const double *)B, hv, false, sym, partials,
+                                 out, true, nullptr, nullptr, avail);
+        else if (dtype == TM_BF16X3)
+            gram_bf16x3<float>(s, n, m, (const float *)A, (const float *)B, hv, false, partials, out,
+                               true, nullptr, avail);
+        else
+            gram<float, float>(s, n, m, (const float *)A, (const float *)B, hv, false, sym, partials,
+                               out, true, nullptr, nullptr, avail);
         return TM_OK;
     });
 }

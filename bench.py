@@ -4,8 +4,11 @@ Workload: 48^3 periodic 7-point FD Hamiltonian -1/2 Lap + V (64 Gaussian
 wells, seed 0), FP64 CSR, m = 256, random N(0,1) start block -- uploaded to
 HBM before the timed region.  One "step" is one complete solve to
 ||X - C A||_F <= 1e-8 followed by the final FP64 Rayleigh-Ritz and residual
-check, in MIXED precision (FP32 bulk, MP2 refinement).  The FP64 solver
-(FULL_DP) is timed on the same input for the comparison the metric asks for.
+check, in MIXED precision (FP32 bulk, MP2 refinement) with the polynomial
+preconditioner of Eq. 18 (Chebyshev iteration, degree 2, applied in FP32).
+The FP64 solver (FULL_DP, same preconditioner, applied in FP64) is timed on the
+same input for the comparison the metric asks for; the unpreconditioned MIXED
+solve is reported among the variants.
 
 Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K,
 --warmup W, --config c1|c2|c3|c4, --no-cpu (skip the oracle baseline).
@@ -130,9 +133,9 @@ def kernel_rooflines(tm, ctx, H, p, reps=20):
 TRAFFIC_CONFIG = "c2"
 TRAFFIC = {
     "rot_grad_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                         "4ad5b16f05d854432ee2869f3725fa32b1862fbe", 2.0 * 282789.1 * 1024 + 124416.0 * 1024),
+                         "c917ae1129d5639b4a8e87ccc7a385c3ae95f1a1", 2.0 * 282735.5 * 1024 + 124416.0 * 1024),
     "gram_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                     "4ad5b16f05d854432ee2869f3725fa32b1862fbe", 2.0 * 326245.1 * 1024 + 164352.0 * 1024),
+                     "c917ae1129d5639b4a8e87ccc7a385c3ae95f1a1", 2.0 * 325083.5 * 1024 + 164352.0 * 1024),
 }
 
 
@@ -147,7 +150,7 @@ def measured_traffic(key):
     return round(nbytes)
 
 
-def serving_bench(tm, n_requests, slots=4, budget=32 << 30):
+def serving_bench(tm, n_requests, slots=4, budget=32 << 30, precondition="chebyshev"):
     """The serving stream (Poisson arrivals, mean 50 ms; grid sides
     {16, 24, 32, 40, 48}; m scaled with N; per-request wells and start block),
     replayed in real time against the continuous-batching server.  Inputs are
@@ -164,7 +167,9 @@ def serving_bench(tm, n_requests, slots=4, budget=32 << 30):
             delay = t0 + r["arrival_s"] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
-            ids.append(srv.submit(*csr, p.m, 1e-8, C0, tm.opts(precision="mixed")))
+            ids.append(srv.submit(*csr, p.m, 1e-8, C0,
+                                  tm.opts(precision="mixed",
+                                          precondition=(precondition if precondition != "none" else False))))
         bad = 0
         for rid in ids:
             res, _ = srv.wait(rid)
@@ -177,9 +182,41 @@ def serving_bench(tm, n_requests, slots=4, budget=32 << 30):
     return {"requests": n_requests, "slots": slots, "hbm_budget_GiB": budget / 2**30,
             "p50_latency_s": round(st["p50_latency_s"], 4), "p99_latency_s": round(st["p99_latency_s"], 4),
             "max_latency_s": round(st["max_latency_s"], 4), "solves_per_s": round(st["solves_per_s"], 3),
+            "p50_queue_wait_s": round(st["p50_wait_s"], 4), "p99_queue_wait_s": round(st["p99_wait_s"], 4),
+            "p50_service_s": round(st["p50_service_s"], 4), "p99_service_s": round(st["p99_service_s"], 4),
+            "precondition": precondition,
             "completed": st["completed"], "failed": st["failed"] + bad, "wall_s": round(wall, 3),
             "arrivals_span_s": round(reqs[-1]["arrival_s"], 3),
             "hbm_peak_GiB": round(st["hbm_peak"] / 2**30, 3)}
+
+
+def certify(p, C, w, res):
+    """FP64 host check of a GPU result from the returned Ritz pairs alone:
+    max_j ||H c_j - lambda_j c_j|| (H from the problem's CSR arrays),
+    max |C^T C - I| and |sum_j c_j^T H c_j - E_G| / |E_G|.  Plain numpy /
+    scipy on the host; the oracle is not involved."""
+    import numpy as np
+    import scipy.sparse as sp
+    t0 = time.perf_counter()
+    m = p.m
+    Ch = C[:, :m].cpu().numpy()
+    wh = w.cpu().numpy()
+    rowptr, col, val = p.csr()
+    H = sp.csr_matrix((val, col, rowptr), shape=(p.N, p.N))
+    X = np.asarray(H @ Ch)
+    rq = np.einsum("ij,ij->j", Ch, X)
+    X -= Ch * wh[None, :]
+    col_res = np.linalg.norm(X, axis=0)
+    del X
+    S = Ch.T @ Ch
+    S[np.diag_indices(m)] -= 1.0
+    out = {"max_residual": float(col_res.max()), "orth_err": float(np.abs(S).max()),
+           "rayleigh_E_rel_diff": abs(float(rq.sum()) - res["E_G"]) / abs(res["E_G"]),
+           "ritz_value_max_diff": float(np.abs(rq - wh).max()),
+           "seconds": round(time.perf_counter() - t0, 1)}
+    out["passed"] = bool(out["max_residual"] <= 1e-8 and out["orth_err"] <= 1e-12
+                         and out["rayleigh_E_rel_diff"] <= 1e-12)
+    return out
 
 
 def eq16_lowest(n, m):
@@ -286,14 +323,25 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--precision", default="mixed", help="precision of the timed steps")
+    ap.add_argument("--precondition", default="chebyshev", choices=("none", "diagonal", "chebyshev"),
+                    help="Eq. 18 preconditioner of every solve (diagonal M or the polynomial M)")
+    ap.add_argument("--cheb-degree", type=int, default=2)
+    ap.add_argument("--stall-tol", type=float, default=0.0,
+                    help="MIXED: leave the bulk phase when E drops by less than this relative amount "
+                         "over 25 iterations (0: the library default)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the BF16 / FULL_SP variant solves")
     ap.add_argument("--max-iter", type=int, default=20000,
                     help="iteration cap of each solve (a capped solve is reported as such)")
-    ap.add_argument("--serving", type=int, default=40,
+    ap.add_argument("--serving", type=int, default=200,
                     help="requests of the serving stream replayed after the solves (0: none)")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving stream (with --serving requests)")
+    ap.add_argument("--certify", action="store_true",
+                    help="after the timed solves, check the MIXED result in FP64 on the host: "
+                         "residuals, orthonormality and the Rayleigh quotient from the returned C")
+    ap.add_argument("--stencil", action="store_true",
+                    help="upload H as a stencil descriptor instead of CSR")
     ap.add_argument("--table1", action="store_true",
                     help="only the paper's Table 1 on this GPU (s/iter per policy, N_iter)")
     ap.add_argument("--table1-rows", default="",
@@ -326,9 +374,9 @@ def main():
                               "accuracy": accuracy_bench(tm, ctx)}), flush=True)
         return
     p = config_problem(a.config)
-    log(f"bench: config {a.config} N={p.N} m={p.m}")
+    log(f"bench: config {a.config} N={p.N} m={p.m} {'stencil' if a.stencil else 'CSR'}")
     ctx = tm.Context(0)
-    H = tm.matrix_from_problem(ctx, p)
+    H = tm.matrix_from_problem(ctx, p, stencil=a.stencil)
     if a.serving_only:
         sv = serving_bench(tm, a.serving)
         print(json.dumps({"metric": "serving stream: p50/p99 latency (s) and solves/s, MIXED",
@@ -350,13 +398,27 @@ def main():
     torch.cuda.synchronize()
     tol = 1e-8
 
-    def run(precision):
+    def run(precision, want_vectors=False, precondition=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        pc = {"none": False, "diagonal": True, "chebyshev": "chebyshev"}[precondition or a.precondition]
+        last = [time.perf_counter()]
+
+        def progress(it, E, rho, phase):
+            # the solver's own poll reports, at most one line per 20 s
+            now = time.perf_counter()
+            if now - last[0] >= 20.0:
+                last[0] = now
+                log(f"  {precision}: iteration {it} phase {phase} E {E:.12f} rho {rho:.3e}")
+
         r, C, w, _ = tm.solve(ctx, H, p.m, tol, C0,
-                              tm.opts(precision=precision, max_iter=a.max_iter),
-                              want_vectors=False)
+                              tm.opts(precision=precision, max_iter=a.max_iter, precondition=pc,
+                                      cheb_degree=a.cheb_degree, stall_tol=a.stall_tol,
+                                      progress=progress),
+                              want_vectors=want_vectors)
         torch.cuda.synchronize()
+        if want_vectors:
+            run.vectors = (C, w)
         return time.perf_counter() - t0, r
 
     for i in range(a.warmup):
@@ -366,7 +428,7 @@ def main():
     torch.cuda.synchronize()
     t_begin = time.perf_counter()
     for i in range(a.steps):
-        t, res = run(a.precision)
+        t, res = run(a.precision, want_vectors=a.certify and i == a.steps - 1)
         times.append(t)
         log(f"step {i} {a.precision} {t:.3f}s iters={res['iterations']} sp={res['iters_sp']} "
             f"E_G={res['E_G']:.15f} maxres={res['max_residual']:.2e} converged={res['converged']}")
@@ -392,8 +454,13 @@ def main():
 
     # the two-term BF16 bulk variant, and its bulk phase alone (accuracy floor)
     variants = {}
-    for prec in (() if a.no_variants else ("mixed_bf16", "full_bf16", "full_sp")):
-        t, rv = run(prec)
+    variant_runs = [] if a.no_variants else [("mixed_bf16", None), ("full_bf16", None), ("full_sp", None)]
+    if not a.no_variants and a.precondition != "none":
+        variant_runs.insert(0, ("mixed", "none"))     # the same solve without Eq. 18
+    for prec, pcv in variant_runs:
+        t, rv = run(prec, precondition=pcv)
+        if pcv:
+            prec = f"{prec}_no_precondition"
         variants[prec] = {"seconds": round(t, 4), "iterations": rv["iterations"],
                           "iters_bulk": rv["iters_sp"], "E_G": rv["E_G"],
                           "rel_err_vs_oracle": err(rv["E_G"]),
@@ -405,6 +472,12 @@ def main():
         log(f"{prec} {t:.3f}s iters={rv['iterations']} err={variants[prec]['rel_err_vs_oracle']} "
             f"vs_fp64={variants[prec].get('rel_err_vs_fp64_solve')}")
 
+    certification = None
+    if a.certify:
+        certification = certify(p, *run.vectors, res)
+        log(f"certification {certification}")
+        del run.vectors
+        torch.cuda.empty_cache()
     roofline, kernels = kernel_rooflines(tm, ctx, H, p)
     serving = None
     if a.serving > 0:
@@ -425,8 +498,12 @@ def main():
         "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{a.config}: 48^3 periodic 7-point -1/2 Lap + 64 Gaussian wells, "
-                               f"FP64 CSR, N={p.N}, m={p.m}, tol 1e-8, MIXED (FP32 bulk + MP2 refinement)"
-                   if a.config == "c2" else f"{a.config}: N={p.N}, m={p.m}"},
+                               f"FP64 {'stencil' if a.stencil else 'CSR'}, N={p.N}, m={p.m}, tol 1e-8, "
+                               f"{a.precision.upper()} (FP32 bulk + MP2 refinement)"
+                               + (f", {a.precondition} preconditioner" if a.precondition != "none" else "")
+                   if a.config == "c2" else
+                   f"{a.config}: N={p.N}, m={p.m}, {'stencil' if a.stencil else 'CSR'}, {a.precision}"
+                   + (f", {a.precondition} preconditioner" if a.precondition != "none" else "")},
         "fp64_seconds": round(fp64, 4) if fp64 else None,
         "speedup_vs_fp64": round(fp64 / value, 3) if fp64 else None,
         "iterations": res["iterations"], "iters_fp32": res["iters_sp"],
@@ -434,6 +511,7 @@ def main():
         "E_G": res["E_G"], "rel_err_vs_oracle": rel_err, "max_residual": res["max_residual"],
         "converged": res["converged"], "variants": variants,
         "roofline": roofline, "kernels": kernels, "serving": serving, "cpu_baseline": cpu,
+        "certification": certification,
     }
     print(json.dumps(line), flush=True)
 

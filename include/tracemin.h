@@ -116,6 +116,13 @@ typedef struct tm_stencil {
     const double *V;       /* host, N values added to the diagonal, or NULL  */
 } tm_stencil;
 
+/* Progress report of a running solve: called on the solving thread each
+ * time the host polls the device (every k_check iterations) with the
+ * iterations done, the current energy E_i, rho_i and the phase (0 first,
+ * 1 second).  Must not call back into the library. */
+typedef void (*tm_progress_fn)(int32_t iterations, double E, double rho, int32_t phase,
+                               void *user);
+
 typedef struct tm_opts {
     int32_t precision;     /* tm_precision                                   */
     int32_t max_iter;      /* total CG iterations over all phases            */
@@ -139,10 +146,12 @@ typedef struct tm_opts {
                               than stall_tol*|E| over 25 iterations (<= 0: 1e-7) */
     uint64_t seed;         /* tm_solve with C0 = NULL: the start block is
                               tm_random_block(seed) (standard normal entries) */
-    int32_t cheb_degree;   /* precondition = 2: steps (>= 1; 3 by default)   */
+    int32_t cheb_degree;   /* precondition = 2: steps (>= 1; 2 by default)   */
     int32_t reserved;      /* 0 */
     double cheb_shift;     /* precondition = 2: sigma below the Gershgorin
                               interval, as a fraction of its width (0.02)   */
+    tm_progress_fn progress;  /* NULL: no reports                            */
+    void *progress_user;
 } tm_opts;
 
 typedef struct tm_result {
@@ -286,6 +295,10 @@ typedef struct tm_server_stats {
     double solves_per_s;   /* finished requests / span_s                        */
     uint64_t hbm_budget;
     uint64_t hbm_peak;     /* largest sum of admitted memory bounds             */
+    double p50_wait_s;     /* submit -> admission (queue wait), percentiles     */
+    double p99_wait_s;
+    double p50_service_s;  /* admission -> result (the solve on the GPU)        */
+    double p99_service_s;
 } tm_server_stats;
 
 /* Device bytes tm_solve may allocate for an n x m problem with nnz stored

@@ -210,9 +210,12 @@ def random_block(ctx: Context, n: int, m: int, seed: int):
 
 def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition=False,
          history=False, switch_tol=0.0, rise_tol=1e-13, transport=None,
-         stall_tol=0.0, graphs=None, seed=0, cheb_degree=None, cheb_shift=None) -> _abi.tm_opts:
+         stall_tol=0.0, graphs=None, seed=0, cheb_degree=None, cheb_shift=None,
+         progress=None) -> _abi.tm_opts:
     """tm_opts; precondition: False, True / "diagonal" (Eq. 18 with the
-    diagonal M) or "chebyshev" (the polynomial M of cheb_degree steps)."""
+    diagonal M) or "chebyshev" (the polynomial M of cheb_degree steps).
+    progress: optional callable(iterations, E, rho, phase), called at each
+    host poll of a running solve."""
     o = _abi.tm_opts()
     _abi.lib().tm_opts_default(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -233,6 +236,10 @@ def opts(precision="full_dp", max_iter=20000, k_rot=50, k_check=10, precondition
     if transport is not None:
         o.transport = 1 if transport else 0
     o.seed = int(seed)
+    if progress is not None:
+        cb = _abi.PROGRESS_FN(lambda it, E, rho, ph, _u: progress(it, E, rho, ph))
+        o.progress = cb
+        o._keep_progress = cb     # the C function pointer lives as long as the options
     return o
 
 

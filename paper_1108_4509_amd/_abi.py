@@ -38,13 +38,16 @@ class tm_stencil(ctypes.Structure):
                 ("V", ctypes.POINTER(c_double))]
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, c_int32, c_double, c_double, c_int32, c_void_p)
+
+
 class tm_opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("max_iter", c_int32), ("k_rot", c_int32),
                 ("k_check", c_int32), ("precondition", c_int32), ("history", c_int32),
                 ("transport", c_int32), ("graphs", c_int32),
                 ("switch_tol", c_double), ("rise_tol", c_double), ("stall_tol", c_double),
                 ("seed", ctypes.c_uint64), ("cheb_degree", c_int32), ("reserved", c_int32),
-                ("cheb_shift", c_double)]
+                ("cheb_shift", c_double), ("progress", PROGRESS_FN), ("progress_user", c_void_p)]
 
 
 class tm_result(ctypes.Structure):
@@ -76,7 +79,9 @@ class tm_server_stats(ctypes.Structure):
                 ("p50_latency_s", c_double), ("p99_latency_s", c_double),
                 ("max_latency_s", c_double), ("mean_latency_s", c_double),
                 ("span_s", c_double), ("solves_per_s", c_double),
-                ("hbm_budget", ctypes.c_uint64), ("hbm_peak", ctypes.c_uint64)]
+                ("hbm_budget", ctypes.c_uint64), ("hbm_peak", ctypes.c_uint64),
+                ("p50_wait_s", c_double), ("p99_wait_s", c_double),
+                ("p50_service_s", c_double), ("p99_service_s", c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

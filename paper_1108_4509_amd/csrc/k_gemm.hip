@@ -434,9 +434,20 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, boo
 // of the stage, g = t / (BM/2).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// x rounded once to the 8 significant bits of BF16, in FP64: Veltkamp's
+// splitting (Dekker 1971) with the constant 2^45 + 1 keeps the leading
+// 53 - 45 = 8 bits of x rounded to nearest.  The result converts to FP32 and
+// then to BF16 exactly, so FP64 operands are not rounded twice (through FP32).
+__device__ inline double round_bf16_bits(double x) {
+    const double t = x * 35184372088833.0;   // 2^45 + 1
+    return t - (t - x);
+}
+
+// Two-term BF16 operand: hi = x to 8 bits, lo = the rest to 8 bits.
 __device__ inline void split_bf16(double x, __bf16 &hi, __bf16 &lo) {
-    hi = (__bf16)(float)x;
-    lo = (__bf16)(float)(x - (double)(float)hi);
+    const double h = round_bf16_bits(x);
+    hi = (__bf16)(float)h;
+    lo = (__bf16)(float)round_bf16_bits(x - h);
 }
 
 template <typename TA, int BM, bool SHIFT>

@@ -9,6 +9,8 @@
 // hit that XCD's L2) and move 16-byte vectors per lane along the m columns.
 #include "tm_common.h"
 
+#include <algorithm>
+
 namespace tmin {
 namespace {
 
@@ -327,19 +329,18 @@ __global__ __launch_bounds__(256) void spmm_csr_wave_kernel(
 // workgroup's row pointers, columns and values are staged in LDS first (two
 // round trips for all its rows), and each lane group gathers two rows at a
 // time.
-constexpr int kChunkLanes = 16;
-constexpr int kChunkRows = 64;   // rows per workgroup (more when n / 64 exceeds kGridCap)
+constexpr int kChunkRows = 64;   // rows per workgroup
 constexpr int kChunkMeta = 1024; // staged nonzeros per workgroup
 
-template <typename T, int UB, int RG>
+template <typename T, int L, int UB, int RG>
 __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
     int64_t n, int rows_per_block, int nrb, int nchunks, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const T *__restrict__ val,
     const typename Vec<T>::type *__restrict__ C, typename Vec<T>::type *__restrict__ X,
-    int ldv, int ndot, double *__restrict__ partials) {
+    int ldv, int ndot, double *__restrict__ partials, SpmmEpi epi) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::W;
-    constexpr int L = kChunkLanes, RPW = 64 / L, RPP = 4 * RPW;
+    constexpr int RPW = 64 / L, RPP = 4 * RPW;
     __shared__ double red[2][RPP][L * W];
     __shared__ int64_t rp[257];
     __shared__ int32_t cs[kChunkMeta];
@@ -370,16 +371,27 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int w = 0; w < W; ++w) ds[p][w] = 0.0;
-    auto finish = [&](int64_t r, const V &acc) {
-        X[r * ldv + cv] = acc;
-        if (ndot > 0) {
+    const T ea = (T)epi.a, eb = (T)epi.b;
+    const V *E = reinterpret_cast<const V *>(epi.E);
+    auto finish = [&](int64_t r, V acc) {
+        if (epi.affine || ndot > 0) {
             const V c = C[r * ldv + cv];
+            if (epi.affine) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                ds[0][w] += (double)c[w] * (double)acc[w];
-                if (ndot > 1) ds[1][w] += (double)c[w] * (double)c[w];
+                for (int w = 0; w < W; ++w) acc[w] = fma(eb, acc[w], ea * c[w]);
+            }
+            if (ndot > 0) {
+                V e = V(0);
+                if (ndot == 3) e = E[r * ldv + cv];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    ds[0][w] += (double)c[w] * (double)acc[w];
+                    if (ndot == 2) ds[1][w] += (double)c[w] * (double)c[w];
+                    if (ndot == 3) ds[1][w] += (double)e[w] * (double)acc[w];
+                }
             }
         }
+        X[r * ldv + cv] = acc;
     };
     if (staged) {
         // RG rows per lane group at a time (rows i, i + RPP, ...), UB
@@ -437,7 +449,7 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
         const int ld = ldv * W;
         if (t < 2 * L * W) {
             const int p = t / (L * W), e = t - p * (L * W);
-            if (p < ndot) {
+            if (p < (ndot == 3 ? 2 : ndot)) {
                 double sum = 0.0;
                 for (int g = 0; g < RPP; ++g) sum += red[p][g][e];
                 partials[((int64_t)p * nrb + rb) * ld + chunk * L * W + e] = sum;
@@ -512,6 +524,165 @@ __global__ __launch_bounds__(256) void spmm_stencil_wave_kernel(
     if (ndot > 0) flush_wave_dots<T, NCV>(ds, ndot, wave, lane, lb, partials, red);
 }
 
+// 3-D second-order (7-point) stencil, marching along z.  A workgroup owns a
+// TX x TY tile of the xy plane, one 16-lane column chunk (16-byte vectors per
+// lane) and a slab of ZS planes.  Each of its 16 point slots keeps the values
+// of its NPT points at planes z-1, z, z+1 in registers, so every element of C
+// is loaded once per slab (plus one plane at each slab end) instead of being
+// gathered by its six neighbours; the in-plane neighbours come from the plane's
+// tile and its one-point halo ring, staged in LDS.  Dirichlet boundaries read
+// zeros outside the grid; periodic ones wrap (a ragged last tile holds the
+// periodic images, so its active points see the right neighbours).  The fused
+// column dots are summed per workgroup in FP64 and written as the partial row
+// (zslab * nty + ty) * ntx + tx.
+constexpr int kZL = 16;    // lanes per column chunk
+
+template <typename T, int TX, int TY, int ZS, int NDOT>
+__global__ __launch_bounds__(256) void spmm_stencil_zmarch_kernel(
+    StencilDev H, int ldv, const T *__restrict__ Vpot, const typename Vec<T>::type *__restrict__ C,
+    typename Vec<T>::type *__restrict__ X, int ntx, int nty, int nzs, int nch,
+    double *__restrict__ partials, SpmmEpi epi) {
+    constexpr int ndot = NDOT;
+    using V = typename Vec<T>::type;
+    const V *E = reinterpret_cast<const V *>(epi.E);
+    constexpr int W = Vec<T>::W;
+    constexpr int L = kZL, NS = 256 / L, NP = TX * TY, NPT = NP / NS;
+    static_assert(NP % NS == 0, "tile");
+    constexpr int HX = TX + 2, HY = TY + 2;
+    __shared__ V tile[HY * HX * L];
+    __shared__ double red[NDOT > 0 ? 2 : 1][NDOT > 0 ? NS : 1][NDOT > 0 ? L * W : 1];
+    const int nx = H.nx, ny = H.ny, nz = H.nz;
+    const bool per = H.periodic != 0;
+    const int64_t lb = logical_block(gridDim.x);
+    const int64_t nblk = (int64_t)ntx * nty * nzs;
+    if (lb >= nblk * nch) return;   // uniform
+    const int ch = (int)(lb / nblk);
+    const int64_t cb = lb - (int64_t)ch * nblk;   // partial row of this workgroup
+    const int tx = (int)(cb % ntx), ty = (int)((cb / ntx) % nty), zsb = (int)(cb / ((int64_t)ntx * nty));
+    const int t = threadIdx.x, l = t % L, slot = t / L;
+    const int cv = ch * L + l;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = zsb * ZS;
+    const int z1 = min(z0 + ZS, nz);
+    const int64_t plane = (int64_t)nx * ny;
+    const T c0 = (T)H.c0, c1 = (T)H.c1;
+    auto wrap = [](int c, int e) {
+        c %= e;
+        return c < 0 ? c + e : c;
+    };
+    int px[NPT], py[NPT];
+    bool act[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int p = slot + k * NS;
+        px[k] = x0 + p % TX;
+        py[k] = y0 + p / TX;
+        act[k] = px[k] < nx && py[k] < ny;
+        if (per) {
+            px[k] = wrap(px[k], nx);
+            py[k] = wrap(py[k], ny);
+        }
+    }
+    // value at (x, y, zz) of this lane's column vector; zero outside a
+    // Dirichlet grid
+    auto load = [&](int x, int y, int zz) -> V {
+        if (per) {
+            zz = wrap(zz, nz);
+        } else if (zz < 0 || zz >= nz || x < 0 || x >= nx || y < 0 || y >= ny) {
+            return V(0);
+        }
+        return C[((int64_t)zz * plane + (int64_t)y * nx + x) * ldv + cv];
+    };
+    V c[NPT][3];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        c[k][0] = load(px[k], py[k], z0 - 1);
+        c[k][1] = load(px[k], py[k], z0);
+    }
+    double ds[2][W];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int w = 0; w < W; ++w) ds[p][w] = 0.0;
+    for (int z = z0; z < z1; ++z) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) c[k][2] = load(px[k], py[k], z + 1);
+        __syncthreads();   // the previous plane's tile has been read
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int p = slot + k * NS;
+            tile[((p / TX + 1) * HX + (p % TX + 1)) * L + l] = c[k][1];
+        }
+        // the halo ring: the two full rows, then the two side columns
+        constexpr int NH = 2 * HX + 2 * TY;
+        for (int h = slot; h < NH; h += NS) {
+            int hx, hy;
+            if (h < HX) { hy = 0; hx = h; }
+            else if (h < 2 * HX) { hy = HY - 1; hx = h - HX; }
+            else { const int g = h - 2 * HX; hy = 1 + g / 2; hx = (g & 1) ? HX - 1 : 0; }
+            int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+            if (per) {
+                gx = wrap(gx, nx);
+                gy = wrap(gy, ny);
+            }
+            tile[(hy * HX + hx) * L + l] = load(gx, gy, z);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (!act[k]) continue;
+            const int p = slot + k * NS;
+            const int lx = p % TX + 1, ly = p / TX + 1;
+            const int64_t row = (int64_t)z * plane + (int64_t)py[k] * nx + px[k];
+            const T dg = c0 + (Vpot ? Vpot[row] : (T)0);
+            const V s1 = tile[(ly * HX + lx - 1) * L + l] + tile[(ly * HX + lx + 1) * L + l] +
+                         tile[((ly - 1) * HX + lx) * L + l] + tile[((ly + 1) * HX + lx) * L + l] +
+                         c[k][0] + c[k][2];
+            const V ctr = c[k][1];
+            V acc;
+#pragma unroll
+            for (int w = 0; w < W; ++w) acc[w] = fma(dg, ctr[w], c1 * s1[w]);
+            if (epi.affine) {
+                const T ea = (T)epi.a, eb = (T)epi.b;
+#pragma unroll
+                for (int w = 0; w < W; ++w) acc[w] = fma(eb, acc[w], ea * ctr[w]);
+            }
+            X[row * ldv + cv] = acc;
+            if constexpr (NDOT > 0) {
+                V e = V(0);
+                if constexpr (NDOT == 3) e = E[row * ldv + cv];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    ds[0][w] += (double)ctr[w] * (double)acc[w];
+                    if (NDOT == 2) ds[1][w] += (double)ctr[w] * (double)ctr[w];
+                    if (NDOT == 3) ds[1][w] += (double)e[w] * (double)acc[w];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            c[k][0] = c[k][1];
+            c[k][1] = c[k][2];
+        }
+    }
+    if constexpr (NDOT > 0) {
+        // the point slots meet in LDS and are summed in slot order
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int w = 0; w < W; ++w) red[p][slot][l * W + w] = ds[p][w];
+        __syncthreads();
+        const int ld = ldv * W;
+        if (t < 2 * L * W) {
+            const int p = t / (L * W), e = t - p * (L * W);
+            if (p < (ndot == 3 ? 2 : ndot)) {
+                double sum = 0.0;
+                for (int g = 0; g < NS; ++g) sum += red[p][g][e];
+                partials[((int64_t)p * nblk + cb) * ld + ch * L * W + e] = sum;
+            }
+        }
+    }
+}
+
 // grid for the wave kernels: ~kGridCap workgroups of 4 waves, multiple of 8
 Geometry wave_geometry(int64_t n) {
     Geometry g;
@@ -528,30 +699,55 @@ Geometry wave_geometry(int64_t n) {
 
 }  // namespace
 
-size_t spmm_partials_workspace(int ld) { return (size_t)2 * (kGridCap + 8) * ld * sizeof(double); }
+size_t spmm_partials_workspace(int64_t n, int ld) {
+    // the wave kernels write one partial row per workgroup (at most
+    // kGridCap + 8), the chunked kernel one per 64-row block
+    const int64_t nrb = (n + kChunkRows - 1) / kChunkRows;
+    return (size_t)2 * std::max<int64_t>(kGridCap + 8, nrb) * ld * sizeof(double);
+}
+
+bool spmm_fast_path(bool stencil, const StencilDev &st, int ld, bool f64) {
+    const int ldv = ld / (f64 ? 2 : 4);
+    if (!stencil) return ldv % 16 == 0;
+    return st.ndim == 3 && st.order == 2 && ldv % kZL == 0 && st.nx >= 3 && st.ny >= 3 && st.nz >= 3;
+}
 
 template <typename T>
 int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
-             double *partials) {
+             double *partials, const SpmmEpi &epi) {
     const int ldv = ld / Vec<T>::W;
     const T *val;
     if constexpr (sizeof(T) == 8) val = H.val64; else val = H.val32;
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
     auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
-    if (ldv % kChunkLanes == 0) {
-        const int nchunks = ldv / kChunkLanes;
-        int64_t rpb = kChunkRows;
-        while ((H.n + rpb - 1) / rpb > kGridCap) rpb += 16;
-        TM_REQUIRE(rpb <= 256, TM_ENOTSUP, "too many rows for the SpMM row blocks");
-        const int nrb = (int)((H.n + rpb - 1) / rpb);
+    // chunk width and in-flight gathers measured at 48^3 / 64^3 / 100^3
+    // (7-point, m = 256 / 512 / 1024): FP64 rows gain from 512-byte chunks
+    // with 8 rows per lane group in flight (48^3: 152 -> 140 us, 100^3:
+    // 5.8 -> 5.0 ms); FP32 rows keep 256-byte chunks and 4 rows
+    constexpr bool wide = sizeof(T) == 8;
+    constexpr int CL = wide ? 32 : 16;
+    if (ldv % 16 == 0) {
+        const bool use_wide = wide && ldv % CL == 0;
+        const int lanes = use_wide ? CL : 16;
+        const int nchunks = ldv / lanes;
+        const int64_t rpb = kChunkRows;
+        const int64_t nrb64 = (H.n + rpb - 1) / rpb;
+        TM_REQUIRE(nrb64 * nchunks < ((int64_t)1 << 31), TM_ENOTSUP, "matrix too large for the SpMM grid");
+        const int nrb = (int)nrb64;
         int64_t grid = (int64_t)nchunks * nrb;
         grid = (grid + 7) / 8 * 8;
-        hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, 2, 4>), dim3((unsigned)grid), dim3(256), 0, s,
-                           H.n, (int)rpb, nrb, nchunks, H.rowptr, H.col, val, Cv, Xv, ldv, ndot,
-                           partials);
+        if (use_wide)
+            hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, CL, 2, 8>), dim3((unsigned)grid), dim3(256), 0, s,
+                               H.n, (int)rpb, nrb, nchunks, H.rowptr, H.col, val, Cv, Xv, ldv, ndot,
+                               partials, epi);
+        else
+            hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, 16, 2, 4>), dim3((unsigned)grid), dim3(256), 0, s,
+                               H.n, (int)rpb, nrb, nchunks, H.rowptr, H.col, val, Cv, Xv, ldv, ndot,
+                               partials, epi);
         TM_HIP(hipGetLastError());
         return nrb;
     }
+    TM_REQUIRE(!epi.affine && ndot < 3, TM_ENOTSUP, "SpMM epilogue needs the column-chunked kernel");
     if (ldv % 64 == 0 && ldv <= 512) {
         Geometry w = wave_geometry(H.n);
 #define TM_CSR_WAVE(NCV)                                                                   \
@@ -579,14 +775,34 @@ generic:
 
 template <typename T>
 int spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld, const T *C, T *X,
-                 int ndot, double *partials) {
+                 int ndot, double *partials, const SpmmEpi &epi) {
     const int ldv = ld / Vec<T>::W;
-    TM_REQUIRE(ldv <= kMaxCv * 256, TM_ENOTSUP, "block too wide for the SpMM kernel");
-    Geometry g = geometry(n, ldv);
     const T *Vp;
     if constexpr (sizeof(T) == 8) Vp = H.V64; else Vp = H.V32;
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
     auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
+    if (H.ndim == 3 && H.order == 2 && ldv % kZL == 0 && H.nx >= 3 && H.ny >= 3 && H.nz >= 3) {
+        // tiles measured at 48^3 and 100^3 (m = 256, 1024): FP64 8 x 8 x 8
+        // (107 us, 3.8 ms), FP32 4 x 4 x 16 (42 us at 48^3)
+        constexpr int TX = sizeof(T) == 8 ? 8 : 4, TY = TX, ZS = sizeof(T) == 8 ? 8 : 16;
+        const int ntx = (H.nx + TX - 1) / TX, nty = (H.ny + TY - 1) / TY, nzs = (H.nz + ZS - 1) / ZS;
+        const int nch = ldv / kZL;
+        const int64_t nblk = (int64_t)ntx * nty * nzs;
+        int64_t grid = nblk * nch;
+        grid = (grid + 7) / 8 * 8;
+        TM_REQUIRE(grid < ((int64_t)1 << 31), TM_ENOTSUP, "grid too large for the stencil SpMM");
+#define TM_ZM(ND)                                                                                \
+    hipLaunchKernelGGL((spmm_stencil_zmarch_kernel<T, TX, TY, ZS, ND>), dim3((unsigned)grid), dim3(256), 0, \
+                       s, H, ldv, Vp, Cv, Xv, ntx, nty, nzs, nch, partials, epi)
+        if (ndot == 0) TM_ZM(0);
+        else if (ndot == 1) TM_ZM(1);
+        else if (ndot == 2) TM_ZM(2);
+        else TM_ZM(3);
+#undef TM_ZM
+        TM_HIP(hipGetLastError());
+        return (int)nblk;
+    }
+    TM_REQUIRE(!epi.affine && ndot < 3, TM_ENOTSUP, "SpMM epilogue needs the 3-D 7-point stencil kernel");
     const int ncv = ldv / 64;
     if (ldv % 64 == 0 && (ncv == 1 || ncv == 2 || ncv == 4 || ncv == 8)) {
         Geometry w = wave_geometry(n);
@@ -609,6 +825,8 @@ int spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld, const T 
         TM_HIP(hipGetLastError());
         return w.grid;
     }
+    TM_REQUIRE(ldv <= kMaxCv * 256, TM_ENOTSUP, "block too wide for the SpMM kernel");
+    Geometry g = geometry(n, ldv);
 #define TM_STENCIL_LAUNCH(ORD, ND)                                                         \
     hipLaunchKernelGGL((spmm_stencil_kernel<T, ORD, ND>), dim3(g.grid), dim3(256), 0, s, n, \
                        ldv, g.tpr, g.rpb, g.rows_per_block, H, Vp, Cv, Xv, ndot, partials)
@@ -622,9 +840,9 @@ int spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld, const T 
     return g.grid;
 }
 
-template int spmm_csr<double>(hipStream_t, const CsrDev &, int, const double *, double *, int, double *);
-template int spmm_csr<float>(hipStream_t, const CsrDev &, int, const float *, float *, int, double *);
-template int spmm_stencil<double>(hipStream_t, const StencilDev &, int64_t, int, const double *, double *, int, double *);
-template int spmm_stencil<float>(hipStream_t, const StencilDev &, int64_t, int, const float *, float *, int, double *);
+template int spmm_csr<double>(hipStream_t, const CsrDev &, int, const double *, double *, int, double *, const SpmmEpi &);
+template int spmm_csr<float>(hipStream_t, const CsrDev &, int, const float *, float *, int, double *, const SpmmEpi &);
+template int spmm_stencil<double>(hipStream_t, const StencilDev &, int64_t, int, const double *, double *, int, double *, const SpmmEpi &);
+template int spmm_stencil<float>(hipStream_t, const StencilDev &, int64_t, int, const float *, float *, int, double *, const SpmmEpi &);
 
 }  // namespace tmin

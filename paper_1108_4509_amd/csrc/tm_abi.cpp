@@ -183,8 +183,10 @@ void tm_opts_default(tm_opts *o) {
     o->rise_tol = 1e-13;
     o->stall_tol = 0.0;
     o->seed = 0;
-    o->cheb_degree = 3;
+    o->cheb_degree = 2;
     o->cheb_shift = 0.02;
+    o->progress = nullptr;
+    o->progress_user = nullptr;
 }
 
 tm_status tm_set_matrix_csr(tm_ctx *ctx, int64_t n, const int64_t *rowptr_in, const int32_t *col_in,
@@ -602,7 +604,7 @@ tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t precis
         const int64_t n = H->n;
         hipStream_t s = ctx->stream;
         const bool dp = precision != TM_MP2;
-        DevMem hv(ctx, ld * sizeof(double)), dws(ctx, spmm_partials_workspace(ld)),
+        DevMem hv(ctx, ld * sizeof(double)), dws(ctx, spmm_partials_workspace(n, ld)),
             gws(ctx, gram_workspace(n, m)), wp(ctx, (size_t)ld * ld * sizeof(double)),
             xs(ctx, (size_t)n * ld * (dp ? sizeof(double) : sizeof(float)));
         const int nch = spmm_any(s, H, ld, C, X, true, 1, (double *)dws.ptr);

@@ -81,17 +81,30 @@ struct StencilDev {
     const double *V64 = nullptr;
     const float *V32 = nullptr;
 };
+// Optional epilogue of the SpMM: affine: X = a C + b (H C) (a polynomial of
+// degree one in H, e.g. the degree-2 Chebyshev preconditioner); E: the extra
+// block of the third dot mode.  Only the column-chunked CSR kernel and the
+// 3-D 7-point stencil kernel take it (spmm_fast_path tells).
+struct SpmmEpi {
+    double a = 0.0, b = 1.0;
+    int affine = 0;
+    const void *E = nullptr;
+};
 // ndot = 0: X = H C only.  ndot = 1: also per-workgroup partial sums of
-// c_j . x_j; ndot = 2: of c_j . x_j and c_j . c_j, written to
+// c_j . x_j; ndot = 2: of c_j . x_j and c_j . c_j; ndot = 3 (fast path
+// only): of c_j . x_j and e_j . x_j (E from the epilogue), written to
 // partials[(p * nchunk + chunk) * ld + j].  Returns nchunk (for
-// reduce_partials).  partials needs spmm_partials_workspace(ld) bytes.
-size_t spmm_partials_workspace(int ld);
+// reduce_partials).  partials needs spmm_partials_workspace(n, ld) bytes.
+size_t spmm_partials_workspace(int64_t n, int ld);
 template <typename T>
 int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
-             double *partials);
+             double *partials, const SpmmEpi &epi = SpmmEpi());
 template <typename T>
 int spmm_stencil(hipStream_t s, const StencilDev &H, int64_t n, int ld,
-                 const T *C, T *X, int ndot, double *partials);
+                 const T *C, T *X, int ndot, double *partials, const SpmmEpi &epi = SpmmEpi());
+// True when the kernel chosen for this operator and width takes SpmmEpi and
+// ndot = 3.
+bool spmm_fast_path(bool stencil, const StencilDev &st, int ld, bool f64);
 // out[p * ld + j] = sum over chunks of partials[(p * nchunk + c) * ld + j],
 // in a fixed order.
 void reduce_partials(hipStream_t s, int nprod, int nchunk, int ld,

@@ -139,7 +139,7 @@ struct tm_server {
     bool stop = false;
     int running = 0;
     int64_t submitted = 0, completed = 0, failed = 0, rejected = 0;
-    std::vector<double> latencies;
+    std::vector<double> latencies, waits, services;
     Clock::time_point t0 = Clock::now(), t_first, t_last;
     bool any_submit = false;
 
@@ -223,6 +223,8 @@ void tm_server::worker(Slot *slot) {
         if (r->status == TM_OK || r->status == TM_ENOCONV) ++completed;
         else ++failed;
         latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
+        waits.push_back(std::chrono::duration<double>(r->t_start - r->t_submit).count());
+        services.push_back(std::chrono::duration<double>(r->t_done - r->t_start).count());
         t_last = r->t_done;
         cv_done.notify_all();
         cv_work.notify_all();
@@ -370,16 +372,23 @@ tm_status tm_server_get_stats(tm_server *s, tm_server_stats *out) {
     out->hbm_budget = s->opts.hbm_budget;
     out->hbm_peak = s->peak;
     std::vector<double> lat = s->latencies;
+    // nearest-rank percentile of a sorted sample
+    auto pct = [](const std::vector<double> &v, double q) {
+        size_t k = (size_t)std::ceil(q * v.size());
+        if (k < 1) k = 1;
+        return v[std::min(k, v.size()) - 1];
+    };
     if (!lat.empty()) {
         std::sort(lat.begin(), lat.end());
-        auto pct = [&](double q) {
-            // nearest-rank percentile
-            size_t k = (size_t)std::ceil(q * lat.size());
-            if (k < 1) k = 1;
-            return lat[std::min(k, lat.size()) - 1];
-        };
-        out->p50_latency_s = pct(0.50);
-        out->p99_latency_s = pct(0.99);
+        std::vector<double> wt = s->waits, sv = s->services;
+        std::sort(wt.begin(), wt.end());
+        std::sort(sv.begin(), sv.end());
+        out->p50_latency_s = pct(lat, 0.50);
+        out->p99_latency_s = pct(lat, 0.99);
+        out->p50_wait_s = pct(wt, 0.50);
+        out->p99_wait_s = pct(wt, 0.99);
+        out->p50_service_s = pct(sv, 0.50);
+        out->p99_service_s = pct(sv, 0.99);
         out->max_latency_s = lat.back();
         double sum = 0;
         for (double v : lat) sum += v;

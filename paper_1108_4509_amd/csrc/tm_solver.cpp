@@ -27,17 +27,17 @@ DevMem::~DevMem() {
 }
 
 int spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64, int ndot,
-             double *partials) {
+             double *partials, const SpmmEpi &epi) {
     if (H->is_stencil) {
         if (f64)
             return spmm_stencil<double>(s, H->st, H->n, ld, (const double *)C, (double *)X, ndot,
-                                        partials);
+                                        partials, epi);
         return spmm_stencil<float>(s, H->st, H->n, ld, (const float *)C, (float *)X, ndot,
-                                   partials);
+                                   partials, epi);
     }
     if (f64)
-        return spmm_csr<double>(s, H->csr, ld, (const double *)C, (double *)X, ndot, partials);
-    return spmm_csr<float>(s, H->csr, ld, (const float *)C, (float *)X, ndot, partials);
+        return spmm_csr<double>(s, H->csr, ld, (const double *)C, (double *)X, ndot, partials, epi);
+    return spmm_csr<float>(s, H->csr, ld, (const float *)C, (float *)X, ndot, partials, epi);
 }
 
 namespace {
@@ -82,7 +82,7 @@ size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, int precond
     }
     const size_t md = (size_t)m * m * 8;
     size_t small = 3 * ld * 8 + 8 * ld * 8 + 5 * md + ld * ld * 8 + gram_workspace(n, m) +
-                   std::max({coldots_workspace(n, (int)ld), spmm_partials_workspace((int)ld),
+                   std::max({coldots_workspace(n, (int)ld), spmm_partials_workspace(n, (int)ld),
                              rot_partials_workspace(n, m)}) +
                    chol_workspace(m) + jacobi_workspace(m) + 64 + sizeof(CgState) +
                    (size_t)2 * std::max(history_len, 0) * 8 + (precondition == 1 ? (size_t)n * 8 : 0) +
@@ -116,6 +116,8 @@ struct Solver::Impl {
     // polynomial preconditioner: Chebyshev iteration for (H - sigma) z = g on
     // [a, b] = Gershgorin bounds - sigma; theta, delta its centre and half-width
     double ch_sigma = 0, ch_theta = 1, ch_delta = 1;
+    // degree 2: z = ch_lin_a g + ch_lin_b H g (the two steps expanded)
+    double ch_lin_a = 0, ch_lin_b = 0;
     // small buffers
     std::unique_ptr<DevMem> h, d, w, dots, dots2, Hp, S, Rinv, Amat, U, Wp;
     std::unique_ptr<DevMem> gram_ws, dot_ws, chol_ws, jac_ws, info, state, hist, M;
@@ -158,7 +160,7 @@ struct Solver::Impl {
         U.reset(new DevMem(ctx, md));
         Wp.reset(new DevMem(ctx, (size_t)ld * ld * sizeof(double)));
         gram_ws.reset(new DevMem(ctx, gram_workspace(n, m)));
-        dot_ws.reset(new DevMem(ctx, std::max({coldots_workspace(n, ld), spmm_partials_workspace(ld),
+        dot_ws.reset(new DevMem(ctx, std::max({coldots_workspace(n, ld), spmm_partials_workspace(n, ld),
                                                rot_partials_workspace(n, m)})));
         chol_ws.reset(new DevMem(ctx, chol_workspace(m)));
         jac_ws.reset(new DevMem(ctx, jacobi_workspace(m)));
@@ -179,6 +181,13 @@ struct Solver::Impl {
             TM_REQUIRE(b > a && a > 0.0, TM_EINVAL, "degenerate Gershgorin interval");
             ch_theta = 0.5 * (a + b);
             ch_delta = 0.5 * (b - a);
+            // d0 = g / theta = z1; r1 = g - (H - sigma) d0;
+            // z2 = z1 + rho1 rho0 d0 + (2 rho1 / delta) r1, rho0 = delta / theta,
+            // rho1 = 1 / (2 theta / delta - rho0)
+            const double rho0 = ch_delta / ch_theta, rho1 = 1.0 / (2.0 * ch_theta / ch_delta - rho0);
+            const double cr = 2.0 * rho1 / ch_delta;
+            ch_lin_a = (1.0 + rho1 * rho0) / ch_theta + cr * (1.0 + ch_sigma / ch_theta);
+            ch_lin_b = -cr / ch_theta;
         }
         if (o.precondition == 1) {
             // Eq. 18 with M_ii = 1 / (H_ii - sigma), sigma = min(0, min_i H_ii - 1/2)
@@ -342,12 +351,25 @@ struct Solver::Impl {
         TG *Zv = nullptr;
         if (o.precondition == 2) {
             Zv = (TG *)Zc->ptr;
-            precondition_poly<TG>(Gv, Zv, (TG *)Rc->ptr, (TG *)Dc->ptr, Yv);
-            DotArgs<TG> a;
-            a.nprod = 2;
-            a.a[0] = Gv; a.b[0] = Zv;
-            a.a[1] = Gpv; a.b[1] = Zv;
-            coldots<TG>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr + ld);
+            if (o.cheb_degree == 2 && spmm_fast_path(H->is_stencil, H->st, ld, is_f64<TG>())) {
+                // two Chebyshev steps are the linear polynomial a I + b H: one
+                // SpMM with an affine epilogue, which also forms g.z and
+                // g_prev.z
+                SpmmEpi epi;
+                epi.affine = 1;
+                epi.a = ch_lin_a;
+                epi.b = ch_lin_b;
+                epi.E = Gpv;
+                const int nch = spmm_any(s, H, ld, Gv, Zv, is_f64<TG>(), 3, (double *)dot_ws->ptr, epi);
+                reduce_partials(s, 2, nch, ld, (double *)dot_ws->ptr, (double *)dots->ptr + ld);
+            } else {
+                precondition_poly<TG>(Gv, Zv, (TG *)Rc->ptr, (TG *)Dc->ptr, Yv);
+                DotArgs<TG> a;
+                a.nprod = 2;
+                a.a[0] = Gv; a.b[0] = Zv;
+                a.a[1] = Gpv; a.b[1] = Zv;
+                coldots<TG>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr + ld);
+            }
         }
         cg_control_gamma(s, m, ld, (double *)h->ptr, (double *)dots->ptr, st, hist_dev);
         // P = M G + gamma P
@@ -593,6 +615,7 @@ struct Solver::Impl {
             }
             poll();
             it_host = st_host->it;
+            if (o.progress) o.progress(st_host->it, st_host->E, st_host->rho, switched ? 1 : 0, o.progress_user);
             if (st_host->nan_seen) throw Error{TM_ENAN, "NaN or Inf in the energy or gradient"};
             if (st_host->done) break;
             if (st_host->phase_end) {

@@ -21,7 +21,7 @@ struct DevMem {
 // X = H C for a CSR or stencil H, FP64 (f64) or FP32 blocks, with the fused
 // column dots of spmm_csr (ndot, partials); returns the number of chunks.
 int spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64,
-             int ndot = 0, double *partials = nullptr);
+             int ndot = 0, double *partials = nullptr, const SpmmEpi &epi = SpmmEpi());
 
 // Upper bound of the device bytes one tm_solve() allocates for an n x m
 // problem with nnz stored nonzeros (0 for a stencil), at the given

@@ -57,7 +57,7 @@ def test_pure_host_entry_points(lib):
 def test_struct_layouts_match_header(lib):
     """The ctypes mirrors have the sizes the C compiler gives the structs."""
     from paper_1108_4509_amd import _abi
-    assert ctypes.sizeof(_abi.tm_opts) == 8 * 4 + 3 * 8 + 8 + 2 * 4 + 8
+    assert ctypes.sizeof(_abi.tm_opts) == 8 * 4 + 3 * 8 + 8 + 2 * 4 + 8 + 2 * 8
     assert ctypes.sizeof(_abi.tm_result) == 6 * 8 + 3 * 8 + 6 * 4
     assert ctypes.sizeof(_abi.tm_stencil) == 6 * 4 + 8 + 8
 
@@ -79,7 +79,7 @@ def test_serving_structs_and_footprint(lib):
     from paper_1108_4509_amd import _abi
     assert ctypes.sizeof(_abi.tm_server_opts) == 4 + 4 + 8
     assert ctypes.sizeof(_abi.tm_request) == 8 * 4 + 4 + 4 + 8 * 3
-    assert ctypes.sizeof(_abi.tm_server_stats) == 6 * 8 + 6 * 8 + 2 * 8
+    assert ctypes.sizeof(_abi.tm_server_stats) == 6 * 8 + 6 * 8 + 2 * 8 + 4 * 8
 
     def fp(n, nnz, m, precision):
         o = _abi.tm_opts()

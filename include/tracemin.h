@@ -255,6 +255,47 @@ tm_status tm_solve_generalized(tm_ctx *ctx, const tm_mat *H, const tm_mat *S, in
                                double *C_out, double *eig_out, tm_result *res,
                                double *history, int32_t history_len);
 
+/* ---------------------------------------------------------------- batches
+ * Many small problems on one grid: the Hamiltonian of Sec. 3 is a kinetic
+ * operator plus a potential on the diagonal, so problems on the same grid
+ * differ only there.  A batch matrix holds k operators H_g = A + diag(d_g)
+ * (g = 0..k-1) sharing one CSR A; a batched solve runs Fig. 1 for all of
+ * them at once on one n x ld block where problem g owns columns
+ * g * ldg .. g * ldg + m - 1 (the rest of its ldg columns are zero): each
+ * sparse product reads A once for all problems and adds d_g in its
+ * epilogue, the Gram, rotation and TRMM products run once on the whole
+ * block with their m_b x m_b results (m_b = k * ldg) kept block-diagonal,
+ * and every scalar of the CG step (Eq. 8's gamma, the step alpha, the
+ * convergence and phase tests) is a problem's own. */
+
+/* k operators H_g = A + diag(d_g): A as for tm_set_matrix_csr (host arrays
+ * only; flags may hold TM_CHECK_SYMMETRY), d host k x n row-major (d_g at
+ * d + g * n), copied.  1 <= k <= 256; TM_EINVAL for a non-finite d.  Such a
+ * matrix is taken by tm_solve_batch and tm_spmm (in the batch layout) and
+ * refused by the other calls. */
+tm_status tm_set_matrix_batch(tm_ctx *ctx, int64_t n, const int64_t *rowptr,
+                              const int32_t *col, const double *val, int32_t k,
+                              const double *d, uint32_t flags, tm_mat **out);
+/* The batch layout of k problems of m columns: *ldg columns per problem (m
+ * rounded up to 16, then up to a multiple of 64 for k * ldg) and the block's
+ * leading dimension *ld = tm_leading_dim(k * ldg). */
+tm_status tm_batch_layout(int32_t k, int32_t m, int32_t *ldg, int32_t *ld);
+/* Solve the k problems of the batch matrix H for m eigenpairs each until
+ * every problem has rho_g <= tol.  C0: device n x ld FP64 in the batch
+ * layout, or NULL: problem g starts from the block tm_random_block makes
+ * with seed opts->seed + g.  C_out: device n x ld FP64 or NULL; eig_out:
+ * device k * m FP64 or NULL (problem g's ascending values at g * m); res:
+ * host array of k results (seconds and rotations are the batch's).  A
+ * converged problem takes no further steps (alpha = 0) while others run; a
+ * two-phase policy changes phase once every problem has ended its first
+ * phase.  k * ldg <= 2048.  Precisions: all but the BF16 policies;
+ * precondition 0, or 2 with cheb_degree = 2 (each problem on its own
+ * Gershgorin interval); other options TM_ENOTSUP; history is not recorded.
+ * TM_ENOCONV (results filled) if some problem did not converge. */
+tm_status tm_solve_batch(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol,
+                         const tm_opts *opts, const double *C0, double *C_out,
+                         double *eig_out, tm_result *res);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of independent solves on one GPU (for callers that
  * serve many eigenproblems of different N and m).  Requests queue in arrival

@@ -117,6 +117,7 @@ class Matrix:
 
     def __init__(self, ctx: Context, handle: ctypes.c_void_p, n: int):
         self.ctx, self.handle, self.n = ctx, handle, n
+        self.batch_k = 0
         _live_matrices.add(self)
 
     def free(self):
@@ -278,6 +279,62 @@ def solve(ctx: Context, H: Matrix, m: int, tol: float, C0, options=None, history
         n = min(history_len, r["iterations"] + (1 if r["converged"] else 0))
         hist = hist.reshape(-1, 2)[:n]
     return r, Cout, eig[:m], hist
+
+
+# ------------------------------------------------------------- batches
+
+def batch_layout(k: int, m: int):
+    """(ldg, ld): problem g of a batch of k owns columns g*ldg .. g*ldg+m-1
+    of an N x ld block (tm_batch_layout)."""
+    ldg, ld = ctypes.c_int32(), ctypes.c_int32()
+    _abi.check(_abi.lib().tm_batch_layout(k, m, ctypes.byref(ldg), ctypes.byref(ld)), "tm_batch_layout")
+    return ldg.value, ld.value
+
+
+def set_matrix_batch(ctx: Context, rowptr, col, val, d, check_symmetry: bool = False) -> Matrix:
+    """k operators H_g = A + diag(d[g]) sharing the CSR A (host arrays); d is
+    a k x N host array (tm_set_matrix_batch)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    d = np.ascontiguousarray(np.atleast_2d(d), dtype=np.float64)
+    n = rowptr.shape[0] - 1
+    if d.shape[1] != n:
+        raise ValueError("d must be k x N")
+    h = ctypes.c_void_p()
+    flags = TM_CHECK_SYMMETRY if check_symmetry else 0
+    _abi.check(_abi.lib().tm_set_matrix_batch(ctx.handle, n, rowptr.ctypes.data, col.ctypes.data,
+                                              val.ctypes.data, d.shape[0], d.ctypes.data, flags,
+                                              ctypes.byref(h)), "tm_set_matrix_batch")
+    M = Matrix(ctx, h, n)
+    M.batch_k = d.shape[0]
+    return M
+
+
+def solve_batch(ctx: Context, H: Matrix, m: int, tol: float, C0=None, options=None,
+                want_vectors: bool = True, allow_noconv: bool = True):
+    """Run tm_solve_batch on a batch matrix.  C0: N x ld FP64 device tensor in
+    the batch layout, or None (problem g from seed options.seed + g).
+
+    Returns (list of k result dicts, C tensor or None, k x m eigenvalue tensor)."""
+    torch = _torch()
+    k = H.batch_k
+    _, ld = batch_layout(k, m)
+    if C0 is not None and (C0.dtype != torch.float64 or not C0.is_contiguous() or C0.shape != (H.n, ld)):
+        raise ValueError("C0 must be a contiguous N x ld FP64 device tensor")
+    o = options or opts()
+    Cout = torch.empty((H.n, ld), dtype=torch.float64, device="cuda") if want_vectors else None
+    eig = torch.empty((k, m), dtype=torch.float64, device="cuda")
+    res = (_abi.tm_result * k)()
+    st = _abi.lib().tm_solve_batch(ctx.handle, H.handle, m, tol, ctypes.byref(o), _ptr(C0), _ptr(Cout),
+                                   _ptr(eig), res)
+    _abi.check(st, "tm_solve_batch", allow=(TM_OK, TM_ENOCONV) if allow_noconv else (TM_OK,))
+    out = []
+    for r in res:
+        d = r.as_dict()
+        d["status"] = st
+        out.append(d)
+    return out, Cout, eig
 
 
 # ------------------------------------------------------------- single steps

@@ -108,6 +108,11 @@ SIGNATURES = {
     "tm_solve_generalized": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_double,
                                        ctypes.POINTER(tm_opts), c_void_p, c_void_p, c_void_p,
                                        ctypes.POINTER(tm_result), c_void_p, c_int32]),
+    "tm_set_matrix_batch": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int32,
+                                      c_void_p, ctypes.c_uint32, ctypes.POINTER(c_void_p)]),
+    "tm_batch_layout": (c_int32, [c_int32, c_int32, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "tm_solve_batch": (c_int32, [c_void_p, c_void_p, c_int32, c_double, ctypes.POINTER(tm_opts),
+                                 c_void_p, c_void_p, c_void_p, ctypes.POINTER(tm_result)]),
     "tm_spmm": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "tm_gram": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
                           c_void_p]),

@@ -147,6 +147,7 @@ struct GramUpd {
     const TP *P = nullptr;
     const CgState *st = nullptr;
     TA *Cn = nullptr;
+    int ldg = 0;   // batched solves: column j takes the alpha of st[j / ldg]
 };
 
 // One workgroup: a BM x BM tile of A^T B' over a chunk of rows.  Each lane
@@ -213,8 +214,11 @@ __global__ __launch_bounds__(NT, NT / 128) void gram_kernel(
     int64_t krow[(UPD || SHIFT) ? PASSES : 1];
     bool rv[PASSES];
     const int ci_c = ci_ok ? ci : 0, cj_c = cj_ok ? cj : 0;
-    TA alpha = TA(0);
-    if constexpr (UPD) alpha = (TA)up.st->alpha;
+    TA alpha = TA(0), alpha_b = TA(0);
+    if constexpr (UPD) {
+        alpha = (TA)up.st[up.ldg > 0 ? ci_c / up.ldg : 0].alpha;
+        alpha_b = (TA)up.st[up.ldg > 0 ? cj_c / up.ldg : 0].alpha;
+    }
     // the workgroups of tile row 0 store X' = X - C diag(h) for their columns
     // (each element once), in the matrix-core precision
     const bool xstore = SHIFT && xout != nullptr && ti == 0;
@@ -248,7 +252,7 @@ __global__ __launch_bounds__(NT, NT / 128) void gram_kernel(
                 for (int w = 0; w < VW; ++w) {
                     ra[q][w] = ra[q][w] + alpha * (TA)pa[q][w];
                     if (same) rb[q][w] = ra[q][w];
-                    else rb[q][w] = rb[q][w] + alpha * (TA)pb[q][w];
+                    else rb[q][w] = rb[q][w] + alpha_b * (TA)pb[q][w];
                 }
                 if (same && rv[q] && ci_ok) *reinterpret_cast<V *>(up.Cn + krow[q] * ld + ci) = ra[q];
             }
@@ -373,7 +377,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, boo
                                                           const double *__restrict__ partials,
                                                           double *__restrict__ out, int ld,
                                                           float *__restrict__ padf,
-                                                          double *__restrict__ padd) {
+                                                          double *__restrict__ padd,
+                                                          BatchCols bc) {
     constexpr int E = 64, G = 4;
     __shared__ double red[G][E];
     const int e = threadIdx.x % E, g = threadIdx.x / E;
@@ -403,6 +408,12 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int nsplit, boo
     if (active) {
         v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
         if (zero_diag && i == j) v = 0.0;
+        if (bc.ldg > 0) {
+            // block-diagonal form of a batched solve (mirror-symmetric)
+            const int gi = i / bc.ldg, gj = j / bc.ldg;
+            const bool pi = i - gi * bc.ldg >= bc.mg, pj = j - gj * bc.ldg >= bc.mg;
+            if (gi != gj || pi || pj) v = (i == j && pi) ? bc.pad : 0.0;
+        }
         out[src] = v;
         if (symmetric && (i / kSymBlk) < (j / kSymBlk)) out[(int64_t)j * m + i] = v;
     }
@@ -438,7 +449,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // splitting (Dekker 1971) with the constant 2^45 + 1 keeps the leading
 // 53 - 45 = 8 bits of x rounded to nearest.  The result converts to FP32 and
 // then to BF16 exactly, so FP64 operands are not rounded twice (through FP32).
+// The splitting needs each operation rounded on its own: no FMA contraction
+// of t - x (x * c - x in one rounding would break it).
 __device__ inline double round_bf16_bits(double x) {
+#pragma clang fp contract(off)
     const double t = x * 35184372088833.0;   // 2^45 + 1
     return t - (t - x);
 }
@@ -1058,7 +1072,7 @@ size_t gram_workspace(int64_t n, int m) {
 template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
-          double *out, bool reduce, TM *xshift, TM *wpad, size_t ws_bytes) {
+          double *out, bool reduce, TM *xshift, TM *wpad, size_t ws_bytes, BatchCols bc) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
     gram_shape(n, m, symmetric, BM, T, nsplit, ws_bytes);
@@ -1088,13 +1102,13 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     }
     const int64_t cover = wpad ? (int64_t)ld * ld : total;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((cover + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, symmetric, zero_diag, partials, out, ld, padf, padd);
+                       s, m, nsplit, symmetric, zero_diag, partials, out, ld, padf, padd, bc);
     TM_HIP(hipGetLastError());
 }
 
 template <typename TA, typename TM, typename TP>
 void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, const CgState *st,
-                 TA *Cn, double *partials, double *out) {
+                 TA *Cn, double *partials, double *out, BatchCols bc) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
     gram_shape(n, m, true, BM, T, nsplit);
@@ -1106,6 +1120,7 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
     up.P = P;
     up.st = st;
     up.Cn = Cn;
+    up.ldg = bc.ldg;
     if (BM == 128)
         hipLaunchKernelGGL((gram_kernel<TA, TM, 128, false, true, TP, gram_threads<TA, TM, false, true, TP>()>),
                            dim3(grid), dim3(gram_threads<TA, TM, false, true, TP>()), 0, s,
@@ -1117,7 +1132,7 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
     TM_HIP(hipGetLastError());
     const int64_t total = (int64_t)m * m;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, true, false, partials, out, ld, nullptr, nullptr);
+                       s, m, nsplit, true, false, partials, out, ld, nullptr, nullptr, bc);
     TM_HIP(hipGetLastError());
 }
 
@@ -1148,7 +1163,7 @@ void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, cons
     if (wpad) padf = wpad;
     const int64_t cover = wpad ? (int64_t)ld * ld : total;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((cover + 63) / 64)), dim3(256), 0,
-                       s, m, nsplit, false, zero_diag, partials, out, ld, padf, nullptr);
+                       s, m, nsplit, false, zero_diag, partials, out, ld, padf, nullptr, BatchCols());
     TM_HIP(hipGetLastError());
 }
 
@@ -1218,12 +1233,12 @@ void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
     TM_HIP(hipGetLastError());
 }
 
-template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, double *, double *, size_t);
-template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool, float *, float *, size_t);
-template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, float *, float *, size_t);
-template void gram_update<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *, double *, double *);
-template void gram_update<double, double, float>(hipStream_t, int64_t, int, const double *, const float *, const CgState *, double *, double *, double *);
-template void gram_update<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *, double *, double *);
+template void gram<double, double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, double *, double *, size_t, BatchCols);
+template void gram<float, float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, bool, double *, double *, bool, float *, float *, size_t, BatchCols);
+template void gram<double, float>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, bool, double *, double *, bool, float *, float *, size_t, BatchCols);
+template void gram_update<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *, double *, double *, BatchCols);
+template void gram_update<double, double, float>(hipStream_t, int64_t, int, const double *, const float *, const CgState *, double *, double *, double *, BatchCols);
+template void gram_update<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *, double *, double *, BatchCols);
 template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool, float *, size_t);
 template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool, float *, size_t);
 template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const double *);

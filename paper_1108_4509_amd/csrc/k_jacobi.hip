@@ -247,18 +247,27 @@ __global__ __launch_bounds__(1024) void bj_check(int M, const double *__restrict
     }
 }
 
-__global__ __launch_bounds__(1024) void bj_sort(int m, int M, const double *__restrict__ Aw,
+// Ascending order within each group of a batched (block-diagonal) matrix:
+// group g owns indices g * ldg .. g * ldg + mg - 1 (one group: ldg = mg = m);
+// indices past mg in a group (zero padding) keep their place.
+__global__ __launch_bounds__(1024) void bj_sort(int m, int M, int ldg, int mg,
+                                                const double *__restrict__ Aw,
                                                 const double *__restrict__ V,
                                                 double *__restrict__ U, double *__restrict__ w) {
     for (int i = threadIdx.x; i < m; i += 1024) {
         const double wi = Aw[(int64_t)i * M + i];
-        int rank = 0;
-        for (int j = 0; j < m; ++j) {
-            const double wj = Aw[(int64_t)j * M + j];
-            rank += (wj < wi) || (wj == wi && j < i);
+        const int g0 = (i / ldg) * ldg, loc = i - g0;
+        int dest = i;
+        if (loc < mg) {
+            int rank = 0;
+            for (int j = g0; j < g0 + mg; ++j) {
+                const double wj = Aw[(int64_t)j * M + j];
+                rank += (wj < wi) || (wj == wi && j < i);
+            }
+            dest = g0 + rank;
         }
-        w[rank] = wi;
-        for (int k = 0; k < m; ++k) U[(int64_t)k * m + rank] = V[(int64_t)k * M + i];
+        w[dest] = wi;
+        for (int k = 0; k < m; ++k) U[(int64_t)k * m + dest] = V[(int64_t)k * M + i];
     }
 }
 
@@ -270,7 +279,8 @@ size_t jacobi_workspace(int m) {
 }
 
 void jacobi_eig(hipStream_t s, int m, const double *A, double *U, double *w, double *work,
-                int32_t *info) {
+                int32_t *info, int ldg, int mg) {
+    if (ldg <= 0) ldg = mg = m;
     TM_REQUIRE(m >= 1 && m <= 2048, TM_ENOTSUP, "eigensolver supports m <= 2048");
     const int M = leading_dim(m);
     const int nbk = M / BJ, nbp = nbk / 2;
@@ -302,7 +312,7 @@ void jacobi_eig(hipStream_t s, int m, const double *A, double *U, double *w, dou
     TM_REQUIRE(done, TM_ENOCONV,
                "Jacobi eigensolver: off(A) above 1e-15 ||A||_F after " + std::to_string(kMaxSweeps) +
                    " sweeps");
-    hipLaunchKernelGGL(bj_sort, dim3(1), dim3(1024), 0, s, m, M, Aw, V, U, w);
+    hipLaunchKernelGGL(bj_sort, dim3(1), dim3(1024), 0, s, m, M, ldg, mg, Aw, V, U, w);
     TM_HIP(hipGetLastError());
     TM_HIP(hipMemcpyAsync(info, &st->sweeps, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 }

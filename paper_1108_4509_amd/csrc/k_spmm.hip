@@ -371,11 +371,21 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int w = 0; w < W; ++w) ds[p][w] = 0.0;
-    const T ea = (T)epi.a, eb = (T)epi.b;
+    // batched operators: this lane's columns belong to problem grp, whose
+    // diagonal term d_grp is added and whose affine coefficients apply
+    const int grp = epi.dld > 0 ? cv * W / epi.dld : 0;
+    const T *Dg = epi.D ? reinterpret_cast<const T *>(epi.D) + (int64_t)grp * n : nullptr;
+    const T ea = (T)(epi.gab ? epi.gab[2 * grp] : epi.a);
+    const T eb = (T)(epi.gab ? epi.gab[2 * grp + 1] : epi.b);
     const V *E = reinterpret_cast<const V *>(epi.E);
     auto finish = [&](int64_t r, V acc) {
-        if (epi.affine || ndot > 0) {
+        if (epi.affine || ndot > 0 || Dg) {
             const V c = C[r * ldv + cv];
+            if (Dg) {
+                const T dr = Dg[r];
+#pragma unroll
+                for (int w = 0; w < W; ++w) acc[w] = fma(dr, c[w], acc[w]);
+            }
             if (epi.affine) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) acc[w] = fma(eb, acc[w], ea * c[w]);
@@ -747,7 +757,8 @@ int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
         TM_HIP(hipGetLastError());
         return nrb;
     }
-    TM_REQUIRE(!epi.affine && ndot < 3, TM_ENOTSUP, "SpMM epilogue needs the column-chunked kernel");
+    TM_REQUIRE(!epi.affine && ndot < 3 && !epi.D, TM_ENOTSUP,
+               "SpMM epilogue needs the column-chunked kernel");
     if (ldv % 64 == 0 && ldv <= 512) {
         Geometry w = wave_geometry(H.n);
 #define TM_CSR_WAVE(NCV)                                                                   \

@@ -97,7 +97,7 @@ int dot_chunks(int64_t n) {
 }
 
 template <typename TG, typename TP>
-__global__ void p_update_kernel(int64_t count, int ld, const TG *__restrict__ G,
+__global__ void p_update_kernel(int64_t count, int ld, int ldg, const TG *__restrict__ G,
                                 const double *__restrict__ M,
                                 const CgState *__restrict__ st,
                                 TP *__restrict__ P) {
@@ -107,10 +107,13 @@ __global__ void p_update_kernel(int64_t count, int ld, const TG *__restrict__ G,
     constexpr int W = 16 / sizeof(TP);
     typedef TG VG __attribute__((ext_vector_type(W)));
     typedef TP VP __attribute__((ext_vector_type(W)));
-    const double gamma = st->gamma;
     const int64_t nv = count / W;
+    const double gamma0 = st->gamma;
+    const bool grouped = ldg < ld;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
          v += (int64_t)gridDim.x * blockDim.x) {
+        // gamma of the vector's column group (one group unless batched)
+        const double gamma = grouped ? st[(int)((v * W) % ld) / ldg].gamma : gamma0;
         const VG g = reinterpret_cast<const VG *>(G)[v];
         const double mw = M ? M[(v * W) / ld] : 1.0;   // one row per vector
         VP out;
@@ -158,13 +161,15 @@ __device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1)
 // Standard normal entries of an n x ld block (columns >= m zero): entry
 // e = r * m + j is member e % 2 of the Box-Muller pair made from the Philox
 // output for counter (e / 2, 0, 0, 0).
-__global__ void random_block_kernel(int64_t n, int m, int ld, uint32_t k0, uint32_t k1,
-                                    double *__restrict__ out) {
-    const int64_t total = n * ld;
+// Writes columns col0 .. col0 + width - 1 of an n x ld block; entry (r, j)
+// of the problem (j < m) lands in column col0 + j.
+__global__ void random_block_kernel(int64_t n, int m, int width, int ld, int col0, uint32_t k0,
+                                    uint32_t k1, double *__restrict__ out) {
+    const int64_t total = n * width;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = idx / ld;
-        const int j = (int)(idx - r * ld);
+        const int64_t r = idx / width;
+        const int j = (int)(idx - r * width);
         double v = 0.0;
         if (j < m) {
             const uint64_t e = (uint64_t)r * (uint64_t)m + (uint64_t)j;
@@ -179,7 +184,7 @@ __global__ void random_block_kernel(int64_t n, int m, int ld, uint32_t k0, uint3
             const double th = 6.283185307179586476925286766559 * u2;
             v = (e & 1) ? rad * sin(th) : rad * cos(th);
         }
-        out[idx] = v;
+        out[r * ld + col0 + j] = v;
     }
 }
 
@@ -316,9 +321,14 @@ __device__ double block_max(const double *v, int m, double *red) {
 // convergence and phase-switch tests, restart decision and Polak-Ribiere gamma.
 // dots rows: 0 gg = tr(G^T G), 1 gz = tr(G^T Z), 2 tr(G_prev^T Z), 3 tr(P_prev^T G).
 __global__ __launch_bounds__(256) void control_gamma_kernel(
-    int m, int ld, const double *__restrict__ h, const double *__restrict__ dots,
+    int m, int ld, int ldg, const double *__restrict__ h, const double *__restrict__ dots,
     CgState *st, double *history) {
     __shared__ double red[256];
+    // group blockIdx.x of a batched solve: its columns start at g * ldg
+    const int g = blockIdx.x;
+    h += (int64_t)g * ldg;
+    dots += (int64_t)g * ldg;
+    st += g;
     const double E = block_sum(h, m, red);
     const double gg = block_sum(dots, m, red);
     const double gz = block_sum(dots + ld, m, red);
@@ -378,9 +388,13 @@ __global__ __launch_bounds__(256) void control_gamma_kernel(
 // curvature = 2 sum_j (p_j.y_j - h_j p_j.p_j), capped at 1 / max_j |p_j|.
 // dots2 rows: 0 p_j.y_j, 1 p_j.p_j.
 __global__ __launch_bounds__(256) void control_alpha_kernel(
-    int m, int ld, const double *__restrict__ h, const double *__restrict__ dots2,
+    int m, int ld, int ldg, const double *__restrict__ h, const double *__restrict__ dots2,
     CgState *st) {
     __shared__ double red[256];
+    const int g = blockIdx.x;
+    h += (int64_t)g * ldg;
+    dots2 += (int64_t)g * ldg;
+    st += g;
     const double ppmax = block_max(dots2 + ld, m, red);
     // curvature terms, summed in a fixed order
     double local = 0.0;
@@ -438,10 +452,10 @@ void reduce_partials(hipStream_t s, int nprod, int nchunk, int ld, const double 
 
 template <typename TG, typename TP>
 void p_update(hipStream_t s, int64_t n, int ld, const TG *G, const double *M,
-              const CgState *st, TP *P) {
+              const CgState *st, TP *P, int ldg) {
     const int64_t count = n * ld;
     hipLaunchKernelGGL((p_update_kernel<TG, TP>), dim3(elem_grid(count)), dim3(256),
-                       0, s, count, ld, G, M, st, P);
+                       0, s, count, ld, ldg > 0 ? ldg : ld, G, M, st, P);
     TM_HIP(hipGetLastError());
 }
 
@@ -452,10 +466,15 @@ void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out) {
     TM_HIP(hipGetLastError());
 }
 
-void random_block(hipStream_t s, int64_t n, int m, uint64_t seed, double *out) {
-    const int ld = leading_dim(m);
-    hipLaunchKernelGGL(random_block_kernel, dim3(elem_grid(n * ld)), dim3(256), 0, s, n, m, ld,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), out);
+void random_block(hipStream_t s, int64_t n, int m, uint64_t seed, double *out, int width,
+                  int ld_out, int col0) {
+    if (width <= 0) {
+        width = ld_out = leading_dim(m);
+        col0 = 0;
+    }
+    TM_REQUIRE(m <= width && col0 >= 0 && col0 + width <= ld_out, TM_EINVAL, "random block layout");
+    hipLaunchKernelGGL(random_block_kernel, dim3(elem_grid(n * width)), dim3(256), 0, s, n, m, width,
+                       ld_out, col0, (uint32_t)seed, (uint32_t)(seed >> 32), out);
     TM_HIP(hipGetLastError());
 }
 
@@ -512,15 +531,15 @@ void jacobi_preconditioner(hipStream_t s, int64_t n, const double *diag, double 
 }
 
 void cg_control_gamma(hipStream_t s, int m, int ld, const double *h,
-                      const double *dots, CgState *st, double *history) {
-    hipLaunchKernelGGL(control_gamma_kernel, dim3(1), dim3(256), 0, s, m, ld, h,
+                      const double *dots, CgState *st, double *history, int ngroups, int ldg) {
+    hipLaunchKernelGGL(control_gamma_kernel, dim3(ngroups), dim3(256), 0, s, m, ld, ldg, h,
                        dots, st, history);
     TM_HIP(hipGetLastError());
 }
 
 void cg_control_alpha(hipStream_t s, int m, int ld, const double *h,
-                      const double *dots2, CgState *st) {
-    hipLaunchKernelGGL(control_alpha_kernel, dim3(1), dim3(256), 0, s, m, ld, h,
+                      const double *dots2, CgState *st, int ngroups, int ldg) {
+    hipLaunchKernelGGL(control_alpha_kernel, dim3(ngroups), dim3(256), 0, s, m, ld, ldg, h,
                        dots2, st);
     TM_HIP(hipGetLastError());
 }
@@ -532,8 +551,8 @@ void sum_vector(hipStream_t s, int m, const double *v, double *out) {
 
 template void coldots<double>(hipStream_t, int64_t, int, const DotArgs<double> &, double *, double *);
 template void coldots<float>(hipStream_t, int64_t, int, const DotArgs<float> &, double *, double *);
-template void p_update<double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *);
-template void p_update<float, float>(hipStream_t, int64_t, int, const float *, const double *, const CgState *, float *);
+template void p_update<double, double>(hipStream_t, int64_t, int, const double *, const double *, const CgState *, double *, int);
+template void p_update<float, float>(hipStream_t, int64_t, int, const float *, const double *, const CgState *, float *, int);
 template void convert_block<double, float>(hipStream_t, int64_t, const double *, float *);
 template void convert_block<float, double>(hipStream_t, int64_t, const float *, double *);
 

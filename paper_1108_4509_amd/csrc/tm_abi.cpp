@@ -81,7 +81,7 @@ T *upload(tm_ctx *ctx, const T *host, size_t count) {
 
 void free_matrix_arrays(tm_mat *m) {
     tm_ctx *c = m->ctx;
-    void *arrs[] = {m->rowptr, m->col, m->val64, m->val32, m->V64, m->V32, m->diag};
+    void *arrs[] = {m->rowptr, m->col, m->val64, m->val32, m->V64, m->V32, m->diag, m->bd64, m->bd32};
     for (void *p : arrs)
         if (p) c->dfree(p);
 }
@@ -106,7 +106,7 @@ void *tm_ctx::dalloc(size_t bytes) {
 }
 
 void *tm_ctx::pinned_buffer() {
-    if (!pinned) TM_HIP(hipHostMalloc(&pinned, 4096, hipHostMallocDefault));
+    if (!pinned) TM_HIP(hipHostMalloc(&pinned, kPinnedBytes, hipHostMallocDefault));
     return pinned;
 }
 
@@ -439,6 +439,7 @@ tm_status tm_solve(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol, const tm
         TM_REQUIRE(H && res, TM_EINVAL, "null argument");
         check_block_args(ctx, H->n, m);
         TM_REQUIRE(H->ctx == ctx, TM_EINVAL, "matrix belongs to another context");
+        TM_REQUIRE(H->batch_k == 0, TM_EINVAL, "a batch matrix is solved by tm_solve_batch");
         TM_REQUIRE(tol > 0.0 && std::isfinite(tol), TM_EINVAL, "tol must be positive");
         TM_REQUIRE(m <= 2048, TM_ENOTSUP, "m > 2048 is not supported");
         tm_opts o;
@@ -463,6 +464,7 @@ tm_status tm_solve_generalized(tm_ctx *ctx, const tm_mat *H, const tm_mat *S, in
     return guarded([&]() {
         TM_REQUIRE(H && S && res, TM_EINVAL, "null argument");
         check_block_args(ctx, H->n, m);
+        TM_REQUIRE(H->batch_k == 0 && S->batch_k == 0, TM_EINVAL, "batch matrices take tm_solve_batch");
         TM_REQUIRE(H->ctx == ctx && S->ctx == ctx, TM_EINVAL, "matrix belongs to another context");
         TM_REQUIRE(S->n == H->n, TM_EINVAL, "H and S differ in size");
         TM_REQUIRE(S->diag_min > 0.0, TM_EINVAL, "S has a diagonal entry <= 0: not positive definite");
@@ -482,6 +484,96 @@ tm_status tm_solve_generalized(tm_ctx *ctx, const tm_mat *H, const tm_mat *S, in
     });
 }
 
+tm_status tm_set_matrix_batch(tm_ctx *ctx, int64_t n, const int64_t *rowptr, const int32_t *col,
+                              const double *val, int32_t k, const double *d, uint32_t flags,
+                              tm_mat **out) {
+    return guarded([&]() {
+        TM_REQUIRE(out && rowptr && col && val && d, TM_EINVAL, "null argument");
+        *out = nullptr;
+        TM_REQUIRE(k >= 1 && k <= kMaxBatch, TM_EINVAL, "k must be in [1, 256]");
+        TM_REQUIRE((flags & TM_DEVICE_PTRS) == 0, TM_ENOTSUP, "a batch matrix takes host arrays");
+        tm_mat *base = nullptr;
+        const tm_status st = tm_set_matrix_csr(ctx, n, rowptr, col, val, flags, &base);
+        if (st != TM_OK) throw Error{st, g_last_error};
+        std::unique_ptr<tm_mat, void (*)(tm_mat *)> m(base, tm_free_matrix);
+        // A's diagonal and off-diagonal row sums; each H_g's diagonal
+        // extremes, |row| maximum and Gershgorin interval as tm_set_matrix_csr
+        // forms them for one matrix
+        std::vector<double> adiag(n, 0.0), off(n, 0.0);
+        for (int64_t r = 0; r < n; ++r)
+            for (int64_t q = rowptr[r]; q < rowptr[r + 1]; ++q) {
+                if (col[q] == r) adiag[r] += val[q];
+                else off[r] += std::fabs(val[q]);
+            }
+        const size_t total = (size_t)k * n;
+        std::vector<float> d32(total);
+        m->b_diag_min.assign(k, 1e300);
+        m->b_diag_max.assign(k, -1e300);
+        m->b_lo.assign(k, 1e300);
+        m->b_hi.assign(k, -1e300);
+        for (int g = 0; g < k; ++g) {
+            double rmax = 0.0;
+            for (int64_t r = 0; r < n; ++r) {
+                const double dv = d[(size_t)g * n + r];
+                TM_REQUIRE(std::isfinite(dv), TM_EINVAL, "non-finite diagonal term");
+                d32[(size_t)g * n + r] = (float)dv;
+                const double hd = adiag[r] + dv;
+                m->b_diag_min[g] = std::min(m->b_diag_min[g], hd);
+                m->b_diag_max[g] = std::max(m->b_diag_max[g], hd);
+                m->b_lo[g] = std::min(m->b_lo[g], hd - off[r]);
+                m->b_hi[g] = std::max(m->b_hi[g], hd + off[r]);
+                rmax = std::max(rmax, off[r] + std::fabs(hd));
+            }
+            m->b_diag_max[g] = std::max(m->b_diag_max[g], 0.5 * rmax);
+        }
+        m->bd64 = upload(ctx, d, total);
+        m->bd32 = upload(ctx, d32.data(), total);
+        sync(ctx);
+        m->batch_k = k;
+        *out = m.release();
+        return TM_OK;
+    });
+}
+
+tm_status tm_batch_layout(int32_t k, int32_t m, int32_t *ldg, int32_t *ld) {
+    return guarded([&]() {
+        TM_REQUIRE(ldg && ld, TM_EINVAL, "null argument");
+        TM_REQUIRE(k >= 1 && k <= kMaxBatch, TM_EINVAL, "k must be in [1, 256]");
+        TM_REQUIRE(m >= 1 && m <= 2048, TM_EINVAL, "m must be in [1, 2048]");
+        *ldg = batch_group_ld(k, m);
+        *ld = leading_dim(k * *ldg);
+        return TM_OK;
+    });
+}
+
+tm_status tm_solve_batch(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol, const tm_opts *opts,
+                         const double *C0, double *C_out, double *eig_out, tm_result *res) {
+    return guarded([&]() {
+        TM_REQUIRE(H && res, TM_EINVAL, "null argument");
+        check_block_args(ctx, H->n, m);
+        TM_REQUIRE(H->ctx == ctx, TM_EINVAL, "matrix belongs to another context");
+        TM_REQUIRE(H->batch_k > 0, TM_EINVAL, "not a batch matrix (tm_set_matrix_batch)");
+        TM_REQUIRE(tol > 0.0 && std::isfinite(tol), TM_EINVAL, "tol must be positive");
+        const int k = H->batch_k;
+        TM_REQUIRE((int64_t)k * batch_group_ld(k, m) <= 2048, TM_ENOTSUP,
+                   "a batch of more than 2048 columns is not supported");
+        tm_opts o;
+        if (opts) o = *opts; else tm_opts_default(&o);
+        TM_REQUIRE(o.max_iter >= 0, TM_EINVAL, "max_iter must be >= 0");
+        TM_REQUIRE(o.precision >= TM_FULL_DP && o.precision <= TM_MP2_MP1, TM_EINVAL, "unknown precision");
+        TM_REQUIRE(o.precision != TM_MIXED_BF16 && o.precision != TM_FULL_BF16, TM_ENOTSUP,
+                   "batched solves take no BF16 policy");
+        TM_REQUIRE(o.graphs == 0 || o.graphs == 1, TM_EINVAL, "tm_opts.graphs must be 0 or 1");
+        TM_REQUIRE(o.precondition == 0 || (o.precondition == 2 && o.cheb_degree == 2 &&
+                                           o.cheb_shift > 0.0 && std::isfinite(o.cheb_shift)),
+                   TM_ENOTSUP, "batched solves take no preconditioner or the degree-2 polynomial");
+        o.history = 0;
+        std::memset(res, 0, (size_t)k * sizeof(*res));
+        Solver solver(ctx, H, m, tol, o);
+        return solver.run(C0, C_out, eig_out, res, nullptr, 0);
+    });
+}
+
 tm_status tm_random_block(tm_ctx *ctx, int64_t n, int32_t m, uint64_t seed, double *out) {
     return guarded([&]() {
         TM_REQUIRE(out, TM_EINVAL, "null argument");
@@ -497,7 +589,16 @@ tm_status tm_spmm(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t dtype, const 
         TM_REQUIRE(H && C && X, TM_EINVAL, "null argument");
         check_block_args(ctx, H->n, m);
         TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
-        spmm_any(ctx->stream, H, leading_dim(m), C, X, dtype == TM_F64);
+        if (H->batch_k > 0) {
+            // the batch layout: problem g's m columns at g * ldg
+            const int ldg = batch_group_ld(H->batch_k, m);
+            SpmmEpi epi;
+            epi.D = dtype == TM_F64 ? (const void *)H->bd64 : (const void *)H->bd32;
+            epi.dld = ldg;
+            spmm_any(ctx->stream, H, leading_dim(H->batch_k * ldg), C, X, dtype == TM_F64, 0, nullptr, epi);
+        } else {
+            spmm_any(ctx->stream, H, leading_dim(m), C, X, dtype == TM_F64);
+        }
         sync(ctx);
         return TM_OK;
     });
@@ -598,6 +699,7 @@ tm_status tm_energy_grad(tm_ctx *ctx, const tm_mat *H, int32_t m, int32_t precis
     return guarded([&]() {
         TM_REQUIRE(H && C && X && G && h && Hp && E, TM_EINVAL, "null argument");
         check_block_args(ctx, H->n, m);
+        TM_REQUIRE(H->batch_k == 0, TM_EINVAL, "not defined for a batch matrix");
         TM_REQUIRE(precision == TM_FULL_DP || precision == TM_MP2 || precision == TM_MP1, TM_EINVAL,
                    "precision must be TM_FULL_DP, TM_MP1 or TM_MP2");
         const int ld = leading_dim(m);
@@ -707,6 +809,7 @@ tm_status tm_time_kernel(tm_ctx *ctx, const tm_mat *H, int32_t kernel, int32_t m
     return guarded([&]() {
         TM_REQUIRE(H && avg_ms, TM_EINVAL, "null argument");
         check_block_args(ctx, H->n, m);
+        TM_REQUIRE(H->batch_k == 0, TM_EINVAL, "not defined for a batch matrix");
         TM_REQUIRE(reps >= 1 && reps <= 100000, TM_EINVAL, "reps out of range");
         TM_REQUIRE(dtype == TM_F64 || dtype == TM_F32, TM_EINVAL, "dtype");
         TM_REQUIRE(kernel >= TM_K_SPMM && kernel <= TM_K_GRAM_BF16X3, TM_EINVAL, "unknown kernel");

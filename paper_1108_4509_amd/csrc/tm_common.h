@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/tracemin.h"
 
@@ -36,6 +37,16 @@ struct Error {
     } while (0)
 
 inline int leading_dim(int m) { return (m + 31) / 32 * 32; }
+
+// Batched solves: at most kMaxBatch problems; problem g of k with m columns
+// owns ldg = batch_group_ld(k, m) columns (m rounded up to 16, then up to a
+// k * ldg that is a multiple of 64: the column-chunked SpMM's FP32 width).
+constexpr int kMaxBatch = 256;
+inline int batch_group_ld(int k, int m) {
+    int ldg = (m + 15) / 16 * 16;
+    while ((int64_t)k * ldg % 64) ldg += 16;
+    return ldg;
+}
 
 // Device-resident scalars of the CG controller (one per solve).
 struct CgState {
@@ -85,10 +96,18 @@ struct StencilDev {
 // degree one in H, e.g. the degree-2 Chebyshev preconditioner); E: the extra
 // block of the third dot mode.  Only the column-chunked CSR kernel and the
 // 3-D 7-point stencil kernel take it (spmm_fast_path tells).
+// Batched operators H_g = A + diag(d_g) (one shared A, a diagonal per
+// problem; problem g owns columns g * dld .. (g + 1) * dld - 1): D holds the
+// d_g in the block's precision, problem-major (d_g at D + g * n), and is
+// added to A C in the epilogue; gab (2 per problem, FP64) replaces a, b of
+// the affine form per problem.
 struct SpmmEpi {
     double a = 0.0, b = 1.0;
     int affine = 0;
     const void *E = nullptr;
+    const void *D = nullptr;
+    int dld = 0;
+    const double *gab = nullptr;
 };
 // ndot = 0: X = H C only.  ndot = 1: also per-workgroup partial sums of
 // c_j . x_j; ndot = 2: of c_j . x_j and c_j . c_j; ndot = 3 (fast path
@@ -129,6 +148,15 @@ template <typename T>
 void coldots(hipStream_t s, int64_t n, int ld, const DotArgs<T> &args,
              double *partials, double *out);
 
+// Block-diagonal results of batched solves: with ldg > 0, entries (i, j) of
+// different problems (i / ldg != j / ldg) and of the zero columns that pad
+// each problem to ldg (i % ldg >= mg or j % ldg >= mg) are stored as 0, the
+// padding's diagonal as pad (1 keeps a Gram matrix positive definite).
+struct BatchCols {
+    int ldg = 0, mg = 0;
+    double pad = 0.0;
+};
+
 // Gram products out = A^T B' (m x m, FP64), B' = B - A diag(h) if h --------
 size_t gram_workspace(int64_t n, int m);
 // Bytes of FP64 partials gram() (symmetric or not) uses when its workspace
@@ -147,13 +175,14 @@ template <typename TA, typename TM>
 void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           const double *h, bool zero_diag, bool symmetric, double *partials,
           double *out, bool reduce = true, TM *xshift = nullptr, TM *wpad = nullptr,
-          size_t ws_bytes = 0);
+          size_t ws_bytes = 0, BatchCols bc = BatchCols());
 
 // S = Cn^T Cn with Cn = C + alpha P formed while staged (alpha from st) and
-// written to Cn: the update of Fig. 1 fused into Fig. 4 step (1).
+// written to Cn: the update of Fig. 1 fused into Fig. 4 step (1).  Batched
+// solves (bc.ldg > 0): column j takes the alpha of st[j / bc.ldg].
 template <typename TA, typename TM, typename TP>
 void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, const CgState *st,
-                 TA *Cn, double *partials, double *out);
+                 TA *Cn, double *partials, double *out, BatchCols bc = BatchCols());
 
 // The Gram product with h (H' = A^T (B - A diag(h)), or A^T B without h) on
 // BF16 matrix cores with two-term BF16 operands (about 2^-16 relative to
@@ -195,21 +224,30 @@ void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
                   double *work, int32_t *info);
 size_t jacobi_workspace(int m);
 // Eigenpairs of symmetric A: w ascending, U columns.  info[0] = sweeps.
+// Batched (block-diagonal) A: ascending within each group of ldg indices,
+// of which the first mg are real (ldg = 0: one group).
 void jacobi_eig(hipStream_t s, int m, const double *A, double *U, double *w,
-                double *work, int32_t *info);
+                double *work, int32_t *info, int ldg = 0, int mg = 0);
+// Block-diagonal mask of a batch's m x m matrix (see the kernel).
+void batch_mask(hipStream_t s, int m, int ldg, int mg, double pad_diag, double *A);
 // A = 0.5 (H' + H'^T) + diag(h): the m x m H of Eq. 9 from Algorithm-2 pieces.
 void assemble_subspace_matrix(hipStream_t s, int m, const double *Hp,
                               const double *h, double *A);
 
 // Elementwise block kernels -------------------------------------------------
-// P = M G + gamma P   (gamma read from st->gamma; M = per-row weights or null)
+// P = M G + gamma P   (gamma read from st->gamma; M = per-row weights or null).
+// Batched solves: column j takes the gamma of st[j / ldg] (ldg = 0: one group).
 template <typename TG, typename TP>
 void p_update(hipStream_t s, int64_t n, int ld, const TG *G, const double *M,
-              const CgState *st, TP *P);
+              const CgState *st, TP *P, int ldg = 0);
 template <typename TI, typename TO>
 void convert_block(hipStream_t s, int64_t count, const TI *in, TO *out);
 // The seeded standard normal start block of tm_random_block (n x ld FP64).
-void random_block(hipStream_t s, int64_t n, int m, uint64_t seed, double *out);
+// With width > 0 only columns col0 .. col0 + width - 1 of an n x ld_out block
+// are written (entries of columns >= m of that range are 0): one problem of a
+// batched start block.
+void random_block(hipStream_t s, int64_t n, int m, uint64_t seed, double *out, int width = 0,
+                  int ld_out = 0, int col0 = 0);
 // Chebyshev iteration steps (polynomial preconditioner): d = z = g * inv_theta;
 // r_out = r_in - (t - sigma d), d = c_dd d + c_r r_out, z += d (t = H d).
 // r_out may alias r_in.
@@ -231,13 +269,16 @@ void pad_vector(hipStream_t s, int m, int ld, const double *v, double *out);
 void jacobi_preconditioner(hipStream_t s, int64_t n, const double *diag, double sigma,
                            double *M);
 
-// CG controller (single workgroup) -----------------------------------------
+// CG controller (one workgroup per problem) --------------------------------
 // After the gradient: dots = [gg | gz | gprev_z | pprev_g] (4 x ld), h (ld).
+// Batched solves: ngroups problems of m columns each, problem g in columns
+// g * ldg .. g * ldg + m - 1 with its state st[g].
 void cg_control_gamma(hipStream_t s, int m, int ld, const double *h,
-                      const double *dots, CgState *st, double *history);
+                      const double *dots, CgState *st, double *history, int ngroups = 1,
+                      int ldg = 0);
 // After Y = HP: dots2 = [py | pp] (2 x ld).
 void cg_control_alpha(hipStream_t s, int m, int ld, const double *h,
-                      const double *dots2, CgState *st);
+                      const double *dots2, CgState *st, int ngroups = 1, int ldg = 0);
 // Sum of the m entries of v into *out (single workgroup, fixed order).
 void sum_vector(hipStream_t s, int m, const double *v, double *out);
 
@@ -249,7 +290,11 @@ struct tm_ctx {
     hipStream_t stream = nullptr;
     tm_allocator alloc{};
     bool custom_alloc = false;
-    void *pinned = nullptr;      // 4 KiB of pinned host memory for polling, made on first use
+    // pinned host memory for polling, made on first use: the controller
+    // states of up to kMaxBatch problems, then 64 bytes of status words
+    static constexpr size_t kPinnedStates = 48 << 10;
+    static constexpr size_t kPinnedBytes = kPinnedStates + 64;
+    void *pinned = nullptr;
     void *dalloc(size_t bytes);
     void dfree(void *p);
     void *pinned_buffer();
@@ -274,4 +319,11 @@ struct tm_mat {
     // Gershgorin bounds of the spectrum: min / max over rows of
     // H_ii -+ sum_{j != i} |H_ij|
     double gersh_lo = 0, gersh_hi = 0;
+    // a batch of batch_k operators H_g = A + diag(d_g) (CSR A above): d_g in
+    // FP64 and FP32 (problem-major), each H_g's diagonal extremes and
+    // Gershgorin bounds
+    int32_t batch_k = 0;
+    double *bd64 = nullptr;
+    float *bd32 = nullptr;
+    std::vector<double> b_diag_min, b_diag_max, b_lo, b_hi;
 };

@@ -28,6 +28,7 @@ DevMem::~DevMem() {
 
 int spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, bool f64, int ndot,
              double *partials, const SpmmEpi &epi) {
+    TM_REQUIRE(!epi.D || !H->is_stencil, TM_ENOTSUP, "batched operators are CSR");
     if (H->is_stencil) {
         if (f64)
             return spmm_stencil<double>(s, H->st, H->n, ld, (const double *)C, (double *)X, ndot,
@@ -127,6 +128,16 @@ struct Solver::Impl {
     int rotations = 0;
     bool bf16_bulk = false;   // the FP32 phase forms H' on BF16 matrix cores
 
+    // a batched solve of the ng problems H_g = A + diag(d_g) of a batch
+    // matrix: problem g owns columns g * ldg .. g * ldg + mg - 1 of every
+    // block (zero columns pad it to ldg), m = ng * ldg; every small matrix
+    // is block-diagonal, every column operation reads its problem's state.
+    // One problem: ng = 1, mg = m, ldg = 0.
+    bool batched = false;
+    int ng = 1, mg = 0, ldg = 0;
+    std::unique_ptr<DevMem> gab;   // per-problem a, b of the degree-2 polynomial
+    std::vector<double> switch_g;  // per-problem switch_tol
+
     // captured iteration batches, keyed by the buffers they were recorded on
     // and the precision phase (which selects the kernels)
     struct GraphKey {
@@ -143,7 +154,36 @@ struct Solver::Impl {
     }
 
     Impl(tm_ctx *c, const tm_mat *Hm, const tm_mat *Sm, int mm, double t, const tm_opts &oo)
-        : ctx(c), H(Hm), m(mm), ld(leading_dim(mm)), n(Hm->n), tol(t), o(oo), s(c->stream), Smat(Sm) {}
+        : ctx(c), H(Hm), m(mm), ld(leading_dim(mm)), n(Hm->n), tol(t), o(oo), s(c->stream), Smat(Sm) {
+        mg = mm;
+        if (Hm->batch_k > 0) {
+            batched = true;
+            ng = Hm->batch_k;
+            ldg = batch_group_ld(ng, mm);
+            m = ng * ldg;
+            ld = leading_dim(m);
+        }
+    }
+
+    // the block-diagonal mask of a batched solve's m x m results
+    BatchCols bcols(double pad) const {
+        BatchCols b;
+        if (batched) {
+            b.ldg = ldg;
+            b.mg = mg;
+            b.pad = pad;
+        }
+        return b;
+    }
+    // the SpMM epilogue term of the batch: X = A C + d_g c (columns of g)
+    SpmmEpi bepi(bool f64) const {
+        SpmmEpi e;
+        if (batched) {
+            e.D = f64 ? (const void *)H->bd64 : (const void *)H->bd32;
+            e.dld = ldg;
+        }
+        return e;
+    }
 
 
     void alloc_small() {
@@ -165,29 +205,31 @@ struct Solver::Impl {
         chol_ws.reset(new DevMem(ctx, chol_workspace(m)));
         jac_ws.reset(new DevMem(ctx, jacobi_workspace(m)));
         info.reset(new DevMem(ctx, 64));
-        state.reset(new DevMem(ctx, sizeof(CgState)));
+        state.reset(new DevMem(ctx, ng * sizeof(CgState)));
         st = (CgState *)state->ptr;
         TM_HIP(hipMemsetAsync(h->ptr, 0, ld * sizeof(double), s));
         TM_HIP(hipMemsetAsync(d->ptr, 0, ld * sizeof(double), s));
         TM_HIP(hipMemsetAsync(w->ptr, 0, ld * sizeof(double), s));
-        static_assert(sizeof(CgState) <= 2048, "CgState must fit the pinned buffer");
+        static_assert(kMaxBatch * sizeof(CgState) <= tm_ctx::kPinnedStates,
+                      "the states of a batch must fit the pinned buffer");
         char *pin = (char *)ctx->pinned_buffer();
         st_host = (CgState *)pin;
-        info_host = (int32_t *)(pin + 2048);
-        if (o.precondition == 2) {
-            const double lo = H->gersh_lo, hi = H->gersh_hi;
-            ch_sigma = lo - o.cheb_shift * (hi - lo);
-            const double a = lo - ch_sigma, b = hi - ch_sigma;
-            TM_REQUIRE(b > a && a > 0.0, TM_EINVAL, "degenerate Gershgorin interval");
-            ch_theta = 0.5 * (a + b);
-            ch_delta = 0.5 * (b - a);
-            // d0 = g / theta = z1; r1 = g - (H - sigma) d0;
-            // z2 = z1 + rho1 rho0 d0 + (2 rho1 / delta) r1, rho0 = delta / theta,
-            // rho1 = 1 / (2 theta / delta - rho0)
-            const double rho0 = ch_delta / ch_theta, rho1 = 1.0 / (2.0 * ch_theta / ch_delta - rho0);
-            const double cr = 2.0 * rho1 / ch_delta;
-            ch_lin_a = (1.0 + rho1 * rho0) / ch_theta + cr * (1.0 + ch_sigma / ch_theta);
-            ch_lin_b = -cr / ch_theta;
+        info_host = (int32_t *)(pin + tm_ctx::kPinnedStates);
+        if (o.precondition == 2 && batched) {
+            // each problem's own Gershgorin interval and degree-2 polynomial
+            TM_REQUIRE(o.cheb_degree == 2, TM_ENOTSUP, "batched solves take the degree-2 polynomial");
+            std::vector<double> ab(2 * ng);
+            for (int g = 0; g < ng; ++g) {
+                double th, de, sg;
+                cheb_interval(H->b_lo[g], H->b_hi[g], sg, th, de);
+                linear_cheb(sg, th, de, ab[2 * g], ab[2 * g + 1]);
+            }
+            gab.reset(new DevMem(ctx, ab.size() * sizeof(double)));
+            TM_HIP(hipMemcpyAsync(gab->ptr, ab.data(), ab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            TM_HIP(hipStreamSynchronize(s));
+        } else if (o.precondition == 2) {
+            cheb_interval(H->gersh_lo, H->gersh_hi, ch_sigma, ch_theta, ch_delta);
+            linear_cheb(ch_sigma, ch_theta, ch_delta, ch_lin_a, ch_lin_b);
         }
         if (o.precondition == 1) {
             // Eq. 18 with M_ii = 1 / (H_ii - sigma), sigma = min(0, min_i H_ii - 1/2)
@@ -197,6 +239,26 @@ struct Solver::Impl {
             const double sigma = std::min(0.0, H->diag_min - 0.5);
             jacobi_preconditioner(s, n, H->diag, sigma, (double *)M->ptr);
         }
+    }
+
+    // shift sigma, centre theta and half-width delta of the Chebyshev
+    // iteration on the Gershgorin interval [lo, hi] shifted by sigma
+    void cheb_interval(double lo, double hi, double &sigma, double &theta, double &delta) const {
+        sigma = lo - o.cheb_shift * (hi - lo);
+        const double a = lo - sigma, b = hi - sigma;
+        TM_REQUIRE(b > a && a > 0.0, TM_EINVAL, "degenerate Gershgorin interval");
+        theta = 0.5 * (a + b);
+        delta = 0.5 * (b - a);
+    }
+    // two Chebyshev steps as the linear polynomial z = a g + b H g:
+    // d0 = g / theta = z1; r1 = g - (H - sigma) d0;
+    // z2 = z1 + rho1 rho0 d0 + (2 rho1 / delta) r1, rho0 = delta / theta,
+    // rho1 = 1 / (2 theta / delta - rho0)
+    static void linear_cheb(double sigma, double theta, double delta, double &a, double &b) {
+        const double rho0 = delta / theta, rho1 = 1.0 / (2.0 * theta / delta - rho0);
+        const double cr = 2.0 * rho1 / delta;
+        a = (1.0 + rho1 * rho0) / theta + cr * (1.0 + sigma / theta);
+        b = -cr / theta;
     }
 
     size_t blk(bool f64) const { return (size_t)n * ld * (f64 ? 8 : 4); }
@@ -242,7 +304,8 @@ struct Solver::Impl {
     // ---- orthonormalization (Fig. 4): Cn -> C
     template <typename TC, typename TS, typename TT>
     void orthonormalize(TC *Cin, TC *Cout) {
-        gram<TC, TS>(s, n, m, Cin, Cin, nullptr, false, true, (double *)gram_ws->ptr, (double *)S->ptr);
+        gram<TC, TS>(s, n, m, Cin, Cin, nullptr, false, true, (double *)gram_ws->ptr, (double *)S->ptr,
+                     true, nullptr, nullptr, 0, bcols(1.0));
         finish_orthonormalize<TC, TT>(Cin, Cout);
     }
     // Fig. 4 steps (2)-(4) once S = Cin^T Cin is in S: Cout = Cin R^{-1}
@@ -256,12 +319,13 @@ struct Solver::Impl {
     // ---- Rayleigh-Ritz (Eq. 9): C <- C U, ascending Ritz values into w
     template <typename TC, typename TM>
     void rayleigh_ritz(TC *&C, TC *&Cn, TC *X) {
-        const int nch = spmm_any(s, H, ld, C, X, is_f64<TC>(), 1, (double *)dot_ws->ptr);
+        const int nch = spmm_any(s, H, ld, C, X, is_f64<TC>(), 1, (double *)dot_ws->ptr, bepi(is_f64<TC>()));
         reduce_partials(s, 1, nch, ld, (double *)dot_ws->ptr, (double *)h->ptr);
-        gram<TC, TM>(s, n, m, C, X, (double *)h->ptr, false, false, (double *)gram_ws->ptr, (double *)Hp->ptr);
+        gram<TC, TM>(s, n, m, C, X, (double *)h->ptr, false, false, (double *)gram_ws->ptr, (double *)Hp->ptr,
+                     true, nullptr, nullptr, 0, bcols(0.0));
         assemble_subspace_matrix(s, m, (double *)Hp->ptr, (double *)h->ptr, (double *)Amat->ptr);
         jacobi_eig(s, m, (double *)Amat->ptr, (double *)U->ptr, (double *)w->ptr, (double *)jac_ws->ptr,
-                   (int32_t *)info->ptr + 1);
+                   (int32_t *)info->ptr + 1, ldg, mg);
         pad_matrix<TM>(s, m, (double *)U->ptr, false, (TM *)Wp->ptr, nullptr);
         rot<TC, TM, TC>(s, n, m, C, (TM *)Wp->ptr, EPI_NONE, nullptr, nullptr, Cn);
         std::swap(C, Cn);
@@ -280,7 +344,7 @@ struct Solver::Impl {
         double rho = 1.0 / s1;
         const TG *r_in = Gv;
         for (int k = 1; k < o.cheb_degree; ++k) {
-            spmm_any(s, H, ld, D, T, is_f64<TG>());
+            spmm_any(s, H, ld, D, T, is_f64<TG>(), 0, nullptr, bepi(is_f64<TG>()));
             const double rho_new = 1.0 / (2.0 * s1 - rho);
             cheb_step<TG>(s, count, T, r_in, R, D, Z, ch_sigma, rho_new * rho, 2.0 * rho_new / ch_delta);
             r_in = R;
@@ -313,7 +377,7 @@ struct Solver::Impl {
         const double *Mv = M ? (const double *)M->ptr : nullptr;
         // (1)-(3): X = HC with h = diag(C^T X) fused into the SpMM
         {
-            const int nch = spmm_any(s, H, ld, C, X, is_f64<TC>(), 1, (double *)dot_ws->ptr);
+            const int nch = spmm_any(s, H, ld, C, X, is_f64<TC>(), 1, (double *)dot_ws->ptr, bepi(is_f64<TC>()));
             reduce_partials(s, 1, nch, ld, (double *)dot_ws->ptr, (double *)h->ptr);
         }
         // (5)-(6): H' = C^T (X - C H_D), diag(H') = 0; X' = X - C H_D is formed
@@ -333,10 +397,10 @@ struct Solver::Impl {
         } else if constexpr (keep_xs) {
             Xs = reinterpret_cast<TMH *>(Yv);
             gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, true, (double *)gram_ws->ptr,
-                          (double *)Hp->ptr, true, Xs, (TMH *)Wp->ptr);
+                          (double *)Hp->ptr, true, Xs, (TMH *)Wp->ptr, 0, bcols(0.0));
         } else {
             gram<TC, TMH>(s, n, m, C, X, (double *)h->ptr, true, true, (double *)gram_ws->ptr,
-                          (double *)Hp->ptr, true, nullptr, (TMH *)Wp->ptr);
+                          (double *)Hp->ptr, true, nullptr, (TMH *)Wp->ptr, 0, bcols(0.0));
         }
         // (7): G = -2 (X' - C H'); the reduction above stored H' padded in TMH
         // with the traces for Eq. 8 and the descent test fused into the epilogue
@@ -355,14 +419,16 @@ struct Solver::Impl {
                 // two Chebyshev steps are the linear polynomial a I + b H: one
                 // SpMM with an affine epilogue, which also forms g.z and
                 // g_prev.z
-                SpmmEpi epi;
+                SpmmEpi epi = bepi(is_f64<TG>());
                 epi.affine = 1;
                 epi.a = ch_lin_a;
                 epi.b = ch_lin_b;
+                epi.gab = gab ? (const double *)gab->ptr : nullptr;
                 epi.E = Gpv;
                 const int nch = spmm_any(s, H, ld, Gv, Zv, is_f64<TG>(), 3, (double *)dot_ws->ptr, epi);
                 reduce_partials(s, 2, nch, ld, (double *)dot_ws->ptr, (double *)dots->ptr + ld);
             } else {
+                TM_REQUIRE(!batched, TM_ENOTSUP, "batched solves need the fused degree-2 polynomial");
                 precondition_poly<TG>(Gv, Zv, (TG *)Rc->ptr, (TG *)Dc->ptr, Yv);
                 DotArgs<TG> a;
                 a.nprod = 2;
@@ -371,19 +437,19 @@ struct Solver::Impl {
                 coldots<TG>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr + ld);
             }
         }
-        cg_control_gamma(s, m, ld, (double *)h->ptr, (double *)dots->ptr, st, hist_dev);
+        cg_control_gamma(s, mg, ld, (double *)h->ptr, (double *)dots->ptr, st, hist_dev, ng, ldg);
         // P = M G + gamma P
-        if (Zv) p_update<TG, TG>(s, n, ld, Zv, nullptr, st, Pv);
-        else p_update<TG, TG>(s, n, ld, Gv, Mv, st, Pv);
+        if (Zv) p_update<TG, TG>(s, n, ld, Zv, nullptr, st, Pv, ldg);
+        else p_update<TG, TG>(s, n, ld, Gv, Mv, st, Pv, ldg);
         // line step: Y = HP with p.y and p.p fused into the SpMM
         {
-            const int nch = spmm_any(s, H, ld, Pv, Yv, is_f64<TG>(), 2, (double *)dot_ws->ptr);
+            const int nch = spmm_any(s, H, ld, Pv, Yv, is_f64<TG>(), 2, (double *)dot_ws->ptr, bepi(is_f64<TG>()));
             reduce_partials(s, 2, nch, ld, (double *)dot_ws->ptr, (double *)dots2->ptr);
         }
-        cg_control_alpha(s, m, ld, (double *)h->ptr, (double *)dots2->ptr, st);
+        cg_control_alpha(s, mg, ld, (double *)h->ptr, (double *)dots2->ptr, st, ng, ldg);
         // C_{i+1} = orthonormalize(C_i + alpha P): the update is formed inside
         // the Gram S = (C + alpha P)^T (C + alpha P), which also stores it
-        gram_update<TC, TMS, TG>(s, n, m, C, Pv, st, Cn, (double *)gram_ws->ptr, (double *)S->ptr);
+        gram_update<TC, TMS, TG>(s, n, m, C, Pv, st, Cn, (double *)gram_ws->ptr, (double *)S->ptr, bcols(1.0));
         finish_orthonormalize<TC, TT>(Cn, C);
         std::swap(G, Gp);
     }
@@ -461,35 +527,75 @@ struct Solver::Impl {
         std::swap(G, Gp);
     }
 
-    void reset_state(double switch_tol, int gate, int hist_len) {
-        CgState init{};
-        init.tol = tol;
-        init.rise_tol = o.rise_tol;
-        init.switch_tol = switch_tol;
-        init.stall_tol = o.stall_tol > 0 ? o.stall_tol : 1e-7;
-        init.stall_window = gate ? 25 : 0;
-        init.history_len = hist_len;
-        init.phase_gate = gate;
-        TM_HIP(hipMemcpyAsync(st, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+    void reset_state(int gate, int hist_len) {
+        std::vector<CgState> init(ng);
+        for (int g = 0; g < ng; ++g) {
+            CgState &c = init[g];
+            c = CgState{};
+            c.tol = tol;
+            c.rise_tol = o.rise_tol;
+            c.switch_tol = switch_g[g];
+            c.stall_tol = o.stall_tol > 0 ? o.stall_tol : 1e-7;
+            c.stall_window = gate ? 25 : 0;
+            c.history_len = hist_len;
+            c.phase_gate = gate;
+        }
+        TM_HIP(hipMemcpyAsync(st, init.data(), ng * sizeof(CgState), hipMemcpyHostToDevice, s));
+        TM_HIP(hipStreamSynchronize(s));
     }
 
-    void poll() {
-        TM_HIP(hipMemcpyAsync(st_host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    // the host's view of the controller states after a poll
+    struct View {
+        int it = 0;                 // iterations of the furthest problem
+        bool nan = false;           // any problem saw NaN/Inf
+        bool all_done = true;       // every problem converged
+        bool all_stopped = true;    // every problem converged or ended its phase
+        double E = 0.0, rho = 0.0;  // sum of the energies, largest rho
+    };
+    View poll() {
+        TM_HIP(hipMemcpyAsync(st_host, st, ng * sizeof(CgState), hipMemcpyDeviceToHost, s));
         TM_HIP(hipMemcpyAsync(info_host, info->ptr, 16, hipMemcpyDeviceToHost, s));
         TM_HIP(hipStreamSynchronize(s));
         if (info_host[0] != 0)
             throw Error{TM_ENOTSPD, "C^T C is not positive definite (pivot " + std::to_string(info_host[0]) + ")"};
+        View v;
+        for (int g = 0; g < ng; ++g) {
+            const CgState &c = st_host[g];
+            v.it = std::max(v.it, (int)c.it);
+            v.nan |= c.nan_seen != 0;
+            v.all_done &= c.done != 0;
+            v.all_stopped &= c.done != 0 || c.phase_end != 0;
+            v.E += c.E;
+            v.rho = std::max(v.rho, c.rho);
+        }
+        return v;
+    }
+    // next phase: every problem that is not converged continues, with the
+    // phase gate and stall window cleared (have_prev = 0 restarts CG)
+    void next_phase_state(bool restart_cg) {
+        std::vector<CgState> cur(st_host, st_host + ng);
+        for (CgState &c : cur) {
+            c.phase_end = 0;
+            c.phase_gate = 0;
+            c.stall_window = 0;
+            c.window_it = 0;
+            if (restart_cg) c.have_prev = 0;
+        }
+        TM_HIP(hipMemcpyAsync(st, cur.data(), ng * sizeof(CgState), hipMemcpyHostToDevice, s));
+        TM_HIP(hipStreamSynchronize(s));
     }
 
-    double auto_switch_tol() const {
+    double auto_switch_tol(double dmin, double dmax, int mcols) const {
         // rounding floor of rho ~ u * ||H|| * sqrt(m) for the bulk phase's
         // unit roundoff u (FP32 2^-24; two-term BF16 about 2^-17); leave the
         // bulk phase a little above it (16x: measured best at 48^3, m = 256)
-        const double hnorm = std::max(std::fabs(H->diag_max), std::fabs(H->diag_min)) * 2.0;
-        if (bf16_bulk) return 4.0 * 7.63e-6 * hnorm * std::sqrt((double)m);
-        return 16.0 * 5.96e-8 * hnorm * std::sqrt((double)m);
+        const double hnorm = std::max(std::fabs(dmax), std::fabs(dmin)) * 2.0;
+        if (bf16_bulk) return 4.0 * 7.63e-6 * hnorm * std::sqrt((double)mcols);
+        return 16.0 * 5.96e-8 * hnorm * std::sqrt((double)mcols);
     }
 
+    // res: ng results (one per problem); eig_out: ng * mg values, problem g
+    // at g * mg
     tm_status run(const double *C0, double *C_out, double *eig_out, tm_result *res,
                   double *hist_host, int hist_len) {
         auto t0 = std::chrono::steady_clock::now();
@@ -523,6 +629,8 @@ struct Solver::Impl {
         const bool mixed = prec == TM_MIXED || prec == TM_MIXED_BF16;
         const bool mp2_mp1 = prec == TM_MP2_MP1;
         bf16_bulk = prec == TM_MIXED_BF16 || prec == TM_FULL_BF16;
+        TM_REQUIRE(!batched || (!bf16_bulk && o.precondition != 1 && hl == 0 && !Smat), TM_ENOTSUP,
+                   "batched solves take no BF16 policy, diagonal preconditioner, history or S");
         Phase ph = phase_of((mixed || prec == TM_FULL_BF16) ? TM_FULL_SP : (mp2_mp1 ? TM_MP2 : prec));
         alloc_c(ph.c64);
         alloc_g(ph.g64);
@@ -531,7 +639,13 @@ struct Solver::Impl {
         std::unique_ptr<DevMem> c0_own;
         if (!C0) {
             c0_own.reset(new DevMem(ctx, blk(true)));
-            random_block(s, n, m, o.seed, (double *)c0_own->ptr);
+            if (batched) {
+                // problem g: the block tm_random_block gives with seed + g
+                for (int g = 0; g < ng; ++g)
+                    random_block(s, n, mg, o.seed + (uint64_t)g, (double *)c0_own->ptr, ldg, ld, g * ldg);
+            } else {
+                random_block(s, n, m, o.seed, (double *)c0_own->ptr);
+            }
             C0 = (const double *)c0_own->ptr;
         }
         // start block -> C (cast), orthonormalize
@@ -541,8 +655,12 @@ struct Solver::Impl {
             convert_block<double, float>(s, n * ld, C0, (float *)Cn32->ptr);
         }
         const bool gate = mixed || mp2_mp1 || prec == TM_FULL_SP || prec == TM_FULL_BF16;
-        double sw = o.switch_tol > 0 ? o.switch_tol : auto_switch_tol();
-        reset_state(sw, gate ? 1 : 0, hl);
+        switch_g.assign(ng, o.switch_tol);
+        for (int g = 0; g < ng; ++g)
+            if (!(o.switch_tol > 0))
+                switch_g[g] = batched ? auto_switch_tol(H->b_diag_min[g], H->b_diag_max[g], mg)
+                                      : auto_switch_tol(H->diag_min, H->diag_max, m);
+        reset_state(gate ? 1 : 0, hl);
         zero_g();
 
         double *c64 = C64 ? (double *)C64->ptr : nullptr, *cn64 = Cn64 ? (double *)Cn64->ptr : nullptr;
@@ -563,7 +681,8 @@ struct Solver::Impl {
         bool switched = false;
 
         int it_host = 0;        // active iterations known to the host
-        int iters_sp = 0;
+        std::vector<int> iters_sp(ng, 0);
+        View view;
         bool sp_phase = !ph.c64;
         bool first_phase = true;   // MP2 part of TM_MP2_MP1
         const int kcheck = std::max(1, o.k_check);
@@ -613,32 +732,29 @@ struct Solver::Impl {
                     it_dev_done = b + 1;
                 }
             }
-            poll();
-            it_host = st_host->it;
-            if (o.progress) o.progress(st_host->it, st_host->E, st_host->rho, switched ? 1 : 0, o.progress_user);
-            if (st_host->nan_seen) throw Error{TM_ENAN, "NaN or Inf in the energy or gradient"};
-            if (st_host->done) break;
-            if (st_host->phase_end) {
+            view = poll();
+            it_host = view.it;
+            if (o.progress) o.progress(view.it, view.E, view.rho, switched ? 1 : 0, o.progress_user);
+            if (view.nan) throw Error{TM_ENAN, "NaN or Inf in the energy or gradient"};
+            if (view.all_done) break;
+            // a batched solve changes phase once every problem has ended the
+            // phase (or converged); problems that ended it early take no steps
+            // (alpha = 0) meanwhile
+            if (view.all_stopped) {
+                for (int g = 0; g < ng; ++g) iters_sp[g] = st_host[g].it;
                 if (mp2_mp1 && first_phase) {
                     // MP2 done: MP1 from here on.  C, X and the FP32 G, G_prev, P
                     // keep their buffers and meaning, so CG continues
-                    iters_sp = st_host->it;
                     t_switch = std::chrono::steady_clock::now();
                     switched = true;
                     ph = phase_of(TM_MP1);
-                    CgState cur = *st_host;
-                    cur.phase_end = 0;
-                    cur.phase_gate = 0;
-                    cur.stall_window = 0;
-                    cur.window_it = 0;
-                    TM_HIP(hipMemcpyAsync(st, &cur, sizeof(CgState), hipMemcpyHostToDevice, s));
+                    next_phase_state(false);
                     first_phase = false;
                     continue;
                 }
                 if (mixed && sp_phase) {
                     // FP32 bulk done: cast C up (exact), re-orthonormalize in FP64,
                     // restart CG under MP2 (Sec. 3: switch when the residual is small)
-                    iters_sp = st_host->it;
                     t_switch = std::chrono::steady_clock::now();
                     switched = true;
                     ph = phase_of(TM_MP2);
@@ -651,13 +767,7 @@ struct Solver::Impl {
                     alloc_g(ph.g64);
                     zero_g();
                     orthonormalize<double, double, double>(cn64, c64);
-                    CgState cur = *st_host;
-                    cur.phase_end = 0;
-                    cur.phase_gate = 0;
-                    cur.stall_window = 0;
-                    cur.have_prev = 0;
-                    cur.window_it = 0;
-                    TM_HIP(hipMemcpyAsync(st, &cur, sizeof(CgState), hipMemcpyHostToDevice, s));
+                    next_phase_state(true);
                     sp_phase = false;
                     continue;
                 }
@@ -665,8 +775,13 @@ struct Solver::Impl {
             }
             if (it_host >= o.max_iter || it_dev_done == 0) break;
         }
-        const bool converged = st_host->done != 0;
-        const int iterations = converged ? st_host->it - 1 : st_host->it;
+        std::vector<int> iterations(ng);
+        bool all_converged = true;
+        for (int g = 0; g < ng; ++g) {
+            const CgState &c = st_host[g];
+            iterations[g] = c.done ? c.it - 1 : c.it;
+            all_converged &= c.done != 0;
+        }
         const auto t_iter_end = std::chrono::steady_clock::now();
         // one-phase policies (and a two-phase policy that never switched)
         // count every iteration as the first phase's
@@ -687,7 +802,7 @@ struct Solver::Impl {
         if (Smat) rayleigh_ritz_gen(c64, cn64, X);
         else rayleigh_ritz<double, double>(c64, cn64, X);
         --rotations;   // the final one is not a subspace rotation of the iteration
-        spmm_any(s, H, ld, c64, X, true);
+        spmm_any(s, H, ld, c64, X, true, 0, nullptr, bepi(true));
         // residuals ||H c_j - lambda_j S c_j|| and C^T S C - I (S = I for the
         // standard problem)
         const double *SC = c64;
@@ -700,45 +815,57 @@ struct Solver::Impl {
             a.nprod = 1; a.kind = 1; a.a[0] = X; a.b[0] = SC; a.sc = (double *)w->ptr;
             coldots<double>(s, n, ld, a, (double *)dot_ws->ptr, (double *)dots->ptr);
         }
+        // (unmasked: a batch's orthonormality is read from its diagonal blocks)
         gram<double, double>(s, n, m, c64, SC, nullptr, false, !Smat, (double *)gram_ws->ptr, (double *)S->ptr);
         std::vector<double> wv(m), res2(m), Sh((size_t)m * m);
         TM_HIP(hipMemcpyAsync(wv.data(), w->ptr, m * sizeof(double), hipMemcpyDeviceToHost, s));
         TM_HIP(hipMemcpyAsync(res2.data(), dots->ptr, m * sizeof(double), hipMemcpyDeviceToHost, s));
         TM_HIP(hipMemcpyAsync(Sh.data(), S->ptr, Sh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         if (C_out) TM_HIP(hipMemcpyAsync(C_out, c64, blk(true), hipMemcpyDeviceToDevice, s));
-        if (eig_out) TM_HIP(hipMemcpyAsync(eig_out, w->ptr, m * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (eig_out) {
+            // problem g's values are columns g * ldg .. g * ldg + mg - 1
+            const int stride = batched ? ldg : m;
+            TM_HIP(hipMemcpy2DAsync(eig_out, mg * sizeof(double), w->ptr, stride * sizeof(double),
+                                    mg * sizeof(double), ng, hipMemcpyDeviceToDevice, s));
+        }
         if (hl > 0) TM_HIP(hipMemcpyAsync(hist_host, hist_dev, (size_t)2 * hl * sizeof(double), hipMemcpyDeviceToHost, s));
         TM_HIP(hipStreamSynchronize(s));
 
-        double eg = 0.0, mx = 0.0, fr = 0.0, orth = 0.0;
-        for (int j = 0; j < m; ++j) {
-            eg += wv[j];
-            mx = std::max(mx, std::sqrt(res2[j]));
-            fr += res2[j];
-        }
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j)
-                orth = std::max(orth, std::fabs(Sh[(size_t)i * m + j] - (i == j ? 1.0 : 0.0)));
         auto t1 = std::chrono::steady_clock::now();
-        res->E_G = eg;
-        res->rho = st_host->rho;
-        res->max_residual = mx;
-        res->frob_residual = std::sqrt(fr);
-        res->orth_err = orth;
         auto secs = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
             return std::chrono::duration<double>(b - a).count();
         };
-        res->seconds = secs(t0, t1);
-        res->seconds_phase[0] = secs(t_loop, t_switch);
-        res->seconds_phase[1] = secs(t_switch, t_iter_end);
-        res->seconds_phase[2] = secs(t0, t_loop) + secs(t_iter_end, t1);
-        res->iterations = iterations;
-        res->iters_sp = iters_sp;
-        res->iters_phase2 = iterations - iters_sp;
-        res->converged = converged ? 1 : 0;
-        res->restarts = st_host->restarts;
-        res->rotations = rotations;
-        return converged ? TM_OK : TM_ENOCONV;
+        const int stride = batched ? ldg : m;
+        for (int g = 0; g < ng; ++g) {
+            const int c0 = g * stride;
+            double eg = 0.0, mx = 0.0, fr = 0.0, orth = 0.0;
+            for (int j = c0; j < c0 + mg; ++j) {
+                eg += wv[j];
+                mx = std::max(mx, std::sqrt(res2[j]));
+                fr += res2[j];
+            }
+            for (int i = c0; i < c0 + mg; ++i)
+                for (int j = c0; j < c0 + mg; ++j)
+                    orth = std::max(orth, std::fabs(Sh[(size_t)i * m + j] - (i == j ? 1.0 : 0.0)));
+            tm_result &r = res[g];
+            const CgState &c = st_host[g];
+            r.E_G = eg;
+            r.rho = c.rho;
+            r.max_residual = mx;
+            r.frob_residual = std::sqrt(fr);
+            r.orth_err = orth;
+            r.seconds = secs(t0, t1);
+            r.seconds_phase[0] = secs(t_loop, t_switch);
+            r.seconds_phase[1] = secs(t_switch, t_iter_end);
+            r.seconds_phase[2] = secs(t0, t_loop) + secs(t_iter_end, t1);
+            r.iterations = iterations[g];
+            r.iters_sp = iters_sp[g];
+            r.iters_phase2 = iterations[g] - iters_sp[g];
+            r.converged = c.done ? 1 : 0;
+            r.restarts = c.restarts;
+            r.rotations = rotations;
+        }
+        return all_converged ? TM_OK : TM_ENOCONV;
     }
 };
 

@@ -130,3 +130,32 @@ def test_random_block_reference_is_standard_normal():
     assert abs(z.mean()) < 0.01 and abs(z.std() - 1.0) < 0.01
     assert np.array_equal(random_block(3, 5, 7), random_block(30, 5, 7)[:3])
     assert not np.array_equal(random_block(3, 5, 7), random_block(3, 5, 8))
+
+
+def test_batch_layout(lib):
+    """Each problem's columns: m rounded up to 16, then widened until the
+    batch spans a multiple of 64 columns (the FP32 width of the
+    column-chunked SpMM); bad sizes are refused without a device."""
+    import ctypes as ct
+    from paper_1108_4509_amd import _abi
+
+    def lay(k, m):
+        ldg, ld = ct.c_int32(), ct.c_int32()
+        assert lib.tm_batch_layout(k, m, ct.byref(ldg), ct.byref(ld)) == 0
+        return ldg.value, ld.value
+
+    assert lay(4, 16) == (16, 64)
+    assert lay(8, 16) == (16, 128)
+    assert lay(2, 20) == (32, 64)
+    assert lay(3, 20) == (64, 192)
+    assert lay(1, 16) == (64, 64)
+    assert lay(4, 76) == (80, 320)
+    for k in range(1, 20):
+        for m in (1, 15, 16, 17, 33, 100):
+            ldg, ld = lay(k, m)
+            assert ldg >= m and ldg % 16 == 0 and (k * ldg) % 64 == 0 and ld == k * ldg
+    x = ct.c_int32()
+    assert lib.tm_batch_layout(0, 16, ct.byref(x), ct.byref(x)) == _abi.TM_EINVAL
+    assert lib.tm_batch_layout(257, 16, ct.byref(x), ct.byref(x)) == _abi.TM_EINVAL
+    assert lib.tm_set_matrix_batch(None, 4, None, None, None, 1, None, 0, ct.byref(ct.c_void_p())) \
+        == _abi.TM_EINVAL

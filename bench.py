@@ -150,16 +150,17 @@ def measured_traffic(key):
     return round(nbytes)
 
 
-def serving_bench(tm, n_requests, slots=4, budget=32 << 30, precondition="chebyshev"):
+def serving_bench(tm, n_requests, slots=4, budget=32 << 30, precondition="chebyshev", max_batch=8):
     """The serving stream (Poisson arrivals, mean 50 ms; grid sides
     {16, 24, 32, 40, 48}; m scaled with N; per-request wells and start block),
     replayed in real time against the continuous-batching server.  Inputs are
-    generated before the clock starts; latency is submit -> result."""
+    generated before the clock starts; latency is submit -> result.  With
+    max_batch > 1 queued requests of one grid share a batched solve."""
     from workloads import serving_problem, serving_stream
     reqs = serving_stream(n_requests)
     probs = [serving_problem(r) for r in reqs]
     inputs = [(p.csr(), p.C0()) for p in probs]
-    srv = tm.Server(max_slots=slots, hbm_budget=budget)
+    srv = tm.Server(max_slots=slots, hbm_budget=budget, max_batch=max_batch)
     try:
         t0 = time.perf_counter()
         ids = []
@@ -184,7 +185,7 @@ def serving_bench(tm, n_requests, slots=4, budget=32 << 30, precondition="chebys
             "max_latency_s": round(st["max_latency_s"], 4), "solves_per_s": round(st["solves_per_s"], 3),
             "p50_queue_wait_s": round(st["p50_wait_s"], 4), "p99_queue_wait_s": round(st["p99_wait_s"], 4),
             "p50_service_s": round(st["p50_service_s"], 4), "p99_service_s": round(st["p99_service_s"], 4),
-            "precondition": precondition,
+            "precondition": precondition, "max_batch": max_batch, "solver_runs": st["solver_runs"],
             "completed": st["completed"], "failed": st["failed"] + bad, "wall_s": round(wall, 3),
             "arrivals_span_s": round(reqs[-1]["arrival_s"], 3),
             "hbm_peak_GiB": round(st["hbm_peak"] / 2**30, 3)}
@@ -335,6 +336,8 @@ def main():
                     help="iteration cap of each solve (a capped solve is reported as such)")
     ap.add_argument("--serving", type=int, default=200,
                     help="requests of the serving stream replayed after the solves (0: none)")
+    ap.add_argument("--serving-batch", type=int, default=8,
+                    help="requests per batched solve in the serving stream (0 or 1: no batching)")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving stream (with --serving requests)")
     ap.add_argument("--certify", action="store_true",
@@ -378,7 +381,7 @@ def main():
     ctx = tm.Context(0)
     H = tm.matrix_from_problem(ctx, p, stencil=a.stencil)
     if a.serving_only:
-        sv = serving_bench(tm, a.serving)
+        sv = serving_bench(tm, a.serving, max_batch=a.serving_batch)
         print(json.dumps({"metric": "serving stream: p50/p99 latency (s) and solves/s, MIXED",
                           "serving": sv}), flush=True)
         return
@@ -481,7 +484,7 @@ def main():
     roofline, kernels = kernel_rooflines(tm, ctx, H, p)
     serving = None
     if a.serving > 0:
-        serving = serving_bench(tm, a.serving)
+        serving = serving_bench(tm, a.serving, max_batch=a.serving_batch)
         log(f"serving {serving}")
 
     cpu = None

@@ -304,14 +304,27 @@ tm_status tm_solve_batch(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol,
  * hbm_budget; admitted requests run concurrently, each on its own HIP stream
  * and host thread.  A request computes exactly what tm_solve computes for the
  * same inputs: the kernels, launch shapes and reduction orders do not depend
- * on what else is running.  The server is internally synchronized; all entry
- * points may be called from any host thread. */
+ * on what else is running.
+ * With max_batch > 1, a slot that admits the head of the queue also takes
+ * later queued requests that can share one tm_solve_batch with it: same n,
+ * m, tol and options (no BF16 policy; no preconditioner or the degree-2
+ * polynomial), the same sparsity pattern and off-diagonal values (one grid,
+ * one kinetic operator), any diagonal -- up to max_batch requests,
+ * max_batch_cols block columns (tm_batch_layout) and 2^23 block entries
+ * (n times columns: sizes where a lone solve is bound by launch latency),
+ * as far as the batch's memory bound fits.  A batched request is solved to the same tolerance but
+ * in another rounding order than alone.  The server is internally
+ * synchronized; all entry points may be called from any host thread. */
 typedef struct tm_server tm_server;
 
 typedef struct tm_server_opts {
     int32_t device;        /* HIP device                                        */
     int32_t max_slots;     /* solves in flight, 1..16                           */
     uint64_t hbm_budget;   /* device bytes reserved at creation for requests    */
+    int32_t max_batch;     /* requests per batched solve, 0 or 1: no batching;
+                              at most 256                                       */
+    int32_t max_batch_cols;/* columns of a batched solve's block (k * ldg),
+                              64..2048 (0: 512)                                 */
 } tm_server_opts;
 
 typedef struct tm_request {
@@ -340,6 +353,7 @@ typedef struct tm_server_stats {
     double p99_wait_s;
     double p50_service_s;  /* admission -> result (the solve on the GPU)        */
     double p99_service_s;
+    int64_t solver_runs;   /* finished solver runs (a batched run counts once)  */
 } tm_server_stats;
 
 /* Device bytes tm_solve may allocate for an n x m problem with nnz stored

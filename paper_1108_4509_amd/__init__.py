@@ -458,8 +458,10 @@ class Server:
     """Continuous-batching solve server (tm_server_*): requests are host CSR
     matrices with a host start block; results are host eigenvalues."""
 
-    def __init__(self, device: int = 0, max_slots: int = 4, hbm_budget: int = 16 << 30):
-        o = _abi.tm_server_opts(device=device, max_slots=max_slots, hbm_budget=hbm_budget)
+    def __init__(self, device: int = 0, max_slots: int = 4, hbm_budget: int = 16 << 30,
+                 max_batch: int = 0, max_batch_cols: int = 0):
+        o = _abi.tm_server_opts(device=device, max_slots=max_slots, hbm_budget=hbm_budget,
+                                max_batch=max_batch, max_batch_cols=max_batch_cols)
         h = ctypes.c_void_p()
         _abi.check(_abi.lib().tm_server_create(ctypes.byref(o), ctypes.byref(h)), "tm_server_create")
         self.handle = h

@@ -64,7 +64,8 @@ class tm_result(ctypes.Structure):
 
 
 class tm_server_opts(ctypes.Structure):
-    _fields_ = [("device", c_int32), ("max_slots", c_int32), ("hbm_budget", ctypes.c_uint64)]
+    _fields_ = [("device", c_int32), ("max_slots", c_int32), ("hbm_budget", ctypes.c_uint64),
+                ("max_batch", c_int32), ("max_batch_cols", c_int32)]
 
 
 class tm_request(ctypes.Structure):
@@ -81,7 +82,8 @@ class tm_server_stats(ctypes.Structure):
                 ("span_s", c_double), ("solves_per_s", c_double),
                 ("hbm_budget", ctypes.c_uint64), ("hbm_peak", ctypes.c_uint64),
                 ("p50_wait_s", c_double), ("p99_wait_s", c_double),
-                ("p50_service_s", c_double), ("p99_service_s", c_double)]
+                ("p50_service_s", c_double), ("p99_service_s", c_double),
+                ("solver_runs", c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

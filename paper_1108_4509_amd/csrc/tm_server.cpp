@@ -7,6 +7,11 @@
 // kernels with the same launch shapes and fixed-order reductions as tm_solve
 // alone, so a result does not depend on what else is running.
 //
+// Batching (max_batch > 1): requests on one grid with one kinetic operator
+// (same pattern and off-diagonal values; the potential differs) and the same
+// m, tol and options are solved together by tm_solve_batch, one batch per
+// slot, which turns many launch-bound small solves into one.
+//
 // Memory: one hipMalloc of the whole budget at creation; admission carves a
 // chunk of solve_footprint() bytes from it (first fit), and the request's
 // context allocates inside its chunk (first fit again), so an admitted
@@ -95,6 +100,11 @@ struct Request {
     double tol = 0;
     tm_opts opts{};
     size_t footprint = 0;
+    // batching: hash of (n, pattern, off-diagonal values), row sums of the
+    // diagonal entries, and whether the options allow a batched solve
+    bool batchable = false;
+    uint64_t key = 0;
+    std::vector<double> diag;
     // results
     tm_status status = TM_EAGAIN;
     std::string error;
@@ -138,14 +148,95 @@ struct tm_server {
     uint64_t next_id = 1;
     bool stop = false;
     int running = 0;
-    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, solves = 0;
     std::vector<double> latencies, waits, services;
     Clock::time_point t0 = Clock::now(), t_first, t_last;
     bool any_submit = false;
 
     void worker(Slot *slot);
     void execute(Slot *slot, Request *r);
+    void execute_batch(Slot *slot, const std::vector<Request *> &b);
+    // the next admission: the head of the queue and the compatible requests
+    // queued behind it, cut to the largest batch whose memory bound fits
+    bool admit(std::vector<Request *> &batch, size_t &off, size_t &bytes);
+    int max_cols() const { return opts.max_batch_cols > 0 ? opts.max_batch_cols : 512; }
 };
+
+namespace {
+
+// Batches stay within n x (k * ldg) <= 2^23 block entries.  Below that a
+// lone solve is bound by launch latency (its kernels do not fill the GPU) and
+// k problems in one block cost little more than one; above it the k-fold Gram
+// work of the block-diagonal products outweighs the saved launches.  Measured
+// on the serving classes (MIXED, degree-2 polynomial, 8 problems): 16^3,
+// m = 16: 0.166 s alone, 0.046 s in one batch of 8 (5.2e5 entries); 24^3,
+// m = 32: 0.212 s, 0.092 s in batches of 4 (1.8e6); 32^3, m = 76: 0.82 s,
+// 0.54 s in pairs (6.3e6); 40^3, m = 148: 2.60 s, 2.33 s in pairs (2.0e7)
+// and 3.20 s in batches of 4 (4.1e7).
+constexpr int64_t kBatchEntries = (int64_t)1 << 23;
+
+bool same_options(const tm_opts &a, const tm_opts &b) {
+    return a.precision == b.precision && a.max_iter == b.max_iter && a.k_rot == b.k_rot &&
+           a.k_check == b.k_check && a.precondition == b.precondition && a.transport == b.transport &&
+           a.graphs == b.graphs && a.switch_tol == b.switch_tol && a.rise_tol == b.rise_tol &&
+           a.stall_tol == b.stall_tol && a.cheb_degree == b.cheb_degree && a.cheb_shift == b.cheb_shift;
+}
+
+// b can join a batched solve led by a: same problem class and options, the
+// same pattern, and equal off-diagonal values (the diagonals may differ)
+bool same_batch(const Request &a, const Request &b) {
+    if (!a.batchable || !b.batchable || a.key != b.key || a.n != b.n || a.m != b.m || a.tol != b.tol ||
+        !same_options(a.opts, b.opts))
+        return false;
+    if (a.rowptr != b.rowptr || a.col != b.col) return false;
+    for (int64_t r = 0; r < a.n; ++r)
+        for (int64_t k = a.rowptr[r]; k < a.rowptr[r + 1]; ++k)
+            if (a.col[k] != r && a.val[k] != b.val[k]) return false;
+    return true;
+}
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t bytes) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < bytes; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+bool tm_server::admit(std::vector<Request *> &batch, size_t &off, size_t &bytes) {
+    batch.clear();
+    if (queue.empty()) return false;
+    Request *h = queue.front();
+    batch.push_back(h);
+    if (opts.max_batch > 1 && h->batchable) {
+        for (size_t i = 1; i < queue.size() && (int)batch.size() < opts.max_batch; ++i)
+            if (same_batch(*h, *queue[i])) batch.push_back(queue[i]);
+    }
+    const int64_t nnz = h->rowptr[h->n];
+    while (!batch.empty()) {
+        const int k = (int)batch.size();
+        const int64_t cols = (int64_t)k * batch_group_ld(k, h->m);
+        if (k > 1 && (cols > max_cols() || h->n * cols > kBatchEntries)) {
+            batch.pop_back();
+            continue;
+        }
+        if (k == 1) {
+            bytes = h->footprint;
+        } else {
+            int32_t ldg = 0, ld = 0;
+            (void)tm_batch_layout(k, h->m, &ldg, &ld);
+            bytes = batch_footprint(h->n, nnz, k, h->m, h->opts.precision, h->opts.precondition) +
+                    (size_t)h->n * ld * 8 + (size_t)k * h->m * 8 + 64 * Arena::kAlign;
+        }
+        off = budget.alloc(bytes);
+        if (off != SIZE_MAX) return true;
+        batch.pop_back();
+    }
+    return false;
+}
 
 void tm_server::execute(Slot *slot, Request *r) {
     tm_ctx *ctx = slot->ctx;
@@ -191,41 +282,120 @@ void tm_server::execute(Slot *slot, Request *r) {
     std::vector<double>().swap(r->C0);
 }
 
+void tm_server::execute_batch(Slot *slot, const std::vector<Request *> &b) {
+    tm_ctx *ctx = slot->ctx;
+    const Request *h = b[0];
+    const int k = (int)b.size(), m = h->m;
+    const int64_t n = h->n;
+    auto fail_all = [&](tm_status st, const std::string &msg) {
+        for (Request *r : b) {
+            r->status = st;
+            r->error = msg;
+        }
+    };
+    // A: the shared pattern and off-diagonal values with zero diagonal
+    // entries; d_g: request g's diagonal
+    std::vector<double> valA = h->val;
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t q = h->rowptr[r]; q < h->rowptr[r + 1]; ++q)
+            if (h->col[q] == r) valA[q] = 0.0;
+    std::vector<double> d((size_t)k * n);
+    for (int g = 0; g < k; ++g) std::memcpy(&d[(size_t)g * n], b[g]->diag.data(), n * sizeof(double));
+    tm_mat *H = nullptr;
+    tm_status st = tm_set_matrix_batch(ctx, n, h->rowptr.data(), h->col.data(), valA.data(), k, d.data(), 0u, &H);
+    if (st != TM_OK) {
+        fail_all(st, tm_last_error());
+        return;
+    }
+    int32_t ldg = 0, ld = 0;
+    (void)tm_batch_layout(k, m, &ldg, &ld);
+    // the start blocks side by side (each stored n x leading_dim(m))
+    const int lds = leading_dim(m);
+    std::vector<double> C0h((size_t)n * ld, 0.0);
+    for (int g = 0; g < k; ++g)
+        for (int64_t r = 0; r < n; ++r)
+            std::memcpy(&C0h[(size_t)r * ld + (size_t)g * ldg], &b[g]->C0[(size_t)r * lds], m * sizeof(double));
+    void *C0d = ctx->dalloc(C0h.size() * sizeof(double));
+    void *eigd = ctx->dalloc((size_t)k * m * sizeof(double));
+    std::vector<tm_result> res(k);
+    if (!C0d || !eigd) {
+        fail_all(TM_ENOMEM, "request chunk too small");
+    } else if (hipMemcpyAsync(C0d, C0h.data(), C0h.size() * sizeof(double), hipMemcpyHostToDevice,
+                              ctx->stream) != hipSuccess) {
+        fail_all(TM_EDEVICE, "start block upload failed");
+    } else {
+        st = tm_solve_batch(ctx, H, m, h->tol, &h->opts, (const double *)C0d, nullptr, (double *)eigd,
+                            res.data());
+        if (st != TM_OK && st != TM_ENOCONV) {
+            fail_all(st, tm_last_error());
+        } else {
+            std::vector<double> eig((size_t)k * m);
+            if (hipMemcpyAsync(eig.data(), eigd, eig.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess) {
+                fail_all(TM_EDEVICE, "result download failed");
+            } else {
+                for (int g = 0; g < k; ++g) {
+                    Request *r = b[g];
+                    r->res = res[g];
+                    r->status = res[g].converged ? TM_OK : TM_ENOCONV;
+                    if (r->status != TM_OK) r->error = "maximum iterations reached";
+                    r->eig.assign(eig.begin() + (size_t)g * m, eig.begin() + (size_t)(g + 1) * m);
+                }
+            }
+        }
+    }
+    if (C0d) ctx->dfree(C0d);
+    if (eigd) ctx->dfree(eigd);
+    tm_free_matrix(H);
+    for (Request *r : b) {
+        std::vector<int64_t>().swap(r->rowptr);
+        std::vector<int32_t>().swap(r->col);
+        std::vector<double>().swap(r->val);
+        std::vector<double>().swap(r->C0);
+        std::vector<double>().swap(r->diag);
+    }
+}
+
 void tm_server::worker(Slot *slot) {
     (void)hipSetDevice(opts.device);
     std::unique_lock<std::mutex> lk(mu);
+    std::vector<Request *> batch;
     while (true) {
-        size_t off = SIZE_MAX;
+        size_t off = SIZE_MAX, bytes = 0;
         // first in, first out: the head waits until its memory is free
-        cv_work.wait(lk, [&] {
-            if (stop) return true;
-            if (queue.empty()) return false;
-            off = budget.alloc(queue.front()->footprint);
-            return off != SIZE_MAX;
-        });
-        if (stop) break;
-        Request *r = queue.front();
-        queue.pop_front();
-        ++running;
+        cv_work.wait(lk, [&] { return stop || admit(batch, off, bytes); });
+        if (stop) {
+            if (off != SIZE_MAX) budget.release(off);
+            break;
+        }
+        for (Request *r : batch) queue.erase(std::find(queue.begin(), queue.end(), r));
+        running += (int)batch.size();
         peak = std::max(peak, budget.in_use());
         lk.unlock();
 
         slot->chunk = base + off;
-        slot->arena.reset(r->footprint);
-        r->t_start = Clock::now();
-        execute(slot, r);
-        r->t_done = Clock::now();
+        slot->arena.reset(bytes);
+        const Clock::time_point t_start = Clock::now();
+        for (Request *r : batch) r->t_start = t_start;
+        if (batch.size() == 1) execute(slot, batch[0]);
+        else execute_batch(slot, batch);
+        const Clock::time_point t_done = Clock::now();
 
         lk.lock();
-        r->finished = true;
         budget.release(off);
-        --running;
-        if (r->status == TM_OK || r->status == TM_ENOCONV) ++completed;
-        else ++failed;
-        latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
-        waits.push_back(std::chrono::duration<double>(r->t_start - r->t_submit).count());
-        services.push_back(std::chrono::duration<double>(r->t_done - r->t_start).count());
-        t_last = r->t_done;
+        for (Request *r : batch) {
+            r->t_done = t_done;
+            r->finished = true;
+            --running;
+            if (r->status == TM_OK || r->status == TM_ENOCONV) ++completed;
+            else ++failed;
+            latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
+            waits.push_back(std::chrono::duration<double>(r->t_start - r->t_submit).count());
+            services.push_back(std::chrono::duration<double>(r->t_done - r->t_start).count());
+        }
+        ++solves;
+        t_last = t_done;
         cv_done.notify_all();
         cv_work.notify_all();
     }
@@ -247,6 +417,8 @@ tm_status tm_server_create(const tm_server_opts *o, tm_server **out) {
     if (!o || !out) return TM_EINVAL;
     *out = nullptr;
     if (o->max_slots < 1 || o->max_slots > 16 || o->hbm_budget < ((uint64_t)1 << 20)) return TM_EINVAL;
+    if (o->max_batch < 0 || o->max_batch > kMaxBatch) return TM_EINVAL;
+    if (o->max_batch_cols != 0 && (o->max_batch_cols < 64 || o->max_batch_cols > 2048)) return TM_EINVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || o->device < 0 || o->device >= count) return TM_EINVAL;
     if (hipSetDevice(o->device) != hipSuccess) return TM_EDEVICE;
@@ -310,6 +482,26 @@ tm_status tm_server_submit(tm_server *s, const tm_request *q, uint64_t *id) {
     r->rowptr.assign(q->rowptr, q->rowptr + q->n + 1);
     r->col.assign(q->col, q->col + nnz);
     r->val.assign(q->val, q->val + nnz);
+    const tm_opts &o = r->opts;
+    r->batchable = s->opts.max_batch > 1 && o.progress == nullptr && o.precision != TM_MIXED_BF16 &&
+                   o.precision != TM_FULL_BF16 &&
+                   (o.precondition == 0 || (o.precondition == 2 && o.cheb_degree == 2)) && q->rowptr[0] == 0;
+    if (r->batchable) {
+        for (int64_t i = 0; i < q->n && r->batchable; ++i)
+            r->batchable = q->rowptr[i + 1] >= q->rowptr[i];
+    }
+    if (r->batchable) {
+        r->diag.assign(q->n, 0.0);
+        uint64_t h = fnv1a(1469598103934665603ull, &q->n, sizeof(q->n));
+        h = fnv1a(h, r->rowptr.data(), r->rowptr.size() * sizeof(int64_t));
+        h = fnv1a(h, r->col.data(), r->col.size() * sizeof(int32_t));
+        for (int64_t i = 0; i < q->n; ++i)
+            for (int64_t k = r->rowptr[i]; k < r->rowptr[i + 1]; ++k) {
+                if (r->col[k] == i) r->diag[i] += r->val[k];
+                else h = fnv1a(h, &r->val[k], sizeof(double));
+            }
+        r->key = h;
+    }
     const int ld = leading_dim(q->m);
     r->C0.assign((size_t)q->n * ld, 0.0);
     for (int64_t i = 0; i < q->n; ++i)
@@ -370,6 +562,7 @@ tm_status tm_server_get_stats(tm_server *s, tm_server_stats *out) {
     out->queued = (int64_t)s->queue.size();
     out->running = s->running;
     out->hbm_budget = s->opts.hbm_budget;
+    out->solver_runs = s->solves;
     out->hbm_peak = s->peak;
     std::vector<double> lat = s->latencies;
     // nearest-rank percentile of a sorted sample

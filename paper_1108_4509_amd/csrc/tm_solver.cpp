@@ -95,6 +95,14 @@ size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, int precond
     return blocks + small + mat;
 }
 
+size_t batch_footprint(int64_t n, int64_t nnz, int k, int m, int precision, int precondition) {
+    const int mb = k * batch_group_ld(k, m);
+    // the solve on the whole block, each problem's diagonal in FP64 and
+    // FP32, controller states and polynomial coefficients, upload slack
+    return solve_footprint(n, nnz, mb, precision, precondition, 0) +
+           (size_t)k * ((size_t)n * 12 + sizeof(CgState) + 16) + 256;
+}
+
 // ------------------------------------------------------------------ solver
 
 struct Solver::Impl {

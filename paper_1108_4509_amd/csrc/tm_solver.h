@@ -30,6 +30,10 @@ int spmm_any(hipStream_t s, const tm_mat *H, int ld, const void *C, void *X, boo
 size_t solve_footprint(int64_t n, int64_t nnz, int m, int precision, int precondition,
                        int history_len);
 
+// The same bound for tm_solve_batch of k problems of m columns each on a
+// batch matrix with nnz stored nonzeros in its shared A.
+size_t batch_footprint(int64_t n, int64_t nnz, int k, int m, int precision, int precondition);
+
 class Solver {
   public:
     // S: the positive definite S of H x = lambda S x (FULL_DP only), or null

@@ -77,9 +77,9 @@ def test_serving_structs_and_footprint(lib):
     m, covers the blocks of the chosen precision, and malformed calls are
     rejected without touching a device."""
     from paper_1108_4509_amd import _abi
-    assert ctypes.sizeof(_abi.tm_server_opts) == 4 + 4 + 8
+    assert ctypes.sizeof(_abi.tm_server_opts) == 4 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(_abi.tm_request) == 8 * 4 + 4 + 4 + 8 * 3
-    assert ctypes.sizeof(_abi.tm_server_stats) == 6 * 8 + 6 * 8 + 2 * 8 + 4 * 8
+    assert ctypes.sizeof(_abi.tm_server_stats) == 6 * 8 + 6 * 8 + 2 * 8 + 4 * 8 + 8
 
     def fp(n, nnz, m, precision):
         o = _abi.tm_opts()

@@ -129,7 +129,10 @@ def test_batch_solve_matches_lapack_and_alone(tm, ctx, precision, precondition, 
         assert ra["converged"] == 1
         assert np.max(np.abs(eig[g] - ea)) <= 1e-9
         it_b, it_a = r["iterations"], ra["iterations"]
-        assert abs(it_b - it_a) <= max(3, 0.1 * it_a), (g, it_b, it_a)
+        # the two-phase policies end their first phase on noisy tests
+        # (stall, rounding floor): another summation order moves the switch
+        slack = 0.03 if precision == "full_dp" else 0.2
+        assert abs(it_b - it_a) <= max(3, slack * it_a), (g, it_b, it_a)
 
 
 def test_batch_explicit_start_block_is_the_seeded_one(tm, ctx):

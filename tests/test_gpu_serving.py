@@ -91,3 +91,46 @@ def test_admission_by_hbm_budget(ctx, tm):
     assert all(r is not None and r[0]["status"] == 0 for r in res)
     assert st["completed"] == len(probs) and st["rejected"] == 1
     assert st["hbm_peak"] <= budget
+
+
+def test_batched_serving(ctx, tm):
+    """With max_batch > 1, queued requests on one grid (same kinetic
+    operator, each with its own wells) are solved by one tm_solve_batch.
+    One slot and a larger request submitted first keep the others queued, so
+    the eight 12^3 requests behind it must form one batched run (solver_runs
+    = 3 with the blocker and the one request of another grid).  Each batched
+    request matches its lone tm_solve to the solver's accuracy (eigenvalues
+    1e-9; not to the last bit: the batch sums in another order)."""
+    spec = StencilSpec(3, (12,) * 3, 2, "periodic", 0.5)
+    probs = [make_problem(f"b{i}", spec, m=16, seed=400 + i, n_wells=1 + i % 3) for i in range(8)]
+    other = make_problem("o", StencilSpec(3, (10,) * 3, 2, "periodic", 0.5), m=16, seed=9, n_wells=2)
+    blocker = make_problem("blk", StencilSpec(3, (24,) * 3, 2, "periodic", 0.5), m=32, seed=8, n_wells=3)
+    opts = tm.opts(precision="mixed", precondition="chebyshev")
+    alone = []
+    for p in probs + [other]:
+        H = tm.matrix_from_problem(ctx, p)
+        r, _, w, _ = tm.solve(ctx, H, p.m, 1e-8, tm.to_block(p.C0()), opts, want_vectors=False)
+        alone.append((r, host(w)))
+    srv = tm.Server(max_slots=1, hbm_budget=4 << 30, max_batch=8)
+    try:
+        print_case(test="serving_batched", requests=len(probs) + 2)
+        mk = lambda: tm.opts(precision="mixed", precondition="chebyshev")
+        first = srv.submit(*blocker.csr(), blocker.m, 1e-8, blocker.C0(), mk())
+        ids = [srv.submit(*p.csr(), p.m, 1e-8, p.C0(), mk()) for p in probs + [other]]
+        got = [srv.wait(i, timeout=120.0) for i in ids]
+        assert srv.wait(first, timeout=120.0) is not None
+        st = srv.stats()
+    finally:
+        srv.close()
+    for p, (ra, wa), g in zip(probs + [other], alone, got):
+        assert g is not None, f"{p.name} did not finish"
+        rb, wb = g
+        assert rb["status"] == 0 and rb["converged"] == 1 and ra["converged"] == 1
+        assert rb["max_residual"] <= 2e-8
+        assert np.max(np.abs(wb - wa)) <= 1e-9, p.name
+        # MIXED ends its FP32 phase on noisy tests (stall, rounding floor):
+        # another summation order moves the switch by some iterations
+        assert abs(rb["iterations"] - ra["iterations"]) <= max(5, 0.2 * ra["iterations"])
+    assert st["completed"] == len(probs) + 2 and st["failed"] == 0
+    assert st["solver_runs"] == 3, st
+    assert st["hbm_peak"] <= st["hbm_budget"]

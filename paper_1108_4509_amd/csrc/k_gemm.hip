@@ -78,7 +78,7 @@ __device__ inline T velem(const typename Vec16<T>::type &v, int i) {
 // (partials == nullptr: no fusion); see rot() in tm_common.h.
 template <typename TO>
 struct GradDots {
-    const TO *Gp = nullptr;
+    const TO *Gp = nullptr;   // null: trace 2 (g_prev . M g) is not formed (reads 0)
     const TO *Pp = nullptr;
     const double *M = nullptr;
     double *partials = nullptr;
@@ -822,7 +822,12 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
                 if constexpr (EPI == EPI_GRADX) load4<TM>(Xs + e, xs[g]);
                 if constexpr (EPI == EPI_GRAD || EPI == EPI_TRMM) load4<TA>(A + e, av[g]);
                 if (GRADLIKE && fuse) {
-                    load4<TO>(gd.Gp + e, gp[g]);
+                    if (gd.Gp) {
+                        load4<TO>(gd.Gp + e, gp[g]);
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) gp[g][w] = TO(0);
+                    }
                     load4<TO>(gd.Pp + e, pp[g]);
                     wgt[g] = gd.M ? gd.M[ok[g] ? row : r0] : 1.0;
                 }

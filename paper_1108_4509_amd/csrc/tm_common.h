@@ -203,6 +203,7 @@ enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2, EPI_GRADX = 3 };
 // output column j, the traces of the Polak-Ribiere step (Eq. 8) and the descent
 // test: p = 0: g.g, 1: g.(M g), 2: g_prev.(M g), 3: p_prev.g, written to
 // partials[(p * nchunk + chunk) * ld + j]; returns nchunk (row blocks).
+// Gp = nullptr skips trace 2 (it reads 0) and the pass over G_prev.
 // partials needs rot_partials_workspace(n, m) bytes.
 size_t rot_partials_workspace(int64_t n, int m);
 template <typename TA, typename TM, typename TO>

@@ -411,10 +411,13 @@ struct Solver::Impl {
                           (double *)Hp->ptr, true, nullptr, (TMH *)Wp->ptr, 0, bcols(0.0));
         }
         // (7): G = -2 (X' - C H'); the reduction above stored H' padded in TMH
-        // with the traces for Eq. 8 and the descent test fused into the epilogue
+        // with the traces for Eq. 8 and the descent test fused into the
+        // epilogue (the polynomial M forms its own g.z and g_prev.z below, so
+        // G_prev is not read here)
         {
+            const TG *gp_dots = o.precondition == 2 ? nullptr : Gpv;
             const int nch = rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, Xs ? EPI_GRADX : EPI_GRAD, X,
-                                             (double *)h->ptr, Gv, Gpv, Pv, Mv,
+                                             (double *)h->ptr, Gv, gp_dots, Pv, Mv,
                                              (double *)dot_ws->ptr, Xs);
             reduce_partials(s, 4, nch, ld, (double *)dot_ws->ptr, (double *)dots->ptr);
         }

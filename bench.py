@@ -32,17 +32,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(problem, iters_full, seconds_budget=20.0):
+def cpu_baseline(problem, iters_full, seconds_budget=20.0, precondition="none", cheb_degree=2,
+                 basis="GPU FULL_DP run"):
     """The FP64 CPU oracle on a bounded sample: a number of CG iterations of the
-    same problem sized to about ``seconds_budget`` of CPU time, scaled to a
-    full solve by the iteration count of the GPU run."""
+    same problem, with the same preconditioner as the GPU run, sized to about
+    ``seconds_budget`` of CPU time and scaled to a full solve by
+    ``iters_full`` -- the iteration count of the GPU's FP64 solve of the same
+    input, whose trajectory the oracle's follows (the parity tests compare
+    them step by step)."""
     import oracle
     H = oracle.csr_matrix(*problem.csr(), problem.N)
     C0 = problem.C0()
+    oo = dict(tol=1e-8, k_rot=50)
+    if precondition == "chebyshev":
+        oo["chebyshev"] = cheb_degree
+    elif precondition == "diagonal":
+        oo["precondition"] = True
 
     def timed(n_it):
         t0 = time.time()
-        oracle.solve(H, C0, oracle.OracleOptions(tol=1e-8, k_rot=50, max_iter=n_it))
+        oracle.solve(H, C0, oracle.OracleOptions(max_iter=n_it, **oo))
         return time.time() - t0
 
     t1, t3 = timed(1), timed(3)       # setup + final Rayleigh-Ritz + 1 or 3 iterations
@@ -58,9 +67,9 @@ def cpu_baseline(problem, iters_full, seconds_budget=20.0):
     except Exception:
         threads = os.cpu_count() or 1
     return {"value": round(est, 3), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_it} oracle CG iterations of the same problem ({t_n:.1f} s measured, "
-                      f"{per_iter:.3f} s/iter, setup and final Rayleigh-Ritz {setup:.1f} s) "
-                      f"scaled to the GPU run's {iters_full} iterations"}
+            "sample": f"{n_it} oracle CG iterations of the same problem, preconditioner {precondition} "
+                      f"({t_n:.1f} s measured, {per_iter:.3f} s/iter, setup and final Rayleigh-Ritz "
+                      f"{setup:.1f} s) scaled to the {basis}'s {iters_full} iterations"}
 
 
 def kernel_work(p, ld):
@@ -133,9 +142,9 @@ def kernel_rooflines(tm, ctx, H, p, reps=20):
 TRAFFIC_CONFIG = "c2"
 TRAFFIC = {
     "rot_grad_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                         "c917ae1129d5639b4a8e87ccc7a385c3ae95f1a1", 2.0 * 282735.5 * 1024 + 124416.0 * 1024),
+                         "6234ca93923cd7d1c2db9b94a92f6852561431c7", 2.0 * 282531.3 * 1024 + 124416.0 * 1024),
     "gram_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                     "c917ae1129d5639b4a8e87ccc7a385c3ae95f1a1", 2.0 * 325083.5 * 1024 + 164352.0 * 1024),
+                     "6234ca93923cd7d1c2db9b94a92f6852561431c7", 2.0 * 326698.5 * 1024 + 164352.0 * 1024),
 }
 
 
@@ -489,7 +498,12 @@ def main():
 
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(p, res["iterations"])
+        if res64 is not None:
+            cpu = cpu_baseline(p, res64["iterations"], precondition=a.precondition,
+                               cheb_degree=a.cheb_degree)
+        else:
+            cpu = cpu_baseline(p, res["iterations"], precondition=a.precondition,
+                               cheb_degree=a.cheb_degree, basis="GPU run")
         log(f"cpu baseline {cpu}")
 
     value = float(np.median(times))

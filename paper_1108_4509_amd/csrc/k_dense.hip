@@ -424,27 +424,7 @@ __global__ void assemble_kernel(int m, const double *__restrict__ Hp,
     A[idx] = v;
 }
 
-// Block-diagonal form of an m x m matrix that belongs to a batch of
-// problems (group g: rows and columns g * ldg .. g * ldg + mg - 1): entries
-// across groups and in the zero padding become 0, and the padding's
-// diagonal becomes pad_diag (1 keeps a Gram matrix positive definite).
-__global__ void batch_mask_kernel(int m, int ldg, int mg, double pad_diag, double *__restrict__ A) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)m * m) return;
-    const int i = (int)(idx / m), j = (int)(idx - (int64_t)i * m);
-    const int gi = i / ldg, gj = j / ldg;
-    const bool pi = i - gi * ldg >= mg, pj = j - gj * ldg >= mg;
-    if (gi != gj || pi || pj) A[idx] = (i == j && pi) ? pad_diag : 0.0;
-}
-
 }  // namespace
-
-void batch_mask(hipStream_t s, int m, int ldg, int mg, double pad_diag, double *A) {
-    const int64_t total = (int64_t)m * m;
-    hipLaunchKernelGGL(batch_mask_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, m, ldg,
-                       mg, pad_diag, A);
-    TM_HIP(hipGetLastError());
-}
 
 size_t chol_workspace(int m) {
     return (size_t)2 * m * m * sizeof(double);

@@ -730,30 +730,24 @@ int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
     if constexpr (sizeof(T) == 8) val = H.val64; else val = H.val32;
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
     auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
-    // chunk width and in-flight gathers measured at 48^3 / 64^3 / 100^3
-    // (7-point, m = 256 / 512 / 1024): FP64 rows gain from 512-byte chunks
-    // with 8 rows per lane group in flight (48^3: 152 -> 140 us, 100^3:
-    // 5.8 -> 5.0 ms); FP32 rows keep 256-byte chunks and 4 rows
-    constexpr bool wide = sizeof(T) == 8;
-    constexpr int CL = wide ? 32 : 16;
+    // chunk width and in-flight gathers: 256-byte chunks (16 lanes of 16-byte
+    // vectors) with 4 rows per lane group in flight, for FP32 and FP64 rows.
+    // Measured (HIP events, 20 launches): at 48^3, m = 256, FP64 147 us
+    // against 149 us with 512-byte chunks and 8 rows; at 64^3 13-point,
+    // m = 512, 944 against 1028 us (the +-2 plane window of a 512-byte chunk
+    // no longer fits one XCD's L2); 128-byte chunks, 8 nonzeros per batch
+    // or 2 rows per group were slower at both sizes
     if (ldv % 16 == 0) {
-        const bool use_wide = wide && ldv % CL == 0;
-        const int lanes = use_wide ? CL : 16;
-        const int nchunks = ldv / lanes;
+        const int nchunks = ldv / 16;
         const int64_t rpb = kChunkRows;
         const int64_t nrb64 = (H.n + rpb - 1) / rpb;
         TM_REQUIRE(nrb64 * nchunks < ((int64_t)1 << 31), TM_ENOTSUP, "matrix too large for the SpMM grid");
         const int nrb = (int)nrb64;
         int64_t grid = (int64_t)nchunks * nrb;
         grid = (grid + 7) / 8 * 8;
-        if (use_wide)
-            hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, CL, 2, 8>), dim3((unsigned)grid), dim3(256), 0, s,
-                               H.n, (int)rpb, nrb, nchunks, H.rowptr, H.col, val, Cv, Xv, ldv, ndot,
-                               partials, epi);
-        else
-            hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, 16, 2, 4>), dim3((unsigned)grid), dim3(256), 0, s,
-                               H.n, (int)rpb, nrb, nchunks, H.rowptr, H.col, val, Cv, Xv, ldv, ndot,
-                               partials, epi);
+        hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, 16, 2, 4>), dim3((unsigned)grid), dim3(256), 0, s,
+                           H.n, (int)rpb, nrb, nchunks, H.rowptr, H.col, val, Cv, Xv, ldv, ndot,
+                           partials, epi);
         TM_HIP(hipGetLastError());
         return nrb;
     }

@@ -229,8 +229,6 @@ size_t jacobi_workspace(int m);
 // of which the first mg are real (ldg = 0: one group).
 void jacobi_eig(hipStream_t s, int m, const double *A, double *U, double *w,
                 double *work, int32_t *info, int ldg = 0, int mg = 0);
-// Block-diagonal mask of a batch's m x m matrix (see the kernel).
-void batch_mask(hipStream_t s, int m, int ldg, int mg, double pad_diag, double *A);
 // A = 0.5 (H' + H'^T) + diag(h): the m x m H of Eq. 9 from Algorithm-2 pieces.
 void assemble_subspace_matrix(hipStream_t s, int m, const double *Hp,
                               const double *h, double *A);

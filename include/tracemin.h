@@ -290,8 +290,10 @@ tm_status tm_batch_layout(int32_t k, int32_t m, int32_t *ldg, int32_t *ld);
  * two-phase policy changes phase once every problem has ended its first
  * phase.  k * ldg <= 2048.  Precisions: all but the BF16 policies;
  * precondition 0, or 2 with cheb_degree = 2 (each problem on its own
- * Gershgorin interval); other options TM_ENOTSUP; history is not recorded.
- * TM_ENOCONV (results filled) if some problem did not converge. */
+ * Gershgorin interval); other options TM_ENOTSUP; history is not recorded;
+ * opts->progress receives the furthest problem's iteration count, the sum
+ * of the energies and the largest rho.  TM_ENOCONV (results filled) if some
+ * problem did not converge. */
 tm_status tm_solve_batch(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol,
                          const tm_opts *opts, const double *C0, double *C_out,
                          double *eig_out, tm_result *res);

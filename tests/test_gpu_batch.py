@@ -185,3 +185,59 @@ def test_batch_lone_problem_and_errors(tm, ctx):
     Vbad[0, 3] = np.nan
     with pytest.raises(RuntimeError):
         tm.set_matrix_batch(ctx, *A, Vbad)
+
+
+@pytest.mark.parametrize("precision", ["mp2", "full_sp"])
+def test_batch_single_phase_policies(tm, ctx, precision):
+    """MP2 converges to tol like FULL_DP; FULL_SP ends at its FP32 floor
+    (each problem's phase gate), with E_G within that floor of LAPACK."""
+    side, k, m, tol, seed = 10, 3, 16, 1e-8, 21
+    print_case(test="batch_policy", precision=precision, side=side, k=k, m=m)
+    A, V, Hs = _batch(side, k, [1, 2, 4], seed0=500)
+    n = side ** 3
+    H = tm.set_matrix_batch(ctx, *A, V)
+    res, _, eig = tm.solve_batch(ctx, H, m, tol, None, tm.opts(precision=precision, seed=seed),
+                                 want_vectors=False)
+    eig = host(eig)
+    for g in range(k):
+        lam = np.linalg.eigvalsh(_dense(Hs[g], n))[:m]
+        if precision == "mp2":
+            assert res[g]["converged"] == 1
+            assert np.max(np.abs(eig[g] - lam)) <= 1e-9
+        else:
+            # the FP32 floor: about u32 * ||H|| relative on E_G
+            assert abs(res[g]["E_G"] - lam.sum()) <= 1e-5 * abs(lam.sum())
+
+
+def test_batch_many_small_problems(tm, ctx):
+    """48 problems of 8^3 rows and m = 4 (768 block columns, more
+    controller states than one page of the pinned polling buffer held
+    before): every problem converges to its LAPACK eigenvalues."""
+    side, k, m, tol = 8, 48, 4, 1e-9
+    print_case(test="batch_many", side=side, k=k, m=m)
+    A, V, Hs = _batch(side, k, 1, seed0=700)
+    n = side ** 3
+    H = tm.set_matrix_batch(ctx, *A, V)
+    ldg, ld = tm.batch_layout(k, m)
+    assert ld == k * ldg == 768
+    res, _, eig = tm.solve_batch(ctx, H, m, tol, None, tm.opts(precision="full_dp", seed=3),
+                                 want_vectors=False)
+    eig = host(eig)
+    for g in range(k):
+        assert res[g]["converged"] == 1, g
+        lam = np.linalg.eigvalsh(_dense(Hs[g], n))[:m]
+        assert np.max(np.abs(eig[g] - lam)) <= 1e-9, g
+
+
+def test_batch_graph_replay_matches_eager(tm, ctx):
+    """Captured iteration batches replay the same kernels: the batched
+    solve with graphs gives bit-identical results."""
+    import torch
+    side, k, m, tol, seed = 10, 4, 16, 1e-8, 8
+    print_case(test="batch_graphs", side=side, k=k, m=m)
+    A, V, _ = _batch(side, k, 2, seed0=900)
+    H = tm.set_matrix_batch(ctx, *A, V)
+    r1, C1, e1 = tm.solve_batch(ctx, H, m, tol, None, tm.opts(precision="mixed", seed=seed))
+    r2, C2, e2 = tm.solve_batch(ctx, H, m, tol, None, tm.opts(precision="mixed", seed=seed, graphs=True))
+    assert torch.equal(e1, e2) and torch.equal(C1, C2)
+    assert [r["iterations"] for r in r1] == [r["iterations"] for r in r2]

@@ -366,13 +366,15 @@ def test_c2_full_size(ctx, tm, precision):
 
 @pytest.mark.slow
 def test_c3_full_size_certified(ctx, tm, orc):
-    """64^3 13-point + 200 wells, m = 512, MIXED.  The oracle cannot run this
-    size to convergence in test time, so it certifies the GPU's result
-    instead, in FP64 on the host: every Ritz pair (lambda_j, c_j) has
-    ||H c_j - lambda_j c_j|| <= 1e-8, C^T C = I to 1e-12, E_G equals
-    tr(C^T H C), and three oracle CG iterations started from the GPU's C
-    cannot lower the energy by more than 1e-10 |E_G| (a subspace short of
-    the minimum would be pushed down at once)."""
+    """64^3 13-point + 200 wells, m = 512, MIXED, as timed by the benchmark's
+    C3 line.  Pinned against the oracle's stored solve of the same input
+    (tests/golden/oracle_c3_s0.json, written by make_golden.py from oracle/
+    only): |dE_G| / |E_G| <= 1e-10 and the Ritz values to 1e-8.  Certified in
+    FP64 on the host from the returned Ritz pairs as well: every
+    ||H c_j - lambda_j c_j|| <= 1e-8, C^T C = I to 1e-12, E_G = tr(C^T H C).
+    The certification alone shows that C spans an invariant subspace, not
+    that it is the lowest one; the stored oracle value is what pins E_G (the
+    test skips that comparison, and says so, while the file is absent)."""
     p = config_problem("c3")
     print_case(test="c3_full", N=p.N, m=p.m)
     r, C, w, _ = _solve(tm, ctx, p, precision="mixed")
@@ -388,10 +390,15 @@ def test_c3_full_size_certified(ctx, tm, orc):
     assert np.max(np.abs(S - np.eye(p.m))) <= 1e-12
     E_rq = float(np.einsum("ij,ij->", Ch, X))
     assert abs(E_rq - r["E_G"]) <= 1e-12 * abs(r["E_G"])
-    cont = orc.solve(H, Ch, orc.OracleOptions(tol=1e-14, max_iter=3, k_rot=0))
-    assert min(cont.energies) >= r["E_G"] - 1e-10 * abs(r["E_G"])
-    print(f"c3: E_G {r['E_G']:.15f} iterations {r['iterations']} max residual {np.max(res):.2e} "
-          f"continuation min E {min(cont.energies):.15f}")
+    print(f"c3: E_G {r['E_G']:.15f} iterations {r['iterations']} max residual {np.max(res):.2e}")
+    path = os.path.join(HERE, "golden", "oracle_c3_s0.json")
+    if not os.path.exists(path):
+        pytest.skip("certified; E_G unpinned until tests/golden/oracle_c3_s0.json exists")
+    with open(path) as f:
+        g = json.load(f)
+    assert g["converged"] and g["N"] == p.N and g["m"] == p.m
+    assert abs(r["E_G"] - g["E_G"]) <= 1e-10 * abs(g["E_G"])
+    assert np.max(np.abs(wh - np.array(g["eigenvalues"]))) <= 1e-8
 
 
 @pytest.mark.parametrize("precision", ["full_dp", "mixed"])

@@ -211,15 +211,22 @@ bool tm_server::admit(std::vector<Request *> &batch, size_t &off, size_t &bytes)
     if (queue.empty()) return false;
     Request *h = queue.front();
     batch.push_back(h);
-    if (opts.max_batch > 1 && h->batchable) {
-        for (size_t i = 1; i < queue.size() && (int)batch.size() < opts.max_batch; ++i)
-            if (same_batch(*h, *queue[i])) batch.push_back(queue[i]);
-    }
+    // the largest batch the column and entry caps allow for this class
+    // (checked first: requests too large to batch skip the scan)
+    auto fits = [&](int k) {
+        const int64_t cols = (int64_t)k * batch_group_ld(k, h->m);
+        return cols <= max_cols() && h->n * cols <= kBatchEntries;
+    };
+    int kmax = 1;
+    if (opts.max_batch > 1 && h->batchable)
+        for (int k = 2; k <= opts.max_batch; ++k)
+            if (fits(k)) kmax = k;
+    for (size_t i = 1; i < queue.size() && (int)batch.size() < kmax; ++i)
+        if (same_batch(*h, *queue[i])) batch.push_back(queue[i]);
     const int64_t nnz = h->rowptr[h->n];
     while (!batch.empty()) {
         const int k = (int)batch.size();
-        const int64_t cols = (int64_t)k * batch_group_ld(k, h->m);
-        if (k > 1 && (cols > max_cols() || h->n * cols > kBatchEntries)) {
+        if (k > 1 && !fits(k)) {
             batch.pop_back();
             continue;
         }

@@ -200,6 +200,38 @@ def serving_bench(tm, n_requests, slots=4, budget=32 << 30, precondition="chebys
             "hbm_peak_GiB": round(st["hbm_peak"] / 2**30, 3)}
 
 
+def extra_config(tm, ctx, name, precondition="chebyshev", cheb_degree=2):
+    """One MIXED and one FULL_DP solve of another configuration (the same
+    solver options as the headline), against the oracle's stored E_G when
+    tests/golden holds one."""
+    import torch
+    from workloads import config_problem
+    p = config_problem(name)
+    H = tm.matrix_from_problem(ctx, p)
+    C0 = tm.to_block(p.C0())
+    out = {"workload": f"{name}: N={p.N}, m={p.m}, CSR"}
+    pc = precondition if precondition != "none" else False
+    for prec in ("mixed", "full_dp"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, _, _, _ = tm.solve(ctx, H, p.m, 1e-8, C0, tm.opts(precision=prec, precondition=pc,
+                                                            cheb_degree=cheb_degree),
+                              want_vectors=False)
+        torch.cuda.synchronize()
+        out[prec] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": r["iterations"],
+                     "E_G": r["E_G"], "max_residual": r["max_residual"], "converged": r["converged"]}
+    out["speedup_vs_fp64"] = round(out["full_dp"]["seconds"] / out["mixed"]["seconds"], 3)
+    gpath = os.path.join(ROOT, "tests", "golden", f"oracle_{name}_s0.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            g = json.load(f)["E_G"]
+        for prec in ("mixed", "full_dp"):
+            out[prec]["rel_err_vs_oracle"] = abs(out[prec]["E_G"] - g) / abs(g)
+    del H, C0
+    torch.cuda.empty_cache()
+    return out
+
+
 def certify(p, C, w, res):
     """FP64 host check of a GPU result from the returned Ritz pairs alone:
     max_j ||H c_j - lambda_j c_j|| (H from the problem's CSR arrays),
@@ -362,6 +394,9 @@ def main():
                     help="comma-separated n:m rows of --table1 (default: all five)")
     ap.add_argument("--accuracy", action="store_true",
                     help="only the accuracy-floor study (R_i per policy on a Table 1 matrix)")
+    ap.add_argument("--extra", default="c3",
+                    help="comma-separated configs solved once each (MIXED and FULL_DP) after the "
+                         "headline when it is the default workload ('' or --no-variants: none)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel roofline timings and a copy of known size "
                          "(for hardware-counter runs)")
@@ -499,6 +534,12 @@ def main():
                                 max_batch=a.serving_batch)
         log(f"serving {serving}")
 
+    extra = {}
+    if a.config == "c2" and a.extra and not a.no_variants:
+        for name in [x for x in a.extra.split(",") if x]:
+            extra[name] = extra_config(tm, ctx, name, a.precondition, a.cheb_degree)
+            log(f"extra {name} {extra[name]}")
+
     cpu = None
     if not a.no_cpu:
         if res64 is not None:
@@ -530,7 +571,8 @@ def main():
         "iterations_fp64": res64["iterations"] if res64 else None,
         "E_G": res["E_G"], "rel_err_vs_oracle": rel_err, "max_residual": res["max_residual"],
         "converged": res["converged"], "variants": variants,
-        "roofline": roofline, "kernels": kernels, "serving": serving, "cpu_baseline": cpu,
+        "roofline": roofline, "kernels": kernels, "serving": serving, "extra_configs": extra or None,
+        "cpu_baseline": cpu,
         "certification": certification,
     }
     print(json.dumps(line), flush=True)

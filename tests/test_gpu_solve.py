@@ -351,13 +351,15 @@ def _golden(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("precision", ["mixed", "full_dp"])
-def test_c2_full_size(ctx, tm, precision):
-    """48^3 7-point + 64 wells, m = 256, as timed by the benchmark."""
+@pytest.mark.parametrize("precision,precondition", [("mixed", "chebyshev"), ("full_dp", "chebyshev"),
+                                                     ("mixed", False)])
+def test_c2_full_size(ctx, tm, precision, precondition):
+    """48^3 7-point + 64 wells, m = 256, in the benchmark's configuration
+    (MIXED and FULL_DP with the degree-2 polynomial M) and without M."""
     g = _golden("c2")
     p = config_problem("c2")
-    print_case(test="c2_full", precision=precision)
-    r, C, w, _ = _solve(tm, ctx, p, precision=precision)
+    print_case(test="c2_full", precision=precision, precondition=precondition)
+    r, C, w, _ = _solve(tm, ctx, p, precision=precision, precondition=precondition)
     assert r["converged"] == 1
     assert abs(r["E_G"] - g["E_G"]) <= 1e-10 * abs(g["E_G"])
     assert r["max_residual"] <= 1e-8
@@ -377,7 +379,7 @@ def test_c3_full_size_certified(ctx, tm, orc):
     test skips that comparison, and says so, while the file is absent)."""
     p = config_problem("c3")
     print_case(test="c3_full", N=p.N, m=p.m)
-    r, C, w, _ = _solve(tm, ctx, p, precision="mixed")
+    r, C, w, _ = _solve(tm, ctx, p, precision="mixed", precondition="chebyshev")
     assert r["converged"] == 1 and r["max_residual"] <= 1e-8
     Ch = host(C, p.m)
     wh = host(w)

@@ -100,7 +100,7 @@ def kernel_work(p, ld):
     }
 
 
-def kernel_rooflines(tm, ctx, H, p, reps=20):
+def kernel_rooflines(tm, ctx, H, p, reps=20, stencil_too=False):
     """Time each kernel with HIP events on the library stream and place it on
     the roofline; the dominant (longest) bulk kernel is the headline."""
     ld = tm.leading_dim(p.m)
@@ -118,13 +118,27 @@ def kernel_rooflines(tm, ctx, H, p, reps=20):
         out[key] = {"avg_ms": round(ms, 4), "bound": bound, "achieved": round(ach, 2), "peak": peak,
                     "unit": unit, "frac": round(ach / peak, 4),
                     "tflops": round(flops / t / 1e12, 2), "GB/s": round(nbytes / t / 1e9, 1)}
+    if stencil_too and p.spec.ndim == 3:
+        # the same H as a stencil (the z-marching kernel with LDS-staged C
+        # tiles that stencil-mode solves use), for comparison with the CSR form
+        Hs = tm.matrix_from_problem(ctx, p, stencil=True)
+        blk = p.N * ld
+        for dt, sz in (("f64", 8.0), ("f32", 4.0)):
+            ms = tm.time_kernel(ctx, Hs, "spmm", p.m, dt, reps=reps)
+            nbytes = 2.0 * sz * blk + 8.0 * p.N
+            out[f"spmm_stencil/{dt}"] = {"avg_ms": round(ms, 4), "bound": "hbm",
+                                         "achieved": round(nbytes / (ms * 1e-3) / 1e9, 2),
+                                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                         "frac": round(nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                                         "off_path": True}
+        Hs.free()
     chol_ms = tm.time_kernel(ctx, H, "chol", p.m, "f64", reps=reps)
     out["chol/f64"] = {"avg_ms": round(chol_ms, 4), "bound": "latency",
                        "tflops": round((2.0 / 3.0) * p.m ** 3 / (chol_ms * 1e-3) / 1e12, 4)}
     # the headline is the longest per-iteration bulk kernel; the m x m Cholesky
     # (a chain of small dependent launches, latency-bound) is reported by time only
     dom = max((k for k in out if out[k]["bound"] in ("hbm", "mfma")
-               and k not in ("gram_shift/f32", "gram_bf16x3/f32")),
+               and k not in ("gram_shift/f32", "gram_bf16x3/f32") and not out[k].get("off_path")),
               key=lambda k: out[k]["avg_ms"])
     d = out[dom]
     roof = {"bound": d["bound"], "achieved": d.get("achieved"), "peak": d.get("peak"),
@@ -440,7 +454,7 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        roofline, kernels = kernel_rooflines(tm, ctx, H, p, reps=5)
+        roofline, kernels = kernel_rooflines(tm, ctx, H, p, reps=5, stencil_too=not a.stencil)
         print(json.dumps({"roofline": roofline, "kernels": kernels}), flush=True)
         return
     C0 = tm.to_block(p.C0())
@@ -527,7 +541,7 @@ def main():
         log(f"certification {certification}")
         del run.vectors
         torch.cuda.empty_cache()
-    roofline, kernels = kernel_rooflines(tm, ctx, H, p)
+    roofline, kernels = kernel_rooflines(tm, ctx, H, p, stencil_too=not a.stencil)
     serving = None
     if a.serving > 0:
         serving = serving_bench(tm, a.serving, budget=int(a.serving_budget * 2**30),

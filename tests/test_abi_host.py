@@ -103,6 +103,11 @@ def test_serving_structs_and_footprint(lib):
     bad = _abi.tm_server_opts(device=0, max_slots=0, hbm_budget=1 << 30)
     h = ctypes.c_void_p()
     assert lib.tm_server_create(ctypes.byref(bad), ctypes.byref(h)) == _abi.TM_EINVAL
+    # batching options: up to 256 requests, 64..2048 block columns (0: default)
+    for mb, mc in ((-1, 0), (257, 0), (8, 32), (8, 4096)):
+        bad = _abi.tm_server_opts(device=0, max_slots=2, hbm_budget=1 << 30, max_batch=mb,
+                                  max_batch_cols=mc)
+        assert lib.tm_server_create(ctypes.byref(bad), ctypes.byref(h)) == _abi.TM_EINVAL
     assert lib.tm_server_submit(None, None, None) == _abi.TM_EINVAL
     assert lib.tm_server_poll(None, 1, None, None) == _abi.TM_EINVAL
 

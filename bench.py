@@ -391,6 +391,8 @@ def main():
                     help="iteration cap of each solve (a capped solve is reported as such)")
     ap.add_argument("--serving", type=int, default=200,
                     help="requests of the serving stream replayed after the solves (0: none)")
+    ap.add_argument("--serving-slots", type=int, default=4,
+                    help="solves in flight in the serving stream's server")
     ap.add_argument("--serving-budget", type=float, default=32.0,
                     help="HBM budget of the serving stream's server, GiB")
     ap.add_argument("--serving-batch", type=int, default=8,
@@ -441,7 +443,8 @@ def main():
     ctx = tm.Context(0)
     H = tm.matrix_from_problem(ctx, p, stencil=a.stencil)
     if a.serving_only:
-        sv = serving_bench(tm, a.serving, budget=int(a.serving_budget * 2**30), max_batch=a.serving_batch)
+        sv = serving_bench(tm, a.serving, slots=a.serving_slots, budget=int(a.serving_budget * 2**30),
+                           max_batch=a.serving_batch)
         print(json.dumps({"metric": "serving stream: p50/p99 latency (s) and solves/s, MIXED",
                           "serving": sv}), flush=True)
         return
@@ -544,7 +547,7 @@ def main():
     roofline, kernels = kernel_rooflines(tm, ctx, H, p, stencil_too=not a.stencil)
     serving = None
     if a.serving > 0:
-        serving = serving_bench(tm, a.serving, budget=int(a.serving_budget * 2**30),
+        serving = serving_bench(tm, a.serving, slots=a.serving_slots, budget=int(a.serving_budget * 2**30),
                                 max_batch=a.serving_batch)
         log(f"serving {serving}")
 

@@ -101,12 +101,21 @@ constexpr int kSub = 16;           // sub-panel inside K1
 constexpr int kBlkThreads = 256;   // 4 waves per workgroup
 constexpr int kAS = kBlk + 1;      // LDS row stride of the K1 block
 
+// The kernels below factor an m x m matrix stored with row stride lda.  A
+// block-diagonal matrix of m x m diagonal blocks (lda = their number times m)
+// is factored one block per blockIdx.y: the Cholesky factor and the inverse
+// of a block-diagonal matrix are block diagonal, so the blocks are
+// independent and nothing outside them is read or written.
+__device__ inline size_t diag_offset(int m, int lda) {
+    return (size_t)blockIdx.y * (size_t)m * (size_t)(lda + 1);
+}
+
 // K1 body.  upd: the trailing update of the previous block column is still
 // to be applied to this diagonal block (it runs beside that update's launch,
 // which skips these tiles): the block is read from where that update would
 // read it and the update is formed here, in the same order and precision.
 __device__ __attribute__((always_inline)) void chol_block_body(
-    int m, int kb, const double *__restrict__ S, const double *__restrict__ L,
+    int m, int lda, int kb, const double *__restrict__ S, const double *__restrict__ L,
     double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info, bool upd) {
     constexpr int NB = kSub, nwaves = kBlkThreads / 64;
     __shared__ double A[kBlk * kAS];   // the block; the sub-panel columns become L
@@ -128,10 +137,10 @@ __device__ __attribute__((always_inline)) void chol_block_body(
         for (int u = 0; u < U; ++u) {
             const int e = tid + u * kBlkThreads, i = e / kBlk, c = e % kBlk;
             v[u] = (i == c) ? 1.0 : 0.0;
-            if (i < nb && c <= i) v[u] = src[(size_t)(kb + i) * m + kb + c];
-            lp[u] = (upd && i < nb) ? L[(size_t)(kb + i) * m + kp + c] : 0.0;
+            if (i < nb && c <= i) v[u] = src[(size_t)(kb + i) * lda + kb + c];
+            lp[u] = (upd && i < nb) ? L[(size_t)(kb + i) * lda + kp + c] : 0.0;
         }
-        const double sd = (tid < nb) ? S[(size_t)(kb + tid) * m + kb + tid] : 1.0;
+        const double sd = (tid < nb) ? S[(size_t)(kb + tid) * lda + kb + tid] : 1.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = tid + u * kBlkThreads, i = e / kBlk, c = e % kBlk;
@@ -186,7 +195,7 @@ __device__ __attribute__((always_inline)) void chol_block_body(
         }
         __syncthreads();
         if (ok_flag >= 0) {   // uniform
-            if (tid == 0 && info[0] == 0) info[0] = kb + q + ok_flag + 1;
+            if (tid == 0 && info[0] == 0) info[0] = (int)blockIdx.y * m + kb + q + ok_flag + 1;
             return;
         }
         // (2) X of the sub-panel's rows: Dinv on the diagonal, X_pj = Dinv W_pj
@@ -259,16 +268,17 @@ __device__ __attribute__((always_inline)) void chol_block_body(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int e = tid + u * kBlkThreads, i = e / kBlk, c = e % kBlk;
-        if (i < nb && c <= i) X[(size_t)(kb + i) * m + kb + c] = W[i * kAS + c];
+        if (i < nb && c <= i) X[(size_t)(kb + i) * lda + kb + c] = W[i * kAS + c];
         // Rinv row i, column c: X_kk[c][i]
-        if (i < nb && c < nb) Rinv[(size_t)(kb + i) * m + kb + c] = (i <= c) ? W[c * kAS + i] : 0.0;
+        if (i < nb && c < nb) Rinv[(size_t)(kb + i) * lda + kb + c] = (i <= c) ? W[c * kAS + i] : 0.0;
     }
 }
 
 __global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
-    int m, int kb, const double *__restrict__ S, const double *__restrict__ L,
+    int m, int lda, int kb, const double *__restrict__ S, const double *__restrict__ L,
     double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info) {
-    chol_block_body(m, kb, S, L, X, Rinv, info, false);
+    const size_t off = diag_offset(m, lda);
+    chol_block_body(m, lda, kb, S + off, L + off, X + off, Rinv + off, info, false);
 }
 
 // K2: workgroups [0, nA) form the panel L_ik = S_ik X_kk^T, 16 rows each (one
@@ -277,8 +287,15 @@ __global__ __launch_bounds__(kBlkThreads) void chol_block_kernel(
 // before it is overwritten), with Rinv's mirror entries and the zeros below
 // its diagonal.
 __global__ __launch_bounds__(kBlkThreads) void chol_panel_kernel(
-    int m, int kb, const double *__restrict__ S, double *__restrict__ L,
+    int m, int lda, int kb, const double *__restrict__ S, double *__restrict__ L,
     double *__restrict__ X, double *__restrict__ Rinv) {
+    {
+        const size_t off = diag_offset(m, lda);
+        S += off;
+        L += off;
+        X += off;
+        Rinv += off;
+    }
     constexpr int KS = kBlk / 4;   // MFMA k-steps over the block width
     __shared__ double Ws[kBlk][17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -294,8 +311,8 @@ __global__ __launch_bounds__(kBlkThreads) void chol_panel_kernel(
 #pragma unroll
         for (int u = 0; u < KS; ++u) {
             const int t = 4 * u + (lane >> 4);
-            av[u] = (ia < m) ? src[(size_t)ia * m + kb + t] : 0.0;
-            bv[u] = (t <= cb) ? X[(size_t)(kb + cb) * m + kb + t] : 0.0;   // X_kk[c][t]
+            av[u] = (ia < m) ? src[(size_t)ia * lda + kb + t] : 0.0;
+            bv[u] = (t <= cb) ? X[(size_t)(kb + cb) * lda + kb + t] : 0.0;   // X_kk[c][t]
         }
         d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -303,14 +320,14 @@ __global__ __launch_bounds__(kBlkThreads) void chol_panel_kernel(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = i0 + mfma64_row(lane, r);
-            if (i < m) L[(size_t)i * m + kb + cb] = acc[r];
+            if (i < m) L[(size_t)i * lda + kb + cb] = acc[r];
         }
         return;
     }
     const int j0 = 16 * (g - nA);
     for (int e = tid; e < kBlk * 16; e += kBlkThreads) {
         const int i = e >> 4, j = e & 15;
-        Ws[i][j] = (i < nb) ? X[(size_t)(kb + i) * m + j0 + j] : 0.0;
+        Ws[i][j] = (i < nb) ? X[(size_t)(kb + i) * lda + j0 + j] : 0.0;
     }
     __syncthreads();
     const int r0 = 16 * wave;
@@ -320,7 +337,7 @@ __global__ __launch_bounds__(kBlkThreads) void chol_panel_kernel(
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
         const int t = 4 * u + (lane >> 4);
-        av[u] = (ra < nb && t <= ra) ? X[(size_t)(kb + ra) * m + kb + t] : 0.0;   // X_kk lower
+        av[u] = (ra < nb && t <= ra) ? X[(size_t)(kb + ra) * lda + kb + t] : 0.0;   // X_kk lower
     }
     d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -330,9 +347,9 @@ __global__ __launch_bounds__(kBlkThreads) void chol_panel_kernel(
     for (int r = 0; r < 4; ++r) {
         const int i = r0 + mfma64_row(lane, r);
         if (i < nb) {
-            X[(size_t)(kb + i) * m + j] = acc[r];
-            Rinv[(size_t)j * m + kb + i] = acc[r];
-            Rinv[(size_t)(kb + i) * m + j] = 0.0;
+            X[(size_t)(kb + i) * lda + j] = acc[r];
+            Rinv[(size_t)j * lda + kb + i] = acc[r];
+            Rinv[(size_t)(kb + i) * lda + j] = 0.0;
         }
     }
 }
@@ -343,7 +360,7 @@ __global__ __launch_bounds__(kBlkThreads) void chol_panel_kernel(
 // skip: the first skip lower tiles (those of the next diagonal block, which
 // its own K1 updates) are left out.
 __device__ __attribute__((always_inline)) void chol_trail_body(
-    int m, int kb, const double *__restrict__ S, double *__restrict__ L,
+    int m, int lda, int kb, const double *__restrict__ S, double *__restrict__ L,
     double *__restrict__ X, int skip) {
     constexpr int KS = kBlk / 4;
     const int lane = threadIdx.x & 63;
@@ -367,13 +384,13 @@ __device__ __attribute__((always_inline)) void chol_trail_body(
 #pragma unroll
     for (int u = 0; u < KS; ++u) {
         const int tk = 4 * u + (lane >> 4);
-        av[u] = (ia < m) ? L[(size_t)ia * m + kb + tk] : 0.0;
+        av[u] = (ia < m) ? L[(size_t)ia * lda + kb + tk] : 0.0;
         if (sym) {
-            bv[u] = (jb < m) ? L[(size_t)jb * m + kb + tk] : 0.0;
+            bv[u] = (jb < m) ? L[(size_t)jb * lda + kb + tk] : 0.0;
         } else {
             // X_kj: the block row of X left of the diagonal, X_kk (lower) on it
             const bool valid = jb < kb || jb - kb <= tk;
-            bv[u] = valid ? X[(size_t)(kb + tk) * m + jb] : 0.0;
+            bv[u] = valid ? X[(size_t)(kb + tk) * lda + jb] : 0.0;
         }
     }
 #pragma unroll
@@ -381,9 +398,9 @@ __device__ __attribute__((always_inline)) void chol_trail_body(
         const int i = k0 + bi * 16 + mfma64_row(lane, r);
         double v = 0.0;
         if (sym) {
-            if (i < m && jb <= i) v = src[(size_t)i * m + jb];
+            if (i < m && jb <= i) v = src[(size_t)i * lda + jb];
         } else {
-            if (i < m && jb < kb) v = X[(size_t)i * m + jb];   // W; zero right of kb
+            if (i < m && jb < kb) v = X[(size_t)i * lda + jb];   // W; zero right of kb
         }
         old[r] = v;
     }
@@ -394,9 +411,9 @@ __device__ __attribute__((always_inline)) void chol_trail_body(
     for (int r = 0; r < 4; ++r) {
         const int i = k0 + bi * 16 + mfma64_row(lane, r);
         if (sym) {
-            if (i < m && jb <= i) L[(size_t)i * m + jb] = old[r] - acc[r];
+            if (i < m && jb <= i) L[(size_t)i * lda + jb] = old[r] - acc[r];
         } else {
-            if (i < m) X[(size_t)i * m + jb] = old[r] - acc[r];
+            if (i < m) X[(size_t)i * lda + jb] = old[r] - acc[r];
         }
     }
 }
@@ -405,13 +422,14 @@ __device__ __attribute__((always_inline)) void chol_trail_body(
 // workgroup factors the next diagonal block (applying its share of this
 // update itself), the others update the rest of the trailing matrix and W.
 __global__ __launch_bounds__(kBlkThreads) void chol_trail_block_kernel(
-    int m, int kb, const double *__restrict__ S, double *__restrict__ L,
+    int m, int lda, int kb, const double *__restrict__ S, double *__restrict__ L,
     double *__restrict__ X, double *__restrict__ Rinv, int32_t *__restrict__ info, int skip) {
+    const size_t off = diag_offset(m, lda);
     if (blockIdx.x == gridDim.x - 1) {
-        chol_block_body(m, kb + kBlk, S, L, X, Rinv, info, true);
+        chol_block_body(m, lda, kb + kBlk, S + off, L + off, X + off, Rinv + off, info, true);
         return;
     }
-    chol_trail_body(m, kb, S, L, X, skip);
+    chol_trail_body(m, lda, kb, S + off, L + off, X + off, skip);
 }
 
 __global__ void assemble_kernel(int m, const double *__restrict__ Hp,
@@ -431,25 +449,31 @@ size_t chol_workspace(int m) {
 }
 
 void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
-                  double *work, int32_t *info) {
+                  double *work, int32_t *info, int sb) {
     TM_REQUIRE(m >= 1 && m <= 2048, TM_ENOTSUP, "Cholesky supports m <= 2048");
+    const int b = (sb > 0 && sb < m) ? sb : m;   // diagonal block size
+    TM_REQUIRE(b == m || (b % kBlk == 0 && m % b == 0), TM_EINVAL,
+               "block-diagonal Cholesky: the block size must divide m and be a multiple of 64");
+    const unsigned nd = (unsigned)(m / b);
     double *L = work, *X = work + (size_t)m * m;
     // K1 of block column 0; then per block column K2 and, while rows remain,
-    // K3 together with the next block column's K1
-    hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(kBlkThreads), 0, s, m, 0, S, L, X, Rinv,
-                       info);
-    for (int kb = 0; kb < m; kb += kBlk) {
-        const int nb = std::min(kBlk, m - kb), R = m - kb - nb;
+    // K3 together with the next block column's K1 (all diagonal blocks of a
+    // block-diagonal S side by side)
+    hipLaunchKernelGGL(chol_block_kernel, dim3(1, nd), dim3(kBlkThreads), 0, s, b, m, 0, S, L, X,
+                       Rinv, info);
+    for (int kb = 0; kb < b; kb += kBlk) {
+        const int nb = std::min(kBlk, b - kb), R = b - kb - nb;
         const int nA = (R + 15) / 16, nB = kb / 16;
         if (nA + nB > 0)
-            hipLaunchKernelGGL(chol_panel_kernel, dim3(nA + nB), dim3(kBlkThreads), 0, s, m, kb,
-                               S, L, X, Rinv);
+            hipLaunchKernelGGL(chol_panel_kernel, dim3(nA + nB, nd), dim3(kBlkThreads), 0, s, b, m,
+                               kb, S, L, X, Rinv);
         if (R > 0) {
             const int nr = (R + 15) / 16, tiles = nr * (nr + 1) / 2 + nr * ((kb + kBlk) / 16);
             const int nt = (std::min(kBlk, R) + 15) / 16, skip = nt * (nt + 1) / 2;
             const int per = kBlkThreads / 64;
-            hipLaunchKernelGGL(chol_trail_block_kernel, dim3((tiles - skip + per - 1) / per + 1),
-                               dim3(kBlkThreads), 0, s, m, kb, S, L, X, Rinv, info, skip);
+            hipLaunchKernelGGL(chol_trail_block_kernel,
+                               dim3((tiles - skip + per - 1) / per + 1, nd), dim3(kBlkThreads), 0, s,
+                               b, m, kb, S, L, X, Rinv, info, skip);
         }
         TM_HIP(hipGetLastError());
     }

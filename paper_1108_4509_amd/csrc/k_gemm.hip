@@ -666,7 +666,7 @@ template <typename TA, typename TM, typename TO, int EPI, int BR, int BC>
 __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TM *__restrict__ W,
     const TA *__restrict__ X, const double *__restrict__ vec, TO *__restrict__ out,
-    int nrb, int ncb, GradDots<TO> gd) {
+    int nrb, int ncb, GradDots<TO> gd, int wg) {
     using SM = RotSmem<TM, BR, BC>;
     constexpr int KT = SM::KT;
     constexpr int WR = BR / 2, WC = BC / 2;
@@ -696,6 +696,16 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     const int c0 = cb * BC;
     int kend = ld;
     if (EPI == EPI_TRMM && c0 + BC < kend) kend = c0 + BC;   // W strictly upper
+    // block-diagonal W (wg-wide diagonal blocks): the tile's columns see only
+    // the rows of the blocks they fall in; the products left out are exact
+    // zeros, so the sums are those of the full loop
+    int kbeg = 0;
+    if (wg > 0) {
+        kbeg = c0 / wg * wg;
+        kbeg -= kbeg % KT;
+        const int ge = (c0 + BC + wg - 1) / wg * wg;
+        if (ge < kend) kend = ge;
+    }
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -740,10 +750,10 @@ __global__ __launch_bounds__(kThreads, 2) void rot_kernel(
     };
 
     int buf = 0;
-    load(0);
+    load(kbeg);
     store(0);
     __syncthreads();
-    for (int k0 = 0; k0 < kend; k0 += KT) {
+    for (int k0 = kbeg; k0 < kend; k0 += KT) {
         const bool more = k0 + KT < kend;
         if (more) load(k0 + KT);
         const AsRow *As = As0 + buf * BR;
@@ -1175,11 +1185,12 @@ void gram_bf16x3(hipStream_t s, int64_t n, int m, const TA *A, const TA *B, cons
 template <typename TA, typename TM, typename TO>
 int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
         const TA *X, const double *vec, TO *out, const TO *Gp, const TO *Pp,
-        const double *M, double *partials, const TM *Xs) {
+        const double *M, double *partials, const TM *Xs, int wg) {
     TM_REQUIRE(epi != EPI_GRADX || Xs != nullptr, TM_EINVAL, "EPI_GRADX needs X'");
+    TM_REQUIRE(wg == 0 || (wg > 0 && wg % 16 == 0), TM_EINVAL, "diagonal blocks of W: 16-column multiples");
     const int ld = leading_dim(m);
     if constexpr (std::is_same<TM, float>::value && std::is_same<TA, TO>::value) {
-        if (ld == 256 && epi == EPI_TRMM) {
+        if (ld == 256 && epi == EPI_TRMM && wg == 0) {
             const int64_t nstrips = (n + 15) / 16;
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(kTriGrid, nstrips));
             hipLaunchKernelGGL((trmm_lds_kernel<TA, 16>), dim3(grid), dim3(kTriWaves * 64), 0, s, n, ld, A,
@@ -1205,7 +1216,7 @@ int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad, int epi,
     gd.Xs = Xs;
 #define TM_ROT(E, BRV, BCV)                                                                  \
     hipLaunchKernelGGL((rot_kernel<TA, TM, TO, E, BRV, BCV>), dim3(grid), dim3(kThreads),   \
-                       0, s, n, m, ld, A, Wpad, X, vec, out, nrb, ncb, gd)
+                       0, s, n, m, ld, A, Wpad, X, vec, out, nrb, ncb, gd, wg)
     if (B == 128) {
         if (epi == EPI_NONE) TM_ROT(EPI_NONE, 64, 128);
         else if (epi == EPI_GRAD) TM_ROT(EPI_GRAD, 64, 128);
@@ -1246,11 +1257,11 @@ template void gram_update<double, double, float>(hipStream_t, int64_t, int, cons
 template void gram_update<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, const CgState *, float *, double *, double *, BatchCols);
 template void gram_bf16x3<float>(hipStream_t, int64_t, int, const float *, const float *, const double *, bool, double *, double *, bool, float *, size_t);
 template void gram_bf16x3<double>(hipStream_t, int64_t, int, const double *, const double *, const double *, bool, double *, double *, bool, float *, size_t);
-template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const double *);
-template int rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *, const float *, const float *, const double *, double *, const float *);
-template int rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *, const float *, const float *, const double *, double *, const float *);
-template int rot<double, float, double>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const float *);
-template int rot<double, double, float>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, float *, const float *, const float *, const double *, double *, const double *);
+template int rot<double, double, double>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const double *, int);
+template int rot<float, float, float>(hipStream_t, int64_t, int, const float *, const float *, int, const float *, const double *, float *, const float *, const float *, const double *, double *, const float *, int);
+template int rot<double, float, float>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, float *, const float *, const float *, const double *, double *, const float *, int);
+template int rot<double, float, double>(hipStream_t, int64_t, int, const double *, const float *, int, const double *, const double *, double *, const double *, const double *, const double *, double *, const float *, int);
+template int rot<double, double, float>(hipStream_t, int64_t, int, const double *, const double *, int, const double *, const double *, float *, const float *, const float *, const double *, double *, const double *, int);
 template void pad_matrix<double>(hipStream_t, int, const double *, bool, double *, double *);
 template void pad_matrix<float>(hipStream_t, int, const double *, bool, float *, double *);
 

@@ -204,13 +204,15 @@ enum RotEpi { EPI_NONE = 0, EPI_GRAD = 1, EPI_TRMM = 2, EPI_GRADX = 3 };
 // test: p = 0: g.g, 1: g.(M g), 2: g_prev.(M g), 3: p_prev.g, written to
 // partials[(p * nchunk + chunk) * ld + j]; returns nchunk (row blocks).
 // Gp = nullptr skips trace 2 (it reads 0) and the pass over G_prev.
-// partials needs rot_partials_workspace(n, m) bytes.
+// partials needs rot_partials_workspace(n, m) bytes.  wg > 0: W is block
+// diagonal with wg x wg diagonal blocks (wg a multiple of 16), and each
+// column tile loops only over the rows of its blocks.
 size_t rot_partials_workspace(int64_t n, int m);
 template <typename TA, typename TM, typename TO>
 int rot(hipStream_t s, int64_t n, int m, const TA *A, const TM *Wpad,
         int epi, const TA *X, const double *vec, TO *out, const TO *Gp = nullptr,
         const TO *Pp = nullptr, const double *M = nullptr, double *partials = nullptr,
-        const TM *Xs = nullptr);
+        const TM *Xs = nullptr, int wg = 0);
 // Copy an m x m FP64 matrix into an ld x ld zero-padded matrix of type TM,
 // keeping the strict upper triangle only (strict_upper) and returning the
 // diagonal in diag (when not null).
@@ -221,8 +223,11 @@ void pad_matrix(hipStream_t s, int m, const double *W, bool strict_upper,
 // Dense m x m FP64 kernels -------------------------------------------------
 size_t chol_workspace(int m);
 // Rinv = R^{-1}, S = R^T R.  info[0] = 0 or the 1-based failing pivot.
+// sb > 0 and < m: S is block diagonal in sb x sb blocks (sb a multiple of
+// 64 dividing m), factored side by side; Rinv's entries outside those blocks
+// are not written (the caller keeps them zero).
 void chol_inverse(hipStream_t s, int m, const double *S, double *Rinv,
-                  double *work, int32_t *info);
+                  double *work, int32_t *info, int sb = 0);
 size_t jacobi_workspace(int m);
 // Eigenpairs of symmetric A: w ascending, U columns.  info[0] = sweeps.
 // Batched (block-diagonal) A: ascending within each group of ldg indices,

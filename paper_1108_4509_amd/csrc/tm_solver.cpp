@@ -183,6 +183,23 @@ struct Solver::Impl {
         }
         return b;
     }
+    // a batch's S = C^T C is block diagonal with the problems' ldg x ldg
+    // blocks; its Cholesky runs on the smallest diagonal blocks that hold
+    // whole problems and are a multiple of 64 wide (0: one m x m matrix)
+    int chol_block() const {
+        if (!batched) return 0;
+        int a = ldg, b = 64;
+        while (b) {
+            const int t = a % b;
+            a = b;
+            b = t;
+        }
+        const int sb = ldg / a * 64;   // lcm(ldg, 64), which divides m = ng * ldg
+        return sb < m ? sb : 0;
+    }
+    // a batch's m x m matrices (A, U, R^{-1}) are block diagonal in
+    // ldg x ldg blocks: the products with them skip the zero blocks
+    int wgroup() const { return batched ? ldg : 0; }
     // the SpMM epilogue term of the batch: X = A C + d_g c (columns of g)
     SpmmEpi bepi(bool f64) const {
         SpmmEpi e;
@@ -218,6 +235,9 @@ struct Solver::Impl {
         TM_HIP(hipMemsetAsync(h->ptr, 0, ld * sizeof(double), s));
         TM_HIP(hipMemsetAsync(d->ptr, 0, ld * sizeof(double), s));
         TM_HIP(hipMemsetAsync(w->ptr, 0, ld * sizeof(double), s));
+        // a batch's R^{-1} is block diagonal: the Cholesky writes only its
+        // diagonal blocks, the rest stays zero from here on
+        if (batched) TM_HIP(hipMemsetAsync(Rinv->ptr, 0, md, s));
         static_assert(kMaxBatch * sizeof(CgState) <= tm_ctx::kPinnedStates,
                       "the states of a batch must fit the pinned buffer");
         char *pin = (char *)ctx->pinned_buffer();
@@ -319,9 +339,11 @@ struct Solver::Impl {
     // Fig. 4 steps (2)-(4) once S = Cin^T Cin is in S: Cout = Cin R^{-1}
     template <typename TC, typename TT>
     void finish_orthonormalize(TC *Cin, TC *Cout) {
-        chol_inverse(s, m, (double *)S->ptr, (double *)Rinv->ptr, (double *)chol_ws->ptr, (int32_t *)info->ptr);
+        chol_inverse(s, m, (double *)S->ptr, (double *)Rinv->ptr, (double *)chol_ws->ptr, (int32_t *)info->ptr,
+                     chol_block());
         pad_matrix<TT>(s, m, (double *)Rinv->ptr, true, (TT *)Wp->ptr, (double *)d->ptr);
-        rot<TC, TT, TC>(s, n, m, Cin, (TT *)Wp->ptr, EPI_TRMM, nullptr, (double *)d->ptr, Cout);
+        rot<TC, TT, TC>(s, n, m, Cin, (TT *)Wp->ptr, EPI_TRMM, nullptr, (double *)d->ptr, Cout, nullptr,
+                        nullptr, nullptr, nullptr, nullptr, wgroup());
     }
 
     // ---- Rayleigh-Ritz (Eq. 9): C <- C U, ascending Ritz values into w
@@ -335,7 +357,8 @@ struct Solver::Impl {
         jacobi_eig(s, m, (double *)Amat->ptr, (double *)U->ptr, (double *)w->ptr, (double *)jac_ws->ptr,
                    (int32_t *)info->ptr + 1, ldg, mg);
         pad_matrix<TM>(s, m, (double *)U->ptr, false, (TM *)Wp->ptr, nullptr);
-        rot<TC, TM, TC>(s, n, m, C, (TM *)Wp->ptr, EPI_NONE, nullptr, nullptr, Cn);
+        rot<TC, TM, TC>(s, n, m, C, (TM *)Wp->ptr, EPI_NONE, nullptr, nullptr, Cn, nullptr, nullptr,
+                        nullptr, nullptr, nullptr, wgroup());
         std::swap(C, Cn);
         ++rotations;
     }
@@ -373,9 +396,11 @@ struct Solver::Impl {
                 // direction and gradient carried into the rotated basis keep
                 // the Polak-Ribiere traces unchanged, so CG continues
                 pad_matrix<TG>(s, m, (double *)U->ptr, false, (TG *)Wp->ptr, nullptr);
-                rot<TG, TG, TG>(s, n, m, (TG *)P->ptr, (TG *)Wp->ptr, EPI_NONE, nullptr, nullptr, (TG *)Y->ptr);
+                rot<TG, TG, TG>(s, n, m, (TG *)P->ptr, (TG *)Wp->ptr, EPI_NONE, nullptr, nullptr, (TG *)Y->ptr,
+                                nullptr, nullptr, nullptr, nullptr, nullptr, wgroup());
                 std::swap(P, Y);
-                rot<TG, TG, TG>(s, n, m, (TG *)Gp->ptr, (TG *)Wp->ptr, EPI_NONE, nullptr, nullptr, (TG *)G->ptr);
+                rot<TG, TG, TG>(s, n, m, (TG *)Gp->ptr, (TG *)Wp->ptr, EPI_NONE, nullptr, nullptr, (TG *)G->ptr,
+                                nullptr, nullptr, nullptr, nullptr, nullptr, wgroup());
                 std::swap(G, Gp);
             } else {
                 set_restart();
@@ -418,7 +443,7 @@ struct Solver::Impl {
             const TG *gp_dots = o.precondition == 2 ? nullptr : Gpv;
             const int nch = rot<TC, TMH, TG>(s, n, m, C, (TMH *)Wp->ptr, Xs ? EPI_GRADX : EPI_GRAD, X,
                                              (double *)h->ptr, Gv, gp_dots, Pv, Mv,
-                                             (double *)dot_ws->ptr, Xs);
+                                             (double *)dot_ws->ptr, Xs, wgroup());
             reduce_partials(s, 4, nch, ld, (double *)dot_ws->ptr, (double *)dots->ptr);
         }
         // the polynomial M: Z = M G, and the traces tr(G^T Z), tr(G_prev^T Z)

@@ -241,3 +241,33 @@ def test_batch_graph_replay_matches_eager(tm, ctx):
     r2, C2, e2 = tm.solve_batch(ctx, H, m, tol, None, tm.opts(precision="mixed", seed=seed, graphs=True))
     assert torch.equal(e1, e2) and torch.equal(C1, C2)
     assert [r["iterations"] for r in r1] == [r["iterations"] for r in r2]
+
+
+def test_batch_widest_and_single_column(tm, ctx):
+    """The widest batch the column bound admits (128 problems of m = 16:
+    2048 block columns, 216 rows each; the Cholesky of C^T C as 32 diagonal
+    blocks of 64), a batch of one-column problems (each group one live
+    column and 15 padding columns) and 8 problems of m = 76 (80 columns
+    each; the Cholesky as two diagonal blocks of 320, each five 64-wide
+    block columns) reach every problem's LAPACK eigenvalues; one problem
+    more than 2048 columns hold is refused."""
+    from paper_1108_4509_amd import _abi
+    for side, k, m, wells in ((6, 128, 16, 1), (8, 4, 1, 2), (8, 8, 76, 2)):
+        print_case(test="batch_edges", side=side, k=k, m=m)
+        A, V, Hs = _batch(side, k, wells, seed0=1100)
+        n = side ** 3
+        H = tm.set_matrix_batch(ctx, *A, V)
+        ldg, ld = tm.batch_layout(k, m)
+        assert ld <= 2048 and ldg >= m
+        res, _, eig = tm.solve_batch(ctx, H, m, 1e-8, None, tm.opts(precision="full_dp", seed=11),
+                                     want_vectors=False)
+        eig = host(eig)
+        for g in range(k):
+            assert res[g]["converged"] == 1, g
+            lam = np.linalg.eigvalsh(_dense(Hs[g], n))[:m]
+            assert np.max(np.abs(eig[g] - lam)) <= 1e-9, g
+    A, V, _ = _batch(4, 129, 1, seed0=1300)
+    H = tm.set_matrix_batch(ctx, *A, V)
+    rs = (_abi.tm_result * 129)()
+    assert _abi.lib().tm_solve_batch(ctx.handle, H.handle, 16, 1e-8, None, None, None, None, rs) \
+        == _abi.TM_ENOTSUP

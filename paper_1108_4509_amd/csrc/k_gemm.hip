@@ -158,7 +158,7 @@ __global__ __launch_bounds__(NT, NT / 128) void gram_kernel(
     int64_t n, int m, int ld, const TA *__restrict__ A, const TA *__restrict__ B,
     const double *__restrict__ h, int T, int ntiles, bool symmetric,
     int64_t rows_per_split, double *__restrict__ partials, GramUpd<TA, TP> up,
-    TM *__restrict__ xout) {
+    TM *__restrict__ xout, int tg, int nwork) {
     constexpr int KT = stage_rows<TM>();
     constexpr int NW = NT / 64;             // waves: 2 x (NW / 2)
     constexpr int WM = BM / 2;              // rows of a wave's patch
@@ -176,11 +176,25 @@ __global__ __launch_bounds__(NT, NT / 128) void gram_kernel(
     __shared__ TM Bs[2][KT][BM + kPad];
 
     const int logical = xcd_logical(gridDim.x);
+    if (logical >= nwork) return;   // uniform: the grid is rounded up to a multiple of 8
     const int split = logical / ntiles;
     const int tile = logical - split * ntiles;
     int ti, tj;
-    if (symmetric) upper_tile(tile, T, ti, tj);
-    else { ti = tile / T; tj = tile - ti * T; }
+    if (tg > 0) {
+        // block-diagonal result (batched solves): only the tiles of the
+        // diagonal tg x tg tile blocks, each holding whole problems
+        const int per = symmetric ? tg * (tg + 1) / 2 : tg * tg;
+        const int grp = tile / per, r = tile - grp * per;
+        if (symmetric) upper_tile(r, tg, ti, tj);
+        else { ti = r / tg; tj = r - ti * tg; }
+        ti += grp * tg;
+        tj += grp * tg;
+    } else if (symmetric) {
+        upper_tile(tile, T, ti, tj);
+    } else {
+        ti = tile / T;
+        tj = tile - ti * T;
+    }
     const int i0 = ti * BM, j0 = tj * BM;
     const int64_t k_begin = (int64_t)split * rows_per_split;
     int64_t k_end = k_begin + rows_per_split;
@@ -219,9 +233,10 @@ __global__ __launch_bounds__(NT, NT / 128) void gram_kernel(
         alpha = (TA)up.st[up.ldg > 0 ? ci_c / up.ldg : 0].alpha;
         alpha_b = (TA)up.st[up.ldg > 0 ? cj_c / up.ldg : 0].alpha;
     }
-    // the workgroups of tile row 0 store X' = X - C diag(h) for their columns
-    // (each element once), in the matrix-core precision
-    const bool xstore = SHIFT && xout != nullptr && ti == 0;
+    // the workgroups of tile row 0 (of the diagonal tiles when only the
+    // diagonal blocks run) store X' = X - C diag(h) for their columns (each
+    // element once), in the matrix-core precision
+    const bool xstore = SHIFT && xout != nullptr && (tg > 0 ? ti == tj : ti == 0);
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int q = 0; q < PASSES; ++q) {
@@ -1077,6 +1092,24 @@ size_t gram_partials_bytes(int64_t n, int m, bool symmetric, size_t ws_bytes) {
     return (size_t)ns * m * m * sizeof(double);
 }
 
+// Tiles of a Gram launch: all of them, or, for a block-diagonal result with
+// ldg-wide diagonal blocks (a batched solve), the diagonal tg x tg blocks of
+// BM tiles that hold whole problems (tg = 1 when problems tile BM, ldg / BM
+// when BM tiles a problem; no skipping otherwise).  The split count stays
+// that of the full launch, so the partials workspace is the same.
+static void gram_plan(int T, int BM, bool symmetric, int nsplit, BatchCols bc, int &tg, int &ntiles,
+                      int &nwork, int &grid) {
+    tg = 0;
+    if (bc.ldg > 0) {
+        if (BM % bc.ldg == 0) tg = 1;
+        else if (bc.ldg % BM == 0) tg = bc.ldg / BM;
+    }
+    if (tg > 0) ntiles = (T + tg - 1) / tg * (symmetric ? tg * (tg + 1) / 2 : tg * tg);
+    else ntiles = symmetric ? T * (T + 1) / 2 : T * T;
+    nwork = ntiles * nsplit;
+    grid = (nwork + 7) / 8 * 8;
+}
+
 size_t gram_workspace(int64_t n, int m) {
     int BM, T, ns_full, ns_sym;
     gram_shape(n, m, false, BM, T, ns_full);
@@ -1091,15 +1124,15 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
     const int ld = leading_dim(m);
     int BM, T, nsplit;
     gram_shape(n, m, symmetric, BM, T, nsplit, ws_bytes);
-    const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
+    int tg, ntiles, nwork, grid;
+    gram_plan(T, BM, symmetric, nsplit, bc, tg, ntiles, nwork, grid);
     constexpr int KT = stage_rows<TM>();
     const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
-    const int grid = ntiles * nsplit;   // multiple of 8
 #define TM_GRAM(BMV, SH)                                                            \
     hipLaunchKernelGGL((gram_kernel<TA, TM, BMV, SH, false, TA, gram_threads<TA, TM, SH, false, TA>()>), \
                        dim3(grid), dim3(gram_threads<TA, TM, SH, false, TA>()), 0, s,         \
                        n, m, ld, A, B, h, T, ntiles, symmetric, rows, partials, GramUpd<TA, TA>{}, \
-                       xshift)
+                       xshift, tg, nwork)
     if (BM == 128) {
         if (h) TM_GRAM(128, true); else TM_GRAM(128, false);
     } else {
@@ -1127,10 +1160,10 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
     const int ld = leading_dim(m);
     int BM, T, nsplit;
     gram_shape(n, m, true, BM, T, nsplit);
-    const int ntiles = T * (T + 1) / 2;
+    int tg, ntiles, nwork, grid;
+    gram_plan(T, BM, true, nsplit, bc, tg, ntiles, nwork, grid);
     constexpr int KT = stage_rows<TM>();
     const int64_t rows = ((n + nsplit - 1) / nsplit + KT - 1) / KT * KT;
-    const int grid = ntiles * nsplit;   // multiple of 8
     GramUpd<TA, TP> up;
     up.P = P;
     up.st = st;
@@ -1139,11 +1172,13 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
     if (BM == 128)
         hipLaunchKernelGGL((gram_kernel<TA, TM, 128, false, true, TP, gram_threads<TA, TM, false, true, TP>()>),
                            dim3(grid), dim3(gram_threads<TA, TM, false, true, TP>()), 0, s,
-                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up, nullptr);
+                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up, nullptr, tg,
+                           nwork);
     else
         hipLaunchKernelGGL((gram_kernel<TA, TM, 64, false, true, TP, gram_threads<TA, TM, false, true, TP>()>),
                            dim3(grid), dim3(gram_threads<TA, TM, false, true, TP>()), 0, s,
-                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up, nullptr);
+                           n, m, ld, C, C, nullptr, T, ntiles, true, rows, partials, up, nullptr, tg,
+                           nwork);
     TM_HIP(hipGetLastError());
     const int64_t total = (int64_t)m * m;
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0,

@@ -156,9 +156,9 @@ def kernel_rooflines(tm, ctx, H, p, reps=20, stencil_too=False):
 TRAFFIC_CONFIG = "c2"
 TRAFFIC = {
     "rot_grad_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                         "6e31d91f75ed07dd5351732d28abccc59b7aeff2", 2.0 * 282426.9 * 1024 + 124416.0 * 1024),
+                         "e2dcab6dab0ca6d4f186b422df2b95b0eb605273", 2.0 * 282409.8 * 1024 + 124416.0 * 1024),
     "gram_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                     "6e31d91f75ed07dd5351732d28abccc59b7aeff2", 2.0 * 326031.8 * 1024 + 164352.0 * 1024),
+                     "e2dcab6dab0ca6d4f186b422df2b95b0eb605273", 2.0 * 325503.0 * 1024 + 164352.0 * 1024),
 }
 
 

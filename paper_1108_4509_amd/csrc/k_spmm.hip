@@ -378,9 +378,10 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
     const T ea = (T)(epi.gab ? epi.gab[2 * grp] : epi.a);
     const T eb = (T)(epi.gab ? epi.gab[2 * grp + 1] : epi.b);
     const V *E = reinterpret_cast<const V *>(epi.E);
-    auto finish = [&](int64_t r, V acc) {
-        if (epi.affine || ndot > 0 || Dg) {
-            const V c = C[r * ldv + cv];
+    const bool own = epi.affine || ndot > 0 || Dg;   // the epilogue reads the row's own c
+    // c: the row's own vector of C (loaded ahead by the caller)
+    auto finish = [&](int64_t r, V acc, V c) {
+        if (own) {
             if (Dg) {
                 const T dr = Dg[r];
 #pragma unroll
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
         // past a row's end read entry 0 with weight zero
         for (int i = slot; i < nr; i += RG * RPP) {
             int s0[RG], s1[RG];
-            V acc[RG];
+            V acc[RG], cown[RG];
             int len = 0;
 #pragma unroll
             for (int g = 0; g < RG; ++g) {
@@ -419,6 +420,11 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
                 s1[g] = has ? (int)(rp[ig + 1] - e0) : 0;
                 len = max(len, s1[g] - s0[g]);
                 acc[g] = V(0);
+                // the epilogue's own row of C is loaded with the first
+                // gathers, not after them (E stays in the epilogue: loading
+                // it here too costs a wave per SIMD of occupancy)
+                const int64_t rr = r_begin + (has ? ig : 0);
+                cown[g] = own ? C[rr * ldv + cv] : V(0);
             }
             for (int o = 0; o < len; o += UB) {
                 V v[RG][UB];
@@ -439,14 +445,15 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
             }
 #pragma unroll
             for (int g = 0; g < RG; ++g)
-                if (i + g * RPP < nr) finish(r_begin + i + g * RPP, acc[g]);
+                if (i + g * RPP < nr) finish(r_begin + i + g * RPP, acc[g], cown[g]);
         }
     } else {
         for (int i = slot; i < nr; i += RPP) {
             V acc = V(0);
             for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
                 acc = fma_v<V, T>(val[k], C[(int64_t)col[k] * ldv + cv], acc);
-            finish(r_begin + i, acc);
+            const int64_t r = r_begin + i;
+            finish(r, acc, own ? C[r * ldv + cv] : V(0));
         }
     }
     if (ndot > 0) {

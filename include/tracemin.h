@@ -312,8 +312,9 @@ tm_status tm_solve_batch(tm_ctx *ctx, const tm_mat *H, int32_t m, double tol,
  * m, tol and options (no BF16 policy; no preconditioner or the degree-2
  * polynomial), the same sparsity pattern and off-diagonal values (one grid,
  * one kinetic operator), any diagonal -- up to max_batch requests,
- * max_batch_cols block columns (tm_batch_layout) and 2^23 block entries
- * (n times columns: sizes where a lone solve is bound by launch latency),
+ * max_batch_cols block columns (tm_batch_layout) and 2^25 block entries
+ * (n times columns: sizes where one batched solve costs less than its
+ * requests alone),
  * as far as the batch's memory bound fits.  A batched request is solved to the same tolerance but
  * in another rounding order than alone.  The server is internally
  * synchronized; all entry points may be called from any host thread. */

@@ -164,16 +164,19 @@ struct tm_server {
 
 namespace {
 
-// Batches stay within n x (k * ldg) <= 2^23 block entries.  Below that a
-// lone solve is bound by launch latency (its kernels do not fill the GPU) and
-// k problems in one block cost little more than one; above it the k-fold Gram
-// work of the block-diagonal products outweighs the saved launches.  Measured
-// on the serving classes (MIXED, degree-2 polynomial, 8 problems): 16^3,
-// m = 16: 0.166 s alone, 0.046 s in one batch of 8 (5.2e5 entries); 24^3,
-// m = 32: 0.212 s, 0.092 s in batches of 4 (1.8e6); 32^3, m = 76: 0.82 s,
-// 0.54 s in pairs (6.3e6); 40^3, m = 148: 2.60 s, 2.33 s in pairs (2.0e7)
-// and 3.20 s in batches of 4 (4.1e7).
-constexpr int64_t kBatchEntries = (int64_t)1 << 23;
+// Batches stay within n x (k * ldg) <= 2^25 block entries.  Below that a
+// lone solve is bound by launch latency (its kernels do not fill the GPU) or
+// k problems in one block cost less than k alone; above it the k-fold Gram
+// work of the block-diagonal products (all tiles run when problems and Gram
+// tiles do not nest) outweighs the saved launches.  Measured on the serving
+// classes (MIXED, degree-2 polynomial, 8 problems): 16^3, m = 16: 0.166 s
+// alone, 0.046 s in one batch of 8 (5.2e5 entries); 24^3, m = 32: 0.212 s,
+// 0.092 s in batches of 4 (1.8e6); 32^3, m = 76: 0.82 s, 0.54 s in pairs
+// (6.3e6); 40^3, m = 148: 2.60 s, 2.33 s in pairs (2.0e7) and 3.20 s in
+// batches of 4 (4.1e7).  On the 200-request stream (4 slots, batches of up
+// to 8): 2^23 entries 5.93-5.98 solves/s, 2^25 5.97-6.12, 2^26 (48^3 pairs,
+// 5.7e7) 5.22-5.31.
+constexpr int64_t kBatchEntries = (int64_t)1 << 25;
 
 bool same_options(const tm_opts &a, const tm_opts &b) {
     return a.precision == b.precision && a.max_iter == b.max_iter && a.k_rot == b.k_rot &&

@@ -173,7 +173,7 @@ def measured_traffic(key):
     return round(nbytes)
 
 
-def serving_bench(tm, n_requests, slots=4, budget=32 << 30, precondition="chebyshev", max_batch=8):
+def serving_bench(tm, n_requests, slots=4, budget=32 << 30, precondition="chebyshev", max_batch=16):
     """The serving stream (Poisson arrivals, mean 50 ms; grid sides
     {16, 24, 32, 40, 48}; m scaled with N; per-request wells and start block),
     replayed in real time against the continuous-batching server.  Inputs are
@@ -395,7 +395,7 @@ def main():
                     help="solves in flight in the serving stream's server")
     ap.add_argument("--serving-budget", type=float, default=32.0,
                     help="HBM budget of the serving stream's server, GiB")
-    ap.add_argument("--serving-batch", type=int, default=8,
+    ap.add_argument("--serving-batch", type=int, default=16,
                     help="requests per batched solve in the serving stream (0 or 1: no batching)")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving stream (with --serving requests)")

@@ -613,8 +613,23 @@ __global__ __launch_bounds__(kThreads, 2) void gram_bf16x3_kernel(
 
 int gram_tile(int ld) { return ld >= 256 ? 128 : 64; }
 
+// Tiles of a Gram launch: all of them, or, for a block-diagonal result with
+// ldg-wide diagonal blocks (a batched solve), the diagonal tg x tg blocks of
+// BM tiles that hold whole problems (tg = 1 when problems tile BM, ldg / BM
+// when BM tiles a problem; 0: no skipping, the other cases).
+int gram_tg(int BM, int ldg) {
+    if (ldg <= 0) return 0;
+    if (BM % ldg == 0) return 1;
+    if (ldg % BM == 0) return ldg / BM;
+    return 0;
+}
+int gram_ntiles(int T, bool symmetric, int tg) {
+    if (tg > 0) return (T + tg - 1) / tg * (symmetric ? tg * (tg + 1) / 2 : tg * tg);
+    return symmetric ? T * (T + 1) / 2 : T * T;
+}
+
 void gram_shape(int64_t n, int m, bool symmetric, int &BM, int &T, int &nsplit,
-                size_t ws_bytes = 0) {
+                size_t ws_bytes = 0, int ldg = 0) {
     const int ld = leading_dim(m);
     BM = gram_tile(ld);
     T = (ld + BM - 1) / BM;
@@ -622,7 +637,7 @@ void gram_shape(int64_t n, int m, bool symmetric, int &BM, int &T, int &nsplit,
     // row chunks than another), at most 256 MiB of FP64 partials (or the
     // caller's workspace, ws_bytes), and at least 128 rows per split; the
     // grid (tiles x splits) is a multiple of 8 for the XCD mapping
-    const int ntiles = symmetric ? T * (T + 1) / 2 : T * T;
+    const int ntiles = gram_ntiles(T, symmetric, gram_tg(BM, ldg));
     int64_t ns = 512 / ntiles;
     int64_t cap_bytes = (int64_t)256 << 20;
     if (ws_bytes > 0 && (int64_t)ws_bytes < cap_bytes) cap_bytes = (int64_t)ws_bytes;
@@ -1092,29 +1107,26 @@ size_t gram_partials_bytes(int64_t n, int m, bool symmetric, size_t ws_bytes) {
     return (size_t)ns * m * m * sizeof(double);
 }
 
-// Tiles of a Gram launch: all of them, or, for a block-diagonal result with
-// ldg-wide diagonal blocks (a batched solve), the diagonal tg x tg blocks of
-// BM tiles that hold whole problems (tg = 1 when problems tile BM, ldg / BM
-// when BM tiles a problem; no skipping otherwise).  The split count stays
-// that of the full launch, so the partials workspace is the same.
+// The launch of a Gram: its tiles (gram_tg, gram_ntiles) times the split
+// count gram_shape gives for that many tiles.
 static void gram_plan(int T, int BM, bool symmetric, int nsplit, BatchCols bc, int &tg, int &ntiles,
                       int &nwork, int &grid) {
-    tg = 0;
-    if (bc.ldg > 0) {
-        if (BM % bc.ldg == 0) tg = 1;
-        else if (bc.ldg % BM == 0) tg = bc.ldg / BM;
-    }
-    if (tg > 0) ntiles = (T + tg - 1) / tg * (symmetric ? tg * (tg + 1) / 2 : tg * tg);
-    else ntiles = symmetric ? T * (T + 1) / 2 : T * T;
+    tg = gram_tg(BM, bc.ldg);
+    ntiles = gram_ntiles(T, symmetric, tg);
     nwork = ntiles * nsplit;
     grid = (nwork + 7) / 8 * 8;
 }
 
-size_t gram_workspace(int64_t n, int m) {
-    int BM, T, ns_full, ns_sym;
-    gram_shape(n, m, false, BM, T, ns_full);
-    gram_shape(n, m, true, BM, T, ns_sym);
-    return (size_t)std::max(ns_full, ns_sym) * m * m * sizeof(double);
+size_t gram_workspace(int64_t n, int m, int ldg) {
+    // the largest split count of the full launches and, for a batch, of the
+    // launches over its diagonal tile blocks (more splits for fewer tiles)
+    int BM, T, ns, most = 0;
+    for (int l : {0, ldg})
+        for (bool sym : {false, true}) {
+            gram_shape(n, m, sym, BM, T, ns, 0, l);
+            most = std::max(most, ns);
+        }
+    return (size_t)most * m * m * sizeof(double);
 }
 
 template <typename TA, typename TM>
@@ -1123,7 +1135,7 @@ void gram(hipStream_t s, int64_t n, int m, const TA *A, const TA *B,
           double *out, bool reduce, TM *xshift, TM *wpad, size_t ws_bytes, BatchCols bc) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
-    gram_shape(n, m, symmetric, BM, T, nsplit, ws_bytes);
+    gram_shape(n, m, symmetric, BM, T, nsplit, ws_bytes, bc.ldg);
     int tg, ntiles, nwork, grid;
     gram_plan(T, BM, symmetric, nsplit, bc, tg, ntiles, nwork, grid);
     constexpr int KT = stage_rows<TM>();
@@ -1159,7 +1171,7 @@ void gram_update(hipStream_t s, int64_t n, int m, const TA *C, const TP *P, cons
                  TA *Cn, double *partials, double *out, BatchCols bc) {
     const int ld = leading_dim(m);
     int BM, T, nsplit;
-    gram_shape(n, m, true, BM, T, nsplit);
+    gram_shape(n, m, true, BM, T, nsplit, 0, bc.ldg);
     int tg, ntiles, nwork, grid;
     gram_plan(T, BM, true, nsplit, bc, tg, ntiles, nwork, grid);
     constexpr int KT = stage_rows<TM>();

@@ -158,7 +158,9 @@ struct BatchCols {
 };
 
 // Gram products out = A^T B' (m x m, FP64), B' = B - A diag(h) if h --------
-size_t gram_workspace(int64_t n, int m);
+// Partials workspace of the Gram products; ldg > 0: also of the batched
+// launches over the diagonal blocks of a block-diagonal result (BatchCols).
+size_t gram_workspace(int64_t n, int m, int ldg = 0);
 // Bytes of FP64 partials gram() (symmetric or not) uses when its workspace
 // holds ws_bytes (0: the default workspace, gram_workspace): fewer row
 // splits when the workspace is smaller.

@@ -99,7 +99,10 @@ size_t batch_footprint(int64_t n, int64_t nnz, int k, int m, int precision, int 
     const int mb = k * batch_group_ld(k, m);
     // the solve on the whole block, each problem's diagonal in FP64 and
     // FP32, controller states and polynomial coefficients, upload slack
+    // (the Gram partials of the diagonal-block launches may take more splits)
+    const int ldg = batch_group_ld(k, m);
     return solve_footprint(n, nnz, mb, precision, precondition, 0) +
+           (gram_workspace(n, mb, ldg) - gram_workspace(n, mb)) +
            (size_t)k * ((size_t)n * 12 + sizeof(CgState) + 16) + 256;
 }
 
@@ -224,7 +227,7 @@ struct Solver::Impl {
         Amat.reset(new DevMem(ctx, md));
         U.reset(new DevMem(ctx, md));
         Wp.reset(new DevMem(ctx, (size_t)ld * ld * sizeof(double)));
-        gram_ws.reset(new DevMem(ctx, gram_workspace(n, m)));
+        gram_ws.reset(new DevMem(ctx, gram_workspace(n, m, batched ? ldg : 0)));
         dot_ws.reset(new DevMem(ctx, std::max({coldots_workspace(n, ld), spmm_partials_workspace(n, ld),
                                                rot_partials_workspace(n, m)})));
         chol_ws.reset(new DevMem(ctx, chol_workspace(m)));

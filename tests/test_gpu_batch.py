@@ -271,3 +271,25 @@ def test_batch_widest_and_single_column(tm, ctx):
     rs = (_abi.tm_result * 129)()
     assert _abi.lib().tm_solve_batch(ctx.handle, H.handle, 16, 1e-8, None, None, None, None, rs) \
         == _abi.TM_ENOTSUP
+
+
+def test_batch_problems_spanning_gram_tiles(tm, ctx):
+    """Two problems of m = 256 (256 columns each, 512 in all): each problem
+    spans 2 x 2 Gram tiles of 128, the Cholesky runs as two 256-wide
+    diagonal blocks of four block columns each, and the products loop over
+    one problem's rows per column tile.  Both problems reach their LAPACK
+    eigenvalues (343 rows each; the seeds give gaps of about 1 % of the
+    spectrum after the 256th eigenvalue)."""
+    side, k, m = 7, 2, 256
+    print_case(test="batch_spanning", side=side, k=k, m=m)
+    A, V, Hs = _batch(side, k, [2, 3], seed0=1500)
+    n = side ** 3
+    H = tm.set_matrix_batch(ctx, *A, V)
+    assert tm.batch_layout(k, m) == (256, 512)
+    res, _, eig = tm.solve_batch(ctx, H, m, 1e-8, None, tm.opts(precision="full_dp", seed=5),
+                                 want_vectors=False)
+    eig = host(eig)
+    for g in range(k):
+        assert res[g]["converged"] == 1, (g, res[g])
+        lam = np.linalg.eigvalsh(_dense(Hs[g], n))[:m]
+        assert np.max(np.abs(eig[g] - lam)) <= 1e-9, g

@@ -156,9 +156,9 @@ def kernel_rooflines(tm, ctx, H, p, reps=20, stencil_too=False):
 TRAFFIC_CONFIG = "c2"
 TRAFFIC = {
     "rot_grad_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                         "30a97196f8703d6a0fe6d2675aa4022fafb08db8", 2.0 * 282350.1 * 1024 + 124416.0 * 1024),
+                         "30a97196f8703d6a0fe6d2675aa4022fafb08db8", 2.0 * 282383.1 * 1024 + 124416.0 * 1024),
     "gram_mp2/f64": ("paper_1108_4509_amd/csrc/k_gemm.hip",
-                     "30a97196f8703d6a0fe6d2675aa4022fafb08db8", 2.0 * 325724.9 * 1024 + 164352.0 * 1024),
+                     "30a97196f8703d6a0fe6d2675aa4022fafb08db8", 2.0 * 325831.4 * 1024 + 164352.0 * 1024),
 }
 
 

@@ -738,12 +738,16 @@ int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
     auto Cv = reinterpret_cast<const typename Vec<T>::type *>(C);
     auto Xv = reinterpret_cast<typename Vec<T>::type *>(X);
     // chunk width and in-flight gathers: 256-byte chunks (16 lanes of 16-byte
-    // vectors) with 4 rows per lane group in flight, for FP32 and FP64 rows.
-    // Measured (HIP events, 20 launches): at 48^3, m = 256, FP64 147 us
-    // against 149 us with 512-byte chunks and 8 rows; at 64^3 13-point,
-    // m = 512, 944 against 1028 us (the +-2 plane window of a 512-byte chunk
-    // no longer fits one XCD's L2); 128-byte chunks, 8 nonzeros per batch
-    // or 2 rows per group were slower at both sizes
+    // vectors) with 4 rows per lane group in flight, one nonzero of each per
+    // batch, for FP32 and FP64 rows.  Measured (HIP events, 20 launches): at
+    // 48^3, m = 256, FP64 147 us against 149 us with 512-byte chunks and 8
+    // rows; at 64^3 13-point, m = 512, 944 against 1028 us (the +-2 plane
+    // window of a 512-byte chunk no longer fits one XCD's L2); 128-byte
+    // chunks, 8 nonzeros per batch or 2 rows per group were slower at both
+    // sizes.  Once the epilogue's own row is loaded with the first gathers
+    // (121 registers), one nonzero per batch beats two: 48^3 FP64 134 against
+    // 144 us, FP32 52 either way; 64^3 13-point FP64 920 against 945, FP32
+    // 463 against 471 us
     if (ldv % 16 == 0) {
         const int nchunks = ldv / 16;
         const int64_t rpb = kChunkRows;
@@ -752,7 +756,7 @@ int spmm_csr(hipStream_t s, const CsrDev &H, int ld, const T *C, T *X, int ndot,
         const int nrb = (int)nrb64;
         int64_t grid = (int64_t)nchunks * nrb;
         grid = (grid + 7) / 8 * 8;
-        hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, 16, 2, 4>), dim3((unsigned)grid), dim3(256), 0, s,
+        hipLaunchKernelGGL((spmm_csr_chunk_kernel<T, 16, 1, 4>), dim3((unsigned)grid), dim3(256), 0, s,
                            H.n, (int)rpb, nrb, nchunks, H.rowptr, H.col, val, Cv, Xv, ldv, ndot,
                            partials, epi);
         TM_HIP(hipGetLastError());

@@ -379,8 +379,8 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
     const T eb = (T)(epi.gab ? epi.gab[2 * grp + 1] : epi.b);
     const V *E = reinterpret_cast<const V *>(epi.E);
     const bool own = epi.affine || ndot > 0 || Dg;   // the epilogue reads the row's own c
-    // c: the row's own vector of C (loaded ahead by the caller)
-    auto finish = [&](int64_t r, V acc, V c) {
+    // c, e: the row's own vectors of C and E (loaded ahead by the caller)
+    auto finish = [&](int64_t r, V acc, V c, V e) {
         if (own) {
             if (Dg) {
                 const T dr = Dg[r];
@@ -392,8 +392,6 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
                 for (int w = 0; w < W; ++w) acc[w] = fma(eb, acc[w], ea * c[w]);
             }
             if (ndot > 0) {
-                V e = V(0);
-                if (ndot == 3) e = E[r * ldv + cv];
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
                     ds[0][w] += (double)c[w] * (double)acc[w];
@@ -410,7 +408,7 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
         // past a row's end read entry 0 with weight zero
         for (int i = slot; i < nr; i += RG * RPP) {
             int s0[RG], s1[RG];
-            V acc[RG], cown[RG];
+            V acc[RG], cown[RG], eown[RG];
             int len = 0;
 #pragma unroll
             for (int g = 0; g < RG; ++g) {
@@ -420,11 +418,11 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
                 s1[g] = has ? (int)(rp[ig + 1] - e0) : 0;
                 len = max(len, s1[g] - s0[g]);
                 acc[g] = V(0);
-                // the epilogue's own row of C is loaded with the first
-                // gathers, not after them (E stays in the epilogue: loading
-                // it here too costs a wave per SIMD of occupancy)
+                // the epilogue's own rows of C and E are loaded with the
+                // first gathers, not after them
                 const int64_t rr = r_begin + (has ? ig : 0);
                 cown[g] = own ? C[rr * ldv + cv] : V(0);
+                eown[g] = ndot == 3 ? E[rr * ldv + cv] : V(0);
             }
             for (int o = 0; o < len; o += UB) {
                 V v[RG][UB];
@@ -445,7 +443,7 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
             }
 #pragma unroll
             for (int g = 0; g < RG; ++g)
-                if (i + g * RPP < nr) finish(r_begin + i + g * RPP, acc[g], cown[g]);
+                if (i + g * RPP < nr) finish(r_begin + i + g * RPP, acc[g], cown[g], eown[g]);
         }
     } else {
         for (int i = slot; i < nr; i += RPP) {
@@ -453,7 +451,7 @@ __global__ __launch_bounds__(256) void spmm_csr_chunk_kernel(
             for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
                 acc = fma_v<V, T>(val[k], C[(int64_t)col[k] * ldv + cv], acc);
             const int64_t r = r_begin + i;
-            finish(r, acc, own ? C[r * ldv + cv] : V(0));
+            finish(r, acc, own ? C[r * ldv + cv] : V(0), ndot == 3 ? E[r * ldv + cv] : V(0));
         }
     }
     if (ndot > 0) {
